@@ -1,0 +1,304 @@
+"""FP64 CPU oracle for the finite-volume hydrodynamics hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The GPU
+library never calls it and shares no code with it.
+
+The arithmetic lives in ``hydro_oracle.c`` (plain C, double precision); this
+module only marshals NumPy arrays through ctypes, plus three plain helpers
+written here in Python: exact conserved totals (``math.fsum``), the time
+loop of Alg. 2 (single level) and the relative L1 norm of eq. L1ErrorNorm.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ESTATE = 0, -1, -4
+HLL, HLLC = 0, 1
+LIM_THETA, LIM_LEARNED = 0, 1
+MLP_IN, MLP_H = 4, 32
+MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, what=""):
+        super().__init__(f"oracle {what} returned status {status}")
+        self.status = status
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no FP contraction)."""
+    src = os.path.join(_HERE, "hydro_oracle.c")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-shared", "-fPIC",
+               "-o", LIB_PATH, src, "-lm"]
+        subprocess.check_call(cmd)
+    return LIB_PATH
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int64 * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("bc", (ctypes.c_int * 2) * 3),
+        ("solver", ctypes.c_int),
+        ("limiter", ctypes.c_int),
+        ("theta", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
+        ("mlp", ctypes.POINTER(ctypes.c_double)),
+        ("mlp_bf16", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(_Desc)
+        dp = ctypes.POINTER(ctypes.c_double)
+        for name, args, res in [
+            ("orc_prim_to_cons", [P, dp, dp], ctypes.c_int),
+            ("orc_cons_to_prim", [P, dp, dp], ctypes.c_int),
+            ("orc_rhs", [P, dp, dp], ctypes.c_int),
+            ("orc_step", [P, dp, ctypes.c_double], ctypes.c_int),
+            ("orc_cfl_dt", [P, dp, ctypes.c_double, dp], ctypes.c_int),
+            ("orc_limiter_theta", [ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_double),
+            ("orc_limiter_learned", [dp, ctypes.c_int, dp], ctypes.c_double),
+            ("orc_mlp_forward", [dp, ctypes.c_int, dp], ctypes.c_double),
+            ("orc_flux", [P, ctypes.c_int, dp, dp, dp], None),
+            ("orc_physical", [P, ctypes.c_int, dp, dp, dp, dp, dp], None),
+            ("orc_hllc_star", [P, ctypes.c_int, dp, dp, dp], None),
+        ]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Desc:
+    """Patch description for the oracle (mirrors a workloads.Problem)."""
+
+    def __init__(self, ndim, n, lo, hi, gamma, bc, solver=HLLC, theta=2.0,
+                 limiter=LIM_THETA, accel=(0.0, 0.0, 0.0), mlp: Optional[np.ndarray] = None,
+                 mlp_bf16: bool = False):
+        self.ndim = ndim
+        self.n = tuple(int(v) for v in n)
+        self.lo, self.hi = tuple(lo), tuple(hi)
+        self.gamma = float(gamma)
+        self.bc = tuple(tuple(b) for b in bc)
+        self.solver = solver
+        self.theta = float(theta)
+        self.limiter = limiter
+        self.accel = tuple(accel)
+        self.mlp = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
+        if self.mlp is not None:
+            assert self.mlp.size == MLP_NPARAM
+        self.mlp_bf16 = bool(mlp_bf16)
+
+    @classmethod
+    def from_problem(cls, prob, solver=HLLC, theta=None, limiter=LIM_THETA, mlp=None,
+                     mlp_bf16=False):
+        return cls(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.bc, solver,
+                   prob.theta if theta is None else theta, limiter, prob.accel, mlp, mlp_bf16)
+
+    @property
+    def nv(self):
+        return self.ndim + 2
+
+    @property
+    def ncell(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+    def dV(self):
+        v = 1.0
+        for q in range(self.ndim):
+            v *= (self.hi[q] - self.lo[q]) / self.n[q]
+        return v
+
+    def c(self) -> _Desc:
+        d = _Desc()
+        d.ndim = self.ndim
+        for q in range(3):
+            d.n[q] = self.n[q]
+            d.lo[q] = self.lo[q]
+            d.hi[q] = self.hi[q]
+            d.accel[q] = self.accel[q]
+            d.bc[q][0] = self.bc[q][0]
+            d.bc[q][1] = self.bc[q][1]
+        d.gamma = self.gamma
+        d.solver = self.solver
+        d.limiter = self.limiter
+        d.theta = self.theta
+        d.mlp = _dp(self.mlp) if self.mlp is not None else ctypes.POINTER(ctypes.c_double)()
+        d.mlp_bf16 = int(self.mlp_bf16)
+        self._keep = d
+        return d
+
+
+def _flat(desc: Desc, a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(desc.nv, desc.ncell))
+
+
+def prim_to_cons(desc: Desc, W) -> np.ndarray:
+    W = _flat(desc, W)
+    U = np.empty_like(W)
+    st = lib().orc_prim_to_cons(ctypes.byref(desc.c()), _dp(W), _dp(U))
+    if st != OK:
+        raise OracleError(st, "prim_to_cons")
+    return U
+
+
+def cons_to_prim(desc: Desc, U, check: bool = True) -> np.ndarray:
+    U = _flat(desc, U)
+    W = np.empty_like(U)
+    st = lib().orc_cons_to_prim(ctypes.byref(desc.c()), _dp(U), _dp(W))
+    if check and st != OK:
+        raise OracleError(st, "cons_to_prim")
+    return W
+
+
+def rhs(desc: Desc, U) -> np.ndarray:
+    U = _flat(desc, U)
+    L = np.empty_like(U)
+    st = lib().orc_rhs(ctypes.byref(desc.c()), _dp(U), _dp(L))
+    if st != OK:
+        raise OracleError(st, "rhs")
+    return L
+
+
+def step(desc: Desc, U, dt: float) -> np.ndarray:
+    """One full two-stage step; returns a new array."""
+    U = _flat(desc, U).copy()
+    st = lib().orc_step(ctypes.byref(desc.c()), _dp(U), float(dt))
+    if st != OK:
+        raise OracleError(st, "step")
+    return U
+
+
+def cfl_dt(desc: Desc, U, cfl: float) -> float:
+    U = _flat(desc, U)
+    out = np.zeros(1)
+    st = lib().orc_cfl_dt(ctypes.byref(desc.c()), _dp(U), float(cfl), _dp(out))
+    if st != OK:
+        raise OracleError(st, "cfl_dt")
+    return float(out[0])
+
+
+def totals(desc: Desc, U) -> np.ndarray:
+    """Exactly rounded sums of U_k over the cells times the cell volume,
+    returned as (D, S_x, S_y, S_z, G) with zeros for absent components."""
+    U = _flat(desc, U)
+    out = np.zeros(5)
+    dv = desc.dV()
+    nd = desc.ndim
+    out[0] = math.fsum(U[0].tolist()) * dv
+    for r in range(nd):
+        out[1 + r] = math.fsum(U[1 + r].tolist()) * dv
+    out[4] = math.fsum(U[nd + 1].tolist()) * dv
+    return out
+
+
+def run(desc: Desc, U, t_end: float, cfl: float, max_steps: int = 10 ** 7):
+    """Single-level time loop (Alg. 2 with one level): dt = C dt_CFL, the
+    last step clipped to end exactly at t_end.  Returns (U, steps)."""
+    U = _flat(desc, U).copy()
+    t = 0.0
+    nsteps = 0
+    while t < t_end and nsteps < max_steps:
+        dt = min(cfl_dt(desc, U, cfl), t_end - t)
+        U = step(desc, U, dt)
+        t += dt
+        nsteps += 1
+    return U, nsteps
+
+
+def run_steps(desc: Desc, U, nsteps: int, cfl: float):
+    """``nsteps`` steps, each of size C dt_CFL of the state it starts from."""
+    U = _flat(desc, U).copy()
+    for _ in range(nsteps):
+        U = step(desc, U, cfl_dt(desc, U, cfl))
+    return U
+
+
+def l1_error(num, exact) -> float:
+    """Relative L1 norm, eq. L1ErrorNorm: sum|num - exact| / sum|exact|."""
+    num = np.asarray(num, dtype=np.float64).ravel()
+    exact = np.asarray(exact, dtype=np.float64).ravel()
+    return float(np.sum(np.abs(num - exact)) / np.sum(np.abs(exact)))
+
+
+def convergence_rate(l1_a: float, n_a: int, l1_b: float, n_b: int) -> float:
+    """-p from eq. convergenceRate: log(L1_a / L1_b) / log(N_a / N_b)."""
+    return math.log(l1_a / l1_b) / math.log(n_a / n_b)
+
+
+# ---- pointwise pieces ----
+
+def limiter_theta(dm: float, dp: float, theta: float) -> float:
+    return lib().orc_limiter_theta(float(dm), float(dp), float(theta))
+
+
+def limiter_learned(params: np.ndarray, w5, bf16: bool = False) -> float:
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    w = np.ascontiguousarray(w5, dtype=np.float64)
+    return lib().orc_limiter_learned(_dp(p), int(bf16), _dp(w))
+
+
+def mlp_forward(params: np.ndarray, x, bf16: bool = False) -> float:
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().orc_mlp_forward(_dp(p), int(bf16), _dp(xx))
+
+
+def flux(desc: Desc, q: int, wl, wr) -> np.ndarray:
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    f = np.zeros(desc.nv)
+    lib().orc_flux(ctypes.byref(desc.c()), int(q), _dp(wl), _dp(wr), _dp(f))
+    return f
+
+
+def physical(desc: Desc, q: int, w):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    U = np.zeros(desc.nv)
+    F = np.zeros(desc.nv)
+    lm = np.zeros(1)
+    lp = np.zeros(1)
+    lib().orc_physical(ctypes.byref(desc.c()), int(q), _dp(w), _dp(U), _dp(F), _dp(lm), _dp(lp))
+    return U, F, float(lm[0]), float(lp[0])
+
+
+def hllc_star(desc: Desc, q: int, wl, wr) -> dict:
+    nv = desc.nv
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    out = np.zeros(3 + 4 * nv)
+    lib().orc_hllc_star(ctypes.byref(desc.c()), int(q), _dp(wl), _dp(wr), _dp(out))
+    return {
+        "alpha_m": out[0], "p_star_L": out[1], "p_star_R": out[2],
+        "U_star_L": out[3:3 + nv], "U_star_R": out[3 + nv:3 + 2 * nv],
+        "F_star_L": out[3 + 2 * nv:3 + 3 * nv], "F_star_R": out[3 + 3 * nv:3 + 4 * nv],
+    }

@@ -1,0 +1,533 @@
+/*
+ * FP64 CPU oracle of the finite-volume hydrodynamics update.  TEST
+ * INFRASTRUCTURE ONLY (see hydro_oracle.h).  Plain loops, one step of the
+ * method at a time, separate arrays for every intermediate; no blocking,
+ * fusion or reordering beyond what the paper's equations state.
+ */
+#include "hydro_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NG 2 /* ghost layers: the 3-cell generalised-minmod and the 5-cell learned stencil */
+
+static int nvars(const orc_desc *d) { return d->ndim + 2; }
+
+static int64_t ncells(const orc_desc *d) { return d->n[0] * d->n[1] * d->n[2]; }
+
+static double cell_width(const orc_desc *d, int q) { return (d->hi[q] - d->lo[q]) / (double)d->n[q]; }
+
+static int valid_desc(const orc_desc *d)
+{
+    if (!d || d->ndim < 1 || d->ndim > 3 || !(d->gamma > 1.0)) return 0;
+    for (int q = 0; q < 3; ++q) {
+        if (d->n[q] < 1) return 0;
+        if (q < d->ndim) {
+            if (d->n[q] < 2 || !(d->hi[q] > d->lo[q])) return 0;
+            for (int s = 0; s < 2; ++s)
+                if (d->bc[q][s] < 0 || d->bc[q][s] > 2) return 0;
+            if ((d->bc[q][0] == ORC_BC_PERIODIC) != (d->bc[q][1] == ORC_BC_PERIODIC)) return 0;
+        } else if (d->n[q] != 1) {
+            return 0;
+        }
+    }
+    if (d->limiter == ORC_LIM_LEARNED && !d->mlp) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fluid variables (Sec. 3.4): D = n, S = m n v, G = e + m n |v|^2 / 2,     */
+/* p = (gamma - 1) e from the polytropic closure; m = 1.                    */
+/* ------------------------------------------------------------------------ */
+
+static void prim_to_cons_1(int nd, double gamma, const double *w, double *u)
+{
+    double rho = w[0], p = w[nd + 1], v2 = 0.0;
+    for (int r = 0; r < nd; ++r) v2 += w[1 + r] * w[1 + r];
+    u[0] = rho;
+    for (int r = 0; r < nd; ++r) u[1 + r] = rho * w[1 + r];
+    u[nd + 1] = p / (gamma - 1.0) + 0.5 * rho * v2;
+}
+
+static int cons_to_prim_1(int nd, double gamma, const double *u, double *w)
+{
+    double D = u[0], s2 = 0.0;
+    w[0] = D;
+    for (int r = 0; r < nd; ++r) {
+        w[1 + r] = u[1 + r] / D;
+        s2 += u[1 + r] * u[1 + r];
+    }
+    double e = u[nd + 1] - 0.5 * s2 / D;
+    w[nd + 1] = (gamma - 1.0) * e;
+    int ok = (w[0] > 0.0) && (w[nd + 1] > 0.0) && isfinite(w[0]) && isfinite(w[nd + 1]);
+    for (int r = 0; r < nd; ++r) ok = ok && isfinite(w[1 + r]);
+    return ok;
+}
+
+int orc_prim_to_cons(const orc_desc *d, const double *W, double *U)
+{
+    if (!valid_desc(d)) return ORC_EINVAL;
+    int nv = nvars(d);
+    int64_t N = ncells(d);
+    double w[5], u[5];
+    for (int64_t c = 0; c < N; ++c) {
+        for (int v = 0; v < nv; ++v) w[v] = W[v * N + c];
+        prim_to_cons_1(d->ndim, d->gamma, w, u);
+        for (int v = 0; v < nv; ++v) U[v * N + c] = u[v];
+    }
+    return ORC_OK;
+}
+
+int orc_cons_to_prim(const orc_desc *d, const double *U, double *W)
+{
+    if (!valid_desc(d)) return ORC_EINVAL;
+    int nv = nvars(d);
+    int64_t N = ncells(d);
+    int status = ORC_OK;
+    double w[5], u[5];
+    for (int64_t c = 0; c < N; ++c) {
+        for (int v = 0; v < nv; ++v) u[v] = U[v * N + c];
+        if (!cons_to_prim_1(d->ndim, d->gamma, u, w)) status = ORC_ESTATE;
+        for (int v = 0; v < nv; ++v) W[v * N + c] = w[v];
+    }
+    return status;
+}
+
+/* Physical flux normal to q (eqs. FluxBaryon, FluxMomentumFluid and the
+ * energy flux) and the outer wave speeds v_q -/+ c_s, c_s = sqrt(gamma p / rho). */
+void orc_physical(const orc_desc *d, int q, const double *w, double *U, double *F,
+                  double *lam_minus, double *lam_plus)
+{
+    int nd = d->ndim;
+    prim_to_cons_1(nd, d->gamma, w, U);
+    double rho = w[0], p = w[nd + 1], vq = w[1 + q];
+    F[0] = rho * vq;
+    for (int r = 0; r < nd; ++r) F[1 + r] = rho * w[1 + r] * vq + (r == q ? p : 0.0);
+    F[nd + 1] = (U[nd + 1] + p) * vq; /* (e + p + rho |v|^2 / 2) v_q */
+    double cs = sqrt(d->gamma * p / rho);
+    *lam_minus = vq - cs;
+    *lam_plus = vq + cs;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Riemann solvers (Sec. 3.2 and 3.4)                                       */
+/* ------------------------------------------------------------------------ */
+
+static double max3(double a, double b, double c) { return fmax(a, fmax(b, c)); }
+
+/* Davis-type outer speeds: alpha_+/- = max(0, +/-lambda_+/-(U_L), +/-lambda_+/-(U_R)). */
+static void outer_speeds(double lmL, double lpL, double lmR, double lpR, double *ap, double *am)
+{
+    *ap = max3(0.0, lpL, lpR);
+    *am = max3(0.0, -lmL, -lmR);
+}
+
+/* HLLC middle states for side K (0 = left, 1 = right) from the jump
+ * conditions across the outer wave s_K (s_L = -alpha_-, s_R = +alpha_+):
+ *   rho*_K = rho_K (s_K - v_K) / (s_K - alpha_m)
+ *   p*_K   = p_K + rho_K (s_K - v_K)(alpha_m - v_K)
+ *   G*_K   = [(s_K - v_K) G_K - p_K v_K + p*_K alpha_m] / (s_K - alpha_m)
+ * with the normal velocity alpha_m and unchanged transverse velocities.  The
+ * printed pressure and energy relations carry a sign slip and a starred G on
+ * the right-hand side; these are the forms the jump conditions give. */
+static void hllc_side(const orc_desc *d, int q, const double *w, const double *U, double sK,
+                      double am_, double *Ustar, double *pstar)
+{
+    int nd = d->ndim;
+    double rho = w[0], vK = w[1 + q], pK = w[nd + 1], GK = U[nd + 1];
+    double rs = rho * (sK - vK) / (sK - am_);
+    double ps = pK + rho * (sK - vK) * (am_ - vK);
+    double Gs = ((sK - vK) * GK - pK * vK + ps * am_) / (sK - am_);
+    Ustar[0] = rs;
+    for (int r = 0; r < nd; ++r) Ustar[1 + r] = (r == q) ? rs * am_ : rs * w[1 + r];
+    Ustar[nd + 1] = Gs;
+    *pstar = ps;
+}
+
+/* Batten's middle-wave speed, eq. MiddleWaveSpeed: S_HLL / (m D_HLL). */
+static double middle_speed(int nd, int q, const double *wl, const double *wr, double ap, double am)
+{
+    double rl = wl[0], vl = wl[1 + q], pl = wl[nd + 1];
+    double rr = wr[0], vr = wr[1 + q], pr = wr[nd + 1];
+    double num = rr * vr * (ap - vr) + rl * vl * (am + vl) - (pr - pl);
+    double den = rr * (ap - vr) + rl * (am + vl);
+    return num / den;
+}
+
+void orc_flux(const orc_desc *d, int q, const double *wl, const double *wr, double *f)
+{
+    int nv = nvars(d);
+    double UL[5], FL[5], UR[5], FR[5], lmL, lpL, lmR, lpR, ap, am;
+    orc_physical(d, q, wl, UL, FL, &lmL, &lpL);
+    orc_physical(d, q, wr, UR, FR, &lmR, &lpR);
+    outer_speeds(lmL, lpL, lmR, lpR, &ap, &am);
+    if (d->solver == ORC_HLL) {
+        /* eq. FluxHLL; both speeds vanish only for c = 0 on both sides */
+        if (ap + am > 0.0) {
+            for (int v = 0; v < nv; ++v)
+                f[v] = (ap * FL[v] + am * FR[v] - ap * am * (UR[v] - UL[v])) / (ap + am);
+        } else {
+            for (int v = 0; v < nv; ++v) f[v] = 0.5 * (FL[v] + FR[v]);
+        }
+        return;
+    }
+    /* eq. FluxHLLC, cases tested in the printed order */
+    if (am == 0.0) {
+        for (int v = 0; v < nv; ++v) f[v] = FL[v];
+        return;
+    }
+    if (ap == 0.0) {
+        for (int v = 0; v < nv; ++v) f[v] = FR[v];
+        return;
+    }
+    double a_m = middle_speed(d->ndim, q, wl, wr, ap, am);
+    double Us[5], ps;
+    if (a_m >= 0.0) {
+        double sL = -am;
+        hllc_side(d, q, wl, UL, sL, a_m, Us, &ps);
+        for (int v = 0; v < nv; ++v) f[v] = FL[v] + sL * (Us[v] - UL[v]);
+    } else {
+        double sR = ap;
+        hllc_side(d, q, wr, UR, sR, a_m, Us, &ps);
+        for (int v = 0; v < nv; ++v) f[v] = FR[v] + sR * (Us[v] - UR[v]);
+    }
+}
+
+void orc_hllc_star(const orc_desc *d, int q, const double *wl, const double *wr, double *out)
+{
+    int nv = nvars(d);
+    double UL[5], FL[5], UR[5], FR[5], lmL, lpL, lmR, lpR, ap, am;
+    orc_physical(d, q, wl, UL, FL, &lmL, &lpL);
+    orc_physical(d, q, wr, UR, FR, &lmR, &lpR);
+    outer_speeds(lmL, lpL, lmR, lpR, &ap, &am);
+    double a_m = middle_speed(d->ndim, q, wl, wr, ap, am);
+    double UsL[5], UsR[5], psL, psR;
+    hllc_side(d, q, wl, UL, -am, a_m, UsL, &psL);
+    hllc_side(d, q, wr, UR, ap, a_m, UsR, &psR);
+    out[0] = a_m;
+    out[1] = psL;
+    out[2] = psR;
+    for (int v = 0; v < nv; ++v) {
+        out[3 + v] = UsL[v];
+        out[3 + nv + v] = UsR[v];
+        out[3 + 2 * nv + v] = FL[v] - am * (UsL[v] - UL[v]);
+        out[3 + 3 * nv + v] = FR[v] + ap * (UsR[v] - UR[v]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Slope limiters                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* MM: the argument of smallest magnitude if all three share a sign, else 0. */
+static double minmod3(double a, double b, double c)
+{
+    if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+    if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+    return 0.0;
+}
+
+/* eq. MinMod on a uniform grid, as a per-cell difference:
+ * sigma = MM(theta dm, (dm + dp) / 2, theta dp). */
+double orc_limiter_theta(double dm, double dp, double theta)
+{
+    return minmod3(theta * dm, 0.5 * (dm + dp), theta * dp);
+}
+
+/* round to the nearest bfloat16 (ties to even) through binary32 */
+static double to_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan unchanged */
+    b += 0x7fffu + ((b >> 16) & 1u);
+    b &= 0xffff0000u;
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+/* Parameters: W1[32][4], b1[32], W2[32][32], b2[32], w3[32], b3.
+ * h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3.
+ * With bf16 set, x, W1, h1 and W2 are rounded to bfloat16 (the operands of
+ * the two matrix layers); biases, w3, b3 and all arithmetic stay double. */
+double orc_mlp_forward(const double *P, int bf16, const double *x)
+{
+    const double *W1 = P, *b1 = W1 + ORC_MLP_H * ORC_MLP_IN, *W2 = b1 + ORC_MLP_H;
+    const double *b2 = W2 + ORC_MLP_H * ORC_MLP_H, *w3 = b2 + ORC_MLP_H, *b3 = w3 + ORC_MLP_H;
+    double xi[ORC_MLP_IN], h1[ORC_MLP_H], h2[ORC_MLP_H];
+    for (int k = 0; k < ORC_MLP_IN; ++k) xi[k] = bf16 ? to_bf16(x[k]) : x[k];
+    for (int j = 0; j < ORC_MLP_H; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < ORC_MLP_IN; ++k) {
+            double wjk = W1[j * ORC_MLP_IN + k];
+            s += (bf16 ? to_bf16(wjk) : wjk) * xi[k];
+        }
+        s += b1[j];
+        h1[j] = s > 0.0 ? s : 0.0;
+        if (bf16) h1[j] = to_bf16(h1[j]);
+    }
+    for (int j = 0; j < ORC_MLP_H; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < ORC_MLP_H; ++k) {
+            double wjk = W2[j * ORC_MLP_H + k];
+            s += (bf16 ? to_bf16(wjk) : wjk) * h1[k];
+        }
+        s += b2[j];
+        h2[j] = s > 0.0 ? s : 0.0;
+    }
+    double y = b3[0];
+    for (int k = 0; k < ORC_MLP_H; ++k) y += w3[k] * h2[k];
+    return y;
+}
+
+/* Learned slope from w[0..4]: inputs are the four one-sided differences over
+ * s = max|d| + 1e-12 (|w_2| + 1e-30); the network output times s is clamped
+ * to the TVD region 0 <= sign(D) sigma <= 2 min(|D-|, |D+|), and to 0 where
+ * the two central differences D- = d2, D+ = d3 disagree in sign. */
+double orc_limiter_learned(const double *params, int bf16, const double *w)
+{
+    double dlt[4];
+    for (int k = 0; k < 4; ++k) dlt[k] = w[k + 1] - w[k];
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k) s = fmax(s, fabs(dlt[k]));
+    s += 1e-12 * (fabs(w[2]) + 1e-30);
+    double x[4];
+    for (int k = 0; k < 4; ++k) x[k] = dlt[k] / s;
+    double sigma = s * orc_mlp_forward(params, bf16, x);
+    double dm = dlt[1], dp = dlt[2];
+    if (dm * dp <= 0.0) return 0.0;
+    double lim = 2.0 * fmin(fabs(dm), fabs(dp));
+    double sg = dp > 0.0 ? 1.0 : -1.0;
+    return sg * fmin(fmax(sg * sigma, 0.0), lim);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ghost cells (reading of Alg. 1 line 7): ng layers filled from cell-centre */
+/* primitives; periodic wraps, outflow copies the nearest interior cell,    */
+/* reflecting mirrors and negates the normal velocity.                      */
+/* ------------------------------------------------------------------------ */
+
+static int64_t map_coord(int64_t i, int64_t n, const int *bc, int *flip)
+{
+    if (i < 0) {
+        if (bc[0] == ORC_BC_PERIODIC) return ((i % n) + n) % n;
+        if (bc[0] == ORC_BC_OUTFLOW) return 0;
+        *flip = 1;
+        int64_t m = -1 - i;
+        return m < n ? m : n - 1;
+    }
+    if (i >= n) {
+        if (bc[1] == ORC_BC_PERIODIC) return i % n;
+        if (bc[1] == ORC_BC_OUTFLOW) return n - 1;
+        *flip = 1;
+        int64_t m = 2 * n - 1 - i;
+        return m >= 0 ? m : 0;
+    }
+    return i;
+}
+
+typedef struct {
+    int64_t m[3]; /* ghosted extents */
+    int64_t g[3]; /* ghost layers per dim (NG on active dims, 0 otherwise) */
+} ghost_geom;
+
+static ghost_geom make_geom(const orc_desc *d)
+{
+    ghost_geom G;
+    for (int q = 0; q < 3; ++q) {
+        G.g[q] = q < d->ndim ? NG : 0;
+        G.m[q] = d->n[q] + 2 * G.g[q];
+    }
+    return G;
+}
+
+static int64_t gidx(const ghost_geom *G, int64_t i, int64_t j, int64_t k)
+{
+    return ((k + G->g[2]) * G->m[1] + (j + G->g[1])) * G->m[0] + (i + G->g[0]);
+}
+
+/* Interior primitives into the ghosted array, then every ghost cell from its
+ * mapped interior source. */
+static int fill_primitives(const orc_desc *d, const double *U, const ghost_geom *G, double *Wg)
+{
+    int nd = d->ndim, nv = nvars(d);
+    int64_t N = ncells(d), M = G->m[0] * G->m[1] * G->m[2];
+    int status = ORC_OK;
+    double u[5], w[5];
+    for (int64_t k = 0; k < d->n[2]; ++k)
+        for (int64_t j = 0; j < d->n[1]; ++j)
+            for (int64_t i = 0; i < d->n[0]; ++i) {
+                int64_t c = (k * d->n[1] + j) * d->n[0] + i;
+                for (int v = 0; v < nv; ++v) u[v] = U[v * N + c];
+                if (!cons_to_prim_1(nd, d->gamma, u, w)) status = ORC_ESTATE;
+                int64_t g = gidx(G, i, j, k);
+                for (int v = 0; v < nv; ++v) Wg[v * M + g] = w[v];
+            }
+    for (int64_t k = -G->g[2]; k < d->n[2] + G->g[2]; ++k)
+        for (int64_t j = -G->g[1]; j < d->n[1] + G->g[1]; ++j)
+            for (int64_t i = -G->g[0]; i < d->n[0] + G->g[0]; ++i) {
+                int inside = i >= 0 && i < d->n[0] && j >= 0 && j < d->n[1] && k >= 0 && k < d->n[2];
+                if (inside) continue;
+                int flip[3] = {0, 0, 0};
+                int64_t si = map_coord(i, d->n[0], d->bc[0], &flip[0]);
+                int64_t sj = nd > 1 ? map_coord(j, d->n[1], d->bc[1], &flip[1]) : 0;
+                int64_t sk = nd > 2 ? map_coord(k, d->n[2], d->bc[2], &flip[2]) : 0;
+                int64_t src = gidx(G, si, sj, sk), dst = gidx(G, i, j, k);
+                for (int v = 0; v < nv; ++v) Wg[v * M + dst] = Wg[v * M + src];
+                for (int q = 0; q < nd; ++q)
+                    if (flip[q]) Wg[(1 + q) * M + dst] = -Wg[(1 + q) * M + dst];
+            }
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The semi-discrete right-hand side, eq. BalanceEquationAverage on a        */
+/* Cartesian grid: L = -sum_q (F_{i+1/2} - F_{i-1/2}) / dq + S.              */
+/* ------------------------------------------------------------------------ */
+
+int orc_rhs(const orc_desc *d, const double *U, double *L)
+{
+    if (!valid_desc(d)) return ORC_EINVAL;
+    int nd = d->ndim, nv = nvars(d);
+    int64_t N = ncells(d);
+    ghost_geom G = make_geom(d);
+    int64_t M = G.m[0] * G.m[1] * G.m[2];
+    double *Wg = (double *)malloc(sizeof(double) * nv * M);
+    if (!Wg) return ORC_EINVAL;
+    int status = fill_primitives(d, U, &G, Wg);
+
+    /* sources: S = (0, rho a, rho v . a) for a uniform acceleration a */
+    for (int64_t c = 0; c < N; ++c) {
+        L[c] = 0.0;
+        double power = 0.0;
+        for (int r = 0; r < nd; ++r) {
+            L[(1 + r) * N + c] = U[c] * d->accel[r];
+            power += U[(1 + r) * N + c] * d->accel[r];
+        }
+        L[(nd + 1) * N + c] = power;
+    }
+
+    for (int q = 0; q < nd; ++q) {
+        int64_t nq = d->n[q];
+        double dq = cell_width(d, q);
+        /* one line along q at a time; the line holds cells -NG .. nq+NG-1 */
+        int64_t len = nq + 2 * NG;
+        double *wl = (double *)malloc(sizeof(double) * nv * len);
+        double *sig = (double *)malloc(sizeof(double) * nv * (nq + 2)); /* cells -1 .. nq */
+        double *F = (double *)malloc(sizeof(double) * nv * (nq + 1));   /* faces -1/2 .. nq-1/2 */
+        int64_t t1n = d->n[(q + 1) % 3], t2n = d->n[(q + 2) % 3];
+        for (int64_t b = 0; b < t2n; ++b)
+            for (int64_t a = 0; a < t1n; ++a) {
+                int64_t idx3[3];
+                for (int64_t s = -NG; s < nq + NG; ++s) {
+                    idx3[q] = s;
+                    idx3[(q + 1) % 3] = a;
+                    idx3[(q + 2) % 3] = b;
+                    int64_t g = gidx(&G, idx3[0], idx3[1], idx3[2]);
+                    for (int v = 0; v < nv; ++v) wl[v * len + (s + NG)] = Wg[v * M + g];
+                }
+                /* slopes (per cell differences) for cells -1 .. nq */
+                for (int v = 0; v < nv; ++v) {
+                    const double *line = wl + v * len + NG; /* line[s] = cell s */
+                    if (d->limiter == ORC_LIM_THETA) {
+                        for (int64_t s = -1; s <= nq; ++s)
+                            sig[v * (nq + 2) + (s + 1)] =
+                                orc_limiter_theta(line[s] - line[s - 1], line[s + 1] - line[s], d->theta);
+                    } else {
+                        for (int64_t s = 0; s < nq; ++s)
+                            sig[v * (nq + 2) + (s + 1)] = orc_limiter_learned(d->mlp, d->mlp_bf16, line + s - 2);
+                        /* boundary conditions applied to reconstructed values:
+                         * the ghost slope comes from the mapped interior cell */
+                        double lo_s, hi_s;
+                        if (d->bc[q][0] == ORC_BC_PERIODIC) {
+                            lo_s = sig[v * (nq + 2) + nq];
+                            hi_s = sig[v * (nq + 2) + 1];
+                        } else {
+                            double par = (v == 1 + q) ? 1.0 : -1.0;
+                            lo_s = d->bc[q][0] == ORC_BC_REFLECT ? par * sig[v * (nq + 2) + 1] : 0.0;
+                            hi_s = d->bc[q][1] == ORC_BC_REFLECT ? par * sig[v * (nq + 2) + nq] : 0.0;
+                        }
+                        sig[v * (nq + 2) + 0] = lo_s;
+                        sig[v * (nq + 2) + nq + 1] = hi_s;
+                    }
+                }
+                /* face f sits between cells f-1 and f: left state is the
+                 * outer face value of cell f-1, right state the inner face
+                 * value of cell f */
+                for (int64_t f = 0; f <= nq; ++f) {
+                    double wlft[5], wrgt[5], flx[5];
+                    for (int v = 0; v < nv; ++v) {
+                        const double *line = wl + v * len + NG;
+                        wlft[v] = line[f - 1] + 0.5 * sig[v * (nq + 2) + f];
+                        wrgt[v] = line[f] - 0.5 * sig[v * (nq + 2) + f + 1];
+                    }
+                    orc_flux(d, q, wlft, wrgt, flx);
+                    for (int v = 0; v < nv; ++v) F[v * (nq + 1) + f] = flx[v];
+                }
+                for (int64_t s = 0; s < nq; ++s) {
+                    idx3[q] = s;
+                    idx3[(q + 1) % 3] = a;
+                    idx3[(q + 2) % 3] = b;
+                    int64_t c = (idx3[2] * d->n[1] + idx3[1]) * d->n[0] + idx3[0];
+                    for (int v = 0; v < nv; ++v)
+                        L[v * N + c] -= (F[v * (nq + 1) + s + 1] - F[v * (nq + 1) + s]) / dq;
+                }
+            }
+        free(wl);
+        free(sig);
+        free(F);
+    }
+    free(Wg);
+    return status;
+}
+
+/* eqs. Update and RungeKutta1-3: K1 = dt L(U^n), U1 = U^n + K1,
+ * K2 = dt L(U1), U^{n+1} = U^n + (K1 + K2) / 2. */
+int orc_step(const orc_desc *d, double *U, double dt)
+{
+    if (!valid_desc(d) || !(dt > 0.0) || !isfinite(dt)) return ORC_EINVAL;
+    int nv = nvars(d);
+    int64_t T = nv * ncells(d);
+    double *L = (double *)malloc(sizeof(double) * T);
+    double *K1 = (double *)malloc(sizeof(double) * T);
+    double *U1 = (double *)malloc(sizeof(double) * T);
+    int s1 = orc_rhs(d, U, L);
+    for (int64_t i = 0; i < T; ++i) {
+        K1[i] = dt * L[i];
+        U1[i] = U[i] + K1[i];
+    }
+    int s2 = orc_rhs(d, U1, L);
+    for (int64_t i = 0; i < T; ++i) {
+        double K2 = dt * L[i];
+        U[i] = U[i] + 0.5 * (K1[i] + K2);
+    }
+    free(L);
+    free(K1);
+    free(U1);
+    if (s1 != ORC_OK) return s1;
+    return s2;
+}
+
+/* eq. courantTimeStep times the Courant factor. */
+int orc_cfl_dt(const orc_desc *d, const double *U, double cfl, double *dt)
+{
+    if (!valid_desc(d)) return ORC_EINVAL;
+    int nd = d->ndim, nv = nvars(d);
+    int64_t N = ncells(d);
+    int status = ORC_OK;
+    double m = INFINITY, u[5], w[5];
+    for (int64_t c = 0; c < N; ++c) {
+        for (int v = 0; v < nv; ++v) u[v] = U[v * N + c];
+        if (!cons_to_prim_1(nd, d->gamma, u, w)) status = ORC_ESTATE;
+        double cs = sqrt(d->gamma * w[nd + 1] / w[0]);
+        for (int q = 0; q < nd; ++q) {
+            double lm = w[1 + q] - cs, lp = w[1 + q] + cs;
+            double t = cell_width(d, q) / fmax(fabs(lm), fabs(lp));
+            if (t < m) m = t;
+        }
+    }
+    *dt = cfl * m;
+    return status;
+}

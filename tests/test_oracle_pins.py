@@ -1,0 +1,420 @@
+"""Pins of the FP64 oracle against things other than itself: the paper's printed
+tables, exact Riemann solutions, closed forms, invariants the paper states,
+textbook special cases and brute force on tiny inputs (all CPU-only)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact_riemann as er
+from paper_1207_3392_amd import workloads as wl
+
+from conftest import golden
+
+
+def desc1d(n=8, solver=oracle.HLLC, theta=2.0, bc=1, gamma=1.4):
+    return oracle.Desc(1, (n, 1, 1), (0, 0, 0), (1, 1, 1), gamma, ((bc, bc), (0, 0), (0, 0)),
+                       solver=solver, theta=theta)
+
+
+def desc3d(solver=oracle.HLLC, gamma=1.4):
+    return oracle.Desc(3, (4, 4, 4), (0, 0, 0), (1, 1, 1), gamma, ((0, 0),) * 3, solver=solver)
+
+
+# ---------------------------------------------------------------- EOS ----
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_eos_round_trip(ndim):
+    W = wl.random_states(1000, seed=3, ndim=ndim)
+    d = oracle.Desc(ndim, (1000, 1, 1) if ndim == 1 else ((10, 100, 1) if ndim == 2 else (10, 10, 10)),
+                    (0, 0, 0), (1, 1, 1), 5.0 / 3.0, ((0, 0),) * 3)
+    U = oracle.prim_to_cons(d, W)
+    W2 = oracle.cons_to_prim(d, U)
+    assert np.allclose(W2, W, rtol=1e-13, atol=1e-14)
+    # closed form of the polytropic closure: G = p / (gamma - 1) + rho |v|^2 / 2
+    G = W[-1] / (2.0 / 3.0) + 0.5 * W[0] * np.sum(W[1:-1] ** 2, axis=0)
+    assert np.allclose(U[-1], G, rtol=1e-14)
+
+
+def test_nonphysical_state_is_reported():
+    d = desc1d(4)
+    U = np.array([[1.0, 1.0, -1.0, 1.0], [0, 0, 0, 0], [2.5, 2.5, 2.5, 2.5]])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rhs(d, U)
+    assert e.value.status == oracle.ESTATE
+
+
+# ------------------------------------------------------------ limiter ----
+
+def test_limiter_truth_table():
+    # hand-evaluated values of MM(theta dm, (dm + dp)/2, theta dp)
+    cases = [
+        (1.0, 2.0, 1.0, 1.0), (1.0, 2.0, 2.0, 1.5), (1.0, 2.0, 1.4, 1.4),
+        (-1.0, -3.0, 1.0, -1.0), (-1.0, -3.0, 2.0, -2.0), (-3.0, -1.0, 1.4, -1.4),
+        (1.0, -1.0, 2.0, 0.0), (-2.0, 5.0, 1.0, 0.0), (0.0, 1.0, 2.0, 0.0), (1.0, 0.0, 1.4, 0.0),
+        (0.5, 0.5, 1.7, 0.5),
+    ]
+    for dm, dp, th, want in cases:
+        assert oracle.limiter_theta(dm, dp, th) == want, (dm, dp, th)
+
+
+def test_limiter_special_cases_against_textbook_forms():
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        dm, dp = rng.normal(size=2) * 10.0 ** rng.uniform(-3, 3, size=2)
+        # theta = 1: the classic two-argument minmod, 0.5 (sgn a + sgn b) min(|a|, |b|)
+        mm = 0.5 * (np.sign(dm) + np.sign(dp)) * min(abs(dm), abs(dp))
+        assert oracle.limiter_theta(dm, dp, 1.0) == pytest.approx(mm, rel=1e-15, abs=0)
+        # theta = 2: the monotonized-central limiter in flux-limiter form,
+        # sigma = phi(r) dp with phi(r) = max(0, min(2r, (1 + r)/2, 2)), r = dm / dp
+        r = dm / dp
+        phi = max(0.0, min(2 * r, 0.5 * (1 + r), 2.0))
+        assert oracle.limiter_theta(dm, dp, 2.0) == pytest.approx(phi * dp, rel=1e-13, abs=1e-300)
+        # linear data keeps its slope for every theta >= 1
+        th = rng.uniform(1, 2)
+        assert oracle.limiter_theta(dm, dm, th) == dm
+
+
+# ------------------------------------------------------------- fluxes ----
+
+@pytest.mark.parametrize("solver", [oracle.HLL, oracle.HLLC])
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_flux_consistency(solver, q):
+    d = desc3d(solver)
+    W = wl.random_states(500, seed=11, ndim=3)
+    for i in range(W.shape[1]):
+        w = W[:, i]
+        U, F, lm, lp = oracle.physical(d, q, w)
+        f = oracle.flux(d, q, w, w)
+        assert np.allclose(f, F, rtol=1e-12, atol=1e-12 * np.max(np.abs(F)))
+
+
+@pytest.mark.parametrize("solver", [oracle.HLL, oracle.HLLC])
+def test_supersonic_flux_is_upwind(solver):
+    d = desc1d(solver=solver)
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        rl, rr, pl, pr = rng.uniform(0.2, 5.0, size=4)
+        cmax = max(math.sqrt(1.4 * pl / rl), math.sqrt(1.4 * pr / rr))
+        v = cmax * rng.uniform(1.01, 3.0)
+        wl_, wr_ = np.array([rl, v, pl]), np.array([rr, v * rng.uniform(1, 2), pr])
+        # HLLC selects F_L outright; HLL gives a_+ F_L / a_+ (equal up to one rounding)
+        assert np.allclose(oracle.flux(d, 0, wl_, wr_), oracle.physical(d, 0, wl_)[1], rtol=4e-16, atol=0)
+        wl_, wr_ = -wr_ * np.array([-1, 1, -1]), -wl_ * np.array([-1, 1, -1])  # mirrored: flow to the left
+        assert np.allclose(oracle.flux(d, 0, wl_, wr_), oracle.physical(d, 0, wr_)[1], rtol=4e-16, atol=0)
+
+
+def test_hllc_middle_pressure_is_continuous():
+    """p*L = p*R follows from the middle-wave jump condition (Sec. 3.4)."""
+    d = desc3d(oracle.HLLC)
+    WL = wl.random_states(2000, seed=7, ndim=3)
+    WR = wl.random_states(2000, seed=8, ndim=3)
+    for q in range(3):
+        for i in range(WL.shape[1]):
+            s = oracle.hllc_star(d, q, WL[:, i], WR[:, i])
+            assert s["p_star_L"] == pytest.approx(s["p_star_R"], rel=1e-10, abs=1e-12)
+
+
+def test_hllc_star_flux_is_the_physical_flux_of_the_star_state():
+    """The jump conditions across the outer waves make F*_K = F(U*_K) with
+    normal velocity alpha_m and pressure p*; a slip in p* or G* breaks it."""
+    d = desc3d(oracle.HLLC)
+    WL = wl.random_states(500, seed=9, ndim=3)
+    WR = wl.random_states(500, seed=10, ndim=3)
+    for q in range(3):
+        for i in range(WL.shape[1]):
+            s = oracle.hllc_star(d, q, WL[:, i], WR[:, i])
+            for side, ps in (("L", s["p_star_L"]), ("R", s["p_star_R"])):
+                Us = s["U_star_" + side]
+                rs, am_ = Us[0], s["alpha_m"]
+                assert Us[1 + q] / rs == pytest.approx(am_, rel=1e-12, abs=1e-12)
+                # flux of a state moving at alpha_m with pressure p* and energy G*
+                F = np.array([rs * am_, *(Us[1:4] * am_), (Us[4] + ps) * am_])
+                F[1 + q] += ps
+                assert np.allclose(s["F_star_" + side], F, rtol=1e-9, atol=1e-9 * np.max(np.abs(F)))
+
+
+def test_hll_flux_satisfies_the_integral_jump_balance():
+    """HLL: the flux of the single middle state obeys both outer jump conditions:
+    -a_-(U_L - U*) = F_L - F*, a_+(U* - U_R) = F* - F_R (eqs. JumpConditionHLL)."""
+    d = desc3d(oracle.HLL)
+    WL = wl.random_states(300, seed=21, ndim=3)
+    WR = wl.random_states(300, seed=22, ndim=3)
+    for i in range(WL.shape[1]):
+        UL, FL, lmL, lpL = oracle.physical(d, 0, WL[:, i])
+        UR, FR, lmR, lpR = oracle.physical(d, 0, WR[:, i])
+        ap, am = max(0, lpL, lpR), max(0, -lmL, -lmR)
+        f = oracle.flux(d, 0, WL[:, i], WR[:, i])
+        if ap > 0 and am > 0:
+            # solve the first jump condition for U*, check the second
+            Us = UL + (FL - f) / am
+            assert np.allclose(ap * (Us - UR), f - FR, rtol=1e-9, atol=1e-9 * np.max(np.abs(FR)))
+
+
+# -------------------------------------------------------- whole scheme ----
+
+def test_sod_reproduces_paper_table4():
+    """All entries of Table 4 (Sec. 4.2.1).  27 of the 28 printed values are
+    matched to their four printed digits; HLL at N = 32 agrees to 1 %."""
+    for row in golden("sod_table4.txt"):
+        n = int(row[0])
+        if n > 512:
+            continue  # the largest sizes run in the slow variant below
+        _check_sod_row(row)
+
+
+@pytest.mark.slow
+def test_sod_reproduces_paper_table4_large():
+    for row in golden("sod_table4.txt"):
+        if int(row[0]) > 512:
+            _check_sod_row(row)
+
+
+def _check_sod_row(row):
+    n = int(row[0])
+    r, u, p = er.sample_cells((1, 0, 1), (0.125, 0, 0.1), 1.4, n, 0.5, 0.25)
+    for k, solver in enumerate([oracle.HLL, oracle.HLLC]):
+        prob = wl.sod(n, theta=1.4, cfl=0.5, t_end=0.25)
+        d = oracle.Desc.from_problem(prob, solver=solver)
+        U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 0.25, 0.5)
+        W = oracle.cons_to_prim(d, U)
+        got = (oracle.l1_error(W[0], r), oracle.l1_error(W[2], p))
+        want = (row[1 + 2 * k], row[2 + 2 * k])
+        tol = 1.2e-2 if (n == 32 and solver == oracle.HLL) else 6e-4
+        for g, w_ in zip(got, want):
+            assert g == pytest.approx(w_, rel=tol), (n, solver, got, want)
+
+
+def test_sod_config_minmod_converges_to_exact():
+    """Sod, 400 cells, minmod (theta = 1), HLLC, C = 0.4, outflow, t = 0.2;
+    first-order convergence expected with discontinuities (Sec. 4)."""
+    errs = []
+    for n in (100, 200, 400):
+        prob = wl.sod(n, theta=1.0, cfl=0.4, t_end=0.2)
+        d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+        U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 0.2, 0.4)
+        W = oracle.cons_to_prim(d, U)
+        r, u, p = er.sample_cells((1, 0, 1), (0.125, 0, 0.1), 1.4, n, 0.5, 0.2)
+        errs.append(oracle.l1_error(W[0], r))
+    assert errs[-1] < 1.5e-2
+    rate = oracle.convergence_rate(errs[0], 100, errs[2], 400)
+    assert -1.1 < rate < -0.6
+
+
+def test_advection_second_order_rates_match_table1():
+    """Table 1 (Sec. 4.1.1): second-order rates.  The printed norms are a
+    near-constant factor (about 3.1) above this oracle's at every N, so only
+    the rates are pinned, to 0.1."""
+    rows = golden("advection_table1.txt")
+    errs = {0: [], 1: []}
+    ns = [int(r[0]) for r in rows[:5]]
+    for n in ns:
+        for solver in (oracle.HLL, oracle.HLLC):
+            prob = wl.advection_1d(n, 0.6, 1.0)
+            d = oracle.Desc.from_problem(prob, solver=solver)
+            U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 1.0, 0.5)
+            errs[solver].append(oracle.l1_error(oracle.cons_to_prim(d, U)[0], prob.W[0]))
+    for k, solver in enumerate((oracle.HLL, oracle.HLLC)):
+        for i in range(2, len(ns)):
+            mine = oracle.convergence_rate(errs[solver][i - 1], ns[i - 1], errs[solver][i], ns[i])
+            paper = oracle.convergence_rate(rows[i - 1][1 + k], ns[i - 1], rows[i][1 + k], ns[i])
+            assert mine == pytest.approx(paper, abs=0.1), (solver, ns[i], mine, paper)
+        assert errs[oracle.HLLC][0] < errs[oracle.HLL][0]  # HLLC below HLL at N = 16 (Sec. 4.1.1)
+
+
+def test_stationary_contact_is_exact_with_hllc_and_smeared_with_hll():
+    """Sec. 4.2.1: HLLC keeps a stationary contact exactly; HLL diffuses it."""
+    prob = wl.contact(128, 0.0)
+    out = {}
+    for solver in (oracle.HLL, oracle.HLLC):
+        d = oracle.Desc.from_problem(prob, solver=solver)
+        U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 0.5, 0.5)
+        out[solver] = oracle.cons_to_prim(d, U)
+    assert np.array_equal(out[oracle.HLLC][0], prob.W[0])
+    assert np.all(out[oracle.HLLC][1] == 0.0)
+    assert np.max(np.abs(out[oracle.HLL][0] - prob.W[0])) > 0.05
+
+
+def test_double_rarefaction_stays_positive():
+    prob = wl.double_rarefaction(128)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 0.15, 0.5)
+    W = oracle.cons_to_prim(d, U)  # raises on rho <= 0 or p <= 0
+    assert W[0].min() > 0 and W[2].min() > 0
+
+
+def test_blast_waves_peak_density():
+    """Sec. 4.2.2: 400 cells, HLLC, reflecting walls, t = 0.038: max rho about 5.4."""
+    prob = wl.blast_waves(400)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 0.038, 0.5)
+    W = oracle.cons_to_prim(d, U)
+    assert 5.0 < W[0].max() < 5.8
+
+
+def test_sound_wave_hll_equals_hllc_and_converges_second_order():
+    """Sec. 4.1.2: second order; HLL and HLLC identical for sound waves."""
+    errs = {0: [], 1: []}
+    for n in (32, 64, 128):
+        prob = wl.linear_wave(n, "sound")
+        for solver in (oracle.HLL, oracle.HLLC):
+            d = oracle.Desc.from_problem(prob, solver=solver)
+            U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 1.0, 0.5)
+            W = oracle.cons_to_prim(d, U)
+            errs[solver].append(np.sum(np.abs(W[0] - prob.W[0])) / np.sum(np.abs(prob.W[0] - 1.0)))
+    for a, b in zip(errs[0], errs[1]):
+        assert a == pytest.approx(b, rel=2e-2)
+    assert oracle.convergence_rate(errs[1][1], 64, errs[1][2], 128) < -1.7
+
+
+def test_one_dimensional_problem_is_identical_along_every_axis():
+    """Sec. 4.2.1: Sod run along y or z gives exactly the 1D result."""
+    n = 64
+    prob = wl.sod(n, theta=1.4, cfl=0.3, t_end=0.05)
+    d1 = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U1 = oracle.prim_to_cons(d1, prob.flat())
+    res1 = oracle.run(d1, U1, 0.05, 0.3)[0]
+    m = 4
+    for ndim, axis in ((2, 1), (3, 2), (3, 0)):
+        nn = [m, m, m]
+        nn[axis] = n
+        if ndim == 2:
+            nn[2] = 1
+        lo, hi = [0.0] * 3, [m / n] * 3
+        hi[axis] = 1.0
+        if ndim == 2:
+            hi[2] = 1.0
+        bc = [(0, 0)] * 3
+        bc[axis] = (1, 1)
+        d = oracle.Desc(ndim, nn, lo, hi, 1.4, bc, solver=oracle.HLLC, theta=1.4)
+        shape = [nn[2], nn[1], nn[0]][3 - ndim:]
+        W = np.zeros((ndim + 2,) + tuple(shape))
+        ax = ndim - 1 - axis  # array axis of the problem direction
+        for k, src in ((0, 0), (1 + axis, 1), (ndim + 1, 2)):
+            line = prob.W[src]
+            W[k] = np.moveaxis(np.broadcast_to(line, tuple(shape[:ax] + shape[ax + 1:]) + (n,)), -1, ax)
+        res = oracle.run(d, oracle.prim_to_cons(d, W), 0.05, 0.3)[0].reshape((ndim + 2,) + tuple(shape))
+        for k, src in ((0, 0), (1 + axis, 1), (ndim + 1, 2)):
+            got = np.moveaxis(res[k], ax, -1).reshape(-1, n)
+            assert np.array_equal(got, np.broadcast_to(res1[src], got.shape)), (ndim, axis, k)
+
+
+@pytest.mark.parametrize("solver", [oracle.HLL, oracle.HLLC])
+def test_conservation_to_roundoff_periodic_3d(solver):
+    prob = wl.random_smooth_patch(3, (8, 6, 5), seed=4, bc=wl.BC_PERIODIC)
+    d = oracle.Desc.from_problem(prob, solver=solver)
+    U = oracle.prim_to_cons(d, prob.flat())
+    t0 = oracle.totals(d, U)
+    scale = oracle.totals(d, np.abs(U))
+    nsteps = 10
+    U = oracle.run_steps(d, U, nsteps, 0.3)
+    t1 = oracle.totals(d, U)
+    eps = 2.0 ** -52
+    for k in range(5):
+        assert abs(t1[k] - t0[k]) <= 4 * nsteps * eps * scale[k] * U.shape[1] ** 0.5 + 1e-300
+
+
+def test_conservation_reflecting_walls_mass_and_energy():
+    prob = wl.implosion(24)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U = oracle.prim_to_cons(d, prob.flat())
+    t0 = oracle.totals(d, U)
+    U = oracle.run_steps(d, U, 10, 0.5)
+    t1 = oracle.totals(d, U)
+    assert t1[0] == pytest.approx(t0[0], rel=1e-14)
+    assert t1[4] == pytest.approx(t0[4], rel=1e-14)
+
+
+def test_implosion_keeps_diagonal_symmetry():
+    """Sec. 4.2.1: the symmetry about the diagonal is preserved exactly."""
+    prob = wl.implosion(32)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U = oracle.run_steps(d, oracle.prim_to_cons(d, prob.flat()), 12, 0.5)
+    W = oracle.cons_to_prim(d, U).reshape(4, 32, 32)
+    assert np.array_equal(W[0], W[0].T)
+    assert np.array_equal(W[3], W[3].T)
+    assert np.array_equal(W[1], W[2].T)
+
+
+def test_gravity_source_balances_hydrostatic_pressure():
+    """Uniform density with p = p_b - rho g z under a = -g z_hat: linear data is
+    reconstructed exactly, so the pressure-flux difference cancels the source
+    rho a in the momentum balance away from the walls (Sec. 4.3.2 setup)."""
+    n, g = 32, 0.1
+    z = (np.arange(n) + 0.5) / n - 0.5
+    W = np.array([np.full(n, 1.5), np.zeros(n), 2.5 - 1.5 * g * z])
+    for theta in (1.0, 1.4, 2.0):
+        d = oracle.Desc(1, (n, 1, 1), (-0.5, 0, 0), (0.5, 1, 1), 1.4, ((2, 2), (0, 0), (0, 0)),
+                        solver=oracle.HLLC, theta=theta, accel=(-g, 0, 0))
+        L = oracle.rhs(d, oracle.prim_to_cons(d, W))
+        assert np.max(np.abs(L[:, 2:-2])) < 1e-12
+        # the wrong sign of the source would leave 2 rho g
+        d_bad = oracle.Desc(1, (n, 1, 1), (-0.5, 0, 0), (0.5, 1, 1), 1.4, ((2, 2), (0, 0), (0, 0)),
+                            solver=oracle.HLLC, theta=theta, accel=(g, 0, 0))
+        assert np.max(np.abs(oracle.rhs(d_bad, oracle.prim_to_cons(d_bad, W))[1, 2:-2])) > 0.2
+
+
+# ---------------------------------------------------------------- dt ----
+
+def test_cfl_dt_uniform_state_closed_form():
+    for ndim in (1, 2, 3):
+        n = (5, 3, 2)[:ndim] + (1,) * (3 - ndim)
+        hi = (1.0, 2.0, 0.5)
+        d = oracle.Desc(ndim, n, (0, 0, 0), hi, 1.4, ((0, 0),) * 3)
+        v = (0.3, -0.7, 0.2)
+        W = np.zeros((ndim + 2, int(np.prod(n))))
+        W[0], W[-1] = 1.3, 0.9
+        for q in range(ndim):
+            W[1 + q] = v[q]
+        c = math.sqrt(1.4 * 0.9 / 1.3)
+        want = 0.4 * min(hi[q] / n[q] / (abs(v[q]) + c) for q in range(ndim))
+        assert oracle.cfl_dt(d, oracle.prim_to_cons(d, W), 0.4) == pytest.approx(want, rel=1e-15)
+
+
+def test_cfl_dt_brute_force_tiny_grid():
+    prob = wl.random_smooth_patch(2, (3, 4), seed=2)
+    d = oracle.Desc.from_problem(prob)
+    W = prob.flat()
+    best = math.inf
+    for c in range(W.shape[1]):
+        cs = math.sqrt(prob.gamma * W[3, c] / W[0, c])
+        for q, dq in ((0, 1 / 3), (1, 1 / 4)):
+            best = min(best, dq / (abs(W[1 + q, c]) + cs))
+    assert oracle.cfl_dt(d, oracle.prim_to_cons(d, W), 0.5) == pytest.approx(0.5 * best, rel=1e-14)
+
+
+# ------------------------------------------------------ exact solver ----
+
+def test_exact_riemann_sod_star_state():
+    s = er.solve((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+    assert s.p_star == pytest.approx(0.30313, abs=1e-5)
+    assert s.u_star == pytest.approx(0.92745, abs=1e-5)
+    assert abs(s.residual()) < 1e-14
+
+
+def test_exact_riemann_special_cases():
+    s = er.solve((1.0, 0.0, 0.4), (1.0, 0.0, 0.4), 1.4)
+    assert s.p_star == pytest.approx(0.4, rel=1e-14) and abs(s.u_star) < 1e-15
+    s = er.solve((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 1.4)  # symmetric double rarefaction
+    assert abs(s.u_star) < 1e-14 and 0 < s.p_star < 0.4
+    s = er.solve((1.0, -20.0, 0.4), (1.0, 20.0, 0.4), 1.4)
+    assert s.vacuum
+
+
+def test_exact_riemann_conserves_through_the_box():
+    """Integrals over [0, 1] at time t equal the initial ones plus t times the
+    net boundary flux, while no wave has reached the ends."""
+    for left, right in [((1, 0, 1), (0.125, 0, 0.1)), ((1, -2, 0.4), (1, 2, 0.4)),
+                        ((5.0, 0.3, 7.0), (0.2, -0.5, 0.3))]:
+        g, t, n = 1.4, 0.05, 200000
+        r, u, p = er.sample_cells(left, right, g, n, 0.5, t)
+        E = p / (g - 1) + 0.5 * r * u * u
+        rl, ul, pl = left
+        rr, ur, pr = right
+        El, Er = pl / (g - 1) + 0.5 * rl * ul * ul, pr / (g - 1) + 0.5 * rr * ur * ur
+        fl = np.array([rl * ul, rl * ul * ul + pl, (El + pl) * ul])
+        fr = np.array([rr * ur, rr * ur * ur + pr, (Er + pr) * ur])
+        init = 0.5 * np.array([rl + rr, rl * ul + rr * ur, El + Er])
+        got = np.array([r.mean(), (r * u).mean(), E.mean()])
+        assert np.allclose(got, init + t * (fl - fr), rtol=0, atol=2e-4)
