@@ -1,0 +1,165 @@
+"""Benchmark: zone-updates/s of the two-stage finite-volume step on one MI355X.
+
+Workload: the 3D periodic smooth-flow patch (256^3 cells on the unit cube,
+gamma = 5/3, rho = 1 + 0.2 x mean of 8 random-phase modes with |k| <= 4,
+p = 1, velocities 0.1 x mean of 8 modes each, seed 1207), FP32 state and
+fluxes, HLLC flux, monotonized-central limiter (theta = 2), C_CFL = 0.4.
+One step = both Runge-Kutta stages with the CFL time step chosen on the
+device from the rate the previous second stage reduced (no host round trip),
+i.e. primitive recovery, ghost mapping, slopes, face states, Riemann fluxes,
+divergence, Runge-Kutta combination and the dt min-reduction.  The state is
+resident in HBM before timing starts.
+
+Prints one JSON line.  Extra fields report the HLL run, a 512^3 patch, the
+per-kernel roofline and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/s per RK2 step and % HBM roofline; plain vs learned limiter at matched L1"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {1: 40.0, 2: 60.0}  # stage 1 reads U^n, writes U1; stage 2 reads U1, U^n, writes U^{n+1} (5 FP32 vars)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--solver", default="hllc", choices=["hll", "hllc"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
+    ap.add_argument("--by", type=int, default=0, help="override the tile rows (4, 8, 16)")
+    return ap.parse_args()
+
+
+def time_patch(n, solver, steps, warmup, timing=True):
+    import torch
+
+    from paper_1207_3392_amd import hydro
+    from paper_1207_3392_amd import workloads as wl
+
+    prob = wl.smooth_periodic_3d(n)
+    p = hydro.Patch(prob, precision=32)
+    cfg = p.kernel_config()
+    sv = hydro.HLLC if solver == "hllc" else hydro.HLL
+    p.advance(warmup, 0.4, solver=sv)
+    torch.cuda.synchronize()
+    p.set_timing(timing)
+    p.kernel_times()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.advance(steps, 0.4, solver=sv)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, launches = p.kernel_times()
+    p.cfl_dt(0.4)  # raises if the state went non-physical
+    ncell = n ** 3
+    res = {
+        "wall_s": wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "zone_updates_per_s": ncell * steps / wall,
+        "kernel": cfg,
+        "stage_ms": [float(ms[0] / max(launches[0], 1)), float(ms[1] / max(launches[1], 1))],
+        "ncell": ncell,
+    }
+    p.close()
+    del p
+    return res
+
+
+def roofline(res):
+    ncell = res["ncell"]
+    # dominant kernel: the stage with the larger mean duration
+    k = 1 if res["stage_ms"][1] >= res["stage_ms"][0] else 0
+    dur_s = res["stage_ms"][k] * 1e-3
+    bytes_ = BYTES_PER_CELL[k + 1] * ncell
+    achieved = bytes_ / dur_s / 1e9
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": f"stage {k + 1}", "mean_ms": round(res["stage_ms"][k], 4),
+        "algorithmic_bytes_per_launch": bytes_,
+    }
+
+
+def cpu_baseline(budget_s=12.0):
+    import numpy as np
+
+    import oracle
+    from paper_1207_3392_amd import workloads as wl
+
+    oracle.build()
+    n = 48
+    prob = wl.smooth_periodic_3d(n)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U = oracle.prim_to_cons(d, prob.flat())
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        U = oracle.step(d, U, oracle.cfl_dt(d, U, 0.4))
+        steps += 1
+    wall = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / wall, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n}^3 patch of the same periodic smooth flow, {steps} steps (FP64, single thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.by:
+        os.environ["HY_TILE_BY"] = str(args.by)
+
+    main_res = time_patch(args.n, args.solver, args.steps, args.warmup)
+    extra = {}
+    if not args.no_extra:
+        other = "hll" if args.solver == "hllc" else "hllc"
+        r = time_patch(args.n, other, args.steps, args.warmup)
+        extra[f"{other}_{args.n}"] = {"zone_updates_per_s": r["zone_updates_per_s"],
+                                     "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"]}
+        r = time_patch(512, args.solver, 20, 3)
+        extra[f"{args.solver}_512"] = {"zone_updates_per_s": r["zone_updates_per_s"],
+                                      "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"],
+                                      "roofline": roofline(r)}
+    out = {
+        "metric": METRIC,
+        "value": main_res["zone_updates_per_s"],
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3D periodic smooth flow {args.n}^3, gamma 5/3, {args.solver.upper()}, "
+                               f"MC limiter, C_CFL 0.4, device-side dt", "cells": main_res["ncell"],
+                   "kernel": main_res["kernel"]},
+        "roofline": roofline(main_res),
+        "stage_ms": main_res["stage_ms"],
+        "extra": extra,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

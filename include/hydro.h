@@ -1,0 +1,154 @@
+/*
+ * hydro.h -- C ABI of the gfx950 finite-volume hydrodynamics library
+ * (libhydro.so).  It advances the nonrelativistic Euler equations of
+ * Cardall et al., "GenASiS I" (arXiv:1207.3392), Sec. 3, on one uniform
+ * Cartesian patch held in GPU memory.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns hy_status (0 = HY_OK, negative = error) and never
+ *    throws; hy_last_error() gives a thread-local message for the last error.
+ *  - Host arrays are structure-of-arrays (nv, nz, ny, nx), x fastest, over
+ *    interior cells only, FP64.  nv = ndim + 2.  Conserved order (Sec. 3.4):
+ *    D, S_1..S_ndim, G.  Primitive order: rho, v_1..v_ndim, p.  The baryon
+ *    mass m is 1, so rho = D.  Unused dimensions have n = 1.
+ *  - Device memory is owned by the caller: the library carves everything it
+ *    needs out of one workspace the caller allocates (any device allocator,
+ *    e.g. a torch uint8 tensor) after asking for its size.  The library itself
+ *    allocates only its host-side handle.  hy_destroy frees the handle, never
+ *    the workspace.
+ *  - Work is enqueued on the caller's HIP stream (passed as void*, NULL =
+ *    the default stream) without host synchronisation, except in the calls
+ *    marked "synchronising".
+ *  - A NaN, rho <= 0 or p <= 0 met by a kernel is latched in device memory and
+ *    returned as HY_ESTATE by the next synchronising call; hy_set_state
+ *    clears the latch.
+ *  - One handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HY_OK = 0,
+    HY_EINVAL = -1,       /* bad argument (checked on the host before any launch) */
+    HY_ENOMEM = -2,       /* workspace smaller than hy_*_workspace_bytes */
+    HY_EDEVICE = -3,      /* a HIP runtime call failed */
+    HY_ESTATE = -4,       /* NaN or rho <= 0 or p <= 0 latched on the device */
+    HY_EUNSUPPORTED = -5  /* valid but not built (e.g. learned limiter in FP64) */
+} hy_status;
+
+typedef enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1, HY_BC_REFLECT = 2 } hy_bc;
+typedef enum { HY_HLL = 0, HY_HLLC = 1 } hy_solver;
+typedef enum { HY_LIM_THETA = 0, HY_LIM_LEARNED = 1 } hy_limiter;
+typedef enum { HY_PRIMITIVE = 0, HY_CONSERVED = 1 } hy_kind;
+
+/*
+ * Patch description.
+ *  ndim        1, 2 or 3; n[q] >= 2 cells on active dimensions, 1 elsewhere.
+ *  lo, hi      box corners; cell width (hi - lo) / n (uniform grid, Sec. 3).
+ *  gamma       ideal-gas index, p = (gamma - 1) e (Sec. 3.4, polytropic closure).
+ *  bc[q][s]    boundary kind on the low (s = 0) / high (s = 1) face of
+ *              dimension q.  Ghost cells are filled from cell-centre
+ *              primitives: periodic wraps, outflow copies the nearest interior
+ *              cell, reflecting mirrors and negates the normal velocity (the
+ *              boundary step of Alg. 1 applied through ghost cells).  Periodic
+ *              must be set on both faces of a dimension.
+ *  precision   32 (FP32 state and fluxes; reductions in FP64) or 64.
+ *  limiter     HY_LIM_THETA: generalised minmod of eq. MinMod with parameter
+ *              theta in [1, 2] (1 = minmod, 2 = monotonized central).
+ *              HY_LIM_LEARNED: the MLP slope limiter (weights via hy_set_mlp),
+ *              FP32 only.
+ *  accel       uniform acceleration a = -grad(Phi); the source is
+ *              (0, rho a, rho v . a) (the external force and power of the
+ *              Rayleigh-Taylor setup, Sec. 4.3.2).  Zeros: no source.
+ */
+typedef struct {
+    int ndim;
+    int64_t n[3];
+    double lo[3];
+    double hi[3];
+    double gamma;
+    int bc[3][2];
+    int precision;
+    int limiter;
+    double theta;
+    double accel[3];
+} hy_patch_desc;
+
+typedef struct hy_patch hy_patch; /* opaque, owned by the library */
+
+/* Bytes of device workspace hy_init_patch needs for this description
+ * (two state arrays plus small control blocks).  HY_EINVAL on a bad desc. */
+hy_status hy_patch_workspace_bytes(const hy_patch_desc *desc, size_t *bytes);
+
+/* Bind a patch to caller-owned device memory (at least the size above, any
+ * alignment; contents need not be initialised) and a HIP stream.  The state is
+ * undefined until hy_set_state.  *out receives the handle. */
+hy_status hy_init_patch(const hy_patch_desc *desc, void *dev_workspace, size_t bytes,
+                        void *hip_stream, hy_patch **out);
+
+/* Copy a host FP64 state in (converted to the patch precision on the host,
+ * primitives converted to conserved variables on the device), compute the
+ * CFL rate of the new state, reset the simulation time to 0 and clear the
+ * error latch.  Synchronising. */
+hy_status hy_set_state(hy_patch *p, int kind, const double *host_soa);
+
+/* Copy the current state out as FP64, conserved or primitive.  Synchronising;
+ * HY_ESTATE if the latch is set (the array is still written). */
+hy_status hy_get_state(hy_patch *p, int kind, double *host_soa_out);
+
+/* One full two-stage Runge-Kutta step (eqs. Update, RungeKutta1-3) of size dt
+ * with the HLL (eq. FluxHLL) or HLLC (eq. FluxHLLC) flux.  dt must be finite
+ * and > 0 (HY_EINVAL otherwise).  Asynchronous.  The second stage also
+ * computes the CFL rate of the new state, so a following hy_cfl_dt launches
+ * nothing. */
+hy_status hy_step(hy_patch *p, double dt, int solver);
+
+/* dt = cfl * min over cells and dimensions of dq / max(|v_q - c|, |v_q + c|)
+ * (eq. courantTimeStep) for the current state.  Synchronising. */
+hy_status hy_cfl_dt(hy_patch *p, double cfl, double *dt_out);
+
+/* nsteps steps with the time step chosen on the device before each step:
+ * dt = min(cfl * dt_CFL, t_end - t), t advanced on the device (the
+ * single-level form of Alg. 2 without a host round trip).  Once t reaches
+ * t_end the remaining steps leave the state unchanged.  Asynchronous. */
+hy_status hy_advance(hy_patch *p, int nsteps, double cfl, double t_end, int solver);
+
+/* Simulation time accumulated by hy_step / hy_advance since hy_set_state.
+ * Synchronising. */
+hy_status hy_get_time(hy_patch *p, double *t_out);
+
+/* FP64 totals sum_cells U_k dV in a fixed-order tree (bitwise reproducible),
+ * out = (D, S_x, S_y, S_z, G), zeros for absent momentum components.
+ * Synchronising. */
+hy_status hy_conserved_totals(hy_patch *p, double out[5]);
+
+/* Learned limiter weights: n = 1249 FP32 values, W1[32][4], b1[32],
+ * W2[32][32], b2[32], w3[32], b3.  Copied to the device (matrix weights in
+ * bfloat16).  Required before stepping with HY_LIM_LEARNED.  Synchronising. */
+hy_status hy_set_mlp(hy_patch *p, const float *weights, size_t n);
+
+/* Per-kernel timing with HIP events on the patch stream (off by default).
+ * While on, each stage launch is bracketed by events; hy_kernel_times
+ * synchronises and returns the summed milliseconds and launch counts of the
+ * first and second stage kernels since the last reset, then resets them. */
+hy_status hy_set_timing(hy_patch *p, int on);
+hy_status hy_kernel_times(hy_patch *p, double ms[2], int64_t launches[2]);
+
+/* Name of the stage kernel configuration in use (for profiles). */
+hy_status hy_kernel_config(hy_patch *p, char *buf, size_t len);
+
+hy_status hy_destroy(hy_patch *p);
+
+const char *hy_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

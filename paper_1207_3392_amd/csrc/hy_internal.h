@@ -1,0 +1,76 @@
+// Internal declarations shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hy {
+
+// Device control block: one per patch, inside the caller's workspace.
+// rate[s] holds the bits of a positive double, max over cells and dimensions
+// of (|v_q| + c) / dq, for the state in parity slot s; positive doubles order
+// like their bit patterns, so an unsigned 64-bit atomic max reduces them.
+struct DevCtl {
+    double time[2];
+    unsigned long long rate[2];
+    unsigned int err;
+    unsigned int pad[3];
+    double totals[8];
+};
+
+enum { LIM_THETA = 0, LIM_LEARNED = 1 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+
+// How a stage obtains dt: from the host argument, or from the device control
+// block (dt = min(cfl / rate, t_end - t)).
+enum { DT_HOST = 0, DT_DEVICE = 1 };
+
+template <typename T>
+struct StageArgs {
+    const T *uin;     // state read with the stencil (U^n in stage 1, U^(1) in stage 2)
+    T *uout;          // output (U^(1) in stage 1; U^{n+1} over U^n in stage 2)
+    const T *u0;      // stage 2: U^n, read only at the thread's own cell (aliases uout)
+    const float *slopes;  // learned limiter: (ndim * nv, ncell) slopes of the stage input
+    int64_t n[3];
+    int64_t vstride;  // elements between variables
+    T idx[3];         // 1 / dq
+    T gamma, gm1, inv_gm1, theta;
+    T accel[3];
+    int bc[3][2];
+    int zchunk;       // planes per block along z (3D)
+    DevCtl *ctl;
+    int parity;       // slot of the input state's time / rate
+    int dt_mode;
+    double dt_host, cfl, t_end;
+};
+
+struct LaunchCfg {
+    int by;       // rows per block in the x-y plane tile (block = 64 x by threads)
+    int zchunk;   // planes per block along z
+};
+
+// Stage launchers (defined in stage.hip).  Return hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_stage(int ndim, int solver, int stage, int limiter, const LaunchCfg &cfg,
+                        const StageArgs<T> &a, hipStream_t s);
+
+// Device-side helpers (defined in reduce.hip).
+template <typename T>
+hipError_t launch_prim_to_cons(T *u, int64_t ncell, int64_t vstride, int ndim, T gm1, T inv_gm1,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_cons_to_prim(const T *u, T *w, int64_t ncell, int64_t vstride, int ndim, T gm1,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_cfl_rate(const T *u, int64_t n0, int64_t n1, int64_t n2, int64_t vstride, int ndim,
+                           T gamma, T gm1, const double *idx, DevCtl *ctl, int slot, hipStream_t s);
+template <typename T>
+hipError_t launch_totals(const T *u, int64_t ncell, int64_t vstride, int ndim, double dv,
+                         double *partials, int nblocks, DevCtl *ctl, hipStream_t s);
+
+hipError_t launch_ctl_reset_rate(DevCtl *ctl, int slot, hipStream_t s);
+hipError_t launch_ctl_init(DevCtl *ctl, hipStream_t s);
+
+constexpr int TOTALS_BLOCKS = 512;
+
+}  // namespace hy

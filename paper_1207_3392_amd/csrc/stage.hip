@@ -1,0 +1,585 @@
+// stage.hip -- one Runge-Kutta stage of the finite-volume update, fused into
+// a single gfx950 kernel.
+//
+// Per cell the kernel performs, in the paper's order (Sec. 3, Alg. 1):
+// primitive recovery (Sec. 3.4), ghost values by index mapping (the boundary
+// step), generalised-minmod slopes (eq. MinMod) or learned slopes, face states
+// (eqs. conservedLeft..conservedRight), the HLL or HLLC flux (eqs. FluxHLL,
+// FluxHLLC with eq. MiddleWaveSpeed and the middle states), the flux
+// divergence plus a uniform-gravity source (eq. BalanceEquationAverage), and
+// the Runge-Kutta combination (eqs. RungeKutta1-3, written as
+// U^(1) = U^n + dt L(U^n) and U^{n+1} = (U^n + U^(1) + dt L(U^(1))) / 2).
+// The second stage also reduces the CFL rate (eq. courantTimeStep) of the
+// state it writes.
+//
+// Layout: SoA state arrays, one per conserved variable, x fastest, interior
+// cells only.  Tiling: a block owns a 64 x BY column tile of the x-y plane and
+// marches along z.  The z stencil lives in registers (a 3-plane window of
+// primitives plus the carried z-face flux), so every z face is solved once and
+// no z halo is re-read.  The current x-y plane, with a 2-cell halo, is staged
+// in LDS; slopes and face fluxes go through LDS so every x and y face is also
+// solved once.  Ghost cells are never stored: out-of-range indices are mapped
+// to their interior source (periodic wrap, outflow clamp, reflecting mirror
+// with the normal velocity negated).
+#include "hy_internal.h"
+
+#include <math.h>
+
+namespace hy {
+namespace {
+
+constexpr int BX = 64;
+
+// ---------------------------------------------------------------- math ----
+
+template <typename T> __device__ __forceinline__ T rcp_(T x);
+template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp_<double>(double x) { return 1.0 / x; }
+
+// c_s = sqrt(gamma p / rho), evaluated as (gamma p) rsqrt(gamma p rho)
+template <typename T> __device__ __forceinline__ T sound_(T gamma, T p, T rho);
+template <> __device__ __forceinline__ float sound_<float>(float g, float p, float r)
+{
+    float gp = g * p;
+    return gp * __builtin_amdgcn_rsqf(gp * r);
+}
+template <> __device__ __forceinline__ double sound_<double>(double g, double p, double r)
+{
+    return sqrt(g * p / r);
+}
+
+template <typename T> __device__ __forceinline__ T max3_(T a, T b, T c) { return fmax(a, fmax(b, c)); }
+
+// ------------------------------------------------------- index mapping ----
+
+// Source of index i along a dimension of n interior cells; flip is set when
+// the source is a mirror image.  Indices far outside the ghost range (only
+// met by the unused columns of partial tiles) are clamped into the array.
+__device__ __forceinline__ int64_t map_idx(int64_t i, int64_t n, int bclo, int bchi, bool &flip)
+{
+    if (i >= 0 && i < n) return i;
+    int64_t m;
+    if (i < 0) {
+        if (bclo == BC_PERIODIC) m = i + n;
+        else if (bclo == BC_OUTFLOW) m = 0;
+        else { m = -1 - i; flip = !flip; }
+    } else {
+        if (bchi == BC_PERIODIC) m = i - n;
+        else if (bchi == BC_OUTFLOW) m = n - 1;
+        else { m = 2 * n - 1 - i; flip = !flip; }
+    }
+    return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
+// ------------------------------------------------------ fluid variables ----
+
+// primitives (rho, v, p) from conserved (D, S, G), m = 1; returns false on
+// rho <= 0, p <= 0 or a non-finite value
+template <int ND, typename T>
+__device__ __forceinline__ bool to_prim(const T (&u)[ND + 2], T (&w)[ND + 2], T gm1)
+{
+    const T ir = rcp_(u[0]);
+    T ke = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        w[1 + d] = u[1 + d] * ir;
+        ke += u[1 + d] * w[1 + d];
+    }
+    w[0] = u[0];
+    w[ND + 1] = gm1 * (u[ND + 1] - T(0.5) * ke);
+    const T big = T(3.0e38);
+    return (w[0] > T(0)) & (w[ND + 1] > T(0)) & (w[0] < big) & (w[ND + 1] < big);
+}
+
+template <int ND, typename T>
+__device__ __forceinline__ void load_cell(const T *__restrict__ u, int64_t c, int64_t vs, T (&out)[ND + 2])
+{
+#pragma unroll
+    for (int v = 0; v < ND + 2; ++v) out[v] = u[c + v * vs];
+}
+
+// generalised minmod of eq. MinMod as a per-cell difference:
+// sigma = MM(theta dm, (dm + dp) / 2, theta dp)
+template <typename T>
+__device__ __forceinline__ T slope_mm(T wm, T w0, T wp, T theta)
+{
+    const T dm = w0 - wm, dp = wp - w0;
+    const T a = theta * dm, b = T(0.5) * (dm + dp), c = theta * dp;
+    const T m = fmin(fabs(a), fmin(fabs(b), fabs(c)));
+    return (dm * dp > T(0)) ? copysign(m, b) : T(0);
+}
+
+// ------------------------------------------------------ Riemann solvers ----
+
+// Flux normal to Q from the primitive face states wl (left), wr (right).
+template <int ND, int Q, int SOLVER, typename T>
+__device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2],
+                                        T gamma, T inv_gm1)
+{
+    constexpr int IP = ND + 1;
+    const T rl = wl[0], vl = wl[1 + Q], pl = wl[IP];
+    const T rr = wr[0], vr = wr[1 + Q], pr = wr[IP];
+    const T cl = sound_(gamma, pl, rl), cr = sound_(gamma, pr, rr);
+    // outer speed estimates alpha_+/- = max(0, +/-lambda_+/-(L), +/-lambda_+/-(R))
+    const T ap = max3_(T(0), vl + cl, vr + cr);
+    const T am = max3_(T(0), cl - vl, cr - vr);
+    if constexpr (SOLVER == 0) {
+        T kl = T(0), kr = T(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            kl += wl[1 + d] * wl[1 + d];
+            kr += wr[1 + d] * wr[1 + d];
+        }
+        const T El = pl * inv_gm1 + T(0.5) * rl * kl;
+        const T Er = pr * inv_gm1 + T(0.5) * rr * kr;
+        const T ml = rl * vl, mr = rr * vr;  // mass fluxes
+        T Fl[ND + 2], Fr[ND + 2], Ul[ND + 2], Ur[ND + 2];
+        Fl[0] = ml; Fr[0] = mr; Ul[0] = rl; Ur[0] = rr;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            Fl[1 + d] = ml * wl[1 + d] + (d == Q ? pl : T(0));
+            Fr[1 + d] = mr * wr[1 + d] + (d == Q ? pr : T(0));
+            Ul[1 + d] = rl * wl[1 + d];
+            Ur[1 + d] = rr * wr[1 + d];
+        }
+        Fl[IP] = (El + pl) * vl; Fr[IP] = (Er + pr) * vr;
+        Ul[IP] = El; Ur[IP] = Er;
+        const T den = ap + am;
+        if (den > T(0)) {
+            const T inv = rcp_(den), apam = ap * am;
+#pragma unroll
+            for (int v = 0; v < ND + 2; ++v) f[v] = (ap * Fl[v] + am * Fr[v] - apam * (Ur[v] - Ul[v])) * inv;
+        } else {
+#pragma unroll
+            for (int v = 0; v < ND + 2; ++v) f[v] = T(0.5) * (Fl[v] + Fr[v]);
+        }
+    } else {
+        // Batten's middle-wave speed (eq. MiddleWaveSpeed)
+        const T ql = am + vl, qr = ap - vr;
+        const T am_ = (rr * vr * qr + rl * vl * ql - (pr - pl)) * rcp_(rr * qr + rl * ql);
+        // eq. FluxHLLC: alpha_- = 0 selects L, then alpha_+ = 0 selects R,
+        // then the sign of alpha_m selects the middle state on its side
+        const bool sup = (am == T(0)) | (ap == T(0));
+        const bool useL = (am == T(0)) | ((ap != T(0)) & (am_ >= T(0)));
+        T wk[ND + 2];
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) wk[v] = useL ? wl[v] : wr[v];
+        const T sK = useL ? -am : ap;
+        const T rK = wk[0], vK = wk[1 + Q], pK = wk[IP];
+        T kk = T(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) kk += wk[1 + d] * wk[1 + d];
+        const T EK = pK * inv_gm1 + T(0.5) * rK * kk;
+        const T mK = rK * vK;
+        // middle state from the jump conditions across the K-side outer wave
+        const T qk = sK - vK;
+        const T inv = sup ? T(0) : rcp_(sup ? T(1) : sK - am_);
+        const T rs = rK * qk * inv;
+        const T ps = pK + rK * qk * (am_ - vK);
+        const T Gs = (qk * EK - pK * vK + ps * am_) * inv;
+        // F = F_K + s_K (U*_K - U_K); s_K = 0 in the supersonic cases
+        const T fd = mK + sK * (rs - rK);
+        f[0] = fd;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            if (d == Q) f[1 + d] = mK * vK + pK + sK * (rs * am_ - mK);
+            else f[1 + d] = fd * wk[1 + d];
+        }
+        f[IP] = (EK + pK) * vK + sK * (Gs - EK);
+    }
+}
+
+// ------------------------------------------------------------ kernel ----
+
+template <int ND, typename T>
+__device__ __forceinline__ double stage_dt(const StageArgs<T> &a)
+{
+    if (a.dt_mode == DT_HOST) return a.dt_host;
+    const double rate = __longlong_as_double((long long)a.ctl->rate[a.parity]);
+    const double t = a.ctl->time[a.parity];
+    double dt = fmin(a.cfl / rate, a.t_end - t);
+    return dt > 0.0 ? dt : 0.0;
+}
+
+// learned-limiter slope of variable v along q at cell (gx, gy, gz): interior
+// slopes come from the slope array; a ghost cell along q takes the slope of
+// its interior source (periodic), zero (outflow) or the mirrored slope
+// (reflecting; the normal velocity is odd, the other variables even)
+template <int ND, typename T>
+__device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, int64_t gx, int64_t gy, int64_t gz)
+{
+    int64_t g[3] = {gx, gy, gz};
+    T sgn = T(1);
+    for (int r = 0; r < 3; ++r) {
+        if (r >= ND) { g[r] = 0; continue; }
+        const int64_t n = a.n[r];
+        int64_t i = g[r];
+        if (i >= 0 && i < n) continue;
+        if (r == q) {
+            const int bc = i < 0 ? a.bc[r][0] : a.bc[r][1];
+            if (bc == BC_OUTFLOW) return T(0);
+            if (bc == BC_PERIODIC) i = i < 0 ? i + n : i - n;
+            else { i = i < 0 ? -1 - i : 2 * n - 1 - i; sgn = (v == 1 + q) ? T(1) : T(-1); }
+        }
+        g[r] = i < 0 ? 0 : (i >= n ? n - 1 : i);
+    }
+    const int64_t c = (g[2] * a.n[1] + g[1]) * a.n[0] + g[0];
+    return sgn * (T)a.slopes[(int64_t)(q * (ND + 2) + v) * a.vstride + c];
+}
+
+template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BY>
+__global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
+{
+    constexpr int NP = ND + 2;
+    constexpr int IP = ND + 1;
+    constexpr int NT = BX * BY;
+    constexpr int RY = (ND >= 2) ? BY + 4 : 1;  // LDS rows of primitives (2-cell halo in y)
+    constexpr int OY = (ND >= 2) ? 2 : 0;       // row offset of the tile in LDS
+    constexpr int WX = BX + 4;                  // LDS columns (2-cell halo in x)
+    constexpr int SYR = (ND >= 2) ? BY + 2 : 1;
+    constexpr int FYR = (ND >= 2) ? BY + 1 : 1;
+
+    __shared__ T sW[NP][RY][WX];        // primitives of the current plane
+    __shared__ T sSx[NP][BY][BX + 2];   // x slopes of cells -1 .. BX
+    __shared__ T sSy[NP][SYR][BX];      // y slopes of rows -1 .. BY
+    __shared__ T sFx[NP][BY][BX + 1];   // x faces 0 .. BX (face f between cells f-1, f)
+    __shared__ T sFy[NP][FYR][BX];      // y faces 0 .. BY
+
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * BX + tx;
+    const int64_t nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const int64_t x0 = (int64_t)blockIdx.x * BX;
+    const int64_t y0 = (ND >= 2) ? (int64_t)blockIdx.y * BY : 0;
+    const int64_t z0 = (ND == 3) ? (int64_t)blockIdx.z * a.zchunk : 0;
+    const int nplanes = (ND == 3) ? (int)(z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
+    const int64_t vs = a.vstride;
+    const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1, theta = a.theta;
+
+    const double dtd = stage_dt<ND>(a);
+    const T dt = (T)dtd;
+    if constexpr (STAGE == 1) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) {
+            a.ctl->rate[a.parity ^ 1] = 0ull;
+            a.ctl->time[a.parity ^ 1] = a.ctl->time[a.parity] + dtd;
+        }
+    }
+
+    // own column (mapped, so the unused columns of partial tiles hold ghost values)
+    const int64_t gx = x0 + tx, gy = y0 + ty;
+    bool fxo = false, fyo = false;
+    const int64_t mx = map_idx(gx, nx, a.bc[0][0], a.bc[0][1], fxo);
+    const int64_t my = (ND >= 2) ? map_idx(gy, ny, a.bc[1][0], a.bc[1][1], fyo) : 0;
+    const bool own_valid = (gx < nx) && (gy < ny);
+    const int64_t col_base = my * nx + mx;
+    bool bad = false;
+    T rate = T(0);
+
+    // load + convert one cell of the own column at plane z (mapped along z)
+    auto own_prim = [&](int64_t z, T (&u)[NP], T (&w)[NP]) {
+        bool fz = false;
+        const int64_t mz = (ND == 3) ? map_idx(z, nz, a.bc[2][0], a.bc[2][1], fz) : 0;
+        load_cell<ND>(a.uin, mz * nx * ny + col_base, vs, u);
+        bad |= !to_prim<ND>(u, w, gm1);
+        if (fxo) w[1] = -w[1];
+        if constexpr (ND >= 2) { if (fyo) w[2] = -w[2]; }
+        if constexpr (ND == 3) { if (fz) w[3] = -w[3]; }
+    };
+    auto face_state = [&](const T (&w)[NP], const T (&s)[NP], T h, T (&out)[NP]) {
+#pragma unroll
+        for (int v = 0; v < NP; ++v) out[v] = w[v] + h * s[v];
+    };
+
+    T Uk[NP], Wk[NP];
+    T Uk1[NP], Wk1[NP];
+    T szk[NP], fzlo[NP];
+    if constexpr (ND == 3) {
+        T um[NP], wm2[NP], wm1[NP], sm1[NP];
+        own_prim(z0 - 2, um, wm2);
+        own_prim(z0 - 1, um, wm1);
+        own_prim(z0, Uk, Wk);
+        own_prim(z0 + 1, Uk1, Wk1);
+#pragma unroll
+        for (int v = 0; v < NP; ++v) {
+            if constexpr (LIM == LIM_THETA) {
+                sm1[v] = slope_mm(wm2[v], wm1[v], Wk[v], theta);
+                szk[v] = slope_mm(wm1[v], Wk[v], Wk1[v], theta);
+            } else {
+                sm1[v] = learned_slope<ND>(a, 2, v, gx, gy, z0 - 1);
+                szk[v] = learned_slope<ND>(a, 2, v, gx, gy, z0);
+            }
+        }
+        T fl[NP], fr[NP];
+        face_state(wm1, sm1, T(0.5), fl);
+        face_state(Wk, szk, T(-0.5), fr);
+        riemann<ND, 2, SOLVER>(fl, fr, fzlo, gamma, igm1);
+    } else {
+        own_prim(0, Uk, Wk);
+    }
+
+    for (int it = 0; it < nplanes; ++it) {
+        const int64_t kz = z0 + it;
+        T U2[NP];
+        if constexpr (ND == 3) {
+            bool fz = false;
+            const int64_t mz = map_idx(kz + 2, nz, a.bc[2][0], a.bc[2][1], fz);
+            load_cell<ND>(a.uin, mz * nx * ny + col_base, vs, U2);
+        }
+
+        // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
+#pragma unroll
+        for (int v = 0; v < NP; ++v) sW[v][ty + OY][tx + 2] = Wk[v];
+        {
+            constexpr int HROW = (ND >= 2) ? 4 * WX : 0;  // 4 halo rows, full width
+            constexpr int NH = HROW + 4 * BY;            // + 4 halo columns per tile row
+            for (int h = tid; h < NH; h += NT) {
+                int row, col;
+                if (h < HROW) {
+                    const int hr = h / WX;
+                    row = hr < 2 ? hr - 2 : BY + hr - 2;
+                    col = h - hr * WX - 2;
+                } else {
+                    const int j = h - HROW;
+                    row = j >> 2;
+                    const int cc = j & 3;
+                    col = cc < 2 ? cc - 2 : BX + cc - 2;
+                }
+                bool hfx = false, hfy = false, hfz = false;
+                const int64_t hx = map_idx(x0 + col, nx, a.bc[0][0], a.bc[0][1], hfx);
+                const int64_t hy = (ND >= 2) ? map_idx(y0 + row, ny, a.bc[1][0], a.bc[1][1], hfy) : 0;
+                const int64_t hz = (ND == 3) ? map_idx(kz, nz, a.bc[2][0], a.bc[2][1], hfz) : 0;
+                T u[NP], w[NP];
+                load_cell<ND>(a.uin, (hz * ny + hy) * nx + hx, vs, u);
+                to_prim<ND>(u, w, gm1);
+                if (hfx) w[1] = -w[1];
+                if constexpr (ND >= 2) { if (hfy) w[2] = -w[2]; }
+#pragma unroll
+                for (int v = 0; v < NP; ++v) sW[v][row + OY][col + 2] = w[v];
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 1: x and y slopes of the tile cells and one ring beyond ----
+        for (int f = tid; f < BX * BY + 2 * BY; f += NT) {
+            int row, col;
+            if (f < BX * BY) { row = f / BX; col = f % BX; }
+            else { const int e = f - BX * BY; row = e >> 1; col = (e & 1) ? BX : -1; }
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                if constexpr (LIM == LIM_THETA)
+                    sSx[v][row][col + 1] = slope_mm(sW[v][row + OY][col + 1], sW[v][row + OY][col + 2],
+                                                    sW[v][row + OY][col + 3], theta);
+                else
+                    sSx[v][row][col + 1] = learned_slope<ND>(a, 0, v, x0 + col, y0 + row, kz);
+            }
+        }
+        if constexpr (ND >= 2) {
+            for (int f = tid; f < BX * BY + 2 * BX; f += NT) {
+                int row, col;
+                if (f < BX * BY) { row = f / BX; col = f % BX; }
+                else { const int e = f - BX * BY; col = e % BX; row = (e / BX) ? BY : -1; }
+#pragma unroll
+                for (int v = 0; v < NP; ++v) {
+                    if constexpr (LIM == LIM_THETA)
+                        sSy[v][row + 1][col] = slope_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
+                                                        sW[v][row + 3][col + 2], theta);
+                    else
+                        sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 2: x and y face fluxes, each face once ----
+        for (int f = tid; f < BX * BY + BY; f += NT) {
+            int row, col;
+            if (f < BX * BY) { row = f / BX; col = f % BX; }
+            else { row = f - BX * BY; col = BX; }
+            T wl[NP], wr[NP], fl[NP];
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                wl[v] = sW[v][row + OY][col + 1] + T(0.5) * sSx[v][row][col];
+                wr[v] = sW[v][row + OY][col + 2] - T(0.5) * sSx[v][row][col + 1];
+            }
+            riemann<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1);
+#pragma unroll
+            for (int v = 0; v < NP; ++v) sFx[v][row][col] = fl[v];
+        }
+        if constexpr (ND >= 2) {
+            for (int f = tid; f < BX * BY + BX; f += NT) {
+                int row, col;
+                if (f < BX * BY) { row = f / BX; col = f % BX; }
+                else { row = BY; col = f - BX * BY; }
+                T wl[NP], wr[NP], fl[NP];
+#pragma unroll
+                for (int v = 0; v < NP; ++v) {
+                    wl[v] = sW[v][row + 1][col + 2] + T(0.5) * sSy[v][row][col];
+                    wr[v] = sW[v][row + 2][col + 2] - T(0.5) * sSy[v][row + 1][col];
+                }
+                riemann<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1);
+#pragma unroll
+                for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
+            }
+        }
+        __syncthreads();
+
+        // ---- z faces from the register window ----
+        T W2[NP], sz1[NP], fzhi[NP];
+        if constexpr (ND == 3) {
+            bad |= !to_prim<ND>(U2, W2, gm1);
+            {
+                bool fz = false;
+                map_idx(kz + 2, nz, a.bc[2][0], a.bc[2][1], fz);
+                if (fxo) W2[1] = -W2[1];
+                if (fyo) W2[2] = -W2[2];
+                if (fz) W2[3] = -W2[3];
+            }
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                if constexpr (LIM == LIM_THETA) sz1[v] = slope_mm(Wk[v], Wk1[v], W2[v], theta);
+                else sz1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+            }
+            T fl[NP], fr[NP];
+            face_state(Wk, szk, T(0.5), fl);
+            face_state(Wk1, sz1, T(-0.5), fr);
+            riemann<ND, 2, SOLVER>(fl, fr, fzhi, gamma, igm1);
+        }
+
+        // ---- phase 3: divergence, source, Runge-Kutta combination ----
+        {
+            T L[NP];
+#pragma unroll
+            for (int v = 0; v < NP; ++v) L[v] = (sFx[v][ty][tx] - sFx[v][ty][tx + 1]) * a.idx[0];
+            if constexpr (ND >= 2) {
+#pragma unroll
+                for (int v = 0; v < NP; ++v) L[v] += (sFy[v][ty][tx] - sFy[v][ty + 1][tx]) * a.idx[1];
+            }
+            if constexpr (ND == 3) {
+#pragma unroll
+                for (int v = 0; v < NP; ++v) L[v] += (fzlo[v] - fzhi[v]) * a.idx[2];
+            }
+            // uniform acceleration: momentum += rho a, energy += S . a
+            {
+                T pw = T(0);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    L[1 + d] += Uk[0] * a.accel[d];
+                    pw += Uk[1 + d] * a.accel[d];
+                }
+                L[IP] += pw;
+            }
+            const bool valid = own_valid && (ND < 3 || kz < nz);
+            const int64_t c = (kz * ny + gy) * nx + gx;
+            T out[NP];
+            if constexpr (STAGE == 1) {
+#pragma unroll
+                for (int v = 0; v < NP; ++v) out[v] = Uk[v] + dt * L[v];
+            } else {
+                T u0[NP];
+                if (valid) load_cell<ND>(a.u0, c, vs, u0);
+                else {
+#pragma unroll
+                    for (int v = 0; v < NP; ++v) u0[v] = Uk[v];
+                }
+#pragma unroll
+                for (int v = 0; v < NP; ++v) out[v] = T(0.5) * (u0[v] + Uk[v] + dt * L[v]);
+            }
+            if (valid) {
+#pragma unroll
+                for (int v = 0; v < NP; ++v) a.uout[c + v * vs] = out[v];
+                if constexpr (STAGE == 2) {
+                    // CFL rate of the new state: max_q (|v_q| + c) / dq
+                    T wo[NP];
+                    bad |= !to_prim<ND>(out, wo, gm1);
+                    const T cs = sound_(gamma, wo[IP], wo[0]);
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) rate = fmax(rate, (fabs(wo[1 + d]) + cs) * a.idx[d]);
+                }
+            }
+        }
+
+        if constexpr (ND == 3) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                Uk[v] = Uk1[v]; Wk[v] = Wk1[v];
+                Uk1[v] = U2[v]; Wk1[v] = W2[v];
+                szk[v] = sz1[v]; fzlo[v] = fzhi[v];
+            }
+        }
+    }
+
+    if (bad) atomicOr(&a.ctl->err, 1u);
+    if constexpr (STAGE == 2) {
+        // wave max, then one atomic per wave (positive doubles order as uint64)
+        double r = (double)rate;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+        if ((tid & 63) == 0 && r > 0.0)
+            atomicMax(&a.ctl->rate[a.parity ^ 1], (unsigned long long)__double_as_longlong(r));
+    }
+}
+
+template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BY>
+hipError_t launch_one(const LaunchCfg &cfg, const StageArgs<T> &a, hipStream_t s)
+{
+    dim3 block(BX, BY, 1);
+    dim3 grid((unsigned)((a.n[0] + BX - 1) / BX),
+              (unsigned)(ND >= 2 ? (a.n[1] + BY - 1) / BY : 1),
+              (unsigned)(ND == 3 ? (a.n[2] + cfg.zchunk - 1) / cfg.zchunk : 1));
+    hipLaunchKernelGGL((k_stage<ND, T, SOLVER, STAGE, LIM, BY>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ND, typename T, int SOLVER, int STAGE, int LIM>
+hipError_t launch_by(const LaunchCfg &cfg, const StageArgs<T> &a, hipStream_t s)
+{
+    if constexpr (ND == 1) {
+        return launch_one<ND, T, SOLVER, STAGE, LIM, 1>(cfg, a, s);
+    } else if constexpr (sizeof(T) == 8) {
+        // a 64 x 16 FP64 tile does not fit in the 160 KB of LDS
+        if (cfg.by == 4) return launch_one<ND, T, SOLVER, STAGE, LIM, 4>(cfg, a, s);
+        return launch_one<ND, T, SOLVER, STAGE, LIM, 8>(cfg, a, s);
+    } else {
+        switch (cfg.by) {
+        case 4: return launch_one<ND, T, SOLVER, STAGE, LIM, 4>(cfg, a, s);
+        case 16: return launch_one<ND, T, SOLVER, STAGE, LIM, 16>(cfg, a, s);
+        default: return launch_one<ND, T, SOLVER, STAGE, LIM, 8>(cfg, a, s);
+        }
+    }
+}
+
+template <int ND, typename T, int SOLVER, int STAGE>
+hipError_t launch_lim(int limiter, const LaunchCfg &cfg, const StageArgs<T> &a, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (limiter == LIM_LEARNED) return launch_by<ND, T, SOLVER, STAGE, LIM_LEARNED>(cfg, a, s);
+    }
+    return launch_by<ND, T, SOLVER, STAGE, LIM_THETA>(cfg, a, s);
+}
+
+template <int ND, typename T>
+hipError_t launch_nd(int solver, int stage, int limiter, const LaunchCfg &cfg, const StageArgs<T> &a,
+                     hipStream_t s)
+{
+    if (solver == 0) {
+        return stage == 1 ? launch_lim<ND, T, 0, 1>(limiter, cfg, a, s) : launch_lim<ND, T, 0, 2>(limiter, cfg, a, s);
+    }
+    return stage == 1 ? launch_lim<ND, T, 1, 1>(limiter, cfg, a, s) : launch_lim<ND, T, 1, 2>(limiter, cfg, a, s);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_stage(int ndim, int solver, int stage, int limiter, const LaunchCfg &cfg,
+                        const StageArgs<T> &a, hipStream_t s)
+{
+    switch (ndim) {
+    case 1: return launch_nd<1, T>(solver, stage, limiter, cfg, a, s);
+    case 2: return launch_nd<2, T>(solver, stage, limiter, cfg, a, s);
+    default: return launch_nd<3, T>(solver, stage, limiter, cfg, a, s);
+    }
+}
+
+template hipError_t launch_stage<float>(int, int, int, int, const LaunchCfg &, const StageArgs<float> &, hipStream_t);
+template hipError_t launch_stage<double>(int, int, int, int, const LaunchCfg &, const StageArgs<double> &, hipStream_t);
+
+}  // namespace hy

@@ -1,0 +1,238 @@
+"""Python binding of libhydro.so (include/hydro.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels.  PyTorch supplies
+device memory (the workspace is a uint8 tensor) and the HIP stream (torch's
+current stream).  If the library is not built this module raises; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+
+HY_OK, HY_EINVAL, HY_ENOMEM, HY_EDEVICE, HY_ESTATE, HY_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+HLL, HLLC = 0, 1
+LIM_THETA, LIM_LEARNED = 0, 1
+PRIMITIVE, CONSERVED = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+MLP_NPARAM = 1249
+
+
+class HydroError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hydro status {status}: {msg}")
+        self.status = status
+
+
+class PatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int64 * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("bc", (ctypes.c_int * 2) * 3),
+        ("precision", ctypes.c_int),
+        ("limiter", ctypes.c_int),
+        ("theta", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
+    ]
+
+
+_P = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+SIGNATURES = {
+    "hy_patch_workspace_bytes": [ctypes.POINTER(PatchDesc), ctypes.POINTER(ctypes.c_size_t)],
+    "hy_init_patch": [ctypes.POINTER(PatchDesc), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "hy_set_state": [_P, ctypes.c_int, _dp],
+    "hy_get_state": [_P, ctypes.c_int, _dp],
+    "hy_step": [_P, ctypes.c_double, ctypes.c_int],
+    "hy_cfl_dt": [_P, ctypes.c_double, _dp],
+    "hy_advance": [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int],
+    "hy_get_time": [_P, _dp],
+    "hy_conserved_totals": [_P, _dp],
+    "hy_set_mlp": [_P, _fp, ctypes.c_size_t],
+    "hy_set_timing": [_P, ctypes.c_int],
+    "hy_kernel_times": [_P, _dp, _i64p],
+    "hy_kernel_config": [_P, ctypes.c_char_p, ctypes.c_size_t],
+    "hy_destroy": [_P],
+}
+
+_lib = None
+
+
+def lib():
+    """Load libhydro.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1207_3392_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.hy_last_error.argtypes = []
+        L.hy_last_error.restype = ctypes.c_char_p
+        _extra_signatures(L)
+        _lib = L
+    return _lib
+
+
+def _extra_signatures(L):
+    """Signatures of the batched-launch and training entry points."""
+    for name, args in EXTRA_SIGNATURES.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+
+
+EXTRA_SIGNATURES = {}
+
+
+def check(status: int, what: str = ""):
+    if status != HY_OK:
+        msg = lib().hy_last_error().decode(errors="replace")
+        raise HydroError(status, f"{what}: {msg}")
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def make_desc(ndim, n, lo, hi, gamma, bc, precision=32, limiter=LIM_THETA, theta=2.0,
+              accel=(0.0, 0.0, 0.0)) -> PatchDesc:
+    d = PatchDesc()
+    d.ndim = int(ndim)
+    for q in range(3):
+        d.n[q] = int(n[q])
+        d.lo[q] = float(lo[q])
+        d.hi[q] = float(hi[q])
+        d.bc[q][0] = int(bc[q][0])
+        d.bc[q][1] = int(bc[q][1])
+        d.accel[q] = float(accel[q])
+    d.gamma = float(gamma)
+    d.precision = int(precision)
+    d.limiter = int(limiter)
+    d.theta = float(theta)
+    return d
+
+
+class Patch:
+    """One Cartesian patch in GPU memory.
+
+    ``problem`` is a workloads.Problem (or any object with ndim, n, lo, hi,
+    gamma, bc, theta, accel).  The workspace is allocated as a torch uint8
+    tensor on ``device``; work is enqueued on torch's current stream there."""
+
+    def __init__(self, problem, precision: int = 32, limiter: int = LIM_THETA,
+                 theta: Optional[float] = None, device: str = "cuda", set_initial: bool = True):
+        import torch
+
+        self.problem = problem
+        self.ndim = problem.ndim
+        self.n = tuple(int(v) for v in problem.n)
+        self.nv = self.ndim + 2
+        self.ncell = self.n[0] * self.n[1] * self.n[2]
+        self.desc = make_desc(problem.ndim, problem.n, problem.lo, problem.hi, problem.gamma,
+                              problem.bc, precision, limiter,
+                              problem.theta if theta is None else theta, problem.accel)
+        nbytes = ctypes.c_size_t(0)
+        check(lib().hy_patch_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)),
+              "workspace_bytes")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _P()
+        check(lib().hy_init_patch(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
+                                  nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "init_patch")
+        self.handle = h
+        if set_initial and getattr(problem, "W", None) is not None:
+            self.set_state(problem.W, PRIMITIVE)
+
+    # ---- state ----
+    def set_state(self, arr, kind: int = PRIMITIVE):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(self.nv, self.ncell))
+        check(lib().hy_set_state(self.handle, int(kind), _dptr(a)), "set_state")
+
+    def get_state(self, kind: int = CONSERVED, check_state: bool = True) -> np.ndarray:
+        out = np.empty((self.nv, self.ncell), dtype=np.float64)
+        st = lib().hy_get_state(self.handle, int(kind), _dptr(out))
+        if check_state or st != HY_ESTATE:
+            check(st, "get_state")
+        return out
+
+    # ---- stepping ----
+    def step(self, dt: float, solver: int = HLLC):
+        check(lib().hy_step(self.handle, float(dt), int(solver)), "step")
+
+    def cfl_dt(self, cfl: float) -> float:
+        out = ctypes.c_double(0.0)
+        check(lib().hy_cfl_dt(self.handle, float(cfl), ctypes.byref(out)), "cfl_dt")
+        return out.value
+
+    def advance(self, nsteps: int, cfl: float, t_end: float = float("inf"), solver: int = HLLC):
+        check(lib().hy_advance(self.handle, int(nsteps), float(cfl), float(t_end), int(solver)), "advance")
+
+    def time(self) -> float:
+        out = ctypes.c_double(0.0)
+        check(lib().hy_get_time(self.handle, ctypes.byref(out)), "get_time")
+        return out.value
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(5)
+        check(lib().hy_conserved_totals(self.handle, _dptr(out)), "conserved_totals")
+        return out
+
+    def set_mlp(self, params):
+        w = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        check(lib().hy_set_mlp(self.handle, w.ctypes.data_as(_fp), ctypes.c_size_t(w.size)), "set_mlp")
+
+    # ---- timing ----
+    def set_timing(self, on: bool):
+        check(lib().hy_set_timing(self.handle, int(bool(on))), "set_timing")
+
+    def kernel_times(self):
+        ms = np.zeros(2)
+        n = np.zeros(2, dtype=np.int64)
+        check(lib().hy_kernel_times(self.handle, _dptr(ms), n.ctypes.data_as(_i64p)), "kernel_times")
+        return ms, n
+
+    def kernel_config(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        check(lib().hy_kernel_config(self.handle, buf, 256), "kernel_config")
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- loops ----
+    def run(self, t_end: float, cfl: float, solver: int = HLLC, max_steps: int = 10 ** 8) -> int:
+        """Host-driven single-level loop: dt = min(C dt_CFL, t_end - t)."""
+        t, k = 0.0, 0
+        while t < t_end and k < max_steps:
+            dt = min(self.cfl_dt(cfl), t_end - t)
+            self.step(dt, solver)
+            t += dt
+            k += 1
+        return k

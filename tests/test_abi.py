@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every entry point its header declares,
+and rejects bad descriptions on the host (no GPU needed for either)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1207_3392_amd import hydro
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(hy_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = hydro.lib()
+    names = declared_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_workspace_size_and_host_validation():
+    L = hydro.lib()
+    d = hydro.make_desc(3, (64, 32, 16), (0, 0, 0), (1, 1, 1), 5 / 3, ((0, 0),) * 3, precision=32)
+    nb = ctypes.c_size_t(0)
+    assert L.hy_patch_workspace_bytes(ctypes.byref(d), ctypes.byref(nb)) == hydro.HY_OK
+    ncell = 64 * 32 * 16
+    assert nb.value >= 2 * 5 * ncell * 4
+    d64 = hydro.make_desc(3, (64, 32, 16), (0, 0, 0), (1, 1, 1), 5 / 3, ((0, 0),) * 3, precision=64)
+    nb64 = ctypes.c_size_t(0)
+    assert L.hy_patch_workspace_bytes(ctypes.byref(d64), ctypes.byref(nb64)) == hydro.HY_OK
+    assert nb64.value > nb.value
+    bad = [
+        hydro.make_desc(4, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3),
+        hydro.make_desc(1, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.0, ((0, 0),) * 3),
+        hydro.make_desc(1, (1, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3),
+        hydro.make_desc(1, (8, 2, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3),
+        hydro.make_desc(1, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 1), (0, 0), (0, 0))),
+        hydro.make_desc(1, (8, 1, 1), (1, 0, 0), (0, 1, 1), 1.4, ((0, 0),) * 3),
+        hydro.make_desc(1, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3, precision=16),
+        hydro.make_desc(1, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3, theta=2.5),
+    ]
+    for d in bad:
+        assert L.hy_patch_workspace_bytes(ctypes.byref(d), ctypes.byref(nb)) == hydro.HY_EINVAL
+    learned64 = hydro.make_desc(2, (8, 8, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3, precision=64,
+                                limiter=hydro.LIM_LEARNED)
+    assert L.hy_patch_workspace_bytes(ctypes.byref(learned64), ctypes.byref(nb)) == hydro.HY_EUNSUPPORTED
+    assert b"FP32" in L.hy_last_error()
+
+
+def test_init_rejects_small_workspace_without_touching_the_device():
+    L = hydro.lib()
+    d = hydro.make_desc(1, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((1, 1), (0, 0), (0, 0)))
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.hy_init_patch(ctypes.byref(d), fake, 16, None, ctypes.byref(h)) == hydro.HY_ENOMEM
+    assert L.hy_init_patch(ctypes.byref(d), None, 1 << 20, None, ctypes.byref(h)) == hydro.HY_EINVAL
