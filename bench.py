@@ -36,8 +36,22 @@ def parse():
     ap.add_argument("--solver", default="hllc", choices=["hll", "hllc"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
-    ap.add_argument("--by", type=int, default=0, help="override the tile rows (4, 8, 16)")
+    ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
 def time_patch(n, solver, steps, warmup, timing=True):
@@ -122,8 +136,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if args.by:
-        os.environ["HY_TILE_BY"] = str(args.by)
+    if args.tile:
+        os.environ["HY_TILE"] = args.tile
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     main_res = time_patch(args.n, args.solver, args.steps, args.warmup)
     extra = {}

@@ -38,6 +38,7 @@ struct StageArgs {
     T accel[3];
     int bc[3][2];
     int zchunk;       // planes per block along z (3D)
+    int tiles_x, tiles_y, ntiles;  // tile grid (set by the launcher)
     DevCtl *ctl;
     int parity;       // slot of the input state's time / rate
     int dt_mode;
@@ -45,7 +46,8 @@ struct StageArgs {
 };
 
 struct LaunchCfg {
-    int by;       // rows per block in the x-y plane tile (block = 64 x by threads)
+    int bx;       // plane tile width (block = bx x by threads)
+    int by;       // plane tile rows
     int zchunk;   // planes per block along z
 };
 

@@ -48,7 +48,7 @@ struct hy_patch {
     bool mlp_set = false;
     hipStream_t stream = nullptr;
     int parity = 0;
-    hy::LaunchCfg cfg{8, 32};
+    hy::LaunchCfg cfg{64, 8, 32};
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
@@ -88,7 +88,10 @@ hy_status check_desc(const hy_patch_desc *d)
     if (d->n[0] > (int64_t)1 << 20 || d->n[1] > (int64_t)1 << 20 || d->n[2] > (int64_t)1 << 20)
         return fail(HY_EINVAL, "dimension too large");
     const int64_t N = ncells(*d);
-    if (N > ((int64_t)1 << 33)) return fail(HY_EINVAL, "too many cells");
+    // kernels address cells with 32-bit offsets within one variable's array
+    const int64_t es = d->precision == 64 ? 8 : 4;
+    if (N * es > ((int64_t)1 << 32) - 256)
+        return fail(HY_EINVAL, "patch too large: one variable's array must stay below 4 GiB");
     return HY_OK;
 }
 
@@ -219,15 +222,24 @@ hy_status compute_rate(hy_patch *p)
 
 void pick_config(hy_patch *p)
 {
-    // 64 x BY plane tiles; z chunks sized so that a launch has >= ~1024 blocks
+    // plane tile and z chunk: a launch should have >= ~1024 workgroups
     const hy_patch_desc &d = p->d;
+    p->cfg.bx = 64;
     p->cfg.by = d.ndim == 1 ? 1 : 8;
-    if (const char *e = std::getenv("HY_TILE_BY")) {
-        const int by = std::atoi(e);
-        if (d.ndim > 1 && (by == 4 || by == 8 || by == 16)) p->cfg.by = by;
+    if (d.ndim >= 2 && d.precision == 32) {
+        p->cfg.bx = 32;
+        p->cfg.by = 16;
+    }
+    if (const char *e = std::getenv("HY_TILE")) {  // "BXxBY", for tuning runs
+        int bx = 0, by = 0;
+        if (d.ndim > 1 && std::sscanf(e, "%dx%d", &bx, &by) == 2 &&
+            ((bx == 64 && (by == 8 || by == 4)) || (bx == 32 && (by == 8 || (by == 16 && d.precision == 32))))) {
+            p->cfg.bx = bx;
+            p->cfg.by = by;
+        }
     }
     if (d.ndim == 3) {
-        const int64_t tiles = ((d.n[0] + 63) / 64) * ((d.n[1] + p->cfg.by - 1) / p->cfg.by);
+        const int64_t tiles = ((d.n[0] + p->cfg.bx - 1) / p->cfg.bx) * ((d.n[1] + p->cfg.by - 1) / p->cfg.by);
         int64_t chunks = (1024 + tiles - 1) / tiles;
         if (chunks > d.n[2] / 8) chunks = d.n[2] / 8;
         if (chunks < 1) chunks = 1;
@@ -470,8 +482,8 @@ hy_status hy_kernel_times(hy_patch *p, double ms[2], int64_t launches[2])
 hy_status hy_kernel_config(hy_patch *p, char *buf, size_t len)
 {
     if (!p || !buf || len == 0) return fail(HY_EINVAL, "null argument");
-    std::snprintf(buf, len, "k_stage<nd=%d,%s,by=%d> zchunk=%d", p->d.ndim, p->d.precision == 64 ? "f64" : "f32",
-                  p->cfg.by, p->cfg.zchunk);
+    std::snprintf(buf, len, "k_stage<nd=%d,%s,tile=%dx%d> zchunk=%d", p->d.ndim, p->d.precision == 64 ? "f64" : "f32",
+                  p->cfg.bx, p->cfg.by, p->cfg.zchunk);
     return HY_OK;
 }
 

@@ -28,7 +28,6 @@
 namespace hy {
 namespace {
 
-constexpr int BX = 64;
 
 // ---------------------------------------------------------------- math ----
 
@@ -52,25 +51,6 @@ template <typename T> __device__ __forceinline__ T max3_(T a, T b, T c) { return
 
 // ------------------------------------------------------- index mapping ----
 
-// Source of index i along a dimension of n interior cells; flip is set when
-// the source is a mirror image.  Indices far outside the ghost range (only
-// met by the unused columns of partial tiles) are clamped into the array.
-__device__ __forceinline__ int64_t map_idx(int64_t i, int64_t n, int bclo, int bchi, bool &flip)
-{
-    if (i >= 0 && i < n) return i;
-    int64_t m;
-    if (i < 0) {
-        if (bclo == BC_PERIODIC) m = i + n;
-        else if (bclo == BC_OUTFLOW) m = 0;
-        else { m = -1 - i; flip = !flip; }
-    } else {
-        if (bchi == BC_PERIODIC) m = i - n;
-        else if (bchi == BC_OUTFLOW) m = n - 1;
-        else { m = 2 * n - 1 - i; flip = !flip; }
-    }
-    return m < 0 ? 0 : (m >= n ? n - 1 : m);
-}
-
 // ------------------------------------------------------ fluid variables ----
 
 // primitives (rho, v, p) from conserved (D, S, G), m = 1; returns false on
@@ -91,22 +71,27 @@ __device__ __forceinline__ bool to_prim(const T (&u)[ND + 2], T (&w)[ND + 2], T 
     return (w[0] > T(0)) & (w[ND + 1] > T(0)) & (w[0] < big) & (w[ND + 1] < big);
 }
 
-template <int ND, typename T>
-__device__ __forceinline__ void load_cell(const T *__restrict__ u, int64_t c, int64_t vs, T (&out)[ND + 2])
+template <typename T> __device__ __forceinline__ T med3_(T a, T b, T c);
+template <> __device__ __forceinline__ float med3_<float>(float a, float b, float c)
 {
-#pragma unroll
-    for (int v = 0; v < ND + 2; ++v) out[v] = u[c + v * vs];
+    return __builtin_amdgcn_fmed3f(a, b, c);
+}
+template <> __device__ __forceinline__ double med3_<double>(double a, double b, double c)
+{
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
 }
 
-// generalised minmod of eq. MinMod as a per-cell difference:
-// sigma = MM(theta dm, (dm + dp) / 2, theta dp)
+// Twice the generalised-minmod slope of eq. MinMod as a per-cell difference:
+// with a = 2 theta dm, b = dm + dp, c = 2 theta dp, MM(a, b, c) (the argument
+// of least magnitude when all share a sign, else 0) equals
+// med3(min(a, b, c), max(a, b, c), 0), and MM(a, b, c) = 2 MM(theta dm,
+// (dm + dp) / 2, theta dp) exactly.  Face values are then w +/- slope / 4.
 template <typename T>
-__device__ __forceinline__ T slope_mm(T wm, T w0, T wp, T theta)
+__device__ __forceinline__ T slope2_mm(T wm, T w0, T wp, T theta2)
 {
     const T dm = w0 - wm, dp = wp - w0;
-    const T a = theta * dm, b = T(0.5) * (dm + dp), c = theta * dp;
-    const T m = fmin(fabs(a), fmin(fabs(b), fabs(c)));
-    return (dm * dp > T(0)) ? copysign(m, b) : T(0);
+    const T a = theta2 * dm, b = dm + dp, c = theta2 * dp;
+    return med3_(fmin(a, fmin(b, c)), fmax(a, fmax(b, c)), T(0));
 }
 
 // ------------------------------------------------------ Riemann solvers ----
@@ -201,19 +186,42 @@ __device__ __forceinline__ double stage_dt(const StageArgs<T> &a)
     return dt > 0.0 ? dt : 0.0;
 }
 
-// learned-limiter slope of variable v along q at cell (gx, gy, gz): interior
+constexpr int FLIP = 1 << 30;      // set on a mapped index whose source is a mirror image
+constexpr int IDX = FLIP - 1;
+
+// Source of index i along a dimension of n interior cells; flip toggles when
+// the source is a mirror image.  Indices far outside the ghost range (only
+// met by the unused columns of partial tiles) are clamped into the array.
+__device__ __forceinline__ int map32(int i, int n, int bclo, int bchi, bool &flip)
+{
+    if (i >= 0 && i < n) return i;
+    int m;
+    if (i < 0) {
+        if (bclo == BC_PERIODIC) m = i + n;
+        else if (bclo == BC_OUTFLOW) m = 0;
+        else { m = -1 - i; flip = !flip; }
+    } else {
+        if (bchi == BC_PERIODIC) m = i - n;
+        else if (bchi == BC_OUTFLOW) m = n - 1;
+        else { m = 2 * n - 1 - i; flip = !flip; }
+    }
+    return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
+// Twice the learned-limiter slope of variable v along q at cell (gx, gy, gz): interior
 // slopes come from the slope array; a ghost cell along q takes the slope of
 // its interior source (periodic), zero (outflow) or the mirrored slope
 // (reflecting; the normal velocity is odd, the other variables even)
 template <int ND, typename T>
-__device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, int64_t gx, int64_t gy, int64_t gz)
+__device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, int gx, int gy, int gz)
 {
-    int64_t g[3] = {gx, gy, gz};
+    int g[3] = {gx, gy, gz};
     T sgn = T(1);
+#pragma unroll
     for (int r = 0; r < 3; ++r) {
         if (r >= ND) { g[r] = 0; continue; }
-        const int64_t n = a.n[r];
-        int64_t i = g[r];
+        const int n = (int)a.n[r];
+        int i = g[r];
         if (i >= 0 && i < n) continue;
         if (r == q) {
             const int bc = i < 0 ? a.bc[r][0] : a.bc[r][1];
@@ -223,11 +231,12 @@ __device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, 
         }
         g[r] = i < 0 ? 0 : (i >= n ? n - 1 : i);
     }
-    const int64_t c = (g[2] * a.n[1] + g[1]) * a.n[0] + g[0];
-    return sgn * (T)a.slopes[(int64_t)(q * (ND + 2) + v) * a.vstride + c];
+    const int c = (g[2] * (int)a.n[1] + g[1]) * (int)a.n[0] + g[0];
+    const float *base = a.slopes + (int64_t)(q * (ND + 2) + v) * a.vstride;
+    return T(2) * sgn * (T)base[c];
 }
 
-template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BY>
+template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BX, int BY>
 __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
 {
     constexpr int NP = ND + 2;
@@ -238,122 +247,197 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
     constexpr int WX = BX + 4;                  // LDS columns (2-cell halo in x)
     constexpr int SYR = (ND >= 2) ? BY + 2 : 1;
     constexpr int FYR = (ND >= 2) ? BY + 1 : 1;
+    constexpr int HROW = (ND >= 2) ? 4 * WX : 0;  // halo rows -2, -1, BY, BY+1 (full width)
+    constexpr int NH = HROW + 4 * BY;             // + halo columns -2, -1, BX, BX+1 of each tile row
+    constexpr int HPT = (NH + NT - 1) / NT;       // halo cells per thread
 
     __shared__ T sW[NP][RY][WX];        // primitives of the current plane
     __shared__ T sSx[NP][BY][BX + 2];   // x slopes of cells -1 .. BX
     __shared__ T sSy[NP][SYR][BX];      // y slopes of rows -1 .. BY
     __shared__ T sFx[NP][BY][BX + 1];   // x faces 0 .. BX (face f between cells f-1, f)
     __shared__ T sFy[NP][FYR][BX];      // y faces 0 .. BY
+    __shared__ int sMap[WX + RY];       // mapped x of columns -2 .. BX+1, then mapped y of rows -2 .. BY+1
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
-    const int64_t nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    const int64_t x0 = (int64_t)blockIdx.x * BX;
-    const int64_t y0 = (ND >= 2) ? (int64_t)blockIdx.y * BY : 0;
-    const int64_t z0 = (ND == 3) ? (int64_t)blockIdx.z * a.zchunk : 0;
-    const int nplanes = (ND == 3) ? (int)(z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
-    const int64_t vs = a.vstride;
-    const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1, theta = a.theta;
+    const int nx = (int)a.n[0], ny = (int)a.n[1], nz = (int)a.n[2];
+    const int plane = nx * ny;
+    // XCD-aware tile order: consecutive workgroup ids are dealt round-robin
+    // to the 8 XCDs, so hand each XCD a contiguous band of tiles (x fastest,
+    // then y, then z chunk); neighbouring tiles then share halo lines in the
+    // same L2.  The mapping is a bijection whatever the dispatch order.
+    int bxi, byi, bzi;
+    {
+        const int lid = blockIdx.x, total = a.ntiles;
+        const int per = total >> 3, rem = total & 7, xcd = lid & 7;
+        const int logical = xcd * per + (xcd < rem ? xcd : rem) + (lid >> 3);
+        bxi = logical % a.tiles_x;
+        const int rest = logical / a.tiles_x;
+        byi = rest % a.tiles_y;
+        bzi = rest / a.tiles_y;
+    }
+    const int x0 = bxi * BX;
+    const int y0 = (ND >= 2) ? byi * BY : 0;
+    const int z0 = (ND == 3) ? bzi * a.zchunk : 0;
+    const int nplanes = (ND == 3) ? (z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
+    const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1, theta2 = T(2) * a.theta;
+
+    // per-variable base pointers (uniform), 32-bit cell offsets below
+    const T *uin[NP];
+    const T *u0p[NP];
+    T *uout[NP];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) {
+        uin[v] = a.uin + (int64_t)v * a.vstride;
+        u0p[v] = a.u0 + (int64_t)v * a.vstride;
+        uout[v] = a.uout + (int64_t)v * a.vstride;
+    }
+    // cell offsets are < 2^32 / sizeof(T) (checked on the host), so byte
+    // offsets stay 32-bit and loads use the scalar-base + vector-offset form
+    auto at = [](const T *base, unsigned off) -> const T & {
+        return *(const T *)((const char *)base + off * (unsigned)sizeof(T));
+    };
+    auto load = [&](unsigned off, T (&u)[NP]) {
+#pragma unroll
+        for (int v = 0; v < NP; ++v) u[v] = at(uin[v], off);
+    };
+
+    for (int i = tid; i < WX + RY; i += NT) {
+        bool f = false;
+        int m = 0;
+        if (i < WX) m = map32(x0 + i - 2, nx, a.bc[0][0], a.bc[0][1], f);
+        else if (ND >= 2) m = map32(y0 + (i - WX) - 2, ny, a.bc[1][0], a.bc[1][1], f);
+        sMap[i] = m | (f ? FLIP : 0);
+    }
 
     const double dtd = stage_dt<ND>(a);
     const T dt = (T)dtd;
     if constexpr (STAGE == 1) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) {
+        if (blockIdx.x == 0 && tid == 0) {
             a.ctl->rate[a.parity ^ 1] = 0ull;
             a.ctl->time[a.parity ^ 1] = a.ctl->time[a.parity] + dtd;
         }
     }
+    __syncthreads();
 
-    // own column (mapped, so the unused columns of partial tiles hold ghost values)
-    const int64_t gx = x0 + tx, gy = y0 + ty;
-    bool fxo = false, fyo = false;
-    const int64_t mx = map_idx(gx, nx, a.bc[0][0], a.bc[0][1], fxo);
-    const int64_t my = (ND >= 2) ? map_idx(gy, ny, a.bc[1][0], a.bc[1][1], fyo) : 0;
+    // own column: mapped (the unused columns of partial tiles hold ghost values)
+    const int xm = sMap[tx + 2];
+    const int ym = (ND >= 2) ? sMap[WX + ty + 2] : 0;
+    const bool fxo = (xm & FLIP) != 0, fyo = (ym & FLIP) != 0;
+    const unsigned colo = (unsigned)((ym & IDX) * nx + (xm & IDX));
+    const int gx = x0 + tx, gy = y0 + ty;
     const bool own_valid = (gx < nx) && (gy < ny);
-    const int64_t col_base = my * nx + mx;
+    const unsigned colv = (unsigned)(gy * nx + gx);
+
+    // halo cells of this thread: plane offset, LDS slot, mirror flags
+    unsigned hoff[HPT];
+    int hlds[HPT], hflg[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int h = tid + j * NT;
+        hlds[j] = -1;
+        hoff[j] = 0;
+        hflg[j] = 0;
+        if (h < NH) {
+            int row, col;
+            if (h < HROW) {
+                const int hr = h / WX;
+                row = hr < 2 ? hr - 2 : BY + hr - 2;
+                col = h - hr * WX - 2;
+            } else {
+                const int jj = h - HROW;
+                row = jj >> 2;
+                const int cc = jj & 3;
+                col = cc < 2 ? cc - 2 : BX + cc - 2;
+            }
+            const int hx = sMap[col + 2];
+            const int hy = (ND >= 2) ? sMap[WX + row + 2] : 0;
+            hoff[j] = (unsigned)((hy & IDX) * nx + (hx & IDX));
+            hlds[j] = (row + OY) * WX + col + 2;
+            hflg[j] = ((hx & FLIP) ? 1 : 0) | ((hy & FLIP) ? 2 : 0);
+        }
+    }
+
     bool bad = false;
     T rate = T(0);
 
-    // load + convert one cell of the own column at plane z (mapped along z)
-    auto own_prim = [&](int64_t z, T (&u)[NP], T (&w)[NP]) {
-        bool fz = false;
-        const int64_t mz = (ND == 3) ? map_idx(z, nz, a.bc[2][0], a.bc[2][1], fz) : 0;
-        load_cell<ND>(a.uin, mz * nx * ny + col_base, vs, u);
+    auto to_w = [&](const T (&u)[NP], T (&w)[NP], bool fx, bool fy, bool fz) {
         bad |= !to_prim<ND>(u, w, gm1);
-        if (fxo) w[1] = -w[1];
-        if constexpr (ND >= 2) { if (fyo) w[2] = -w[2]; }
+        if (fx) w[1] = -w[1];
+        if constexpr (ND >= 2) { if (fy) w[2] = -w[2]; }
         if constexpr (ND == 3) { if (fz) w[3] = -w[3]; }
+    };
+    auto zoff = [&](int z, bool &fz) -> unsigned {
+        if constexpr (ND == 3) return (unsigned)(map32(z, nz, a.bc[2][0], a.bc[2][1], fz) * plane);
+        return 0u;
     };
     auto face_state = [&](const T (&w)[NP], const T (&s)[NP], T h, T (&out)[NP]) {
 #pragma unroll
         for (int v = 0; v < NP; ++v) out[v] = w[v] + h * s[v];
     };
 
-    T Uk[NP], Wk[NP];
-    T Uk1[NP], Wk1[NP];
-    T szk[NP], fzlo[NP];
+    // register z window: W (primitives), U (conserved), S (z slopes) and F
+    // (z face fluxes) of three consecutive planes, rotated by renaming
+    T WA[NP], WB[NP], WC[NP], UA[NP], UB[NP], UC[NP], SA[NP], SB[NP], SC[NP], FA[NP], FB[NP], FC[NP];
     if constexpr (ND == 3) {
         T um[NP], wm2[NP], wm1[NP], sm1[NP];
-        own_prim(z0 - 2, um, wm2);
-        own_prim(z0 - 1, um, wm1);
-        own_prim(z0, Uk, Wk);
-        own_prim(z0 + 1, Uk1, Wk1);
+        bool f2 = false, f1 = false, f0 = false, fp = false;
+        load(zoff(z0 - 2, f2) + colo, um);
+        to_w(um, wm2, fxo, fyo, f2);
+        load(zoff(z0 - 1, f1) + colo, um);
+        to_w(um, wm1, fxo, fyo, f1);
+        load(zoff(z0, f0) + colo, UA);
+        to_w(UA, WA, fxo, fyo, f0);
+        load(zoff(z0 + 1, fp) + colo, UB);
+        to_w(UB, WB, fxo, fyo, fp);
 #pragma unroll
         for (int v = 0; v < NP; ++v) {
             if constexpr (LIM == LIM_THETA) {
-                sm1[v] = slope_mm(wm2[v], wm1[v], Wk[v], theta);
-                szk[v] = slope_mm(wm1[v], Wk[v], Wk1[v], theta);
+                sm1[v] = slope2_mm(wm2[v], wm1[v], WA[v], theta2);
+                SA[v] = slope2_mm(wm1[v], WA[v], WB[v], theta2);
             } else {
                 sm1[v] = learned_slope<ND>(a, 2, v, gx, gy, z0 - 1);
-                szk[v] = learned_slope<ND>(a, 2, v, gx, gy, z0);
+                SA[v] = learned_slope<ND>(a, 2, v, gx, gy, z0);
             }
         }
         T fl[NP], fr[NP];
-        face_state(wm1, sm1, T(0.5), fl);
-        face_state(Wk, szk, T(-0.5), fr);
-        riemann<ND, 2, SOLVER>(fl, fr, fzlo, gamma, igm1);
+        face_state(wm1, sm1, T(0.25), fl);
+        face_state(WA, SA, T(-0.25), fr);
+        riemann<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1);
     } else {
-        own_prim(0, Uk, Wk);
+        load(colo, UA);
+        to_w(UA, WA, fxo, fyo, false);
     }
 
-    for (int it = 0; it < nplanes; ++it) {
-        const int64_t kz = z0 + it;
-        T U2[NP];
-        if constexpr (ND == 3) {
-            bool fz = false;
-            const int64_t mz = map_idx(kz + 2, nz, a.bc[2][0], a.bc[2][1], fz);
-            load_cell<ND>(a.uin, mz * nx * ny + col_base, vs, U2);
+    T *sWf = &sW[0][0][0];
+    // one plane: Wk/Uk/Sk/Flo hold plane kz, Wk1/Uk1 plane kz+1; the body
+    // fills W2/U2 (plane kz+2), Sk1 (z slopes of kz+1) and Fhi (face kz+1/2)
+    auto body = [&](int it, T (&Wk)[NP], T (&Wk1)[NP], T (&W2)[NP], T (&Uk)[NP], T (&Uk1)[NP], T (&U2)[NP],
+                    T (&Sk)[NP], T (&Sk1)[NP], T (&Flo)[NP], T (&Fhi)[NP]) {
+        (void)Uk1;
+        const int kz = z0 + it;
+        const unsigned zko = (ND == 3) ? (unsigned)(kz * plane) : 0u;
+        bool fz2 = false;
+        if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
+        T u0[NP];
+        if constexpr (STAGE == 2) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
         }
 
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
 #pragma unroll
         for (int v = 0; v < NP; ++v) sW[v][ty + OY][tx + 2] = Wk[v];
-        {
-            constexpr int HROW = (ND >= 2) ? 4 * WX : 0;  // 4 halo rows, full width
-            constexpr int NH = HROW + 4 * BY;            // + 4 halo columns per tile row
-            for (int h = tid; h < NH; h += NT) {
-                int row, col;
-                if (h < HROW) {
-                    const int hr = h / WX;
-                    row = hr < 2 ? hr - 2 : BY + hr - 2;
-                    col = h - hr * WX - 2;
-                } else {
-                    const int j = h - HROW;
-                    row = j >> 2;
-                    const int cc = j & 3;
-                    col = cc < 2 ? cc - 2 : BX + cc - 2;
-                }
-                bool hfx = false, hfy = false, hfz = false;
-                const int64_t hx = map_idx(x0 + col, nx, a.bc[0][0], a.bc[0][1], hfx);
-                const int64_t hy = (ND >= 2) ? map_idx(y0 + row, ny, a.bc[1][0], a.bc[1][1], hfy) : 0;
-                const int64_t hz = (ND == 3) ? map_idx(kz, nz, a.bc[2][0], a.bc[2][1], hfz) : 0;
-                T u[NP], w[NP];
-                load_cell<ND>(a.uin, (hz * ny + hy) * nx + hx, vs, u);
-                to_prim<ND>(u, w, gm1);
-                if (hfx) w[1] = -w[1];
-                if constexpr (ND >= 2) { if (hfy) w[2] = -w[2]; }
 #pragma unroll
-                for (int v = 0; v < NP; ++v) sW[v][row + OY][col + 2] = w[v];
+        for (int j = 0; j < HPT; ++j) {
+            if (hlds[j] >= 0) {
+                T u[NP], w[NP];
+                load(zko + hoff[j], u);
+                to_prim<ND>(u, w, gm1);
+                if (hflg[j] & 1) w[1] = -w[1];
+                if constexpr (ND >= 2) { if (hflg[j] & 2) w[2] = -w[2]; }
+#pragma unroll
+                for (int v = 0; v < NP; ++v) sWf[v * RY * WX + hlds[j]] = w[v];
             }
         }
         __syncthreads();
@@ -366,8 +450,8 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 if constexpr (LIM == LIM_THETA)
-                    sSx[v][row][col + 1] = slope_mm(sW[v][row + OY][col + 1], sW[v][row + OY][col + 2],
-                                                    sW[v][row + OY][col + 3], theta);
+                    sSx[v][row][col + 1] = slope2_mm(sW[v][row + OY][col + 1], sW[v][row + OY][col + 2],
+                                                    sW[v][row + OY][col + 3], theta2);
                 else
                     sSx[v][row][col + 1] = learned_slope<ND>(a, 0, v, x0 + col, y0 + row, kz);
             }
@@ -380,8 +464,8 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
 #pragma unroll
                 for (int v = 0; v < NP; ++v) {
                     if constexpr (LIM == LIM_THETA)
-                        sSy[v][row + 1][col] = slope_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
-                                                        sW[v][row + 3][col + 2], theta);
+                        sSy[v][row + 1][col] = slope2_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
+                                                        sW[v][row + 3][col + 2], theta2);
                     else
                         sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
                 }
@@ -397,8 +481,8 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                wl[v] = sW[v][row + OY][col + 1] + T(0.5) * sSx[v][row][col];
-                wr[v] = sW[v][row + OY][col + 2] - T(0.5) * sSx[v][row][col + 1];
+                wl[v] = sW[v][row + OY][col + 1] + T(0.25) * sSx[v][row][col];
+                wr[v] = sW[v][row + OY][col + 2] - T(0.25) * sSx[v][row][col + 1];
             }
             riemann<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1);
 #pragma unroll
@@ -412,8 +496,8 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
                 T wl[NP], wr[NP], fl[NP];
 #pragma unroll
                 for (int v = 0; v < NP; ++v) {
-                    wl[v] = sW[v][row + 1][col + 2] + T(0.5) * sSy[v][row][col];
-                    wr[v] = sW[v][row + 2][col + 2] - T(0.5) * sSy[v][row + 1][col];
+                    wl[v] = sW[v][row + 1][col + 2] + T(0.25) * sSy[v][row][col];
+                    wr[v] = sW[v][row + 2][col + 2] - T(0.25) * sSy[v][row + 1][col];
                 }
                 riemann<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1);
 #pragma unroll
@@ -423,88 +507,72 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
         __syncthreads();
 
         // ---- z faces from the register window ----
-        T W2[NP], sz1[NP], fzhi[NP];
         if constexpr (ND == 3) {
-            bad |= !to_prim<ND>(U2, W2, gm1);
-            {
-                bool fz = false;
-                map_idx(kz + 2, nz, a.bc[2][0], a.bc[2][1], fz);
-                if (fxo) W2[1] = -W2[1];
-                if (fyo) W2[2] = -W2[2];
-                if (fz) W2[3] = -W2[3];
-            }
+            to_w(U2, W2, fxo, fyo, fz2);
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM == LIM_THETA) sz1[v] = slope_mm(Wk[v], Wk1[v], W2[v], theta);
-                else sz1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+                if constexpr (LIM == LIM_THETA) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
+                else Sk1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
             }
             T fl[NP], fr[NP];
-            face_state(Wk, szk, T(0.5), fl);
-            face_state(Wk1, sz1, T(-0.5), fr);
-            riemann<ND, 2, SOLVER>(fl, fr, fzhi, gamma, igm1);
+            face_state(Wk, Sk, T(0.25), fl);
+            face_state(Wk1, Sk1, T(-0.25), fr);
+            riemann<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1);
         }
 
         // ---- phase 3: divergence, source, Runge-Kutta combination ----
-        {
-            T L[NP];
+        T L[NP];
 #pragma unroll
-            for (int v = 0; v < NP; ++v) L[v] = (sFx[v][ty][tx] - sFx[v][ty][tx + 1]) * a.idx[0];
-            if constexpr (ND >= 2) {
+        for (int v = 0; v < NP; ++v) L[v] = (sFx[v][ty][tx] - sFx[v][ty][tx + 1]) * a.idx[0];
+        if constexpr (ND >= 2) {
 #pragma unroll
-                for (int v = 0; v < NP; ++v) L[v] += (sFy[v][ty][tx] - sFy[v][ty + 1][tx]) * a.idx[1];
-            }
-            if constexpr (ND == 3) {
-#pragma unroll
-                for (int v = 0; v < NP; ++v) L[v] += (fzlo[v] - fzhi[v]) * a.idx[2];
-            }
-            // uniform acceleration: momentum += rho a, energy += S . a
-            {
-                T pw = T(0);
-#pragma unroll
-                for (int d = 0; d < ND; ++d) {
-                    L[1 + d] += Uk[0] * a.accel[d];
-                    pw += Uk[1 + d] * a.accel[d];
-                }
-                L[IP] += pw;
-            }
-            const bool valid = own_valid && (ND < 3 || kz < nz);
-            const int64_t c = (kz * ny + gy) * nx + gx;
-            T out[NP];
-            if constexpr (STAGE == 1) {
-#pragma unroll
-                for (int v = 0; v < NP; ++v) out[v] = Uk[v] + dt * L[v];
-            } else {
-                T u0[NP];
-                if (valid) load_cell<ND>(a.u0, c, vs, u0);
-                else {
-#pragma unroll
-                    for (int v = 0; v < NP; ++v) u0[v] = Uk[v];
-                }
-#pragma unroll
-                for (int v = 0; v < NP; ++v) out[v] = T(0.5) * (u0[v] + Uk[v] + dt * L[v]);
-            }
-            if (valid) {
-#pragma unroll
-                for (int v = 0; v < NP; ++v) a.uout[c + v * vs] = out[v];
-                if constexpr (STAGE == 2) {
-                    // CFL rate of the new state: max_q (|v_q| + c) / dq
-                    T wo[NP];
-                    bad |= !to_prim<ND>(out, wo, gm1);
-                    const T cs = sound_(gamma, wo[IP], wo[0]);
-#pragma unroll
-                    for (int d = 0; d < ND; ++d) rate = fmax(rate, (fabs(wo[1 + d]) + cs) * a.idx[d]);
-                }
-            }
+            for (int v = 0; v < NP; ++v) L[v] += (sFy[v][ty][tx] - sFy[v][ty + 1][tx]) * a.idx[1];
         }
-
         if constexpr (ND == 3) {
 #pragma unroll
-            for (int v = 0; v < NP; ++v) {
-                Uk[v] = Uk1[v]; Wk[v] = Wk1[v];
-                Uk1[v] = U2[v]; Wk1[v] = W2[v];
-                szk[v] = sz1[v]; fzlo[v] = fzhi[v];
+            for (int v = 0; v < NP; ++v) L[v] += (Flo[v] - Fhi[v]) * a.idx[2];
+        }
+        {
+            // uniform acceleration: momentum += rho a, energy += S . a
+            T pw = T(0);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                L[1 + d] += Uk[0] * a.accel[d];
+                pw += Uk[1 + d] * a.accel[d];
+            }
+            L[IP] += pw;
+        }
+        T out[NP];
+        if constexpr (STAGE == 1) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) out[v] = Uk[v] + dt * L[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) out[v] = T(0.5) * (u0[v] + Uk[v] + dt * L[v]);
+        }
+        if (own_valid) {
+            const unsigned c = zko + colv;
+#pragma unroll
+            for (int v = 0; v < NP; ++v) *(T *)((char *)uout[v] + c * (unsigned)sizeof(T)) = out[v];
+            if constexpr (STAGE == 2) {
+                // CFL rate of the new state: max_q (|v_q| + c) / dq
+                T wo[NP];
+                bad |= !to_prim<ND>(out, wo, gm1);
+                const T cs = sound_(gamma, wo[IP], wo[0]);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) rate = fmax(rate, (fabs(wo[1 + d]) + cs) * a.idx[d]);
             }
         }
+    };
+
+    if constexpr (ND == 3) {
+        for (int it = 0; it < nplanes; it += 3) {
+            body(it, WA, WB, WC, UA, UB, UC, SA, SB, FA, FB);
+            if (it + 1 < nplanes) body(it + 1, WB, WC, WA, UB, UC, UA, SB, SC, FB, FC);
+            if (it + 2 < nplanes) body(it + 2, WC, WA, WB, UC, UA, UB, SC, SA, FC, FA);
+        }
+    } else {
+        body(0, WA, WB, WC, UA, UB, UC, SA, SB, FA, FB);
     }
 
     if (bad) atomicOr(&a.ctl->err, 1u);
@@ -518,32 +586,30 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
     }
 }
 
-template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BY>
-hipError_t launch_one(const LaunchCfg &cfg, const StageArgs<T> &a, hipStream_t s)
+template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BX, int BY>
+hipError_t launch_one(const LaunchCfg &cfg, StageArgs<T> a, hipStream_t s)
 {
-    dim3 block(BX, BY, 1);
-    dim3 grid((unsigned)((a.n[0] + BX - 1) / BX),
-              (unsigned)(ND >= 2 ? (a.n[1] + BY - 1) / BY : 1),
-              (unsigned)(ND == 3 ? (a.n[2] + cfg.zchunk - 1) / cfg.zchunk : 1));
-    hipLaunchKernelGGL((k_stage<ND, T, SOLVER, STAGE, LIM, BY>), grid, block, 0, s, a);
+    a.tiles_x = (int)((a.n[0] + BX - 1) / BX);
+    a.tiles_y = ND >= 2 ? (int)((a.n[1] + BY - 1) / BY) : 1;
+    const int chunks = ND == 3 ? (int)((a.n[2] + cfg.zchunk - 1) / cfg.zchunk) : 1;
+    a.ntiles = a.tiles_x * a.tiles_y * chunks;
+    hipLaunchKernelGGL((k_stage<ND, T, SOLVER, STAGE, LIM, BX, BY>), dim3((unsigned)a.ntiles), dim3(BX, BY, 1), 0, s, a);
     return hipGetLastError();
 }
 
+// Supported plane tiles (BX x BY threads): 64x8, 32x16 (FP32), 64x4, 32x8.
 template <int ND, typename T, int SOLVER, int STAGE, int LIM>
 hipError_t launch_by(const LaunchCfg &cfg, const StageArgs<T> &a, hipStream_t s)
 {
     if constexpr (ND == 1) {
-        return launch_one<ND, T, SOLVER, STAGE, LIM, 1>(cfg, a, s);
-    } else if constexpr (sizeof(T) == 8) {
-        // a 64 x 16 FP64 tile does not fit in the 160 KB of LDS
-        if (cfg.by == 4) return launch_one<ND, T, SOLVER, STAGE, LIM, 4>(cfg, a, s);
-        return launch_one<ND, T, SOLVER, STAGE, LIM, 8>(cfg, a, s);
+        return launch_one<ND, T, SOLVER, STAGE, LIM, 64, 1>(cfg, a, s);
     } else {
-        switch (cfg.by) {
-        case 4: return launch_one<ND, T, SOLVER, STAGE, LIM, 4>(cfg, a, s);
-        case 16: return launch_one<ND, T, SOLVER, STAGE, LIM, 16>(cfg, a, s);
-        default: return launch_one<ND, T, SOLVER, STAGE, LIM, 8>(cfg, a, s);
+        if constexpr (sizeof(T) == 4) {
+            if (cfg.bx == 32 && cfg.by == 16) return launch_one<ND, T, SOLVER, STAGE, LIM, 32, 16>(cfg, a, s);
         }
+        if (cfg.bx == 32 && cfg.by == 8) return launch_one<ND, T, SOLVER, STAGE, LIM, 32, 8>(cfg, a, s);
+        if (cfg.bx == 64 && cfg.by == 4) return launch_one<ND, T, SOLVER, STAGE, LIM, 64, 4>(cfg, a, s);
+        return launch_one<ND, T, SOLVER, STAGE, LIM, 64, 8>(cfg, a, s);
     }
 }
 
