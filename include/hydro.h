@@ -148,6 +148,80 @@ hy_status hy_destroy(hy_patch *p);
 
 const char *hy_last_error(void);
 
+/* ---------------------------------------------------------------------
+ * Batched tubes: many independent 1D patches of uneven length advanced to
+ * one end time in a single persistent launch (captured once in a hipGraph
+ * and replayed).  Each tube runs the single-level loop of Alg. 2 with its
+ * own CFL time step, dt = min(cfl * dt_CFL, t_end - t), and the same
+ * two-stage update as hy_step.  Every description must be ndim = 1,
+ * precision = 32, limiter = HY_LIM_THETA, accel = 0 and n <= 6144
+ * (HY_EUNSUPPORTED / HY_EINVAL otherwise).  Tube states are concatenated in
+ * the caller's workspace; a workgroup holds one tube in LDS at a time, taking
+ * tubes from a device queue in descending order of n^2 max(|v| + c) / L
+ * (estimated from the states given to hy_batch_set_state). */
+typedef struct hy_batch hy_batch;
+
+hy_status hy_batch_workspace_bytes(const hy_patch_desc *descs, int count, size_t *bytes);
+hy_status hy_batch_init(const hy_patch_desc *descs, int count, void *dev_workspace, size_t bytes,
+                        void *hip_stream, hy_batch **out);
+/* State of tube i (3 x n FP64, SoA); synchronising. */
+hy_status hy_batch_set_state(hy_batch *b, int i, int kind, const double *host_soa);
+/* Advance every tube from t = 0 to t_end; asynchronous (one graph launch). */
+hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver);
+/* Milliseconds of the last hy_batch_run_to launch (HIP events); synchronising. */
+hy_status hy_batch_last_ms(hy_batch *b, double *ms);
+/* State of tube i; synchronising; HY_ESTATE if that tube met a bad state. */
+hy_status hy_batch_get_state(hy_batch *b, int i, int kind, double *host_soa_out);
+/* Steps taken and time reached by tube i in the last run; synchronising. */
+hy_status hy_batch_status(hy_batch *b, int i, int64_t *steps, double *t);
+hy_status hy_batch_destroy(hy_batch *b);
+
+/* ---------------------------------------------------------------------
+ * Learned slope limiter: training data and training on the device.  The
+ * network (4 -> 32 -> 32 -> 1, ReLU) replaces eq. MinMod; its inputs are the
+ * four one-sided differences of a 5-cell stencil of one primitive along one
+ * dimension divided by s = max|d| + 1e-12 (|w_c| + 1e-30), and its output
+ * times s is clamped to the TVD region 0 <= sign(D) sigma <= 2 min(|D-|,|D+|).
+ *
+ * Samples come from a fine FP32 patch of the plain method (periodic, every
+ * active n divisible by 4, n >= 20): the state is restricted (averaged) onto
+ * a 4x coarser grid; each (coarse cell, variable, dimension) is one sample
+ * with inputs from the coarse 5-cell stencil and target the clamped
+ * least-squares slope of the four fine sub-cell averages, 0.4 (-3 w1 - w2 +
+ * w3 + 3 w4), divided by s.  x_dev receives (nsamples, 4) FP32, t_dev
+ * (nsamples) FP32, both caller-allocated device buffers; sample index =
+ * (q * nv + v) * ncoarse + coarse cell.  Asynchronous on the patch stream. */
+hy_status hy_lim_sample_count(const hy_patch *fine, int64_t *nsamples);
+hy_status hy_lim_samples_scratch_bytes(const hy_patch *fine, size_t *bytes);
+hy_status hy_lim_make_samples(hy_patch *fine, void *dev_scratch, size_t scratch_bytes, float *x_dev, float *t_dev);
+
+/* Learned slopes of the current state of a HY_LIM_LEARNED patch (weights
+ * set): out_dev (caller device buffer of ndim * nv * ncell FP32) receives
+ * sigma[(q * nv + v) * ncell + cell], the per-cell difference slope of
+ * primitive v along q after the TVD clamp.  Asynchronous. */
+hy_status hy_lim_slopes(hy_patch *p, float *out_dev);
+
+/* Trainer: FP32 master weights and Adam moments (beta1 0.9, beta2 0.999,
+ * eps 1e-8) in a caller workspace.  One step evaluates the network forward
+ * and backward on the samples idx_dev[0..batch) (bf16 MFMA operands, FP32
+ * accumulation), reduces the gradient of the mean squared error of the raw
+ * output against the target in a fixed order, and applies Adam with rate lr.
+ * hy_trainer_gradient computes the same gradient without updating
+ * (synchronising); hy_mlp_eval runs the limiter's inference kernel with the
+ * trainer's current weights on x_dev (batch, 4) into y_dev (batch). */
+typedef struct hy_trainer hy_trainer;
+hy_status hy_trainer_workspace_bytes(size_t *bytes);
+hy_status hy_trainer_init(void *dev_workspace, size_t bytes, const float *init_params, void *hip_stream,
+                          hy_trainer **out);
+hy_status hy_trainer_step(hy_trainer *tr, const float *x_dev, const float *t_dev, const int32_t *idx_dev,
+                          int64_t batch, float lr);
+hy_status hy_trainer_gradient(hy_trainer *tr, const float *x_dev, const float *t_dev, const int32_t *idx_dev,
+                              int64_t batch, float *grad_host, float *loss_host);
+hy_status hy_trainer_loss(hy_trainer *tr, float *loss_host);
+hy_status hy_trainer_get_params(hy_trainer *tr, float *params_host);
+hy_status hy_mlp_eval(hy_trainer *tr, const float *x_dev, float *y_dev, int64_t batch);
+hy_status hy_trainer_destroy(hy_trainer *tr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,284 @@
+// batch.hip -- many independent 1D patches ("tubes") advanced to a common end
+// time in one persistent launch.
+//
+// Each workgroup pulls a tube index from a device-side atomic queue (tubes are
+// listed in descending cost, so the longest tubes start first), holds the
+// tube's primitives and face fluxes in LDS and its conserved state in
+// registers, and runs the full single-level loop of Alg. 2 on it: dt =
+// min(C dt_CFL, t_end - t) from a workgroup max-reduction (eq.
+// courantTimeStep), then the two Runge-Kutta stages (eqs. RungeKutta1-3) of
+// the same finite-volume update as the patch kernel (generalised minmod, HLL
+// or HLLC, ghost cells by boundary kind).  When the queue is empty every
+// workgroup exits.  The host captures the queue reset and this kernel in a
+// hipGraph once and replays it.
+#include "hy_batch.h"
+#include "hy_internal.h"
+
+#include <math.h>
+
+namespace hy {
+namespace {
+
+constexpr int BT = 1024;  // threads per workgroup
+
+__device__ __forceinline__ float rcpf_(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float soundf(float g, float p, float r)
+{
+    const float gp = g * p;
+    return gp * __builtin_amdgcn_rsqf(gp * r);
+}
+
+// twice the generalised minmod slope (see stage.hip): med3(min3, max3, 0) of
+// (2 theta dm, dm + dp, 2 theta dp)
+__device__ __forceinline__ float slope2(float wm, float w0, float wp, float th2)
+{
+    const float dm = w0 - wm, dp = wp - w0;
+    const float a = th2 * dm, b = dm + dp, c = th2 * dp;
+    return __builtin_amdgcn_fmed3f(fminf(a, fminf(b, c)), fmaxf(a, fmaxf(b, c)), 0.f);
+}
+
+// 1D flux from primitive face states (rho, v, p)
+__device__ __forceinline__ void flux1(const float (&wl)[3], const float (&wr)[3], float (&f)[3], float g,
+                                      float igm1, int solver)
+{
+    const float rl = wl[0], vl = wl[1], pl = wl[2];
+    const float rr = wr[0], vr = wr[1], pr = wr[2];
+    const float cl = soundf(g, pl, rl), cr = soundf(g, pr, rr);
+    const float ap = fmaxf(0.f, fmaxf(vl + cl, vr + cr));
+    const float am = fmaxf(0.f, fmaxf(cl - vl, cr - vr));
+    if (solver == 0) {
+        const float El = pl * igm1 + 0.5f * rl * vl * vl, Er = pr * igm1 + 0.5f * rr * vr * vr;
+        const float ml = rl * vl, mr = rr * vr;
+        const float Fl[3] = {ml, ml * vl + pl, (El + pl) * vl};
+        const float Fr[3] = {mr, mr * vr + pr, (Er + pr) * vr};
+        const float Ul[3] = {rl, ml, El}, Ur[3] = {rr, mr, Er};
+        const float den = ap + am;
+        if (den > 0.f) {
+            const float inv = rcpf_(den), apam = ap * am;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) f[v] = (ap * Fl[v] + am * Fr[v] - apam * (Ur[v] - Ul[v])) * inv;
+        } else {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) f[v] = 0.5f * (Fl[v] + Fr[v]);
+        }
+        return;
+    }
+    const float ql = am + vl, qr = ap - vr;
+    const float a_m = (rr * vr * qr + rl * vl * ql - (pr - pl)) * rcpf_(rr * qr + rl * ql);
+    const bool sup = (am == 0.f) | (ap == 0.f);
+    const bool useL = (am == 0.f) | ((ap != 0.f) & (a_m >= 0.f));
+    const float rK = useL ? rl : rr, vK = useL ? vl : vr, pK = useL ? pl : pr;
+    const float sK = useL ? -am : ap;
+    const float EK = pK * igm1 + 0.5f * rK * vK * vK;
+    const float mK = rK * vK;
+    const float qk = sK - vK;
+    const float inv = sup ? 0.f : rcpf_(sup ? 1.f : sK - a_m);
+    const float rs = rK * qk * inv;
+    const float ps = pK + rK * qk * (a_m - vK);
+    const float Gs = (qk * EK - pK * vK + ps * a_m) * inv;
+    f[0] = mK + sK * (rs - rK);
+    f[1] = mK * vK + pK + sK * (rs * a_m - mK);
+    f[2] = (EK + pK) * vK + sK * (Gs - EK);
+}
+
+__global__ void k_batch_reset(BatchCtl *ctl)
+{
+    ctl->next = 0u;
+}
+
+__global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes, const int *__restrict__ order,
+                                              float *__restrict__ U, int64_t ntot, BatchCtl *ctl,
+                                              TubeStatus *__restrict__ status, int ntubes, int nmax)
+{
+    extern __shared__ float lds[];
+    float *sW = lds;                   // 3 x (nmax + 4): primitives with 2 ghost cells each side
+    float *sF = lds + 3 * (nmax + 4);  // 3 x (nmax + 1): face fluxes
+    __shared__ float sred[BT / 64];
+    __shared__ int sidx;
+    constexpr int CPT = BATCH_NMAX / BT;  // cells per thread
+    const int tid = threadIdx.x;
+    const int SW = nmax + 4, SF = nmax + 1;
+    const double t_end = ctl->t_end, cfl = ctl->cfl;
+    const int solver = ctl->solver;
+    const int max_steps = ctl->max_steps;
+
+    for (;;) {
+        if (tid == 0) sidx = (int)atomicAdd(&ctl->next, 1u);
+        __syncthreads();
+        const int q = sidx;
+        __syncthreads();
+        if (q >= ntubes) break;
+        const int ti = order[q];
+        const TubeDesc d = tubes[ti];
+        const int n = d.n;
+        const float g = d.gamma, gm1 = d.gamma - 1.f, igm1 = 1.f / (d.gamma - 1.f), th2 = 2.f * d.theta;
+        const float idx = d.idx;
+
+        // conserved state of the owned cells (cell i = tid + k * BT)
+        float U0[CPT][3], Us[CPT][3];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int i = tid + k * BT;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) U0[k][v] = i < n ? U[v * ntot + d.off + i] : 1.f;
+        }
+
+        bool bad = false;
+        float rate = 0.f;  // max (|v| + c) / dx of the current state, this thread
+        // stage input -> primitives in LDS (+ ghosts)
+        auto fill = [&](const float (&S)[CPT][3], bool want_rate) {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int i = tid + k * BT;
+                if (i < n) {
+                    const float D = S[k][0], ir = rcpf_(D);
+                    const float v = S[k][1] * ir;
+                    const float p = gm1 * (S[k][2] - 0.5f * S[k][1] * v);
+                    bad |= !((D > 0.f) & (p > 0.f) & (D < 3e38f) & (p < 3e38f));
+                    sW[0 * SW + i + 2] = D;
+                    sW[1 * SW + i + 2] = v;
+                    sW[2 * SW + i + 2] = p;
+                    if (want_rate) rate = fmaxf(rate, (fabsf(v) + soundf(g, p, D)) * idx);
+                }
+            }
+            __syncthreads();
+            if (tid < 4) {
+                // ghosts -2, -1 (tid 0, 1) and n, n+1 (tid 2, 3)
+                const int gi = tid < 2 ? tid - 2 : n + tid - 2;
+                const int side = tid < 2 ? 0 : 1;
+                const int bc = side == 0 ? d.bclo : d.bchi;
+                int src;
+                bool flip = false;
+                if (bc == BC_PERIODIC) src = side == 0 ? gi + n : gi - n;
+                else if (bc == BC_OUTFLOW) src = side == 0 ? 0 : n - 1;
+                else { src = side == 0 ? -1 - gi : 2 * n - 1 - gi; flip = true; }
+                sW[0 * SW + gi + 2] = sW[0 * SW + src + 2];
+                sW[1 * SW + gi + 2] = flip ? -sW[1 * SW + src + 2] : sW[1 * SW + src + 2];
+                sW[2 * SW + gi + 2] = sW[2 * SW + src + 2];
+            }
+            __syncthreads();
+        };
+        auto faces = [&]() {
+            for (int f = tid; f <= n; f += BT) {
+                float wl[3], wr[3], fl[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const float *w = sW + v * SW + f;  // w[0..3] = cells f-2 .. f+1
+                    wl[v] = w[1] + 0.25f * slope2(w[0], w[1], w[2], th2);
+                    wr[v] = w[2] - 0.25f * slope2(w[1], w[2], w[3], th2);
+                }
+                flux1(wl, wr, fl, g, igm1, solver);
+#pragma unroll
+                for (int v = 0; v < 3; ++v) sF[v * SF + f] = fl[v];
+            }
+            __syncthreads();
+        };
+        auto block_max = [&](float r) -> float {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
+            if ((tid & 63) == 0) sred[tid >> 6] = r;
+            __syncthreads();
+            float m = 0.f;
+#pragma unroll
+            for (int w = 0; w < BT / 64; ++w) m = fmaxf(m, sred[w]);
+            __syncthreads();
+            return m;
+        };
+
+        double t = 0.0;
+        int steps = 0;
+        rate = 0.f;
+        fill(U0, true);
+        float r = block_max(rate);
+        bool stop = false;
+        while (t < t_end && !stop) {
+            double dt = fmin(cfl / (double)r, t_end - t);
+            if (!(dt > 0.0) || steps >= max_steps) {  // non-finite rate or step cap: stop this tube
+                stop = true;
+                break;
+            }
+            const float dtf = (float)dt;
+            // stage 1: U1 = U^n + dt L(U^n); the primitives of U^n are in LDS
+            faces();
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int i = tid + k * BT;
+#pragma unroll
+                for (int v = 0; v < 3; ++v)
+                    Us[k][v] = i < n ? U0[k][v] + dtf * (sF[v * SF + i] - sF[v * SF + i + 1]) * idx : 1.f;
+            }
+            __syncthreads();
+            fill(Us, false);
+            // stage 2: U^{n+1} = (U^n + U1 + dt L(U1)) / 2
+            faces();
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int i = tid + k * BT;
+#pragma unroll
+                for (int v = 0; v < 3; ++v)
+                    U0[k][v] = i < n ? 0.5f * (U0[k][v] + Us[k][v] + dtf * (sF[v * SF + i] - sF[v * SF + i + 1]) * idx)
+                                     : 1.f;
+            }
+            __syncthreads();
+            rate = 0.f;
+            fill(U0, true);
+            r = block_max(rate);
+            t += dt;
+            ++steps;
+        }
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int i = tid + k * BT;
+            if (i < n)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) U[v * ntot + d.off + i] = U0[k][v];
+        }
+        // per-tube status: any thread's bad flag, steps and time reached
+        __shared__ int sbad;
+        if (tid == 0) sbad = 0;
+        __syncthreads();
+        if (bad) atomicOr(&sbad, 1);
+        __syncthreads();
+        if (tid == 0) {
+            status[ti].steps = steps;
+            status[ti].err = sbad | (stop ? 2 : 0);
+            status[ti].t = t;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_reset(BatchCtl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, ctl);
+    return hipGetLastError();
+}
+
+hipError_t prepare_batch(int nmax)
+{
+    // dynamic LDS above the 64 KiB default must be allowed explicitly
+    return hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)batch_lds_bytes(nmax));
+}
+
+hipError_t launch_batch(const TubeDesc *tubes, const int *order, float *U, int64_t ntot, BatchCtl *ctl,
+                        TubeStatus *status, int ntubes, int nmax, int nblocks, hipStream_t s)
+{
+    const size_t lds = batch_lds_bytes(nmax);
+    hipLaunchKernelGGL(k_batch, dim3(nblocks), dim3(BT), lds, s, tubes, order, U, ntot, ctl, status, ntubes, nmax);
+    return hipGetLastError();
+}
+
+size_t batch_lds_bytes(int nmax) { return sizeof(float) * (3 * (size_t)(nmax + 4) + 3 * (size_t)(nmax + 1)); }
+
+int batch_blocks_per_cu(int nmax)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, BT, batch_lds_bytes(nmax)) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+}  // namespace hy

@@ -25,10 +25,10 @@ struct MlpDevice {
 void mlp_pack(const float *flat, MlpDevice *out);
 
 // Slopes of every (dimension q, variable v, interior cell) of the FP32 state u
-// from the network, clamped to the TVD region; written to
-// slopes[(q * nv + v) * vstride + cell].
-hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[3], int64_t vstride, int ndim,
-                                 float gm1, const int bc[3][2], const MlpDevice *mlp, hipStream_t s);
+// (variable stride vstride) from the network, clamped to the TVD region;
+// written to slopes[(q * nv + v) * svs + cell].
+hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[3], int64_t vstride, int64_t svs,
+                                 int ndim, float gm1, const int bc[3][2], const MlpDevice *mlp, hipStream_t s);
 
 // Network alone on a batch of normalised inputs x (batch, 4) -> y (batch).
 hipError_t launch_mlp_forward(const MlpDevice *mlp, const float *x, float *y, int64_t batch, hipStream_t s);

@@ -161,7 +161,7 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
     hipError_t e;
     if (p->d.limiter == HY_LIM_LEARNED) {
         const T *uin = (const T *)(stage == 1 ? p->A : p->B);
-        e = hy::launch_learned_slopes((const float *)uin, p->slopes, p->d.n, p->vstride, p->d.ndim,
+        e = hy::launch_learned_slopes((const float *)uin, p->slopes, p->d.n, p->vstride, p->vstride, p->d.ndim,
                                       (float)(p->d.gamma - 1.0), p->d.bc, p->mlp, p->stream);
         if (e != hipSuccess) return e;
     }
@@ -494,6 +494,503 @@ hy_status hy_destroy(hy_patch *p)
     for (int k = 0; k < 2; ++k)
         for (auto &ev : p->ev[k]) hipEventDestroy(ev);
     delete p;
+    return HY_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Batched 1D tubes
+// ------------------------------------------------------------------------
+#include "hy_batch.h"
+
+#include <algorithm>
+#include <numeric>
+
+// Per-tube step cap: a bound every workgroup's time loop reaches even if a
+// tube's CFL rate blows up (the tube is then flagged as stopped early).
+constexpr int kBatchMaxSteps = 400000;
+
+struct hy_batch {
+    int count = 0;
+    int nmax = 0;
+    int64_t ntot = 0;
+    std::vector<hy_patch_desc> d;
+    std::vector<int64_t> off;
+    std::vector<double> cost;  // scheduling estimate n * (n * max signal speed) of each tube
+    char *ws = nullptr;
+    hy::BatchCtl *ctl = nullptr;
+    hy::TubeDesc *tubes = nullptr;
+    int *order = nullptr;
+    hy::TubeStatus *status = nullptr;
+    float *U = nullptr;
+    float *W = nullptr;  // scratch for primitive read-back
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int nblocks = 0;
+    bool order_set = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t ctl, tubes, order, status, U, W, total;
+    int64_t ntot;
+    int nmax;
+};
+
+hy_status batch_layout(const hy_patch_desc *descs, int count, BatchLayout *L)
+{
+    if (!descs || count < 1) return fail(HY_EINVAL, "need at least one tube");
+    int64_t ntot = 0;
+    int nmax = 0;
+    for (int i = 0; i < count; ++i) {
+        hy_status st = check_desc(&descs[i]);
+        if (st != HY_OK) return st;
+        const hy_patch_desc &d = descs[i];
+        if (d.ndim != 1 || d.precision != 32 || d.limiter != HY_LIM_THETA)
+            return fail(HY_EUNSUPPORTED, "batched tubes are 1D, FP32, generalised-minmod");
+        if (d.accel[0] != 0.0) return fail(HY_EUNSUPPORTED, "batched tubes carry no source term");
+        if (d.n[0] > hy::BATCH_NMAX) return fail(HY_EINVAL, "tube longer than 6144 cells");
+        ntot += d.n[0];
+        nmax = std::max(nmax, (int)d.n[0]);
+    }
+    size_t o = 0;
+    L->ctl = o;
+    o = align_up(o + sizeof(hy::BatchCtl), 256);
+    L->tubes = o;
+    o = align_up(o + sizeof(hy::TubeDesc) * count, 256);
+    L->order = o;
+    o = align_up(o + sizeof(int) * count, 256);
+    L->status = o;
+    o = align_up(o + sizeof(hy::TubeStatus) * count, 256);
+    L->U = o;
+    o = align_up(o + sizeof(float) * 3 * (size_t)ntot, 256);
+    L->W = o;
+    o = align_up(o + sizeof(float) * 3 * (size_t)ntot, 256);
+    L->total = o + 256;
+    L->ntot = ntot;
+    L->nmax = nmax;
+    return HY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hy_status hy_batch_workspace_bytes(const hy_patch_desc *descs, int count, size_t *bytes)
+{
+    if (!bytes) return fail(HY_EINVAL, "null output");
+    BatchLayout L;
+    hy_status st = batch_layout(descs, count, &L);
+    if (st != HY_OK) return st;
+    *bytes = L.total;
+    return HY_OK;
+}
+
+hy_status hy_batch_init(const hy_patch_desc *descs, int count, void *dev_workspace, size_t bytes, void *hip_stream,
+                        hy_batch **out)
+{
+    if (!out || !dev_workspace) return fail(HY_EINVAL, "null workspace or output handle");
+    BatchLayout L;
+    hy_status st = batch_layout(descs, count, &L);
+    if (st != HY_OK) return st;
+    if (bytes < L.total) return fail(HY_ENOMEM, "workspace too small");
+    hy_batch *b = new (std::nothrow) hy_batch();
+    if (!b) return fail(HY_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->nmax = L.nmax;
+    b->ntot = L.ntot;
+    b->d.assign(descs, descs + count);
+    b->off.resize(count);
+    b->cost.assign(count, 0.0);
+    char *base = (char *)(((uintptr_t)dev_workspace + 255) & ~(uintptr_t)255);
+    b->ws = base;
+    b->ctl = (hy::BatchCtl *)(base + L.ctl);
+    b->tubes = (hy::TubeDesc *)(base + L.tubes);
+    b->order = (int *)(base + L.order);
+    b->status = (hy::TubeStatus *)(base + L.status);
+    b->U = (float *)(base + L.U);
+    b->W = (float *)(base + L.W);
+    b->stream = (hipStream_t)hip_stream;
+    std::vector<hy::TubeDesc> td(count);
+    int64_t o = 0;
+    for (int i = 0; i < count; ++i) {
+        const hy_patch_desc &d = descs[i];
+        td[i].n = (int)d.n[0];
+        td[i].bclo = d.bc[0][0];
+        td[i].bchi = d.bc[0][1];
+        td[i].idx = (float)((double)d.n[0] / (d.hi[0] - d.lo[0]));
+        td[i].gamma = (float)d.gamma;
+        td[i].theta = (float)d.theta;
+        td[i].off = o;
+        b->off[i] = o;
+        o += d.n[0];
+    }
+    std::vector<int> ord(count);
+    std::iota(ord.begin(), ord.end(), 0);
+    hy::BatchCtl c{};
+    c.max_steps = kBatchMaxSteps;
+    int dev = 0, cus = 0;
+    hipError_t e = hipMemcpyAsync(b->tubes, td.data(), sizeof(hy::TubeDesc) * count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->order, ord.data(), sizeof(int) * count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->ctl, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hy::prepare_batch(b->nmax);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev[1]);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch init");
+    }
+    b->nblocks = std::min(count, std::max(1, cus) * hy::batch_blocks_per_cu(b->nmax));
+    *out = b;
+    return HY_OK;
+}
+
+hy_status hy_batch_set_state(hy_batch *b, int i, int kind, const double *host)
+{
+    if (!b || !host) return fail(HY_EINVAL, "null argument");
+    if (i < 0 || i >= b->count) return fail(HY_EINVAL, "tube index out of range");
+    if (kind != HY_PRIMITIVE && kind != HY_CONSERVED) return fail(HY_EINVAL, "unknown state kind");
+    const int64_t n = b->d[i].n[0];
+    std::vector<float> st(3 * n);
+    for (int64_t k = 0; k < 3 * n; ++k) st[k] = (float)host[k];
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < 3 && e == hipSuccess; ++v)
+        e = hipMemcpyAsync(b->U + v * b->ntot + b->off[i], st.data() + v * n, sizeof(float) * n, hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess && kind == HY_PRIMITIVE) {
+        const double gm1 = b->d[i].gamma - 1.0;
+        e = hy::launch_prim_to_cons<float>(b->U + b->off[i], n, b->ntot, 1, (float)gm1, (float)(1.0 / gm1), b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "tube upload");
+    // scheduling estimate only: tube length times the cells a signal crosses
+    // per unit time, n (|v| + c) / L, from the input primitives or conserved
+    // variables (the kernel recomputes everything it uses)
+    double smax = 0.0;
+    const double g = b->d[i].gamma;
+    for (int64_t k = 0; k < n; ++k) {
+        double rho, v, p;
+        if (kind == HY_PRIMITIVE) {
+            rho = host[k]; v = host[n + k]; p = host[2 * n + k];
+        } else {
+            rho = host[k]; v = host[n + k] / rho; p = (g - 1.0) * (host[2 * n + k] - 0.5 * host[n + k] * v);
+        }
+        const double s = std::fabs(v) + std::sqrt(std::max(g * p / rho, 0.0));
+        if (std::isfinite(s)) smax = std::max(smax, s);
+    }
+    b->cost[i] = (double)n * (double)n * smax / (b->d[i].hi[0] - b->d[i].lo[0]);
+    b->order_set = false;
+    return HY_OK;
+}
+
+static hy_status batch_capture(hy_batch *b)
+{
+    hipError_t e = hipSuccess;
+    if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    hipError_t e1 = hy::launch_batch_reset(b->ctl, b->capture);
+    hipError_t e2 = hy::launch_batch(b->tubes, b->order, b->U, b->ntot, b->ctl, b->status, b->count, b->nmax,
+                                     b->nblocks, b->capture);
+    e = hipStreamEndCapture(b->capture, &g);
+    if (e1 != hipSuccess) e = e1;
+    if (e2 != hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    return HY_OK;
+}
+
+hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver)
+{
+    if (!b) return fail(HY_EINVAL, "null batch");
+    if (!(t_end > 0.0) || !std::isfinite(t_end)) return fail(HY_EINVAL, "t_end must be finite and > 0");
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HY_EINVAL, "cfl must be finite and > 0");
+    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    hipError_t e = hipSuccess;
+    if (!b->order_set) {
+        std::vector<int> ord(b->count);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
+        e = hipMemcpyAsync(b->order, ord.data(), sizeof(int) * b->count, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "queue order upload");
+        b->order_set = true;
+    }
+    if (!b->exec) {
+        hy_status st = batch_capture(b);
+        if (st != HY_OK) return st;
+    }
+    hy::BatchCtl c{};
+    c.solver = solver;
+    c.max_steps = kBatchMaxSteps;
+    c.t_end = t_end;
+    c.cfl = cfl;
+    e = hipMemcpyAsync(b->ctl, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return HY_OK;
+}
+
+hy_status hy_batch_last_ms(hy_batch *b, double *ms)
+{
+    if (!b || !ms) return fail(HY_EINVAL, "null argument");
+    hipError_t e = hipEventSynchronize(b->ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, b->ev[0], b->ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "batch timing");
+    *ms = t;
+    return HY_OK;
+}
+
+hy_status hy_batch_get_state(hy_batch *b, int i, int kind, double *out)
+{
+    if (!b || !out) return fail(HY_EINVAL, "null argument");
+    if (i < 0 || i >= b->count) return fail(HY_EINVAL, "tube index out of range");
+    if (kind != HY_PRIMITIVE && kind != HY_CONSERVED) return fail(HY_EINVAL, "unknown state kind");
+    const int64_t n = b->d[i].n[0];
+    const float *src = b->U + b->off[i];
+    hipError_t e = hipSuccess;
+    if (kind == HY_PRIMITIVE) {
+        e = hy::launch_cons_to_prim<float>(src, b->W + b->off[i], n, b->ntot, 1, (float)(b->d[i].gamma - 1.0), b->stream);
+        src = b->W + b->off[i];
+    }
+    std::vector<float> st(3 * n);
+    for (int v = 0; v < 3 && e == hipSuccess; ++v)
+        e = hipMemcpyAsync(st.data() + v * n, src + v * b->ntot, sizeof(float) * n, hipMemcpyDeviceToHost, b->stream);
+    hy::TubeStatus ts{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&ts, b->status + i, sizeof(ts), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "tube download");
+    for (int64_t k = 0; k < 3 * n; ++k) out[k] = st[k];
+    if (ts.err & 1) return fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value in this tube");
+    return HY_OK;
+}
+
+hy_status hy_batch_status(hy_batch *b, int i, int64_t *steps, double *t)
+{
+    if (!b || !steps || !t) return fail(HY_EINVAL, "null argument");
+    if (i < 0 || i >= b->count) return fail(HY_EINVAL, "tube index out of range");
+    hy::TubeStatus ts{};
+    hipError_t e = hipMemcpyAsync(&ts, b->status + i, sizeof(ts), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "status download");
+    *steps = ts.steps;
+    *t = ts.t;
+    if (ts.err & 1) return fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value in this tube");
+    if (ts.err & 2) return fail(HY_ESTATE, "the tube stopped before t_end (time step not > 0)");
+    return HY_OK;
+}
+
+hy_status hy_batch_destroy(hy_batch *b)
+{
+    if (!b) return HY_OK;
+    hipStreamSynchronize(b->stream);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->capture) hipStreamDestroy(b->capture);
+    for (auto &ev : b->ev)
+        if (ev) hipEventDestroy(ev);
+    delete b;
+    return HY_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Learned limiter: training data and trainer
+// ------------------------------------------------------------------------
+#include "hy_train.h"
+
+namespace {
+
+hy_status check_sample_patch(const hy_patch *p)
+{
+    if (!p) return fail(HY_EINVAL, "null patch");
+    if (p->d.precision != 32) return fail(HY_EUNSUPPORTED, "training samples come from FP32 patches");
+    for (int q = 0; q < p->d.ndim; ++q) {
+        if (p->d.n[q] % 4 != 0 || p->d.n[q] < 20) return fail(HY_EINVAL, "sample patch needs n % 4 == 0 and n >= 20");
+        if (p->d.bc[q][0] != HY_BC_PERIODIC) return fail(HY_EUNSUPPORTED, "sample patch must be periodic");
+    }
+    return HY_OK;
+}
+
+int64_t coarse_cells(const hy_patch *p)
+{
+    int64_t nc = 1;
+    for (int q = 0; q < p->d.ndim; ++q) nc *= p->d.n[q] / 4;
+    return nc;
+}
+
+}  // namespace
+
+struct hy_trainer {
+    hy::MlpDevice *m = nullptr;
+    float *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *partial = nullptr, *lpart = nullptr, *loss = nullptr;
+    hipStream_t stream = nullptr;
+    int step = 0;
+};
+
+extern "C" {
+
+hy_status hy_lim_sample_count(const hy_patch *fine, int64_t *nsamples)
+{
+    hy_status st = check_sample_patch(fine);
+    if (st != HY_OK) return st;
+    if (!nsamples) return fail(HY_EINVAL, "null output");
+    *nsamples = coarse_cells(fine) * (fine->d.ndim + 2) * fine->d.ndim;
+    return HY_OK;
+}
+
+hy_status hy_lim_samples_scratch_bytes(const hy_patch *fine, size_t *bytes)
+{
+    hy_status st = check_sample_patch(fine);
+    if (st != HY_OK) return st;
+    if (!bytes) return fail(HY_EINVAL, "null output");
+    const int nv = fine->d.ndim + 2;
+    *bytes = sizeof(float) * (size_t)coarse_cells(fine) * (nv + (size_t)fine->d.ndim * nv * 4) + 256;
+    return HY_OK;
+}
+
+hy_status hy_lim_make_samples(hy_patch *fine, void *dev_scratch, size_t scratch_bytes, float *x_dev, float *t_dev)
+{
+    hy_status st = check_sample_patch(fine);
+    if (st != HY_OK) return st;
+    if (!dev_scratch || !x_dev || !t_dev) return fail(HY_EINVAL, "null buffer");
+    size_t need = 0;
+    hy_lim_samples_scratch_bytes(fine, &need);
+    if (scratch_bytes < need) return fail(HY_ENOMEM, "scratch too small");
+    const int64_t nc = coarse_cells(fine);
+    float *Wc = (float *)(((uintptr_t)dev_scratch + 255) & ~(uintptr_t)255);
+    float *sub = Wc + (size_t)(fine->d.ndim + 2) * nc;
+    const int nf[3] = {(int)fine->d.n[0], (int)fine->d.n[1], (int)fine->d.n[2]};
+    const int ncd[3] = {nf[0] / 4, fine->d.ndim >= 2 ? nf[1] / 4 : 1, fine->d.ndim == 3 ? nf[2] / 4 : 1};
+    hipError_t e = hy::launch_coarsen4((const float *)fine->A, fine->vstride, fine->d.ndim, nf,
+                                       (float)(fine->d.gamma - 1.0), Wc, sub, fine->stream);
+    if (e == hipSuccess) e = hy::launch_samples(Wc, sub, fine->d.ndim, ncd, x_dev, t_dev, fine->stream);
+    if (e != hipSuccess) return hip_fail(e, "sample kernels");
+    return HY_OK;
+}
+
+hy_status hy_lim_slopes(hy_patch *p, float *out_dev)
+{
+    if (!p || !out_dev) return fail(HY_EINVAL, "null argument");
+    if (p->d.limiter != HY_LIM_LEARNED || !p->mlp_set) return fail(HY_EINVAL, "patch has no learned limiter weights");
+    hipError_t e = hy::launch_learned_slopes((const float *)p->A, out_dev, p->d.n, p->vstride, p->ncell, p->d.ndim,
+                                             (float)(p->d.gamma - 1.0), p->d.bc, p->mlp, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "slope kernel");
+    return HY_OK;
+}
+
+hy_status hy_trainer_workspace_bytes(size_t *bytes)
+{
+    if (!bytes) return fail(HY_EINVAL, "null output");
+    *bytes = align_up(sizeof(hy::MlpDevice), 256) +
+             sizeof(float) * ((size_t)hy::MLP_NPARAM * (3 + hy::TRAIN_BLOCKS) + hy::TRAIN_BLOCKS + 64) + 1024;
+    return HY_OK;
+}
+
+hy_status hy_trainer_init(void *dev_workspace, size_t bytes, const float *params, void *hip_stream, hy_trainer **out)
+{
+    size_t need = 0;
+    hy_trainer_workspace_bytes(&need);
+    if (!dev_workspace || !params || !out) return fail(HY_EINVAL, "null argument");
+    if (bytes < need) return fail(HY_ENOMEM, "workspace too small");
+    hy_trainer *tr = new (std::nothrow) hy_trainer();
+    if (!tr) return fail(HY_ENOMEM, "host allocation failed");
+    char *base = (char *)(((uintptr_t)dev_workspace + 255) & ~(uintptr_t)255);
+    tr->m = (hy::MlpDevice *)base;
+    float *f = (float *)(base + align_up(sizeof(hy::MlpDevice), 256));
+    tr->grad = f;
+    tr->m1 = f + hy::MLP_NPARAM;
+    tr->m2 = f + 2 * hy::MLP_NPARAM;
+    tr->partial = f + 3 * hy::MLP_NPARAM;
+    tr->lpart = tr->partial + (size_t)hy::MLP_NPARAM * hy::TRAIN_BLOCKS;
+    tr->loss = tr->lpart + hy::TRAIN_BLOCKS;
+    tr->stream = (hipStream_t)hip_stream;
+    hy::MlpDevice host;
+    hy::mlp_pack(params, &host);
+    std::vector<float> zeros(2 * hy::MLP_NPARAM, 0.f);
+    hipError_t e = hipMemcpyAsync(tr->m, &host, sizeof(host), hipMemcpyHostToDevice, tr->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tr->m1, zeros.data(), sizeof(float) * 2 * hy::MLP_NPARAM, hipMemcpyHostToDevice, tr->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(tr->stream);
+    if (e != hipSuccess) {
+        delete tr;
+        return hip_fail(e, "trainer init");
+    }
+    *out = tr;
+    return HY_OK;
+}
+
+hy_status hy_trainer_step(hy_trainer *tr, const float *x_dev, const float *t_dev, const int32_t *idx_dev, int64_t batch,
+                          float lr)
+{
+    if (!tr || !x_dev || !t_dev || !idx_dev) return fail(HY_EINVAL, "null argument");
+    if (batch < 1 || !(lr > 0.f)) return fail(HY_EINVAL, "batch must be >= 1 and lr > 0");
+    hipError_t e = hy::launch_train_grad(tr->m, x_dev, t_dev, idx_dev, batch, tr->partial, tr->lpart, hy::TRAIN_BLOCKS,
+                                         tr->grad, tr->loss, tr->stream);
+    tr->step += 1;
+    if (e == hipSuccess) e = hy::launch_adam(tr->m, tr->grad, tr->m1, tr->m2, lr, 0.9f, 0.999f, 1e-8f, tr->step, tr->stream);
+    if (e != hipSuccess) return hip_fail(e, "training step");
+    return HY_OK;
+}
+
+hy_status hy_trainer_gradient(hy_trainer *tr, const float *x_dev, const float *t_dev, const int32_t *idx_dev,
+                              int64_t batch, float *grad_host, float *loss_host)
+{
+    if (!tr || !x_dev || !t_dev || !idx_dev || !grad_host || !loss_host) return fail(HY_EINVAL, "null argument");
+    if (batch < 1) return fail(HY_EINVAL, "batch must be >= 1");
+    hipError_t e = hy::launch_train_grad(tr->m, x_dev, t_dev, idx_dev, batch, tr->partial, tr->lpart, hy::TRAIN_BLOCKS,
+                                         tr->grad, tr->loss, tr->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(grad_host, tr->grad, sizeof(float) * hy::MLP_NPARAM, hipMemcpyDeviceToHost, tr->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(loss_host, tr->loss, sizeof(float), hipMemcpyDeviceToHost, tr->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(tr->stream);
+    if (e != hipSuccess) return hip_fail(e, "gradient");
+    return HY_OK;
+}
+
+hy_status hy_trainer_loss(hy_trainer *tr, float *loss_host)
+{
+    if (!tr || !loss_host) return fail(HY_EINVAL, "null argument");
+    hipError_t e = hipMemcpyAsync(loss_host, tr->loss, sizeof(float), hipMemcpyDeviceToHost, tr->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(tr->stream);
+    if (e != hipSuccess) return hip_fail(e, "loss");
+    return HY_OK;
+}
+
+hy_status hy_trainer_get_params(hy_trainer *tr, float *params_host)
+{
+    if (!tr || !params_host) return fail(HY_EINVAL, "null argument");
+    hipError_t e = hipMemcpyAsync(params_host, tr->m, sizeof(float) * hy::MLP_NPARAM, hipMemcpyDeviceToHost, tr->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(tr->stream);
+    if (e != hipSuccess) return hip_fail(e, "parameter download");
+    return HY_OK;
+}
+
+hy_status hy_mlp_eval(hy_trainer *tr, const float *x_dev, float *y_dev, int64_t batch)
+{
+    if (!tr || !x_dev || !y_dev) return fail(HY_EINVAL, "null argument");
+    if (batch < 0) return fail(HY_EINVAL, "batch must be >= 0");
+    hipError_t e = hy::launch_mlp_forward(tr->m, x_dev, y_dev, batch, tr->stream);
+    if (e != hipSuccess) return hip_fail(e, "network evaluation");
+    return HY_OK;
+}
+
+hy_status hy_trainer_destroy(hy_trainer *tr)
+{
+    if (!tr) return HY_OK;
+    hipStreamSynchronize(tr->stream);
+    delete tr;
     return HY_OK;
 }
 

@@ -154,8 +154,8 @@ __device__ __forceinline__ int64_t map1(int64_t i, int64_t n, int lo, int hi, bo
 
 template <int ND>
 __global__ void __launch_bounds__(256) k_learned_slopes(const float *__restrict__ u, float *__restrict__ slopes,
-                                                        int64_t nx, int64_t ny, int64_t nz, int64_t vs, float gm1,
-                                                        Bc bc, const MlpDevice *__restrict__ mlp)
+                                                        int64_t nx, int64_t ny, int64_t nz, int64_t vs, int64_t svs,
+                                                        float gm1, Bc bc, const MlpDevice *__restrict__ mlp)
 {
     constexpr int NP = ND + 2;
     const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) k_learned_slopes(const float *__restrict_
         for (int v = 0; v < NP; ++v) {
             const float w5[5] = {W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]};
             const float sg = learned_sigma(w5, R, grp);
-            if (valid) slopes[(int64_t)(q * NP + v) * vs + c] = sg;
+            if (valid) slopes[(int64_t)(q * NP + v) * svs + c] = sg;
         }
     }
 }
@@ -214,8 +214,8 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDevice *__restrict
 
 }  // namespace
 
-hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[3], int64_t vstride, int ndim,
-                                 float gm1, const int bc[3][2], const MlpDevice *mlp, hipStream_t s)
+hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[3], int64_t vstride, int64_t svs,
+                                 int ndim, float gm1, const int bc[3][2], const MlpDevice *mlp, hipStream_t s)
 {
     Bc b;
     for (int q = 0; q < 3; ++q) {
@@ -225,9 +225,9 @@ hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[
     const int64_t ncell = n[0] * n[1] * n[2];
     const dim3 grid((unsigned)((ncell + 255) / 256));
     switch (ndim) {
-    case 1: hipLaunchKernelGGL(k_learned_slopes<1>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, gm1, b, mlp); break;
-    case 2: hipLaunchKernelGGL(k_learned_slopes<2>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, gm1, b, mlp); break;
-    default: hipLaunchKernelGGL(k_learned_slopes<3>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, gm1, b, mlp); break;
+    case 1: hipLaunchKernelGGL(k_learned_slopes<1>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, svs, gm1, b, mlp); break;
+    case 2: hipLaunchKernelGGL(k_learned_slopes<2>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, svs, gm1, b, mlp); break;
+    default: hipLaunchKernelGGL(k_learned_slopes<3>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, svs, gm1, b, mlp); break;
     }
     return hipGetLastError();
 }

@@ -97,7 +97,28 @@ def _extra_signatures(L):
             f.restype = ctypes.c_int
 
 
-EXTRA_SIGNATURES = {}
+EXTRA_SIGNATURES = {
+    "hy_batch_workspace_bytes": [ctypes.POINTER(PatchDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "hy_batch_init": [ctypes.POINTER(PatchDesc), ctypes.c_int, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "hy_batch_set_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
+    "hy_batch_run_to": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int],
+    "hy_batch_last_ms": [_P, _dp],
+    "hy_batch_get_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
+    "hy_batch_status": [_P, ctypes.c_int, _i64p, _dp],
+    "hy_batch_destroy": [_P],
+    "hy_lim_sample_count": [_P, _i64p],
+    "hy_lim_samples_scratch_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "hy_lim_make_samples": [_P, _P, ctypes.c_size_t, _P, _P],
+    "hy_lim_slopes": [_P, _P],
+    "hy_trainer_workspace_bytes": [ctypes.POINTER(ctypes.c_size_t)],
+    "hy_trainer_init": [_P, ctypes.c_size_t, _fp, _P, ctypes.POINTER(_P)],
+    "hy_trainer_step": [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float],
+    "hy_trainer_gradient": [_P, _P, _P, _P, ctypes.c_int64, _fp, _fp],
+    "hy_trainer_loss": [_P, _fp],
+    "hy_trainer_get_params": [_P, _fp],
+    "hy_mlp_eval": [_P, _P, _P, ctypes.c_int64],
+    "hy_trainer_destroy": [_P],
+}
 
 
 def check(status: int, what: str = ""):
@@ -210,6 +231,34 @@ class Patch:
         check(lib().hy_kernel_times(self.handle, _dptr(ms), n.ctypes.data_as(_i64p)), "kernel_times")
         return ms, n
 
+    def make_samples(self):
+        """Training samples of the learned limiter from this (fine, periodic)
+        patch: returns device tensors x (n, 4) and t (n) (float32)."""
+        import torch
+
+        ns = ctypes.c_int64(0)
+        check(lib().hy_lim_sample_count(self.handle, ctypes.byref(ns)), "lim_sample_count")
+        nb = ctypes.c_size_t(0)
+        check(lib().hy_lim_samples_scratch_bytes(self.handle, ctypes.byref(nb)), "lim_samples_scratch_bytes")
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        x = torch.empty((ns.value, 4), dtype=torch.float32, device=self.device)
+        t = torch.empty((ns.value,), dtype=torch.float32, device=self.device)
+        check(lib().hy_lim_make_samples(self.handle, ctypes.c_void_p(scratch.data_ptr()), nb,
+                                        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr())),
+              "lim_make_samples")
+        torch.cuda.current_stream(self.device).synchronize()
+        del scratch
+        return x, t
+
+    def learned_slopes(self):
+        """Clamped learned slopes of the current state, (ndim * nv, ncell) on the device."""
+        import torch
+
+        out = torch.empty((self.ndim * self.nv, self.ncell), dtype=torch.float32, device=self.device)
+        check(lib().hy_lim_slopes(self.handle, ctypes.c_void_p(out.data_ptr())), "lim_slopes")
+        torch.cuda.current_stream(self.device).synchronize()
+        return out
+
     def kernel_config(self) -> str:
         buf = ctypes.create_string_buffer(256)
         check(lib().hy_kernel_config(self.handle, buf, 256), "kernel_config")
@@ -236,3 +285,130 @@ class Patch:
             t += dt
             k += 1
         return k
+
+
+class Batch:
+    """Independent 1D tubes advanced together in one persistent launch.
+
+    ``problems`` is a sequence of 1D workloads.Problem objects (FP32,
+    generalised minmod, no source)."""
+
+    def __init__(self, problems, device: str = "cuda", theta: Optional[float] = None):
+        import torch
+
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (PatchDesc * n)()
+        for i, pr in enumerate(self.problems):
+            arr[i] = make_desc(pr.ndim, pr.n, pr.lo, pr.hi, pr.gamma, pr.bc, 32, LIM_THETA,
+                               pr.theta if theta is None else theta, pr.accel)
+        self.descs = arr
+        nbytes = ctypes.c_size_t(0)
+        check(lib().hy_batch_workspace_bytes(arr, n, ctypes.byref(nbytes)), "batch_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=torch.device(device))
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        h = _P()
+        check(lib().hy_batch_init(arr, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "batch_init")
+        self.handle = h
+        for i, pr in enumerate(self.problems):
+            self.set_state(i, pr.W, PRIMITIVE)
+
+    def set_state(self, i: int, arr, kind: int = PRIMITIVE):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(3, -1))
+        check(lib().hy_batch_set_state(self.handle, int(i), int(kind), _dptr(a)), "batch_set_state")
+
+    def run_to(self, t_end: float, cfl: float, solver: int = HLLC):
+        check(lib().hy_batch_run_to(self.handle, float(t_end), float(cfl), int(solver)), "batch_run_to")
+
+    def last_ms(self) -> float:
+        out = ctypes.c_double(0.0)
+        check(lib().hy_batch_last_ms(self.handle, ctypes.byref(out)), "batch_last_ms")
+        return out.value
+
+    def get_state(self, i: int, kind: int = PRIMITIVE) -> np.ndarray:
+        n = int(self.problems[i].n[0])
+        out = np.empty((3, n), dtype=np.float64)
+        check(lib().hy_batch_get_state(self.handle, int(i), int(kind), _dptr(out)), "batch_get_state")
+        return out
+
+    def status(self, i: int):
+        steps = ctypes.c_int64(0)
+        t = ctypes.c_double(0.0)
+        check(lib().hy_batch_status(self.handle, int(i), ctypes.byref(steps), ctypes.byref(t)), "batch_status")
+        return steps.value, t.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hy_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trainer:
+    """Device-side trainer of the learned limiter (FP32 master weights, Adam)."""
+
+    def __init__(self, params, device: str = "cuda"):
+        import torch
+
+        nb = ctypes.c_size_t(0)
+        check(lib().hy_trainer_workspace_bytes(ctypes.byref(nb)), "trainer_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=torch.device(device))
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        w = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        assert w.size == MLP_NPARAM
+        h = _P()
+        check(lib().hy_trainer_init(ctypes.c_void_p(self.workspace.data_ptr()), nb, w.ctypes.data_as(_fp),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "trainer_init")
+        self.handle = h
+
+    @staticmethod
+    def _ptr(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def step(self, x, t, idx, lr: float = 1e-3):
+        """x (n, 4), t (n) float32 and idx (batch) int32 device tensors."""
+        check(lib().hy_trainer_step(self.handle, self._ptr(x), self._ptr(t), self._ptr(idx),
+                                    int(idx.numel()), float(lr)), "trainer_step")
+
+    def gradient(self, x, t, idx):
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        check(lib().hy_trainer_gradient(self.handle, self._ptr(x), self._ptr(t), self._ptr(idx),
+                                        int(idx.numel()), g.ctypes.data_as(_fp), loss.ctypes.data_as(_fp)),
+              "trainer_gradient")
+        return g, float(loss[0])
+
+    def loss(self) -> float:
+        out = np.zeros(1, dtype=np.float32)
+        check(lib().hy_trainer_loss(self.handle, out.ctypes.data_as(_fp)), "trainer_loss")
+        return float(out[0])
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        check(lib().hy_trainer_get_params(self.handle, out.ctypes.data_as(_fp)), "trainer_get_params")
+        return out
+
+    def eval(self, x):
+        """Network output (the limiter's MFMA inference kernel) on x (n, 4)."""
+        import torch
+
+        y = torch.empty((x.shape[0],), dtype=torch.float32, device=x.device)
+        check(lib().hy_mlp_eval(self.handle, self._ptr(x), self._ptr(y), int(x.shape[0])), "mlp_eval")
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hy_trainer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

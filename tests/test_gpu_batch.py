@@ -1,0 +1,95 @@
+"""Batched persistent launch of independent 1D tubes: parity with the FP64
+oracle on sampled tubes (relative L1 of each variable within 1e-5, the
+FP32-state bar) and agreement with the exact Riemann solution on the full
+512-tube configuration."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact_riemann as er
+from paper_1207_3392_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+hydro = pytest.importorskip("paper_1207_3392_amd.hydro")
+
+
+def _gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+if not _gpu():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def rel_l1(a, b):
+    return np.sum(np.abs(a - b), axis=1) / np.sum(np.abs(b), axis=1)
+
+
+@pytest.mark.parametrize("solver", [hydro.HLL, hydro.HLLC])
+def test_small_batch_matches_oracle(solver):
+    tubes = wl.batched_tubes(12, seed=77, nmin=64, nmax=700)
+    probs = [wl.tube_problem(t, t_end=0.02) for t in tubes]
+    # mix boundary kinds and limiter strengths across the tubes
+    for k, pr in enumerate(probs):
+        b = (wl.BC_OUTFLOW, wl.BC_REFLECT, wl.BC_PERIODIC)[k % 3]
+        pr.bc = ((b, b), (0, 0), (0, 0))
+        pr.theta = (1.0, 1.4, 2.0)[k % 3]
+    B = hydro.Batch(probs)
+    B.run_to(0.02, 0.4, solver)
+    for i, pr in enumerate(probs):
+        W = B.get_state(i, hydro.PRIMITIVE)
+        steps, t = B.status(i)
+        assert t == pytest.approx(0.02, rel=1e-12) and steps > 0
+        d = oracle.Desc.from_problem(pr, solver=solver)
+        U, osteps = oracle.run(d, oracle.prim_to_cons(d, pr.flat()), 0.02, 0.4)
+        Wr = oracle.cons_to_prim(d, U)
+        assert abs(steps - osteps) <= 1
+        l1 = rel_l1(W[[0, 2]], Wr[[0, 2]])
+        assert np.all(l1 < 1e-5), (i, l1)
+        assert np.max(np.abs(W[1] - Wr[1])) < 1e-3 * (np.max(np.abs(Wr[1])) + 1.0)
+    B.close()
+
+
+def test_batch_replays_and_matches_single_patch_kernel():
+    """Two replays of the captured graph give bitwise identical results, and
+    a tube advanced by the batch equals the same tube advanced by the patch
+    API with the same time steps (same arithmetic, different kernels) to
+    FP32 rounding."""
+    tubes = wl.batched_tubes(6, seed=5, nmin=200, nmax=900)
+    probs = [wl.tube_problem(t, t_end=0.01) for t in tubes]
+    B = hydro.Batch(probs)
+    B.run_to(0.01, 0.4, hydro.HLLC)
+    first = [B.get_state(i, hydro.CONSERVED) for i in range(len(probs))]
+    for i, pr in enumerate(probs):
+        B.set_state(i, pr.W)
+    B.run_to(0.01, 0.4, hydro.HLLC)
+    for i in range(len(probs)):
+        assert np.array_equal(B.get_state(i, hydro.CONSERVED), first[i])
+    p = hydro.Patch(probs[0], precision=32)
+    p.run(0.01, 0.4, hydro.HLLC)
+    Up = p.get_state(hydro.CONSERVED)
+    assert np.max(np.abs(Up - first[0]) / np.max(np.abs(first[0]), axis=1, keepdims=True)) < 1e-4
+
+
+def test_full_512_tube_configuration_against_exact_solutions():
+    tubes = wl.batched_tubes(512)
+    probs = [wl.tube_problem(t) for t in tubes]
+    B = hydro.Batch(probs)
+    B.run_to(0.1, 0.4, hydro.HLLC)
+    ms = B.last_ms()
+    errs = []
+    for i, (t, pr) in enumerate(zip(tubes, probs)):
+        W = B.get_state(i, hydro.PRIMITIVE)
+        steps, tt = B.status(i)
+        assert tt == pytest.approx(0.1, rel=1e-12)
+        r, u, p = er.sample_cells(t.left, t.right, 1.4, t.n, t.x0, 0.1)
+        e = oracle.l1_error(W[0], r)
+        errs.append(e)
+        # first-order convergence near discontinuities: a few cells' worth
+        assert e < 40.0 / t.n + 2e-3, (i, t, e)
+    print(f"512 tubes in {ms:.1f} ms; median L1(rho) {np.median(errs):.2e}")
+    B.close()
