@@ -89,6 +89,54 @@ def time_patch(n, solver, steps, warmup, timing=True):
     return res
 
 
+def time_batch(count=512):
+    """The 512-tube batched configuration: one persistent graph launch to t = 0.1."""
+    from paper_1207_3392_amd import hydro
+    from paper_1207_3392_amd import workloads as wl
+
+    tubes = wl.batched_tubes(count)
+    probs = [wl.tube_problem(t) for t in tubes]
+    B = hydro.Batch(probs)
+    B.run_to(0.1, 0.4, hydro.HLLC)  # warm-up (graph capture, code load)
+    B.last_ms()
+    for i, pr in enumerate(probs):
+        B.set_state(i, pr.W)
+    B.run_to(0.1, 0.4, hydro.HLLC)
+    ms = B.last_ms()
+    zu = 0
+    for i, t in enumerate(tubes):
+        steps, _ = B.status(i)
+        zu += t.n * steps
+    B.close()
+    return {"tubes": count, "ms": ms, "zone_updates": zu, "zone_updates_per_s": zu / (ms * 1e-3),
+            "cells": sum(t.n for t in tubes)}
+
+
+def time_kh(n=2048, steps=20, learned=False):
+    """2D Kelvin-Helmholtz, FP32, HLLC: plain MC limiter or the learned limiter
+    (random-initialised network: the cost does not depend on the weights)."""
+    import torch
+
+    from paper_1207_3392_amd import hydro, limiter
+    from paper_1207_3392_amd import workloads as wl
+
+    prob = wl.kelvin_helmholtz(n)
+    lim = hydro.LIM_LEARNED if learned else hydro.LIM_THETA
+    p = hydro.Patch(prob, precision=32, limiter=lim, set_initial=False)
+    if learned:
+        p.set_mlp(limiter.init_params())
+    p.set_state(prob.W)
+    p.advance(2, 0.4, solver=hydro.HLLC)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.advance(steps, 0.4, solver=hydro.HLLC)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p.cfl_dt(0.4)
+    p.close()
+    return {"zone_updates_per_s": n * n * steps / wall, "ms_per_step": 1e3 * wall / steps}
+
+
 def roofline(res):
     ncell = res["ncell"]
     # dominant kernel: the stage with the larger mean duration
@@ -153,6 +201,9 @@ def main():
         extra[f"{args.solver}_512"] = {"zone_updates_per_s": r["zone_updates_per_s"],
                                       "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"],
                                       "roofline": roofline(r)}
+        extra["batched_tubes"] = time_batch()
+        extra["kh_2048_plain"] = time_kh(learned=False)
+        extra["kh_2048_learned"] = time_kh(learned=True)
     out = {
         "metric": METRIC,
         "value": main_res["zone_updates_per_s"],

@@ -24,9 +24,10 @@ def _prim(U, ndim, gamma):
     return np.concatenate([rho[None], v, p[None]], axis=0)
 
 
-def samples(U, ndim, n, gamma):
+def samples(U, ndim, n, gamma, return_scale=False):
     """U: (nv, ncell) FP64 conserved fine state; n: fine cells per dim (x, y, z).
-    Returns x (ns, 4), t (ns)."""
+    Returns x (ns, 4), t (ns) and, with return_scale, also s (ns) and the
+    stencil centre value w_c (ns)."""
     nv = ndim + 2
     shape = tuple(int(n[q]) for q in reversed(range(ndim)))  # (nz, ny, nx) active
     Uf = np.asarray(U, dtype=np.float64).reshape((nv,) + shape)
@@ -39,7 +40,7 @@ def samples(U, ndim, n, gamma):
     Uc = Ub.mean(axis=sub_axes)
     Wc = _prim(Uc.reshape(nv, -1), ndim, gamma).reshape(Uc.shape)
     nc = Wc[0].size
-    xs, ts = [], []
+    xs, ts, ss, ws = [], [], [], []
     for q in range(ndim):
         ax = ndim - 1 - q  # array axis of dimension q in the coarse field
         sub_ax = 2 + 2 * ax
@@ -54,8 +55,12 @@ def samples(U, ndim, n, gamma):
             d = np.diff(st, axis=0)
             s = np.max(np.abs(d), axis=0) + 1e-12 * (np.abs(w) + 1e-30)
             xs.append(np.stack([(d[k] / s).ravel() for k in range(4)], axis=1))
+            ss.append(s.ravel())
+            ws.append(w.ravel())
             wsub = Ws[v]
             target = 0.4 * (-3 * wsub[..., 0] - wsub[..., 1] + wsub[..., 2] + 3 * wsub[..., 3])
             tc = tvd_clamp(target, d[1], d[2])
             ts.append((tc / s).ravel())
+    if return_scale:
+        return (np.concatenate(xs, axis=0), np.concatenate(ts, axis=0), np.concatenate(ss), np.concatenate(ws))
     return np.concatenate(xs, axis=0), np.concatenate(ts, axis=0)

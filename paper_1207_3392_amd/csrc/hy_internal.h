@@ -6,13 +6,17 @@
 
 namespace hy {
 
+constexpr int RATE_SLOTS = 32;
+
 // Device control block: one per patch, inside the caller's workspace.
-// rate[s] holds the bits of a positive double, max over cells and dimensions
-// of (|v_q| + c) / dq, for the state in parity slot s; positive doubles order
-// like their bit patterns, so an unsigned 64-bit atomic max reduces them.
+// rate[s][k] holds the bits of a positive double: the max over the cells of
+// the blocks with id = k (mod RATE_SLOTS) of (|v_q| + c) / dq, for the state in
+// parity slot s (the CFL rate is the max over k).  Positive doubles order like
+// their bit patterns, so unsigned 64-bit atomic max reduces them; spreading
+// blocks over slots keeps the atomics uncontended.
 struct DevCtl {
     double time[2];
-    unsigned long long rate[2];
+    unsigned long long rate[2][RATE_SLOTS];
     unsigned int err;
     unsigned int pad[3];
     double totals[8];

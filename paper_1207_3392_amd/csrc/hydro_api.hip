@@ -226,10 +226,7 @@ void pick_config(hy_patch *p)
     const hy_patch_desc &d = p->d;
     p->cfg.bx = 64;
     p->cfg.by = d.ndim == 1 ? 1 : 8;
-    if (d.ndim >= 2 && d.precision == 32) {
-        p->cfg.bx = 32;
-        p->cfg.by = 16;
-    }
+
     if (const char *e = std::getenv("HY_TILE")) {  // "BXxBY", for tuning runs
         int bx = 0, by = 0;
         if (d.ndim > 1 && std::sscanf(e, "%dx%d", &bx, &by) == 2 &&
@@ -391,7 +388,9 @@ hy_status hy_cfl_dt(hy_patch *p, double cfl, double *dt_out)
     hy::DevCtl c;
     hy_status st = read_ctl(p, &c);
     if (st != HY_OK) return st;
-    const double rate = __builtin_bit_cast(double, c.rate[p->parity]);
+    unsigned long long rb = 0ull;
+    for (int k = 0; k < hy::RATE_SLOTS; ++k) rb = std::max(rb, c.rate[p->parity][k]);
+    const double rate = __builtin_bit_cast(double, rb);
     *dt_out = cfl / rate;
     if (c.err || !(rate > 0.0) || !std::isfinite(rate))
         return fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value");

@@ -67,9 +67,15 @@ __global__ void __launch_bounds__(RB) k_cfl_rate(const T *u, int64_t ncell, int6
         for (int d = 0; d < ndim; ++d) r = fmax(r, ((double)fabs(v[d]) + (double)cs) * id[d]);
     }
     if (bad) atomicOr(&ctl->err, 1u);
+    __shared__ double sr[RB / 64];
     for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
-    if ((threadIdx.x & 63) == 0 && r > 0.0)
-        atomicMax(&ctl->rate[slot], (unsigned long long)__double_as_longlong(r));
+    if ((threadIdx.x & 63) == 0) sr[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < RB / 64; ++w) m = fmax(m, sr[w]);
+        if (m > 0.0) atomicMax(&ctl->rate[slot][blockIdx.x % RATE_SLOTS], (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 // Deterministic totals: block b sums the fixed chunk [b*C, (b+1)*C) of every
@@ -120,14 +126,19 @@ __global__ void __launch_bounds__(RB) k_totals_final(const double *partials, int
         for (int d = ndim; d < 3; ++d) ctl->totals[1 + d] = 0.0;
 }
 
-__global__ void k_ctl_reset_rate(DevCtl *ctl, int slot) { ctl->rate[slot] = 0ull; }
+__global__ void k_ctl_reset_rate(DevCtl *ctl, int slot)
+{
+    if (threadIdx.x < RATE_SLOTS) ctl->rate[slot][threadIdx.x] = 0ull;
+}
 
 __global__ void k_ctl_init(DevCtl *ctl)
 {
     ctl->time[0] = 0.0;
     ctl->time[1] = 0.0;
-    ctl->rate[0] = 0ull;
-    ctl->rate[1] = 0ull;
+    for (int k = 0; k < RATE_SLOTS; ++k) {
+        ctl->rate[0][k] = 0ull;
+        ctl->rate[1][k] = 0ull;
+    }
     ctl->err = 0u;
 }
 
@@ -161,7 +172,7 @@ hipError_t launch_cfl_rate(const T *u, int64_t n0, int64_t n1, int64_t n2, int64
                            const double *idx, DevCtl *ctl, int slot, hipStream_t s)
 {
     const int64_t ncell = n0 * n1 * n2;
-    hipLaunchKernelGGL(k_ctl_reset_rate, dim3(1), dim3(1), 0, s, ctl, slot);
+    hipLaunchKernelGGL(k_ctl_reset_rate, dim3(1), dim3(64), 0, s, ctl, slot);
     hipLaunchKernelGGL(k_cfl_rate<T>, dim3(grid_for(ncell)), dim3(RB), 0, s, u, ncell, vstride, ndim, gamma, gm1,
                        idx[0], idx[1], idx[2], ctl, slot);
     return hipGetLastError();
@@ -178,7 +189,7 @@ hipError_t launch_totals(const T *u, int64_t ncell, int64_t vstride, int ndim, d
 
 hipError_t launch_ctl_reset_rate(DevCtl *ctl, int slot, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_reset_rate, dim3(1), dim3(1), 0, s, ctl, slot);
+    hipLaunchKernelGGL(k_ctl_reset_rate, dim3(1), dim3(64), 0, s, ctl, slot);
     return hipGetLastError();
 }
 

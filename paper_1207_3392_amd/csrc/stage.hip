@@ -180,7 +180,10 @@ template <int ND, typename T>
 __device__ __forceinline__ double stage_dt(const StageArgs<T> &a)
 {
     if (a.dt_mode == DT_HOST) return a.dt_host;
-    const double rate = __longlong_as_double((long long)a.ctl->rate[a.parity]);
+    unsigned long long rb = 0ull;
+#pragma unroll
+    for (int k = 0; k < RATE_SLOTS; ++k) rb = rb > a.ctl->rate[a.parity][k] ? rb : a.ctl->rate[a.parity][k];
+    const double rate = __longlong_as_double((long long)rb);
     const double t = a.ctl->time[a.parity];
     double dt = fmin(a.cfl / rate, a.t_end - t);
     return dt > 0.0 ? dt : 0.0;
@@ -242,6 +245,7 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
     constexpr int NP = ND + 2;
     constexpr int IP = ND + 1;
     constexpr int NT = BX * BY;
+    static_assert(NT % 64 == 0, "plane tiles are whole wavefronts");
     constexpr int RY = (ND >= 2) ? BY + 4 : 1;  // LDS rows of primitives (2-cell halo in y)
     constexpr int OY = (ND >= 2) ? 2 : 0;       // row offset of the tile in LDS
     constexpr int WX = BX + 4;                  // LDS columns (2-cell halo in x)
@@ -313,9 +317,9 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
     const double dtd = stage_dt<ND>(a);
     const T dt = (T)dtd;
     if constexpr (STAGE == 1) {
-        if (blockIdx.x == 0 && tid == 0) {
-            a.ctl->rate[a.parity ^ 1] = 0ull;
-            a.ctl->time[a.parity ^ 1] = a.ctl->time[a.parity] + dtd;
+        if (blockIdx.x == 0 && tid < RATE_SLOTS) {
+            a.ctl->rate[a.parity ^ 1][tid] = 0ull;
+            if (tid == 0) a.ctl->time[a.parity ^ 1] = a.ctl->time[a.parity] + dtd;
         }
     }
     __syncthreads();
@@ -577,12 +581,21 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
 
     if (bad) atomicOr(&a.ctl->err, 1u);
     if constexpr (STAGE == 2) {
-        // wave max, then one atomic per wave (positive doubles order as uint64)
+        // wave max, block max in LDS, one atomic per block into slot
+        // blockIdx % RATE_SLOTS (positive doubles order as uint64)
+        __shared__ double sRate[NT / 64];
         double r = (double)rate;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
-        if ((tid & 63) == 0 && r > 0.0)
-            atomicMax(&a.ctl->rate[a.parity ^ 1], (unsigned long long)__double_as_longlong(r));
+        if ((tid & 63) == 0) sRate[tid >> 6] = r;
+        __syncthreads();
+        if (tid == 0) {
+            double m = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) m = fmax(m, sRate[w]);
+            if (m > 0.0)
+                atomicMax(&a.ctl->rate[a.parity ^ 1][blockIdx.x % RATE_SLOTS], (unsigned long long)__double_as_longlong(m));
+        }
     }
 }
 
