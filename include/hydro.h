@@ -208,7 +208,11 @@ hy_status hy_lim_slopes(hy_patch *p, float *out_dev);
  * output against the target in a fixed order, and applies Adam with rate lr.
  * hy_trainer_gradient computes the same gradient without updating
  * (synchronising); hy_mlp_eval runs the limiter's inference kernel with the
- * trainer's current weights on x_dev (batch, 4) into y_dev (batch). */
+ * trainer's current weights on x_dev (batch, 4) into y_dev (batch).
+ * Inputs and targets must be finite: the matrix kernels evaluate 64 samples
+ * together, and a non-finite input can turn the outputs (or the gradient) of
+ * other samples of its group into NaN.  The sample generator and the learned
+ * slopes never produce one from a finite state. */
 typedef struct hy_trainer hy_trainer;
 hy_status hy_trainer_workspace_bytes(size_t *bytes);
 hy_status hy_trainer_init(void *dev_workspace, size_t bytes, const float *init_params, void *hip_stream,

@@ -82,7 +82,9 @@ __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, 
     R.b3 = m->b3;
 }
 
-// Network output for the lane's own input x[0..3] (all 64 lanes must be active).
+// Network output for the lane's own input x[0..3] (all 64 lanes must be active,
+// and every lane's input finite: 0 x inf in a zero block of an operand would
+// spread a NaN to the other lanes of the same column).
 __device__ __forceinline__ float mlp_wave(const float (&x)[4], const MlpRegs &R, int grp)
 {
     const s4 xb = {bf(x[0]), bf(x[1]), bf(x[2]), bf(x[3])};
@@ -120,7 +122,12 @@ __device__ __forceinline__ float learned_sigma(const float (&w)[5], const MlpReg
     for (int k = 0; k < 4; ++k) d[k] = w[k + 1] - w[k];
     const float s = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3]))) +
                     1e-12f * (fabsf(w[2]) + 1e-30f);
-    const float rs = 1.0f / s;
+    // The floor term alone (a flat stencil of zeros) is below the FP32 normal
+    // range, and 1/s would overflow; every input must stay finite because a
+    // NaN or infinite input of one lane reaches the other lanes of its column
+    // through the zero blocks of the matrix operands.  Inputs are unchanged
+    // wherever s is a normal number and exact zeros for a flat stencil.
+    const float rs = 1.0f / fmaxf(s, 1.17549435e-38f);
     float x[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = d[k] * rs;

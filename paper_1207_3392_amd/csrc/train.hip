@@ -122,7 +122,11 @@ __global__ void __launch_bounds__(256) k_samples(const float *__restrict__ Wc, c
     }
     float d[4];
     for (int k = 0; k < 4; ++k) d[k] = w[k + 1] - w[k];
-    const float s = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3]))) + 1e-12f * (fabsf(w[2]) + 1e-30f);
+    // s as in the limiter; the division uses s raised to the smallest normal
+    // FP32 number, so a flat stencil of zeros gives x = t = 0, not 0/0
+    const float s = fmaxf(fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3]))) +
+                              1e-12f * (fabsf(w[2]) + 1e-30f),
+                          1.17549435e-38f);
     for (int k = 0; k < 4; ++k) x[i * 4 + k] = d[k] / s;
     const float *sb = sub + (int64_t)(q * NP + v) * 4 * nc;
     const float w1 = sb[c], w2 = sb[nc + c], w3 = sb[2 * nc + c], w4 = sb[3 * nc + c];

@@ -60,8 +60,9 @@ def augment(x, t):
 
 
 def train(x, t, steps: int = 3000, batch: int = 65536, lr: float = 1e-3, seed: int = wl.DEFAULT_SEED,
-          params=None, log_every: int = 0):
-    """Adam on the device; returns (params (1249,) float32, list of losses)."""
+          params=None, log_every: int = 0, log=None):
+    """Adam on the device; returns (params (1249,) float32, list of
+    (step, minibatch loss) every log_every steps, also passed to log)."""
     import torch
 
     tr = hydro.Trainer(init_params(seed) if params is None else params, device=str(x.device))
@@ -74,6 +75,8 @@ def train(x, t, steps: int = 3000, batch: int = 65536, lr: float = 1e-3, seed: i
         tr.step(x, t, idx, lr)
         if log_every and (k % log_every == 0 or k == steps - 1):
             losses.append((k, tr.loss()))
+            if log is not None:
+                log(f"step {k}: loss {losses[-1][1]:.5g}")
     out = tr.params()
     tr.close()
     return out, losses

@@ -1,0 +1,248 @@
+"""Train the learned slope limiter and measure what it buys at matched error.
+
+Training data come from plain-method Kelvin-Helmholtz runs (HLLC, monotonized
+central limiter, FP32; the Sec. 4.3.1 setup) on fine periodic grids, restricted
+4x by the library; several seeds of the initial random perturbation give
+independent runs, and one more seed is held out for validation.
+
+The evaluation is a posteriori: the same problem is run with the plain and
+the learned limiter at a ladder of resolutions N and compared, through the L1
+norm of the density error (the norm of the paper's convergence tables), with
+a plain run at the finest resolution restricted to each N by block averages
+of the conserved density.  "Matched L1" then reads, from the plain method's
+L1(N) curve, the resolution the plain method needs to reach the learned
+limiter's error (log-log interpolation), and the wall time either needs.
+Two 1D problems complete the picture: the Sod shock tube (Sec. 4.2.1) and
+the smooth density wave (Sec. 4.1.1), also against fine plain runs.
+
+Usage:
+    python -m paper_1207_3392_amd.limiter_study train --out weights.npy
+    python -m paper_1207_3392_amd.limiter_study eval --weights weights.npy --json out.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import hydro, limiter
+from . import workloads as wl
+
+HELD_OUT_SEED = 4242
+
+
+# ---------------------------------------------------------------------------
+# training
+
+
+def training_set(n_fine: int, seeds, times, cfl: float = 0.4):
+    """Samples (x, t) on the device from fine KH runs, one per seed."""
+    import torch
+
+    xs, ts = [], []
+    for s in seeds:
+        x, t = limiter.fine_samples(n_fine, times=times, seed=s, cfl=cfl)
+        xs.append(x)
+        ts.append(t)
+    return torch.cat(xs), torch.cat(ts)
+
+
+def mc_normalised(x):
+    """The monotonized-central slope (theta = 2) in the sample's normalised
+    units, from the two central differences of the stencil."""
+    import torch
+
+    dm, dp = x[:, 1], x[:, 2]
+    a, b, c = 2 * dm, 0.5 * (dm + dp), 2 * dp
+    s = torch.sign(b)
+    m = torch.minimum(torch.minimum(a.abs(), b.abs()), c.abs())
+    ok = (torch.sign(a) == s) & (torch.sign(c) == s)
+    return torch.where(ok, s * m, torch.zeros_like(m))
+
+
+def tvd_clamp_normalised(x, y):
+    import torch
+
+    dm, dp = x[:, 1], x[:, 2]
+    sg = torch.where(dp > 0, torch.ones_like(dp), -torch.ones_like(dp))
+    lim = 2 * torch.minimum(dm.abs(), dp.abs())
+    c = sg * torch.minimum(torch.clamp(sg * y, min=0.0), lim)
+    return torch.where(dm * dp > 0, c, torch.zeros_like(c))
+
+
+def a_priori(params, x, t):
+    """Mean squared error, in normalised slope units, of the clamped network,
+    of the monotonized-central limiter and of minmod against the sub-cell
+    target slopes of the samples."""
+    import torch
+
+    tr = hydro.Trainer(params, device=str(x.device))
+    y = torch.empty_like(t)
+    chunk = 1 << 22
+    for i in range(0, x.shape[0], chunk):
+        y[i:i + chunk] = tr.eval(x[i:i + chunk].contiguous())
+    tr.close()
+    net = tvd_clamp_normalised(x, y)
+    mc = mc_normalised(x)
+    dm, dp = x[:, 1], x[:, 2]
+    mm = torch.where(dm * dp > 0, torch.sign(dp) * torch.minimum(dm.abs(), dp.abs()), torch.zeros_like(dp))
+    return {
+        "mse_learned": float(torch.mean((net - t) ** 2)),
+        "mse_mc": float(torch.mean((mc - t) ** 2)),
+        "mse_minmod": float(torch.mean((mm - t) ** 2)),
+        "samples": int(x.shape[0]),
+    }
+
+
+def train_limiter(n_fine: int = 2048, seeds=(1207, 1208, 1209), times=(0.25, 0.5, 0.75, 1.0),
+                  steps: int = 4000, batch: int = 65536, lr: float = 1e-3, log=print):
+    t0 = time.perf_counter()
+    x, t = training_set(n_fine, seeds, times)
+    x, t = limiter.augment(x, t)
+    log(f"training samples: {x.shape[0]} from {len(seeds)} runs at {n_fine}^2 ({time.perf_counter() - t0:.1f} s)")
+    t1 = time.perf_counter()
+    params, losses = limiter.train(x, t, steps=steps, batch=batch, lr=lr, log_every=max(steps // 20, 1), log=log)
+    log(f"trained {steps} steps in {time.perf_counter() - t1:.1f} s; loss {losses[0][1]:.4g} -> {losses[-1][1]:.4g}")
+    del x, t
+    xv, tv = training_set(n_fine, (HELD_OUT_SEED,), times)
+    val = a_priori(params, xv, tv)
+    log(f"held-out seed {HELD_OUT_SEED}: " + json.dumps(val))
+    info = {"n_fine": n_fine, "seeds": list(seeds), "times": list(times), "steps": steps, "batch": batch,
+            "lr": lr, "losses": losses, "validation": val}
+    return params, info
+
+
+# ---------------------------------------------------------------------------
+# evaluation
+
+
+def restrict(a: np.ndarray, n: int) -> np.ndarray:
+    """Block average of a 1D or 2D field onto n cells per dimension."""
+    r = a.shape[-1] // n
+    if a.ndim == 1:
+        return a.reshape(n, r).mean(axis=1)
+    return a.reshape(n, r, n, r).mean(axis=(1, 3))
+
+
+def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64):
+    """Density at each requested time (plain limiter if params is None),
+    with the wall time of the whole run."""
+    import torch
+
+    cfl = prob.cfl if cfl is None else cfl
+    lim = hydro.LIM_LEARNED if params is not None else hydro.LIM_THETA
+    p = hydro.Patch(prob, precision=32, limiter=lim, set_initial=params is None)
+    if params is not None:
+        p.set_mlp(params)
+        p.set_state(prob.W)
+    out = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for T in times:
+        while p.time() < T * (1 - 1e-12):
+            p.advance(chunk, cfl, t_end=T, solver=hydro.HLLC)
+        U = p.get_state(hydro.CONSERVED)
+        shape = (prob.n[1], prob.n[0]) if prob.ndim == 2 else (prob.n[0],)
+        out[T] = U[0].reshape(shape).copy()
+    wall = time.perf_counter() - t0
+    p.close()
+    return out, wall
+
+
+def loglog_resolution(ns, errs, target):
+    """Resolution at which the piecewise log-log interpolant of (ns, errs)
+    reaches target (extrapolated from the end segments if outside)."""
+    ln, le = np.log(np.asarray(ns, float)), np.log(np.asarray(errs, float))
+    lt = math.log(target)
+    for i in range(len(ns) - 1):
+        lo, hi = sorted((le[i], le[i + 1]))
+        if lo <= lt <= hi:
+            break
+    else:
+        i = 0 if lt > le[0] else len(ns) - 2
+    slope = (le[i + 1] - le[i]) / (ln[i + 1] - ln[i])
+    if slope == 0:
+        return float("nan")
+    return float(math.exp(ln[i] + (lt - le[i]) / slope))
+
+
+def ladder(name, make, ns, n_ref, times, params, log=print):
+    """L1 of plain and learned runs at each N against the restricted fine plain run."""
+    ref, ref_wall = run_to_times(make(n_ref), times)
+    log(f"{name}: reference {n_ref} in {ref_wall:.1f} s")
+    rows = []
+    for n in ns:
+        pl, wp = run_to_times(make(n), times)
+        le, wlr = run_to_times(make(n), times, params=params)
+        for T in times:
+            r = restrict(ref[T], n)
+            rows.append({"n": n, "t": T, "l1_plain": float(np.mean(np.abs(pl[T] - r))),
+                         "l1_learned": float(np.mean(np.abs(le[T] - r))), "wall_plain": wp, "wall_learned": wlr})
+        log(f"{name}: N={n} " + " ".join(f"t={r['t']}: plain {r['l1_plain']:.3e} learned {r['l1_learned']:.3e}"
+                                             for r in rows[-len(times):]))
+    matched = []
+    for T in times:
+        sub = [r for r in rows if r["t"] == T]
+        nsub = [r["n"] for r in sub]
+        lp = [r["l1_plain"] for r in sub]
+        for r in sub:
+            n_eq = loglog_resolution(nsub, lp, r["l1_learned"])
+            matched.append({"t": T, "n_learned": r["n"], "l1_learned": r["l1_learned"],
+                            "plain_n_for_same_l1": n_eq, "resolution_gain": n_eq / r["n"]})
+    return {"problem": name, "n_ref": n_ref, "times": list(times), "rows": rows, "matched": matched}
+
+
+def evaluate(params, kh_ns=(128, 256, 512, 1024), kh_ref=4096, kh_times=(0.5, 1.0), seed=HELD_OUT_SEED,
+             log=print):
+    res = {"kelvin_helmholtz": ladder("kelvin_helmholtz",
+                                      lambda n: wl.kelvin_helmholtz(n, seed=seed), kh_ns, kh_ref, kh_times,
+                                      params, log)}
+    res["sod"] = ladder("sod", lambda n: wl.sod(n, theta=2.0, cfl=0.4, t_end=0.2), (128, 256, 512, 1024),
+                        16384, (0.2,), params, log)
+    res["advection_1d"] = ladder("advection_1d", lambda n: wl.advection_1d(n, theta=2.0),
+                                 (32, 64, 128, 256), 8192, (1.0,), params, log)
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--n-fine", type=int, default=2048)
+    t.add_argument("--seeds", default="1207,1208,1209")
+    t.add_argument("--times", default="0.25,0.5,0.75,1.0")
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--batch", type=int, default=65536)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--out", required=True, help="weights (.npy, float32, 1249 values)")
+    t.add_argument("--json", default="", help="training record")
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--kh-ns", default="128,256,512,1024")
+    e.add_argument("--kh-ref", type=int, default=4096)
+    e.add_argument("--json", default="")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    if a.cmd == "train":
+        params, info = train_limiter(a.n_fine, tuple(int(s) for s in a.seeds.split(",")),
+                                     tuple(float(s) for s in a.times.split(",")), a.steps, a.batch, a.lr, log)
+        np.save(a.out, params.astype(np.float32))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(info, f, indent=1)
+    else:
+        params = np.load(a.weights, allow_pickle=False).astype(np.float32)
+        res = evaluate(params, tuple(int(s) for s in a.kh_ns.split(",")), a.kh_ref, log=log)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

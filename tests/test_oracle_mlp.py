@@ -106,3 +106,15 @@ def test_training_targets_on_linear_data():
         if ndim == 2:
             qy = slice(4 * nc, 5 * nc)  # q = 1, variable rho: constant along y
             assert np.all(x[qy] == 0.0) and np.all(t[qy] == 0.0)
+
+
+def test_flat_stencils_give_zero_inputs_and_slope():
+    """A flat stencil (all differences zero, including a field of exact zeros
+    such as the velocity of fluid at rest) normalises to the zero input and a
+    zero slope; the floor term of s keeps the division defined."""
+    P = mlp.init_params(5)
+    for c in (0.0, 1.0, -3.5, 1e-20):
+        w = np.full(5, c)
+        assert oracle.limiter_learned(P, w) == 0.0
+        x, s, _ = mlp.stencil_features(w[None, :])
+        assert s[0] > 0.0 and np.all(x == 0.0)

@@ -418,3 +418,27 @@ def test_exact_riemann_conserves_through_the_box():
         init = 0.5 * np.array([rl + rr, rl * ul + rr * ur, El + Er])
         got = np.array([r.mean(), (r * u).mean(), E.mean()])
         assert np.allclose(got, init + t * (fl - fr), rtol=0, atol=2e-4)
+
+
+def test_courant_04_in_3d_amplifies_roundoff_and_03_does_not():
+    """Linear stability of the two-stage step (eq. courantTimeStep with the
+    minimum over dimensions): the odd-even mode sees a Riemann-diffusion
+    eigenvalue near -2 d C, and Heun's amplification |1 + z + z^2/2| exceeds 1
+    for d = 3, C = 0.4 (1.48) but not for C = 0.3 (0.82).  A 1e-9 relative
+    perturbation of the smooth 3D flow grows by orders of magnitude in 100
+    steps at C = 0.4 and does not grow at C = 0.3."""
+    for z, amp in ((-2 * 3 * 0.4, 1.48), (-2 * 3 * 0.3, 0.82)):
+        assert abs(1 + z + z * z / 2) == pytest.approx(amp, abs=0.01)
+    prob = wl.smooth_periodic_3d(16)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U0 = oracle.prim_to_cons(d, prob.flat())
+    rng = np.random.default_rng(0)
+    U1 = U0 * (1 + 1e-9 * rng.standard_normal(U0.shape))
+    e0 = np.sum(np.abs(U1 - U0), axis=1) / np.sum(np.abs(U0), axis=1)
+    growth = {}
+    for C in (0.4, 0.3):
+        A = oracle.run_steps(d, U0, 100, C)
+        B = oracle.run_steps(d, U1, 100, C)
+        growth[C] = (np.sum(np.abs(A - B), axis=1) / np.sum(np.abs(A), axis=1)) / e0
+    assert np.max(growth[0.4][1:4]) > 100, growth
+    assert np.max(growth[0.3]) < 10, growth
