@@ -129,7 +129,7 @@ def time_batch(count=512):
 
 def time_kh(n=2048, steps=20, learned=False):
     """2D Kelvin-Helmholtz, FP32, HLLC: plain MC limiter or the learned limiter
-    (random-initialised network: the cost does not depend on the weights)."""
+    (the shipped trained network)."""
     import torch
 
     from paper_1207_3392_amd import hydro, limiter
@@ -139,7 +139,7 @@ def time_kh(n=2048, steps=20, learned=False):
     lim = hydro.LIM_LEARNED if learned else hydro.LIM_THETA
     p = hydro.Patch(prob, precision=32, limiter=lim, set_initial=False)
     if learned:
-        p.set_mlp(limiter.init_params())
+        p.set_mlp(limiter.trained_params())
     p.set_state(prob.W)
     p.advance(2, 0.4, solver=hydro.HLLC)
     torch.cuda.synchronize()

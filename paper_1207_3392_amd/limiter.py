@@ -18,6 +18,19 @@ from . import workloads as wl
 IN, H = 4, 32
 
 
+def trained_params() -> np.ndarray:
+    """The shipped network: trained on plain-method Kelvin-Helmholtz runs at
+    2048^2 restricted to 512^2 (three sharp-layer seeds and two smooth layer
+    widths), by ``python -m paper_1207_3392_amd.limiter_study train``; its
+    training and evaluation record is data/kh_limiter_study.json."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "kh_limiter.npy")
+    w = np.load(path, allow_pickle=False).astype(np.float32)
+    assert w.shape == (1249,)
+    return w
+
+
 def init_params(seed: int = 1207) -> np.ndarray:
     """He initialisation (seeded), flat in the library's parameter order."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -33,12 +46,13 @@ def init_params(seed: int = 1207) -> np.ndarray:
 
 
 def fine_samples(n_fine: int = 1024, times=(0.3, 0.6, 0.9), seed: int = wl.DEFAULT_SEED, cfl: float = 0.4,
-                 gamma: float = 5.0 / 3.0):
-    """Kelvin-Helmholtz on an n_fine^2 periodic grid (plain HLLC, MC limiter,
-    FP32) sampled at the given times; returns device tensors x (n, 4), t (n)."""
+                 gamma: float = 5.0 / 3.0, width: float = 0.0):
+    """Kelvin-Helmholtz (shear-layer half-width ``width``, 0 = sharp) on an
+    n_fine^2 periodic grid (plain HLLC, MC limiter, FP32) sampled at the given
+    times; returns device tensors x (n, 4), t (n)."""
     import torch
 
-    prob = wl.kelvin_helmholtz(n_fine, seed=seed, gamma=gamma)
+    prob = wl.kelvin_helmholtz(n_fine, seed=seed, gamma=gamma, width=width)
     p = hydro.Patch(prob, precision=32)
     xs, ts = [], []
     for T in times:
@@ -60,9 +74,12 @@ def augment(x, t):
 
 
 def train(x, t, steps: int = 3000, batch: int = 65536, lr: float = 1e-3, seed: int = wl.DEFAULT_SEED,
-          params=None, log_every: int = 0, log=None):
-    """Adam on the device; returns (params (1249,) float32, list of
-    (step, minibatch loss) every log_every steps, also passed to log)."""
+          params=None, log_every: int = 0, log=None, cosine: bool = False):
+    """Adam on the device (rate lr, or lr (1 + cos(pi k / steps)) / 2 at step k
+    with cosine); returns (params (1249,) float32, list of (step, minibatch
+    loss) every log_every steps, also passed to log)."""
+    import math
+
     import torch
 
     tr = hydro.Trainer(init_params(seed) if params is None else params, device=str(x.device))
@@ -72,7 +89,7 @@ def train(x, t, steps: int = 3000, batch: int = 65536, lr: float = 1e-3, seed: i
     losses = []
     for k in range(steps):
         idx = torch.randint(0, n, (batch,), device=x.device, dtype=torch.int32, generator=gen)
-        tr.step(x, t, idx, lr)
+        tr.step(x, t, idx, lr * 0.5 * (1.0 + math.cos(math.pi * k / steps)) if cosine else lr)
         if log_every and (k % log_every == 0 or k == steps - 1):
             losses.append((k, tr.loss()))
             if log is not None:

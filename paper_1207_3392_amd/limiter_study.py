@@ -38,13 +38,13 @@ HELD_OUT_SEED = 4242
 # training
 
 
-def training_set(n_fine: int, seeds, times, cfl: float = 0.4):
-    """Samples (x, t) on the device from fine KH runs, one per seed."""
+def training_set(n_fine: int, runs, times, cfl: float = 0.4):
+    """Samples (x, t) on the device from fine KH runs, one per (seed, width)."""
     import torch
 
     xs, ts = [], []
-    for s in seeds:
-        x, t = limiter.fine_samples(n_fine, times=times, seed=s, cfl=cfl)
+    for seed, width in runs:
+        x, t = limiter.fine_samples(n_fine, times=times, seed=seed, cfl=cfl, width=width)
         xs.append(x)
         ts.append(t)
     return torch.cat(xs), torch.cat(ts)
@@ -97,21 +97,28 @@ def a_priori(params, x, t):
     }
 
 
-def train_limiter(n_fine: int = 2048, seeds=(1207, 1208, 1209), times=(0.25, 0.5, 0.75, 1.0),
-                  steps: int = 4000, batch: int = 65536, lr: float = 1e-3, log=print):
+TRAIN_RUNS = ((1207, 0.0), (1208, 0.0), (1209, 0.0), (1207, 0.01), (1208, 0.05))
+EVAL_WIDTH = 0.025
+
+
+def train_limiter(n_fine: int = 2048, runs=TRAIN_RUNS, times=(0.25, 0.5, 0.75, 1.0),
+                  steps: int = 40000, batch: int = 65536, lr: float = 1e-3, log=print):
+    """Runs are (seed, shear-layer half-width) pairs; the held-out validation
+    run is the sharp setup with another seed."""
     t0 = time.perf_counter()
-    x, t = training_set(n_fine, seeds, times)
+    x, t = training_set(n_fine, runs, times)
     x, t = limiter.augment(x, t)
-    log(f"training samples: {x.shape[0]} from {len(seeds)} runs at {n_fine}^2 ({time.perf_counter() - t0:.1f} s)")
+    log(f"training samples: {x.shape[0]} from {len(runs)} runs at {n_fine}^2 ({time.perf_counter() - t0:.1f} s)")
     t1 = time.perf_counter()
-    params, losses = limiter.train(x, t, steps=steps, batch=batch, lr=lr, log_every=max(steps // 20, 1), log=log)
+    params, losses = limiter.train(x, t, steps=steps, batch=batch, lr=lr, log_every=max(steps // 20, 1), log=log,
+                                   cosine=True)
     log(f"trained {steps} steps in {time.perf_counter() - t1:.1f} s; loss {losses[0][1]:.4g} -> {losses[-1][1]:.4g}")
     del x, t
-    xv, tv = training_set(n_fine, (HELD_OUT_SEED,), times)
+    xv, tv = training_set(n_fine, ((HELD_OUT_SEED, 0.0),), times)
     val = a_priori(params, xv, tv)
     log(f"held-out seed {HELD_OUT_SEED}: " + json.dumps(val))
-    info = {"n_fine": n_fine, "seeds": list(seeds), "times": list(times), "steps": steps, "batch": batch,
-            "lr": lr, "losses": losses, "validation": val}
+    info = {"n_fine": n_fine, "runs": [list(r) for r in runs], "times": list(times), "steps": steps,
+            "batch": batch, "lr": lr, "schedule": "cosine", "losses": losses, "validation": val}
     return params, info
 
 
@@ -195,11 +202,14 @@ def ladder(name, make, ns, n_ref, times, params, log=print):
     return {"problem": name, "n_ref": n_ref, "times": list(times), "rows": rows, "matched": matched}
 
 
-def evaluate(params, kh_ns=(128, 256, 512, 1024), kh_ref=4096, kh_times=(0.5, 1.0), seed=HELD_OUT_SEED,
+def evaluate(params, kh_ns=(128, 256, 512, 1024), kh_ref=4096, kh_times=(0.5, 1.0, 1.5), seed=HELD_OUT_SEED,
              log=print):
+    """Ladders on the well-posed KH variant (tanh shear layers of half-width
+    0.025, single-mode perturbation, a width no training run used), the Sod
+    tube and the smooth density wave."""
     res = {"kelvin_helmholtz": ladder("kelvin_helmholtz",
-                                      lambda n: wl.kelvin_helmholtz(n, seed=seed), kh_ns, kh_ref, kh_times,
-                                      params, log)}
+                                      lambda n: wl.kelvin_helmholtz(n, seed=seed, width=EVAL_WIDTH, random_amp=0.0),
+                                      kh_ns, kh_ref, kh_times, params, log)}
     res["sod"] = ladder("sod", lambda n: wl.sod(n, theta=2.0, cfl=0.4, t_end=0.2), (128, 256, 512, 1024),
                         16384, (0.2,), params, log)
     res["advection_1d"] = ladder("advection_1d", lambda n: wl.advection_1d(n, theta=2.0),
@@ -212,9 +222,10 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
     t.add_argument("--n-fine", type=int, default=2048)
-    t.add_argument("--seeds", default="1207,1208,1209")
+    t.add_argument("--runs", default=",".join(f"{s}:{w}" for s, w in TRAIN_RUNS),
+                   help="seed:width pairs of the training runs")
     t.add_argument("--times", default="0.25,0.5,0.75,1.0")
-    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--steps", type=int, default=40000)
     t.add_argument("--batch", type=int, default=65536)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--out", required=True, help="weights (.npy, float32, 1249 values)")
@@ -230,7 +241,8 @@ def main(argv=None):
         print(msg, flush=True)
 
     if a.cmd == "train":
-        params, info = train_limiter(a.n_fine, tuple(int(s) for s in a.seeds.split(",")),
+        runs = tuple((int(r.split(":")[0]), float(r.split(":")[1])) for r in a.runs.split(","))
+        params, info = train_limiter(a.n_fine, runs,
                                      tuple(float(s) for s in a.times.split(",")), a.steps, a.batch, a.lr, log)
         np.save(a.out, params.astype(np.float32))
         if a.json:

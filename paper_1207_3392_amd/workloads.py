@@ -253,7 +253,7 @@ def smooth_periodic_3d(n: int = 256, seed: int = DEFAULT_SEED, ny: int = None, n
 
 
 def kelvin_helmholtz(n: int = 2048, seed: int = DEFAULT_SEED, gamma: float = 5.0 / 3.0,
-                     random_amp: float = 1e-3, lattice: int = 64) -> Problem:
+                     random_amp: float = 1e-3, lattice: int = 64, width: float = 0.0) -> Problem:
     """2D Kelvin-Helmholtz on the periodic unit square (Sec. 4.3.1 setup):
     p = 2.5; rho = 2, v_x = +0.5 for |y-0.5| < 0.25, else rho = 1, v_x = -0.5;
     v_y = [0.01 sin(2 pi x) + A_R(x, y)] psi(y) with
@@ -261,20 +261,30 @@ def kelvin_helmholtz(n: int = 2048, seed: int = DEFAULT_SEED, gamma: float = 5.0
 
     The random part A_R is uniform in [-random_amp, random_amp] on a fixed
     ``lattice x lattice`` grid (seeded) and sampled piecewise-constantly, so
-    every resolution sees the same initial condition."""
+    every resolution sees the same initial condition.
+
+    width = 0 gives the paper's sharp shear layers, whose growth rate rises
+    without bound with the wavenumber, so runs at different resolutions do not
+    converge to one solution.  width > 0 replaces the steps in rho and v_x by
+    tanh profiles of that half-width, e.g. rho = 1 + [tanh((y - 0.25)/width)
+    - tanh((y - 0.75)/width)] / 2, a well-posed variant for convergence
+    studies."""
     rng = np.random.Generator(np.random.PCG64(seed))
     lat = rng.uniform(-random_amp, random_amp, size=(lattice, lattice))
     x = _cell_centres(n, 0.0, 1.0)
     y = _cell_centres(n, 0.0, 1.0)
     X, Y = np.meshgrid(x, y)
-    inner = np.abs(Y - 0.5) < 0.25
+    if width > 0.0:
+        inner = 0.5 * (np.tanh((Y - 0.25) / width) - np.tanh((Y - 0.75) / width))
+    else:
+        inner = (np.abs(Y - 0.5) < 0.25).astype(np.float64)
     ix = np.minimum((x * lattice).astype(np.int64), lattice - 1)
     iy = np.minimum((y * lattice).astype(np.int64), lattice - 1)
     AR = lat[iy[:, None], ix[None, :]]
     psi = np.exp(-0.5 * (np.cos(2 * np.pi * Y) / (2 * np.pi * 0.1)) ** 2)
     W = np.empty((4, n, n))
-    W[0] = np.where(inner, 2.0, 1.0)
-    W[1] = np.where(inner, 0.5, -0.5)
+    W[0] = 1.0 + inner
+    W[1] = -0.5 + inner
     W[2] = (0.01 * np.sin(2 * np.pi * X) + AR) * psi
     W[3] = 2.5
     return Problem(2, (n, n, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), gamma,
