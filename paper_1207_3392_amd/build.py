@@ -27,10 +27,18 @@ CFLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
+# The matrix-core kernels keep MFMA accumulators and results in ordinary VGPRs
+# (gfx950 allows either register file), which removes one accumulator-read
+# instruction per result element from their inner loops.
+FILE_FLAGS = {
+    "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "train.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -16,7 +16,8 @@
 //   lane l = (grp = l / 16, col = l % 16) owns stencil (batch grp, column col);
 //   layer 1: for each batch g, A = W1 placed in K-group g (zeros elsewhere),
 //            B = the lanes' own bf16 inputs (K-group = grp), C = b1;
-//   layer 2: A = W2 blocks, B = relu(H1) as bf16, C = b2;
+//   layer 2: A = W2 (one K = 32 block per output block), B = relu(H1) as
+//            bf16, C = b2;
 //   layer 3: per-lane partial dot products, summed over the four lane groups.
 #include "hy_internal.h"
 #include "hy_mlp.h"
@@ -42,6 +43,11 @@ namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ short bf(float x)
 {
@@ -51,10 +57,36 @@ __device__ __forceinline__ short bf(float x)
     return (short)u;
 }
 
+// Four floats to a bf16 MFMA operand, two per conversion instruction
+// (round to nearest even, element 0 in the low half).
+__device__ __forceinline__ s4 bf4(float a, float b, float c, float d)
+{
+    const u2 w = {__builtin_bit_cast(unsigned, __builtin_convertvector((f2){a, b}, b2)),
+                  __builtin_bit_cast(unsigned, __builtin_convertvector((f2){c, d}, b2))};
+    return __builtin_bit_cast(s4, w);
+}
+
+// Eight floats to a K = 32 bf16 operand (lane elements jj = 0..7).
+__device__ __forceinline__ b8 bf8(const s4 lo, const s4 hi)
+{
+    const u2 l = __builtin_bit_cast(u2, lo), h = __builtin_bit_cast(u2, hi);
+    const u4 w = {l[0], l[1], h[0], h[1]};
+    return __builtin_bit_cast(b8, w);
+}
+
+// max(x, 0) on the bit pattern: negative floats (and -0) are negative
+// integers, so one integer max is ReLU without canonicalising the operand.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// Layer 2 runs as one K = 32 product per output block (v_mfma_f32_16x16x32_bf16:
+// lane (grp, col) holds A[col][8 grp + jj] and B[8 grp + jj][col], jj = 0..7).
+// Its K order is permuted so that B is exactly what layer 1 left in the lane:
+// K index 8 grp + jj stands for hidden unit hk(grp, jj) = 4 grp + jj (jj < 4)
+// or 16 + 4 grp + jj - 4 (jj >= 4), the units of both layer-1 output blocks.
 struct MlpRegs {
     s4 a1[4][2];  // layer-1 weights placed in K-group g, per output block
     f4 c1[2];     // b1 as accumulator input
-    s4 a2[2][2];  // layer-2 weight blocks [out block][k block]
+    b8 a2[2];     // layer-2 weights [out block], K permuted as above
     f4 c2[2];     // b2 as accumulator input
     f4 w3[2];
     float b3;
@@ -74,10 +106,9 @@ __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, 
             R.c2[mb][j] = m->b2[16 * mb + 4 * grp + j];
             R.w3[mb][j] = m->w3[16 * mb + 4 * grp + j];
         }
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) R.a2[mb][kb][j] = bf(m->w2[16 * mb + col][16 * kb + 4 * grp + j]);
+        const float *w2r = m->w2[16 * mb + col];
+        R.a2[mb] = bf8(bf4(w2r[4 * grp], w2r[4 * grp + 1], w2r[4 * grp + 2], w2r[4 * grp + 3]),
+                       bf4(w2r[16 + 4 * grp], w2r[17 + 4 * grp], w2r[18 + 4 * grp], w2r[19 + 4 * grp]));
     }
     R.b3 = m->b3;
 }
@@ -87,7 +118,7 @@ __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, 
 // spread a NaN to the other lanes of the same column).
 __device__ __forceinline__ float mlp_wave(const float (&x)[4], const MlpRegs &R, int grp)
 {
-    const s4 xb = {bf(x[0]), bf(x[1]), bf(x[2]), bf(x[3])};
+    const s4 xb = bf4(x[0], x[1], x[2], x[3]);
     float part[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -95,16 +126,15 @@ __device__ __forceinline__ float mlp_wave(const float (&x)[4], const MlpRegs &R,
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             const f4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[g][mb], xb, R.c1[mb], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) h1[mb][j] = bf(fmaxf(d[j], 0.f));
+            h1[mb] = bf4(relu(d[0]), relu(d[1]), relu(d[2]), relu(d[3]));
         }
+        const b8 hb = bf8(h1[0], h1[1]);
         float p = 0.f;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
-            f4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[mb][0], h1[0], R.c2[mb], 0, 0, 0);
-            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[mb][1], h1[1], d, 0, 0, 0);
+            const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a2[mb], hb, R.c2[mb], 0, 0, 0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) p += R.w3[mb][j] * fmaxf(d[j], 0.f);
+            for (int j = 0; j < 4; ++j) p += R.w3[mb][j] * relu(d[j]);
         }
         p += __shfl_xor(p, 16, 64);
         p += __shfl_xor(p, 32, 64);
@@ -127,7 +157,7 @@ __device__ __forceinline__ float learned_sigma(const float (&w)[5], const MlpReg
     // NaN or infinite input of one lane reaches the other lanes of its column
     // through the zero blocks of the matrix operands.  Inputs are unchanged
     // wherever s is a normal number and exact zeros for a flat stencil.
-    const float rs = 1.0f / fmaxf(s, 1.17549435e-38f);
+    const float rs = __builtin_amdgcn_rcpf(fmaxf(s, 1.17549435e-38f));  // 1 ulp
     float x[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = d[k] * rs;
@@ -159,51 +189,104 @@ __device__ __forceinline__ int64_t map1(int64_t i, int64_t n, int lo, int hi, bo
     return m < 0 ? 0 : (m >= n ? n - 1 : m);
 }
 
-template <int ND>
-__global__ void __launch_bounds__(256) k_learned_slopes(const float *__restrict__ u, float *__restrict__ slopes,
-                                                        int64_t nx, int64_t ny, int64_t nz, int64_t vs, int64_t svs,
-                                                        float gm1, Bc bc, const MlpDevice *__restrict__ mlp)
+// Slopes along one dimension Q from a tile of primitives staged in LDS.
+// A workgroup owns 64 cells along x times R rows: for Q = 0 the rows are whole
+// x lines (y + ny z) and the tile carries a 2-cell halo along x; for Q = 1, 2
+// the rows run along y or z at a fixed z or y and the halo is 2 rows each
+// side.  Each cell is read and converted to primitives once per dimension;
+// then every wave takes whole (variable, row) batches of 64 stencils, so the
+// matrix instructions always run with all lanes holding a real stencil.
+constexpr int LS_ROWS = 16;
+
+template <int ND, int Q>
+struct LsTile {
+    static constexpr int NP = ND + 2;
+    static constexpr int R = ND == 1 ? 1 : LS_ROWS;  // rows per tile
+    static constexpr int NW = ND == 1 ? 1 : 4;       // waves per workgroup (launch bounds match)
+    static constexpr int RA = Q == 0 ? R : R + 4;    // LDS rows
+    static constexpr int CA = Q == 0 ? 68 : 64;      // LDS columns
+};
+
+template <int ND, int Q>
+__global__ void __launch_bounds__(ND == 1 ? 64 : 256)
+    k_learned_slopes(const float *__restrict__ u, float *__restrict__ slopes, int nx, int ny, int nz, int64_t vs,
+                     int64_t svs, float gm1, Bc bc, const MlpDevice *__restrict__ mlp)
 {
-    constexpr int NP = ND + 2;
-    const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
-    MlpRegs R;
-    load_regs(mlp, grp, col, R);
-    const int64_t ncell = nx * ny * nz;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool valid = c < ncell;
-    const int64_t cc = valid ? c : ncell - 1;
-    const int64_t ix = cc % nx, iy = (cc / nx) % ny, iz = cc / (nx * ny);
-    const int64_t pos[3] = {ix, iy, iz}, nn[3] = {nx, ny, nz};
-#pragma unroll
-    for (int q = 0; q < ND; ++q) {
-        float W[5][NP];
-#pragma unroll
-        for (int s = 0; s < 5; ++s) {
-            bool flip = false;
-            int64_t g[3] = {ix, iy, iz};
-            g[q] = map1(pos[q] + s - 2, nn[q], bc.v[q][0], bc.v[q][1], flip);
-            const int64_t cell = (g[2] * ny + g[1]) * nx + g[0];
-            float uu[NP];
-#pragma unroll
-            for (int v = 0; v < NP; ++v) uu[v] = u[cell + v * vs];
-            const float ir = 1.0f / uu[0];
-            float ke = 0.f;
-            W[s][0] = uu[0];
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                W[s][1 + d] = uu[1 + d] * ir;
-                ke += uu[1 + d] * W[s][1 + d];
-            }
-            W[s][NP - 1] = gm1 * (uu[NP - 1] - 0.5f * ke);
-            if (flip) W[s][1 + q] = -W[s][1 + q];
+    using G = LsTile<ND, Q>;
+    constexpr int NP = G::NP, R = G::R, NT = 64 * G::NW, RA = G::RA, CA = G::CA;
+    __shared__ float sW[NP][RA][CA];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int grp = lane >> 4, col = lane & 15;
+    const int x0 = blockIdx.x * 64;
+    const int b0 = blockIdx.y * R;  // first row of the tile
+    const int cf = blockIdx.z;      // fixed coordinate (z for Q = 1, y for Q = 2)
+    const int nq = Q == 0 ? nx : (Q == 1 ? ny : nz);
+    const int nrow = Q == 0 ? ny * nz : nq;
+
+    for (int i = tid; i < RA * CA; i += NT) {
+        const int r = i / CA, c = i % CA;
+        bool flip = false;
+        int x, y, z;
+        if constexpr (Q == 0) {
+            x = (int)map1(x0 - 2 + c, nx, bc.v[0][0], bc.v[0][1], flip);
+            const int line = min(b0 + r, nrow - 1);
+            y = line % ny;
+            z = line / ny;
+        } else {
+            x = min(x0 + c, nx - 1);
+            const int qi = (int)map1(b0 - 2 + r, nq, bc.v[Q][0], bc.v[Q][1], flip);
+            y = Q == 1 ? qi : cf;
+            z = Q == 1 ? cf : qi;
         }
+        const int64_t cell = ((int64_t)z * ny + y) * nx + x;
+        float uu[NP];
 #pragma unroll
-        for (int v = 0; v < NP; ++v) {
-            const float w5[5] = {W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]};
-            const float sg = learned_sigma(w5, R, grp);
-            if (valid) slopes[(int64_t)(q * NP + v) * svs + c] = sg;
+        for (int v = 0; v < NP; ++v) uu[v] = u[cell + v * vs];
+        const float ir = 1.0f / uu[0];
+        float w[NP], ke = 0.f;
+        w[0] = uu[0];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            w[1 + d] = uu[1 + d] * ir;
+            ke += uu[1 + d] * w[1 + d];
+        }
+        w[NP - 1] = gm1 * (uu[NP - 1] - 0.5f * ke);
+        if (flip) w[1 + Q] = -w[1 + Q];
+#pragma unroll
+        for (int v = 0; v < NP; ++v) sW[v][r][c] = w[v];
+    }
+    MlpRegs M;
+    load_regs(mlp, grp, col, M);
+    __syncthreads();
+
+    const int x = x0 + lane;
+    for (int k = wv; k < NP * R; k += G::NW) {  // wave-uniform
+        const int v = k / R, r = k % R;
+        float w5[5];
+#pragma unroll
+        for (int s5 = 0; s5 < 5; ++s5) w5[s5] = Q == 0 ? sW[v][r][lane + s5] : sW[v][r + s5][lane];
+        const float sg = learned_sigma(w5, M, grp);
+        const int rowi = b0 + r;
+        if (x < nx && rowi < nrow) {
+            int64_t cell;
+            if constexpr (Q == 0) cell = (int64_t)rowi * nx + x;
+            else if constexpr (Q == 1) cell = ((int64_t)cf * ny + rowi) * nx + x;
+            else cell = ((int64_t)rowi * ny + cf) * nx + x;
+            slopes[(int64_t)(Q * NP + v) * svs + cell] = sg;
         }
     }
+}
+
+template <int ND, int Q>
+void ls_launch(const float *u, float *slopes, int nx, int ny, int nz, int64_t vs, int64_t svs, float gm1, const Bc &b,
+               const MlpDevice *mlp, hipStream_t s)
+{
+    using G = LsTile<ND, Q>;
+    const unsigned gx = (unsigned)((nx + 63) / 64);
+    const unsigned gy = (unsigned)(Q == 0 ? (ny * nz + G::R - 1) / G::R : ((Q == 1 ? ny : nz) + G::R - 1) / G::R);
+    const unsigned gz = (unsigned)(Q == 0 ? 1 : (Q == 1 ? nz : ny));
+    hipLaunchKernelGGL((k_learned_slopes<ND, Q>), dim3(gx, gy, gz), dim3(64 * G::NW), 0, s, u, slopes, nx, ny, nz, vs,
+                       svs, gm1, b, mlp);
 }
 
 __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDevice *__restrict__ mlp, const float *__restrict__ x,
@@ -229,12 +312,18 @@ hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[
         b.v[q][0] = bc[q][0];
         b.v[q][1] = bc[q][1];
     }
-    const int64_t ncell = n[0] * n[1] * n[2];
-    const dim3 grid((unsigned)((ncell + 255) / 256));
+    const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
     switch (ndim) {
-    case 1: hipLaunchKernelGGL(k_learned_slopes<1>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, svs, gm1, b, mlp); break;
-    case 2: hipLaunchKernelGGL(k_learned_slopes<2>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, svs, gm1, b, mlp); break;
-    default: hipLaunchKernelGGL(k_learned_slopes<3>, grid, dim3(256), 0, s, u, slopes, n[0], n[1], n[2], vstride, svs, gm1, b, mlp); break;
+    case 1: ls_launch<1, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s); break;
+    case 2:
+        ls_launch<2, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        ls_launch<2, 1>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        break;
+    default:
+        ls_launch<3, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        ls_launch<3, 1>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        ls_launch<3, 2>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        break;
     }
     return hipGetLastError();
 }
