@@ -118,26 +118,19 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
         const T El = pl * inv_gm1 + T(0.5) * rl * kl;
         const T Er = pr * inv_gm1 + T(0.5) * rr * kr;
         const T ml = rl * vl, mr = rr * vr;  // mass fluxes
-        T Fl[ND + 2], Fr[ND + 2], Ul[ND + 2], Ur[ND + 2];
-        Fl[0] = ml; Fr[0] = mr; Ul[0] = rl; Ur[0] = rr;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            Fl[1 + d] = ml * wl[1 + d] + (d == Q ? pl : T(0));
-            Fr[1 + d] = mr * wr[1 + d] + (d == Q ? pr : T(0));
-            Ul[1 + d] = rl * wl[1 + d];
-            Ur[1 + d] = rr * wr[1 + d];
-        }
-        Fl[IP] = (El + pl) * vl; Fr[IP] = (Er + pr) * vr;
-        Ul[IP] = El; Ur[IP] = Er;
+        // F = (a+ F_L + a- F_R - a+ a- (U_R - U_L)) / (a+ + a-), formed one
+        // variable at a time with the weights folded; a+ + a- = 0 (both sides
+        // at rest with c = 0) gives the mean of the two fluxes
         const T den = ap + am;
-        if (den > T(0)) {
-            const T inv = rcp_(den), apam = ap * am;
+        const bool pos = den > T(0);
+        const T inv = pos ? rcp_(den) : T(0);
+        const T wL = pos ? ap * inv : T(0.5), wR = pos ? am * inv : T(0.5), wD = ap * am * inv;
+        f[0] = wL * ml + wR * mr - wD * (rr - rl);
 #pragma unroll
-            for (int v = 0; v < ND + 2; ++v) f[v] = (ap * Fl[v] + am * Fr[v] - apam * (Ur[v] - Ul[v])) * inv;
-        } else {
-#pragma unroll
-            for (int v = 0; v < ND + 2; ++v) f[v] = T(0.5) * (Fl[v] + Fr[v]);
-        }
+        for (int d = 0; d < ND; ++d)
+            f[1 + d] = wL * (ml * wl[1 + d] + (d == Q ? pl : T(0))) + wR * (mr * wr[1 + d] + (d == Q ? pr : T(0))) -
+                       wD * (rr * wr[1 + d] - rl * wl[1 + d]);
+        f[IP] = wL * ((El + pl) * vl) + wR * ((Er + pr) * vr) - wD * (Er - El);
     } else {
         // Batten's middle-wave speed (eq. MiddleWaveSpeed)
         const T ql = am + vl, qr = ap - vr;
@@ -239,8 +232,10 @@ __device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, 
     return T(2) * sgn * (T)base[c];
 }
 
+// At least 4 waves per SIMD: the LDS plane tile admits two 512-thread
+// workgroups per CU, so registers beyond 128 per lane would only cost occupancy.
 template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BX, int BY>
-__global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
+__global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 {
     constexpr int NP = ND + 2;
     constexpr int IP = ND + 1;
@@ -423,11 +418,6 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
         const unsigned zko = (ND == 3) ? (unsigned)(kz * plane) : 0u;
         bool fz2 = false;
         if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
-        T u0[NP];
-        if constexpr (STAGE == 2) {
-#pragma unroll
-            for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
-        }
 
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
 #pragma unroll
@@ -447,10 +437,11 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
         __syncthreads();
 
         // ---- phase 1: x and y slopes of the tile cells and one ring beyond ----
-        for (int f = tid; f < BX * BY + 2 * BY; f += NT) {
-            int row, col;
-            if (f < BX * BY) { row = f / BX; col = f % BX; }
-            else { const int e = f - BX * BY; row = e >> 1; col = (e & 1) ? BX : -1; }
+        // Every thread takes its own cell; the ring (x: columns -1 and BX of
+        // each row, y: rows -1 and BY) goes to the first threads (y) and the
+        // last ones (x), so no wave carries two extra passes; the z slopes of
+        // plane kz+1 (registers only) fill the wait of the other waves.
+        auto slope_x = [&](int row, int col) {
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 if constexpr (LIM == LIM_THETA)
@@ -459,29 +450,41 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
                 else
                     sSx[v][row][col + 1] = learned_slope<ND>(a, 0, v, x0 + col, y0 + row, kz);
             }
+        };
+        auto slope_y = [&](int row, int col) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                if constexpr (LIM == LIM_THETA)
+                    sSy[v][row + 1][col] = slope2_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
+                                                    sW[v][row + 3][col + 2], theta2);
+                else
+                    sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
+            }
+        };
+        slope_x(ty, tx);
+        if constexpr (ND >= 2) slope_y(ty, tx);
+        if constexpr (ND == 3) {
+            to_w(U2, W2, fxo, fyo, fz2);
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                if constexpr (LIM == LIM_THETA) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
+                else Sk1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+            }
         }
         if constexpr (ND >= 2) {
-            for (int f = tid; f < BX * BY + 2 * BX; f += NT) {
-                int row, col;
-                if (f < BX * BY) { row = f / BX; col = f % BX; }
-                else { const int e = f - BX * BY; col = e % BX; row = (e / BX) ? BY : -1; }
-#pragma unroll
-                for (int v = 0; v < NP; ++v) {
-                    if constexpr (LIM == LIM_THETA)
-                        sSy[v][row + 1][col] = slope2_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
-                                                        sW[v][row + 3][col + 2], theta2);
-                    else
-                        sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
-                }
-            }
+            if (tid < 2 * BX) slope_y(tid < BX ? -1 : BY, tid < BX ? tid : tid - BX);
+        }
+        {
+            const int e = tid - (NT - 2 * BY);
+            if (e >= 0) slope_x(e >> 1, (e & 1) ? BX : -1);
         }
         __syncthreads();
 
         // ---- phase 2: x and y face fluxes, each face once ----
-        for (int f = tid; f < BX * BY + BY; f += NT) {
-            int row, col;
-            if (f < BX * BY) { row = f / BX; col = f % BX; }
-            else { row = f - BX * BY; col = BX; }
+        // own faces (the low x and y face of the own cell), the z face
+        // kz+1/2, then the ring: face column BX (last threads) and face row
+        // BY (first threads)
+        auto face_x = [&](int row, int col) {
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
@@ -491,40 +494,45 @@ __global__ void __launch_bounds__(BX *BY) k_stage(const StageArgs<T> a)
             riemann<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFx[v][row][col] = fl[v];
-        }
-        if constexpr (ND >= 2) {
-            for (int f = tid; f < BX * BY + BX; f += NT) {
-                int row, col;
-                if (f < BX * BY) { row = f / BX; col = f % BX; }
-                else { row = BY; col = f - BX * BY; }
-                T wl[NP], wr[NP], fl[NP];
-#pragma unroll
-                for (int v = 0; v < NP; ++v) {
-                    wl[v] = sW[v][row + 1][col + 2] + T(0.25) * sSy[v][row][col];
-                    wr[v] = sW[v][row + 2][col + 2] - T(0.25) * sSy[v][row + 1][col];
-                }
-                riemann<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1);
-#pragma unroll
-                for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
-            }
-        }
-        __syncthreads();
-
-        // ---- z faces from the register window ----
-        if constexpr (ND == 3) {
-            to_w(U2, W2, fxo, fyo, fz2);
+        };
+        auto face_y = [&](int row, int col) {
+            T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM == LIM_THETA) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
-                else Sk1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+                wl[v] = sW[v][row + 1][col + 2] + T(0.25) * sSy[v][row][col];
+                wr[v] = sW[v][row + 2][col + 2] - T(0.25) * sSy[v][row + 1][col];
             }
+            riemann<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1);
+#pragma unroll
+            for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
+        };
+        // the scheduling barriers keep the solver instances from being
+        // interleaved, which would only raise register pressure
+        face_x(ty, tx);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (ND >= 2) face_y(ty, tx);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (ND == 3) {
             T fl[NP], fr[NP];
             face_state(Wk, Sk, T(0.25), fl);
             face_state(Wk1, Sk1, T(-0.25), fr);
             riemann<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1);
         }
+        if constexpr (ND >= 2) {
+            if (tid < BX) face_y(BY, tid);
+        }
+        {
+            const int e = tid - (NT - BY);
+            if (e >= 0) face_x(e, BX);
+        }
+        __syncthreads();
 
         // ---- phase 3: divergence, source, Runge-Kutta combination ----
+        T u0[NP];  // U^n of the own cell (second stage), loaded late to keep it out of the solver's registers
+        if constexpr (STAGE == 2) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
+        }
         T L[NP];
 #pragma unroll
         for (int v = 0; v < NP; ++v) L[v] = (sFx[v][ty][tx] - sFx[v][ty][tx + 1]) * a.idx[0];
