@@ -69,7 +69,7 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
-def time_patch(n, solver, steps, warmup, timing=True):
+def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4):
     import torch
 
     from paper_1207_3392_amd import hydro
@@ -79,17 +79,17 @@ def time_patch(n, solver, steps, warmup, timing=True):
     p = hydro.Patch(prob, precision=32)
     cfg = p.kernel_config()
     sv = hydro.HLLC if solver == "hllc" else hydro.HLL
-    p.advance(warmup, 0.4, solver=sv)
+    p.advance(warmup, cfl, solver=sv)
     torch.cuda.synchronize()
     p.set_timing(timing)
     p.kernel_times()  # reset
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    p.advance(steps, 0.4, solver=sv)
+    p.advance(steps, cfl, solver=sv)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms, launches = p.kernel_times()
-    p.cfl_dt(0.4)  # raises if the state went non-physical
+    p.cfl_dt(cfl)  # raises if the state went non-physical
     ncell = n ** 3
     res = {
         "wall_s": wall,
@@ -230,17 +230,34 @@ def main():
     main_res = time_patch(args.n, args.solver, args.steps, args.warmup)
     extra = {}
     if not args.no_extra:
-        other = "hll" if args.solver == "hllc" else "hllc"
-        r = time_patch(args.n, other, args.steps, args.warmup)
-        extra[f"{other}_{args.n}"] = {"zone_updates_per_s": r["zone_updates_per_s"],
-                                     "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"]}
-        r = time_patch(512, args.solver, 20, 3)
-        extra[f"{args.solver}_512"] = {"zone_updates_per_s": r["zone_updates_per_s"],
-                                      "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"],
-                                      "roofline": roofline(r)}
-        extra["batched_tubes"] = time_batch()
-        extra["kh_2048_plain"] = time_kh(learned=False)
-        extra["kh_2048_learned"] = time_kh(learned=True)
+        def guarded(name, fn):
+            # an extra workload that fails reports its error instead of
+            # taking the benchmark line with it
+            try:
+                extra[name] = fn()
+            except Exception as e:  # noqa: BLE001
+                extra[name] = {"error": f"{type(e).__name__}: {e}"}
+
+        def other_solver():
+            # HLL at C = 0.3: with the minimum over dimensions in the CFL
+            # condition, C = 0.4 in 3D amplifies roundoff, and the more
+            # diffusive HLL flux breaks down after about 70 steps of this flow
+            # in FP32 (HLLC stays physical); the cost per step does not depend on C
+            other = "hll" if args.solver == "hllc" else "hllc"
+            r = time_patch(args.n, other, args.steps, args.warmup, cfl=0.3)
+            return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
+                    "stage_ms": r["stage_ms"], "cfl": 0.3}
+
+        def big():
+            r = time_patch(512, args.solver, 20, 3)
+            return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
+                    "stage_ms": r["stage_ms"], "roofline": roofline(r)}
+
+        guarded(f"{'hll' if args.solver == 'hllc' else 'hllc'}_{args.n}", other_solver)
+        guarded(f"{args.solver}_512", big)
+        guarded("batched_tubes", time_batch)
+        guarded("kh_2048_plain", lambda: time_kh(learned=False))
+        guarded("kh_2048_learned", lambda: time_kh(learned=True))
     out = {
         "metric": METRIC,
         "value": main_res["zone_updates_per_s"],

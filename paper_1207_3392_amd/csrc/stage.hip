@@ -280,6 +280,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int z0 = (ND == 3) ? bzi * a.zchunk : 0;
     const int nplanes = (ND == 3) ? (z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
     const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1, theta2 = T(2) * a.theta;
+    const bool grav = a.accel[0] != T(0) || a.accel[1] != T(0) || a.accel[2] != T(0);  // uniform
 
     // per-variable base pointers (uniform), 32-bit cell offsets below
     const T *uin[NP];
@@ -408,6 +409,17 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         to_w(UA, WA, fxo, fyo, false);
     }
 
+    // halo cells of the next plane, loaded one plane ahead so their latency
+    // is not on the path to the first barrier of the plane
+    T hnext[HPT][NP];
+    auto load_halo = [&](int z, T (&h)[HPT][NP]) {
+        const unsigned zo = (ND == 3) ? (unsigned)((z < nz ? z : nz - 1) * plane) : 0u;
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+            if (hlds[j] >= 0) load(zo + hoff[j], h[j]);
+    };
+    load_halo(z0, hnext);
+
     T *sWf = &sW[0][0][0];
     // one plane: Wk/Uk/Sk/Flo hold plane kz, Wk1/Uk1 plane kz+1; the body
     // fills W2/U2 (plane kz+2), Sk1 (z slopes of kz+1) and Fhi (face kz+1/2)
@@ -418,16 +430,26 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         const unsigned zko = (ND == 3) ? (unsigned)(kz * plane) : 0u;
         bool fz2 = false;
         if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
+        T u0[NP];  // U^n of the own cell (second stage), issued early, used in phase 3
+        if constexpr (STAGE == 2) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
+        }
 
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
 #pragma unroll
         for (int v = 0; v < NP; ++v) sW[v][ty + OY][tx + 2] = Wk[v];
+        T hcur[HPT][NP];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+#pragma unroll
+            for (int v = 0; v < NP; ++v) hcur[j][v] = hnext[j][v];
+        if constexpr (ND == 3) load_halo(kz + 1, hnext);
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (hlds[j] >= 0) {
-                T u[NP], w[NP];
-                load(zko + hoff[j], u);
-                to_prim<ND>(u, w, gm1);
+                T w[NP];
+                to_prim<ND>(hcur[j], w, gm1);
                 if (hflg[j] & 1) w[1] = -w[1];
                 if constexpr (ND >= 2) { if (hflg[j] & 2) w[2] = -w[2]; }
 #pragma unroll
@@ -528,11 +550,6 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         __syncthreads();
 
         // ---- phase 3: divergence, source, Runge-Kutta combination ----
-        T u0[NP];  // U^n of the own cell (second stage), loaded late to keep it out of the solver's registers
-        if constexpr (STAGE == 2) {
-#pragma unroll
-            for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
-        }
         T L[NP];
 #pragma unroll
         for (int v = 0; v < NP; ++v) L[v] = (sFx[v][ty][tx] - sFx[v][ty][tx + 1]) * a.idx[0];
@@ -544,7 +561,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
             for (int v = 0; v < NP; ++v) L[v] += (Flo[v] - Fhi[v]) * a.idx[2];
         }
-        {
+        if (grav) {
             // uniform acceleration: momentum += rho a, energy += S . a
             T pw = T(0);
 #pragma unroll
