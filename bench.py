@@ -34,9 +34,9 @@ BYTES_PER_CELL = {1: 40.0, 2: 60.0}  # stage 1 reads U^n, writes U1; stage 2 rea
 # to the kernel the traffic is reported as null until the counters are retaken.
 TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h")
 TRAFFIC = {
-    "digest": "5814e584f0bb8339084dc9274291730820cbb85f3db95c88d4ca89bd68f2b447",
+    "digest": "c23588584acc5dd9b5b0b0e81c12dcba97c51b2b3d9c8e025fff095bf4fcf2b2",
     "ncell": 256 ** 3,
-    "bytes_per_launch": {1: (2 * 250563 + 327680) * 1024, 2: (2 * 449469 + 327712) * 1024},
+    "bytes_per_launch": {1: 743940101, 2: 1124125888},
 }
 
 
