@@ -11,7 +11,9 @@ divergence, Runge-Kutta combination and the dt min-reduction.  The state is
 resident in HBM before timing starts.
 
 Prints one JSON line.  Extra fields report the HLL run, a 512^3 patch, the
-per-kernel roofline and the FP64 CPU oracle timed on a bounded sample.
+512 batched tubes, 2D Kelvin-Helmholtz and 3D Rayleigh-Taylor with the plain
+and the learned limiter, the per-kernel roofline and the FP64 CPU oracle timed
+on a bounded sample.
 """
 import argparse
 import json
@@ -30,12 +32,14 @@ BYTES_PER_CELL = {1: 40.0, 2: 60.0}  # stage 1 reads U^n, writes U1; stage 2 rea
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this benchmark, scaled by
 # what the same counters read for a 1 GiB device copy (FETCH x2.0, WRITE x1.0);
 # the summaries are kept under profiles/.  The figures hold only for the
-# kernel source they were taken on, identified by its digest; after any change
-# to the kernel the traffic is reported as null until the counters are retaken.
+# kernel source and launch configuration they were taken on (the source is
+# identified by its digest); after any change the traffic is reported as null
+# until the counters are retaken.
 TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h")
 TRAFFIC = {
     "digest": "c23588584acc5dd9b5b0b0e81c12dcba97c51b2b3d9c8e025fff095bf4fcf2b2",
     "ncell": 256 ** 3,
+    "kernel": "k_stage<nd=3,f32,tile=64x8> zchunk=32",
     "bytes_per_launch": {1: 743940101, 2: 1124125888},
 }
 
@@ -50,7 +54,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
-    ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned"],
+    ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
+                                                   "rt_512_plain", "rt_512_learned"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -163,9 +168,35 @@ def source_digest():
 
 
 def measured_traffic(res, k):
-    ok = (res["ncell"] == TRAFFIC["ncell"] and "nd=3,f32,tile=64x8" in res["kernel"]
+    ok = (res["ncell"] == TRAFFIC["ncell"] and res["kernel"] == TRAFFIC["kernel"]
           and source_digest() == TRAFFIC["digest"])
     return float(TRAFFIC["bytes_per_launch"][k + 1]) if ok else None
+
+
+def time_rt(n=512, steps=10, learned=False):
+    """3D Rayleigh-Taylor (gravity, reflecting z walls), FP32, HLLC, C = 0.3:
+    plain MC limiter or the learned limiter (the shipped trained network)."""
+    import torch
+
+    from paper_1207_3392_amd import hydro, limiter
+    from paper_1207_3392_amd import workloads as wl
+
+    prob = wl.rayleigh_taylor_3d(n)
+    lim = hydro.LIM_LEARNED if learned else hydro.LIM_THETA
+    p = hydro.Patch(prob, precision=32, limiter=lim, set_initial=False)
+    if learned:
+        p.set_mlp(limiter.trained_params())
+    p.set_state(prob.W)
+    del prob
+    p.advance(2, 0.3, solver=hydro.HLLC)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.advance(steps, 0.3, solver=hydro.HLLC)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p.cfl_dt(0.3)
+    p.close()
+    return {"zone_updates_per_s": n ** 3 * steps / wall, "ms_per_step": 1e3 * wall / steps}
 
 
 def roofline(res):
@@ -223,7 +254,8 @@ def main():
 
     if args.only:
         run = {"batched_tubes": time_batch, "kh_2048_plain": lambda: time_kh(learned=False),
-               "kh_2048_learned": lambda: time_kh(learned=True)}[args.only]
+               "kh_2048_learned": lambda: time_kh(learned=True), "rt_512_plain": lambda: time_rt(learned=False),
+               "rt_512_learned": lambda: time_rt(learned=True)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -258,6 +290,8 @@ def main():
         guarded("batched_tubes", time_batch)
         guarded("kh_2048_plain", lambda: time_kh(learned=False))
         guarded("kh_2048_learned", lambda: time_kh(learned=True))
+        guarded("rt_512_plain", lambda: time_rt(learned=False))
+        guarded("rt_512_learned", lambda: time_rt(learned=True))
     out = {
         "metric": METRIC,
         "value": main_res["zone_updates_per_s"],

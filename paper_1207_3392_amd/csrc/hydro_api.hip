@@ -5,6 +5,7 @@
 #include "hy_internal.h"
 #include "hy_mlp.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -222,7 +223,8 @@ hy_status compute_rate(hy_patch *p)
 
 void pick_config(hy_patch *p)
 {
-    // plane tile and z chunk: a launch should have >= ~1024 workgroups
+    // plane tile and z chunk: at least ~512 workgroups (two per CU) and at
+    // most 64 planes per workgroup (measured best at 256^3: 64x8 tile, 64 planes)
     const hy_patch_desc &d = p->d;
     p->cfg.bx = 64;
     p->cfg.by = d.ndim == 1 ? 1 : 8;
@@ -237,10 +239,15 @@ void pick_config(hy_patch *p)
     }
     if (d.ndim == 3) {
         const int64_t tiles = ((d.n[0] + p->cfg.bx - 1) / p->cfg.bx) * ((d.n[1] + p->cfg.by - 1) / p->cfg.by);
-        int64_t chunks = (1024 + tiles - 1) / tiles;
+        int64_t chunks = (512 + tiles - 1) / tiles;
+        chunks = std::max<int64_t>(chunks, (d.n[2] + 63) / 64);
         if (chunks > d.n[2] / 8) chunks = d.n[2] / 8;
         if (chunks < 1) chunks = 1;
         p->cfg.zchunk = (int)((d.n[2] + chunks - 1) / chunks);
+        if (const char *e = std::getenv("HY_ZCHUNK")) {  // planes per workgroup, for tuning runs
+            const int zc = std::atoi(e);
+            if (zc >= 1 && zc <= d.n[2]) p->cfg.zchunk = zc;
+        }
     } else {
         p->cfg.zchunk = 1;
     }
