@@ -1,0 +1,148 @@
+"""Full-size configurations in the benchmark's launch configuration, checked
+on sampled sub-boxes that the FP64 oracle steps one by one.
+
+One two-stage step reaches 2 cells per stage with the generalised minmod (a
+face needs the slopes of its two cells, a slope the neighbours of its cell)
+and 3 with the learned limiter's 5-cell stencil, so an oracle box with a halo
+of 4 (6) cells reproduces its interior exactly.  Where a box touches a
+reflecting wall it starts at the wall and the oracle applies the wall there;
+periodic dimensions wrap."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1207_3392_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+hydro = pytest.importorskip("paper_1207_3392_amd.hydro")
+
+
+def _gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+if not _gpu():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def box_indices(n, lo, size, halo, mode):
+    """Index window along one dimension and the (start, stop) of the compared
+    cells inside it; mode is 'wrap', 'low' (box starts at the wall), 'high'
+    (box ends at the wall) or 'inner' (no wall within reach)."""
+    if mode == "wrap":
+        return np.arange(lo - halo, lo + size + halo) % n, (halo, halo + size)
+    if mode == "low":
+        return np.arange(0, size + halo), (0, size)
+    if mode == "high":
+        return np.arange(n - size - halo, n), (halo, halo + size)
+    assert lo - halo >= 0 and lo + size + halo <= n
+    return np.arange(lo - halo, lo + size + halo), (halo, halo + size)
+
+
+def oracle_box_step(prob, U, lo, size, halo, modes, dt, **desc_kw):
+    nd, nv = prob.ndim, prob.ndim + 2
+    n = list(prob.n)
+    shape = (nv,) + tuple(n[q] for q in reversed(range(3)))  # (nv, nz, ny, nx)
+    U4 = U.reshape(shape)
+    idx, cmp = [], []
+    for q in range(3):
+        if q < nd:
+            i, c = box_indices(n[q], lo[q], size, halo, modes[q])
+        else:
+            i, c = np.arange(1), (0, 1)
+        idx.append(i)
+        cmp.append(c)
+    box = U4[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+    m = [len(idx[q]) for q in range(3)]
+    dx = [(prob.hi[q] - prob.lo[q]) / n[q] for q in range(3)]
+    bc = []
+    for q in range(3):
+        wall = prob.bc[q]
+        lo_bc = wall[0] if modes[q] == "low" else wl.BC_OUTFLOW
+        hi_bc = wall[1] if modes[q] == "high" else wl.BC_OUTFLOW
+        bc.append((lo_bc, hi_bc) if q < nd else (wl.BC_PERIODIC, wl.BC_PERIODIC))
+    d = oracle.Desc(nd, tuple(m), (0.0, 0.0, 0.0), tuple(m[q] * dx[q] for q in range(3)), prob.gamma, tuple(bc),
+                    accel=prob.accel, **desc_kw)
+    ref = oracle.step(d, np.ascontiguousarray(box).reshape(nv, -1), dt).reshape(box.shape)
+    sl = (slice(None),) + tuple(slice(*cmp[q]) for q in reversed(range(3)))
+    return ref[sl], idx, cmp
+
+
+def gpu_box(prob, U1, idx, cmp):
+    nv = prob.ndim + 2
+    shape = (nv,) + tuple(prob.n[q] for q in reversed(range(3)))
+    U4 = U1.reshape(shape)
+    sel = [idx[q][cmp[q][0]:cmp[q][1]] for q in range(3)]
+    return U4[:, sel[2]][:, :, sel[1]][:, :, :, sel[0]]
+
+
+def scale(ref):
+    s = np.max(np.abs(ref.reshape(ref.shape[0], -1)), axis=1)
+    s[1:-1] = np.maximum(s[1:-1], np.sqrt(2.0 * s[0] * s[-1]))
+    return s.reshape((-1,) + (1,) * (ref.ndim - 1))
+
+
+def test_kelvin_helmholtz_2048_plain_and_learned_sampled():
+    """2D Kelvin-Helmholtz at 2048^2 after 40 steps (shear layers rolled
+    into structure), one more step checked on 8 boxes, plain MC limiter and
+    the shipped learned limiter."""
+    from paper_1207_3392_amd import limiter
+
+    prob = wl.kelvin_helmholtz(2048)
+    P = limiter.trained_params()
+    rng = np.random.default_rng(11)
+    for learned in (False, True):
+        lim = hydro.LIM_LEARNED if learned else hydro.LIM_THETA
+        p = hydro.Patch(prob, precision=32, limiter=lim, set_initial=False)
+        if learned:
+            p.set_mlp(P)
+        p.set_state(prob.W)
+        p.advance(40, 0.4, solver=hydro.HLLC)
+        U0 = p.get_state(hydro.CONSERVED)
+        dt = p.cfl_dt(0.4)
+        p.step(dt, hydro.HLLC)
+        U1 = p.get_state(hydro.CONSERVED)
+        p.close()
+        kw = dict(solver=oracle.HLLC, theta=2.0)
+        if learned:
+            kw.update(limiter=oracle.LIM_LEARNED, mlp=P.astype(np.float64), mlp_bf16=True)
+        halo = 6 if learned else 4
+        for _ in range(8):
+            lo = rng.integers(0, 2048, size=3)
+            lo[0] = lo[0] if rng.random() < 0.5 else 2048 - 8  # some boxes across the periodic seam
+            ref, idx, cmp = oracle_box_step(prob, U0, lo, 32, halo, ("wrap", "wrap", None), dt, **kw)
+            got = gpu_box(prob, U1, idx, cmp)
+            err = np.abs(got - ref) / scale(ref)
+            if learned:
+                assert err.mean() < 1e-4 and err.max() < 1e-2, (tuple(lo), err.mean(), err.max())
+            else:
+                assert err.max() < 2e-5 and err.mean() < 2e-6, (tuple(lo), err.max(), err.mean())
+
+
+def test_rayleigh_taylor_512_sampled():
+    """3D Rayleigh-Taylor at 512^3 (gravity, periodic x and y, reflecting z
+    walls), one HLLC step at C = 0.3 after 10 steps, checked on boxes inside
+    the domain and on boxes against each wall."""
+    prob = wl.rayleigh_taylor_3d(512)
+    p = hydro.Patch(prob, precision=32)
+    p.advance(10, 0.3, solver=hydro.HLLC)
+    U0 = p.get_state(hydro.CONSERVED)
+    dt = p.cfl_dt(0.3)
+    p.step(dt, hydro.HLLC)
+    U1 = p.get_state(hydro.CONSERVED)
+    m0 = p.totals()[0]
+    p.close()
+    rng = np.random.default_rng(12)
+    for zmode in ("inner", "inner", "low", "low", "high", "high"):
+        lo = rng.integers(0, 512, size=3)
+        lo[2] = rng.integers(8, 512 - 16)
+        ref, idx, cmp = oracle_box_step(prob, U0, lo, 8, 4, ("wrap", "wrap", zmode), dt, solver=oracle.HLLC,
+                                        theta=2.0)
+        got = gpu_box(prob, U1, idx, cmp)
+        err = np.abs(got - ref) / scale(ref)
+        assert err.max() < 2e-5 and err.mean() < 2e-6, (zmode, tuple(lo), err.max(), err.mean())
+    assert np.isfinite(m0) and m0 > 0
