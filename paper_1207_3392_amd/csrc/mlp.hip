@@ -74,6 +74,23 @@ __device__ __forceinline__ b8 bf8(const s4 lo, const s4 hi)
     return __builtin_bit_cast(b8, w);
 }
 
+// ReLU of four floats, rounded to bf16: rounding keeps the sign, so the ReLU
+// acts on the packed bf16 bit patterns, one packed 16-bit integer max per pair
+// (negative values and -0 are negative integers); equal to bf4(relu(.)) bit for bit.
+__device__ __forceinline__ unsigned pk_relu_bf16(float a, float b)
+{
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const b2 h = __builtin_convertvector((f2){a, b}, b2);
+    const s2 r = __builtin_elementwise_max(__builtin_bit_cast(s2, h), (s2){0, 0});
+    return __builtin_bit_cast(unsigned, r);
+}
+
+__device__ __forceinline__ s4 bf4_relu(float a, float b, float c, float d)
+{
+    const u2 r = {pk_relu_bf16(a, b), pk_relu_bf16(c, d)};
+    return __builtin_bit_cast(s4, r);
+}
+
 // max(x, 0) on the bit pattern: negative floats (and -0) are negative
 // integers, so one integer max is ReLU without canonicalising the operand.
 __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
@@ -126,7 +143,7 @@ __device__ __forceinline__ float mlp_wave(const float (&x)[4], const MlpRegs &R,
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             const f4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[g][mb], xb, R.c1[mb], 0, 0, 0);
-            h1[mb] = bf4(relu(d[0]), relu(d[1]), relu(d[2]), relu(d[3]));
+            h1[mb] = bf4_relu(d[0], d[1], d[2], d[3]);
         }
         const b8 hb = bf8(h1[0], h1[1]);
         float p = 0.f;

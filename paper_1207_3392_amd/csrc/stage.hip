@@ -204,10 +204,11 @@ __device__ __forceinline__ int map32(int i, int n, int bclo, int bchi, bool &fli
     return m < 0 ? 0 : (m >= n ? n - 1 : m);
 }
 
-// Twice the learned-limiter slope of variable v along q at cell (gx, gy, gz): interior
-// slopes come from the slope array; a ghost cell along q takes the slope of
-// its interior source (periodic), zero (outflow) or the mirrored slope
-// (reflecting; the normal velocity is odd, the other variables even)
+// The learned-limiter slope of variable v along q at cell (gx, gy, gz) (face
+// values w +/- slope / 2): interior slopes come from the slope array; a ghost
+// cell along q takes the slope of its interior source (periodic), zero
+// (outflow) or the mirrored slope (reflecting; the normal velocity is odd, the
+// other variables even)
 template <int ND, typename T>
 __device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, int gx, int gy, int gz)
 {
@@ -229,7 +230,7 @@ __device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, 
     }
     const int c = (g[2] * (int)a.n[1] + g[1]) * (int)a.n[0] + g[0];
     const float *base = a.slopes + (int64_t)(q * (ND + 2) + v) * a.vstride;
-    return T(2) * sgn * (T)base[c];
+    return sgn * (T)base[c];
 }
 
 // At least 4 waves per SIMD: the LDS plane tile admits two 512-thread
@@ -280,6 +281,9 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int z0 = (ND == 3) ? bzi * a.zchunk : 0;
     const int nplanes = (ND == 3) ? (z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
     const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1, theta2 = T(2) * a.theta;
+    // face value = w +/- HS * slope: the minmod path stores twice the slope
+    // (median form), the learned path the slope itself
+    constexpr T HS = LIM == LIM_LEARNED ? T(0.5) : T(0.25);
     const bool grav = a.accel[0] != T(0) || a.accel[1] != T(0) || a.accel[2] != T(0);  // uniform
 
     // per-variable base pointers (uniform), 32-bit cell offsets below
@@ -401,8 +405,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             }
         }
         T fl[NP], fr[NP];
-        face_state(wm1, sm1, T(0.25), fl);
-        face_state(WA, SA, T(-0.25), fr);
+        face_state(wm1, sm1, HS, fl);
+        face_state(WA, SA, -HS, fr);
         riemann<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1);
     } else {
         load(colo, UA);
@@ -434,6 +438,19 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         if constexpr (STAGE == 2) {
 #pragma unroll
             for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
+        }
+
+        // learned limiter: the own cell's x and y slopes (and the z slope of
+        // plane kz+1) are loaded here and stored in phase 1, so their latency
+        // overlaps phase 0 and its barrier
+        T lsx[NP], lsy[NP], lsz[NP];
+        if constexpr (LIM == LIM_LEARNED) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                lsx[v] = learned_slope<ND>(a, 0, v, gx, gy, kz);
+                if constexpr (ND >= 2) lsy[v] = learned_slope<ND>(a, 1, v, gx, gy, kz);
+                if constexpr (ND == 3) lsz[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+            }
         }
 
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
@@ -483,14 +500,22 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                     sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
             }
         };
-        slope_x(ty, tx);
-        if constexpr (ND >= 2) slope_y(ty, tx);
+        if constexpr (LIM == LIM_THETA) {
+            slope_x(ty, tx);
+            if constexpr (ND >= 2) slope_y(ty, tx);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                sSx[v][ty][tx + 1] = lsx[v];
+                if constexpr (ND >= 2) sSy[v][ty + 1][tx] = lsy[v];
+            }
+        }
         if constexpr (ND == 3) {
             to_w(U2, W2, fxo, fyo, fz2);
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 if constexpr (LIM == LIM_THETA) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
-                else Sk1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+                else Sk1[v] = lsz[v];
             }
         }
         if constexpr (ND >= 2) {
@@ -510,8 +535,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                wl[v] = sW[v][row + OY][col + 1] + T(0.25) * sSx[v][row][col];
-                wr[v] = sW[v][row + OY][col + 2] - T(0.25) * sSx[v][row][col + 1];
+                wl[v] = sW[v][row + OY][col + 1] + HS * sSx[v][row][col];
+                wr[v] = sW[v][row + OY][col + 2] - HS * sSx[v][row][col + 1];
             }
             riemann<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1);
 #pragma unroll
@@ -521,8 +546,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                wl[v] = sW[v][row + 1][col + 2] + T(0.25) * sSy[v][row][col];
-                wr[v] = sW[v][row + 2][col + 2] - T(0.25) * sSy[v][row + 1][col];
+                wl[v] = sW[v][row + 1][col + 2] + HS * sSy[v][row][col];
+                wr[v] = sW[v][row + 2][col + 2] - HS * sSy[v][row + 1][col];
             }
             riemann<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1);
 #pragma unroll
@@ -536,8 +561,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (ND == 3) {
             T fl[NP], fr[NP];
-            face_state(Wk, Sk, T(0.25), fl);
-            face_state(Wk1, Sk1, T(-0.25), fr);
+            face_state(Wk, Sk, HS, fl);
+            face_state(Wk1, Sk1, -HS, fr);
             riemann<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1);
         }
         if constexpr (ND >= 2) {
