@@ -1,6 +1,6 @@
 """Exact solution of the 1D Riemann problem for the ideal-gas Euler equations.
 
-TEST INFRASTRUCTURE ONLY (used to pin the oracle and to judge the GPU runs on
+TEST INFRASTRUCTURE ONLY (used to pin the oracle and to check the GPU runs on
 shock tubes; the paper compares its Riemann-problem runs with exact solutions
 in Sec. 4.2.1).  Written from the mathematics of the problem: the star-region
 pressure p* is the root of

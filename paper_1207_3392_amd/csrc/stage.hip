@@ -500,6 +500,14 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                     sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
             }
         };
+        // waves that also carry ring items run at raised priority so the
+        // barrier that ends the phase is reached sooner
+        const int wv = tid >> 6;
+        // (3D only: measured 5 % faster at 256^3; the single-plane 2D blocks
+        // gain nothing)
+        const bool ring1 = ND == 3 && (wv < (2 * BX + 63) / 64 || wv >= (NT - 2 * BY) / 64);
+        const bool ring2 = ND == 3 && (wv < (BX + 63) / 64 || wv >= (NT - BY) / 64);
+        if (ring1) __builtin_amdgcn_s_setprio(2);
         if constexpr (LIM == LIM_THETA) {
             slope_x(ty, tx);
             if constexpr (ND >= 2) slope_y(ty, tx);
@@ -525,7 +533,9 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             const int e = tid - (NT - 2 * BY);
             if (e >= 0) slope_x(e >> 1, (e & 1) ? BX : -1);
         }
+        if (ring1) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
+        if (ring2) __builtin_amdgcn_s_setprio(2);
 
         // ---- phase 2: x and y face fluxes, each face once ----
         // own faces (the low x and y face of the own cell), the z face
@@ -572,6 +582,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             const int e = tid - (NT - BY);
             if (e >= 0) face_x(e, BX);
         }
+        if (ring2) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
 
         // ---- phase 3: divergence, source, Runge-Kutta combination ----
