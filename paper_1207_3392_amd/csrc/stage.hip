@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         }
         if (ring1) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
-        if (ring2) __builtin_amdgcn_s_setprio(2);
+        if (ring2) __builtin_amdgcn_s_setprio(3);
 
         // ---- phase 2: x and y face fluxes, each face once ----
         // own faces (the low x and y face of the own cell), the z face
