@@ -12,8 +12,8 @@ resident in HBM before timing starts.
 
 Prints one JSON line.  Extra fields report the HLL run, a 512^3 patch, the
 512 batched tubes, 2D Kelvin-Helmholtz and 3D Rayleigh-Taylor with the plain
-and the learned limiter, the per-kernel roofline and the FP64 CPU oracle timed
-on a bounded sample.
+and the learned limiter, the two limiters compared at matched L1, the
+per-kernel roofline and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
-                                                   "rt_512_plain", "rt_512_learned"],
+                                                   "rt_512_plain", "rt_512_learned", "matched_l1"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -199,6 +199,36 @@ def time_rt(n=512, steps=10, learned=False):
     return {"zone_updates_per_s": n ** 3 * steps / wall, "ms_per_step": 1e3 * wall / steps}
 
 
+def matched_l1(cost_ratio_2d=None):
+    """The learned limiter against the plain one at matched L1: density L1 at
+    a ladder of N against a fine plain run restricted to each N (well-posed
+    Kelvin-Helmholtz with tanh shear layers at t = 1.5, Sod at t = 0.2), the
+    resolution the plain method needs for the learned limiter's L1 (log-log
+    interpolation) and, from the measured cost per zone-update of the two
+    paths at 2048^2, the wall-time ratio learned / plain at equal L1 for a run
+    whose cost scales as N^(d+1)."""
+    from paper_1207_3392_amd import limiter, limiter_study as ls
+    from paper_1207_3392_amd import workloads as wl
+
+    P = limiter.trained_params()
+    quiet = lambda *a, **k: None  # noqa: E731
+    out = {}
+    for key, make, ns, nref, T, d in (
+            ("kelvin_helmholtz_t1.5", lambda n: wl.kelvin_helmholtz(n, seed=ls.HELD_OUT_SEED, width=ls.EVAL_WIDTH,
+                                                                    random_amp=0.0), (128, 256, 512), 2048, 1.5, 2),
+            ("sod_t0.2", lambda n: wl.sod(n, theta=2.0, cfl=0.4, t_end=0.2), (128, 256, 512, 1024), 16384, 0.2, 1)):
+        r = ls.ladder(key, make, ns, nref, (T,), P, log=quiet)
+        gains = [m["resolution_gain"] for m in r["matched"]]
+        entry = {"n": list(ns), "n_reference": nref,
+                 "l1_plain": [x["l1_plain"] for x in r["rows"]], "l1_learned": [x["l1_learned"] for x in r["rows"]],
+                 "resolution_gain": gains}
+        if cost_ratio_2d is not None:
+            entry["time_ratio_learned_over_plain"] = [cost_ratio_2d / g ** (d + 1) for g in gains]
+        out[key] = entry
+    out["cost_per_zone_update_learned_over_plain_2d"] = cost_ratio_2d
+    return out
+
+
 def roofline(res):
     ncell = res["ncell"]
     # dominant kernel: the stage with the larger mean duration
@@ -255,7 +285,7 @@ def main():
     if args.only:
         run = {"batched_tubes": time_batch, "kh_2048_plain": lambda: time_kh(learned=False),
                "kh_2048_learned": lambda: time_kh(learned=True), "rt_512_plain": lambda: time_rt(learned=False),
-               "rt_512_learned": lambda: time_rt(learned=True)}[args.only]
+               "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -292,6 +322,9 @@ def main():
         guarded("kh_2048_learned", lambda: time_kh(learned=True))
         guarded("rt_512_plain", lambda: time_rt(learned=False))
         guarded("rt_512_learned", lambda: time_rt(learned=True))
+        kp, kl = extra.get("kh_2048_plain", {}), extra.get("kh_2048_learned", {})
+        ratio = kl["ms_per_step"] / kp["ms_per_step"] if "ms_per_step" in kp and "ms_per_step" in kl else None
+        guarded("matched_l1", lambda: matched_l1(ratio))
     out = {
         "metric": METRIC,
         "value": main_res["zone_updates_per_s"],
