@@ -205,8 +205,8 @@ def matched_l1(cost_ratio_2d=None):
     Kelvin-Helmholtz with tanh shear layers at t = 1.5, Sod at t = 0.2), the
     resolution the plain method needs for the learned limiter's L1 (log-log
     interpolation) and, from the measured cost per zone-update of the two
-    paths at 2048^2, the wall-time ratio learned / plain at equal L1 for a run
-    whose cost scales as N^(d+1)."""
+    paths at 2048^2, the wall-time ratio learned / plain at equal L1 for the 2D
+    problem, whose cost scales as N^3."""
     from paper_1207_3392_amd import limiter, limiter_study as ls
     from paper_1207_3392_amd import workloads as wl
 
@@ -222,7 +222,7 @@ def matched_l1(cost_ratio_2d=None):
         entry = {"n": list(ns), "n_reference": nref,
                  "l1_plain": [x["l1_plain"] for x in r["rows"]], "l1_learned": [x["l1_learned"] for x in r["rows"]],
                  "resolution_gain": gains}
-        if cost_ratio_2d is not None:
+        if cost_ratio_2d is not None and d == 2:
             entry["time_ratio_learned_over_plain"] = [cost_ratio_2d / g ** (d + 1) for g in gains]
         out[key] = entry
     out["cost_per_zone_update_learned_over_plain_2d"] = cost_ratio_2d

@@ -65,3 +65,21 @@ def test_init_rejects_small_workspace_without_touching_the_device():
     fake = ctypes.c_void_p(0x1000)
     assert L.hy_init_patch(ctypes.byref(d), fake, 16, None, ctypes.byref(h)) == hydro.HY_ENOMEM
     assert L.hy_init_patch(ctypes.byref(d), None, 1 << 20, None, ctypes.byref(h)) == hydro.HY_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No CPU fallback: a missing libhydro.so is an error, not a silent path."""
+    monkeypatch.setattr(hydro, "_lib", None)
+    monkeypatch.setattr(hydro, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libhydro.so"))
+    with pytest.raises(RuntimeError):
+        hydro.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
