@@ -130,8 +130,8 @@ hy_status hy_get_time(hy_patch *p, double *t_out);
 hy_status hy_conserved_totals(hy_patch *p, double out[5]);
 
 /* Learned limiter weights: n = 1249 FP32 values, W1[32][4], b1[32],
- * W2[32][32], b2[32], w3[32], b3.  Copied to the device (matrix weights in
- * bfloat16).  Required before stepping with HY_LIM_LEARNED.  Synchronising. */
+ * W2[32][32], b2[32], w3[32], b3.  Copied to the device (W1, W2 and w3 in
+ * bfloat16, biases in FP32).  Required before stepping with HY_LIM_LEARNED.  Synchronising. */
 hy_status hy_set_mlp(hy_patch *p, const float *weights, size_t n);
 
 /* Per-kernel timing with HIP events on the patch stream (off by default).

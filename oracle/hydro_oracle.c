@@ -250,8 +250,8 @@ static double to_bf16(double x)
 
 /* Parameters: W1[32][4], b1[32], W2[32][32], b2[32], w3[32], b3.
  * h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3.
- * With bf16 set, x, W1, h1 and W2 are rounded to bfloat16 (the operands of
- * the two matrix layers); biases, w3, b3 and all arithmetic stay double. */
+ * With bf16 set, the operands of all three layers are rounded to bfloat16
+ * (x, W1, h1, W2, h2, w3); biases, b3 and all arithmetic stay double. */
 double orc_mlp_forward(const double *P, int bf16, const double *x)
 {
     const double *W1 = P, *b1 = W1 + ORC_MLP_H * ORC_MLP_IN, *W2 = b1 + ORC_MLP_H;
@@ -276,9 +276,10 @@ double orc_mlp_forward(const double *P, int bf16, const double *x)
         }
         s += b2[j];
         h2[j] = s > 0.0 ? s : 0.0;
+        if (bf16) h2[j] = to_bf16(h2[j]);
     }
     double y = b3[0];
-    for (int k = 0; k < ORC_MLP_H; ++k) y += w3[k] * h2[k];
+    for (int k = 0; k < ORC_MLP_H; ++k) y += (bf16 ? to_bf16(w3[k]) : w3[k]) * h2[k];
     return y;
 }
 

@@ -67,6 +67,8 @@ def forward(P, X, bf16: bool = False):
         h1 = bf16_round(h1)
     z2 = h1 @ W2.T + b2
     h2 = np.maximum(z2, 0.0)
+    if bf16:
+        h2, w3 = bf16_round(h2), bf16_round(w3)
     y = h2 @ w3 + b3[0]
     return y, (X, W1, W2, w3, z1, h1, z2, h2)
 

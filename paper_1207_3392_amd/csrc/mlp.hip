@@ -8,9 +8,8 @@
 // differences D-, D+ disagree in sign), so the result never leaves the region
 // that contains minmod and the monotonized-central limiter.
 //
-// Matrix layers run as bf16 MFMA (v_mfma_f32_16x16x16_bf16) with FP32
-// accumulation; biases enter as the accumulator input; layer 3 (32 -> 1) is an
-// FP32 dot product.  One wave evaluates 64 stencils at a time, one per lane,
+// All three layers run as bf16 MFMA with FP32 accumulation; biases enter as
+// the accumulator input.  One wave evaluates 64 stencils at a time, one per lane,
 // in the transposed orientation H^T = W X^T so that each layer's output
 // registers are already the next layer's operand layout:
 //   lane l = (grp = l / 16, col = l % 16) owns stencil (batch grp, column col);
@@ -18,7 +17,12 @@
 //            B = the lanes' own bf16 inputs (K-group = grp), C = b1;
 //   layer 2: A = W2 (one K = 32 block per output block), B = relu(H1) as
 //            bf16, C = b2;
-//   layer 3: per-lane partial dot products, summed over the four lane groups.
+//   layer 3: A = w3 in every row (K = 32), B = relu(H2) as bf16, C = b3, so
+//            every row of the result holds the outputs and each lane reads
+//            its own stencil's value without a cross-lane reduction.
+// The elementwise work between the layers (ReLU and bf16 packing) bounds the
+// kernel, so the third layer is put on the matrix cores rather than the
+// vector ALU.
 #include "hy_internal.h"
 #include "hy_mlp.h"
 
@@ -100,13 +104,14 @@ __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__flo
 // Its K order is permuted so that B is exactly what layer 1 left in the lane:
 // K index 8 grp + jj stands for hidden unit hk(grp, jj) = 4 grp + jj (jj < 4)
 // or 16 + 4 grp + jj - 4 (jj >= 4), the units of both layer-1 output blocks.
+// Layer 3 uses the same K permutation, with w3 replicated over the 16 rows.
 struct MlpRegs {
     s4 a1[4][2];  // layer-1 weights placed in K-group g, per output block
     f4 c1[2];     // b1 as accumulator input
     b8 a2[2];     // layer-2 weights [out block], K permuted as above
     f4 c2[2];     // b2 as accumulator input
-    f4 w3[2];
-    float b3;
+    b8 a3;        // w3, K permuted as above, the same in every row
+    f4 c3;        // b3 as accumulator input
 };
 
 __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, MlpRegs &R)
@@ -121,13 +126,16 @@ __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, 
         for (int j = 0; j < 4; ++j) {
             R.c1[mb][j] = m->b1[16 * mb + 4 * grp + j];
             R.c2[mb][j] = m->b2[16 * mb + 4 * grp + j];
-            R.w3[mb][j] = m->w3[16 * mb + 4 * grp + j];
         }
         const float *w2r = m->w2[16 * mb + col];
         R.a2[mb] = bf8(bf4(w2r[4 * grp], w2r[4 * grp + 1], w2r[4 * grp + 2], w2r[4 * grp + 3]),
                        bf4(w2r[16 + 4 * grp], w2r[17 + 4 * grp], w2r[18 + 4 * grp], w2r[19 + 4 * grp]));
     }
-    R.b3 = m->b3;
+    const float *w3 = m->w3;
+    R.a3 = bf8(bf4(w3[4 * grp], w3[4 * grp + 1], w3[4 * grp + 2], w3[4 * grp + 3]),
+               bf4(w3[16 + 4 * grp], w3[17 + 4 * grp], w3[18 + 4 * grp], w3[19 + 4 * grp]));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) R.c3[j] = m->b3;
 }
 
 // Network output for the lane's own input x[0..3] (all 64 lanes must be active,
@@ -146,19 +154,16 @@ __device__ __forceinline__ float mlp_wave(const float (&x)[4], const MlpRegs &R,
             h1[mb] = bf4_relu(d[0], d[1], d[2], d[3]);
         }
         const b8 hb = bf8(h1[0], h1[1]);
-        float p = 0.f;
+        s4 h2[2];
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a2[mb], hb, R.c2[mb], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) p += R.w3[mb][j] * relu(d[j]);
+            h2[mb] = bf4_relu(d[0], d[1], d[2], d[3]);
         }
-        p += __shfl_xor(p, 16, 64);
-        p += __shfl_xor(p, 32, 64);
-        part[g] = p;
+        const f4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a3, bf8(h2[0], h2[1]), R.c3, 0, 0, 0);
+        part[g] = y[0];
     }
-    const float y = grp == 0 ? part[0] : (grp == 1 ? part[1] : (grp == 2 ? part[2] : part[3]));
-    return y + R.b3;
+    return grp == 0 ? part[0] : (grp == 1 ? part[1] : (grp == 2 ? part[2] : part[3]));
 }
 
 // sigma from the 5-cell stencil w[0..4] (centre w[2])

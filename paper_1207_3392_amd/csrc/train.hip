@@ -154,6 +154,10 @@ __device__ __forceinline__ s4 frag(const unsigned short *base, int si, int sj, i
     return r;
 }
 
+// x rounded to the nearest bfloat16 (ties to even), as a float: the third
+// layer's operands, which the inference kernel feeds to the matrix cores
+__device__ __forceinline__ float bfr(float x) { return __bfloat162float(__float2bfloat16(x)); }
+
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
 
 // Per-wave LDS: X (64 x 16), H1 (64 x 32), dZ (64 x 32), all bf16.
@@ -251,7 +255,7 @@ __global__ void __launch_bounds__(64 * TW) k_train_grad(const MlpDevice *__restr
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     z2[mb][nb][jj] = c[jj];
-                    ypart[mb][jj] += m->w3[16 * nb + col] * fmaxf(c[jj], 0.f);
+                    ypart[mb][jj] += bfr(m->w3[16 * nb + col]) * bfr(fmaxf(c[jj], 0.f));
                 }
             }
         }
@@ -296,8 +300,8 @@ __global__ void __launch_bounds__(64 * TW) k_train_grad(const MlpDevice *__restr
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
                     const float zz = z2[mb][nb][jj];
-                    gw3[nb] += dyr * fmaxf(zz, 0.f);
-                    const float dz = zz > 0.f ? dyr * m->w3[16 * nb + col] : 0.f;
+                    gw3[nb] += dyr * bfr(fmaxf(zz, 0.f));
+                    const float dz = zz > 0.f ? dyr * bfr(m->w3[16 * nb + col]) : 0.f;
                     gb2[nb] += dz;
                     L.dZ[mrow * H + 16 * nb + col] = bfu(dz);
                 }
