@@ -83,3 +83,25 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_roofline_fields():
+    """The stage kernels are ALU-bound: the roofline object reports the FP32
+    vector peak with frac = achieved / peak, and the HBM fraction beside it;
+    measured traffic is attached only for the configuration it was taken on."""
+    import sys
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    res = {"ncell": 256 ** 3, "stage_ms": [0.27, 0.30], "solver": "hllc", "kernel": "other"}
+    r = bench.roofline(res)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3 and r["kernel"] == "stage 2"
+    assert r["algorithmic_flops_per_launch"] == 524 * 256 ** 3
+    assert abs(r["achieved"] - 524 * 256 ** 3 / 0.30e-3 / 1e12) < 0.01
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    assert r["traffic"] is None  # another kernel configuration
+    h = r["hbm"]
+    assert h["peak"] == 8000.0 and abs(h["achieved"] - 60 * 256 ** 3 / 0.30e-3 / 1e9) < 0.1
+    assert abs(h["frac"] - h["achieved"] / h["peak"]) < 1e-3
+    assert bench.roofline(dict(res, solver="hll"))["algorithmic_flops_per_launch"] == 494 * 256 ** 3
