@@ -24,11 +24,23 @@ struct MlpDevice {
 
 void mlp_pack(const float *flat, MlpDevice *out);
 
+// The network as the slope kernel's lanes hold it: for each of the 64 lanes of
+// a wave, the 48 registers of its matrix operands (bf16 weights laid out in the
+// lane's MFMA positions) and accumulator inputs (FP32 biases), built once per
+// weight upload so the slope kernel loads them instead of converting the FP32
+// weights in every workgroup.
+struct MlpImage {
+    uint4 lane[64][12];
+};
+
+// Builds *img from *mlp on the device (one wave).
+hipError_t launch_mlp_image(const MlpDevice *mlp, MlpImage *img, hipStream_t s);
+
 // Slopes of every (dimension q, variable v, interior cell) of the FP32 state u
 // (variable stride vstride) from the network, clamped to the TVD region;
 // written to slopes[(q * nv + v) * svs + cell].
 hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[3], int64_t vstride, int64_t svs,
-                                 int ndim, float gm1, const int bc[3][2], const MlpDevice *mlp, hipStream_t s);
+                                 int ndim, float gm1, const int bc[3][2], const MlpImage *img, hipStream_t s);
 
 // Network alone on a batch of normalised inputs x (batch, 4) -> y (batch).
 hipError_t launch_mlp_forward(const MlpDevice *mlp, const float *x, float *y, int64_t batch, hipStream_t s);

@@ -46,6 +46,7 @@ struct hy_patch {
     void *B = nullptr;  // U^(1)
     float *slopes = nullptr;
     hy::MlpDevice *mlp = nullptr;
+    hy::MlpImage *mlpimg = nullptr;
     bool mlp_set = false;
     hipStream_t stream = nullptr;
     int parity = 0;
@@ -97,7 +98,7 @@ hy_status check_desc(const hy_patch_desc *d)
 }
 
 struct Layout {
-    size_t ctl, partials, A, B, slopes, mlp, total;
+    size_t ctl, partials, A, B, slopes, mlp, mlpimg, total;
     int64_t vstride;
 };
 
@@ -114,6 +115,8 @@ Layout layout(const hy_patch_desc &d)
     o = align_up(o + sizeof(double) * 5 * hy::TOTALS_BLOCKS, 256);
     L.mlp = o;
     o = align_up(o + sizeof(hy::MlpDevice), 256);
+    L.mlpimg = o;
+    o = align_up(o + sizeof(hy::MlpImage), 256);
     L.A = o;
     o = align_up(o + es * nv * (size_t)L.vstride, 256);
     L.B = o;
@@ -163,7 +166,7 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
     if (p->d.limiter == HY_LIM_LEARNED) {
         const T *uin = (const T *)(stage == 1 ? p->A : p->B);
         e = hy::launch_learned_slopes((const float *)uin, p->slopes, p->d.n, p->vstride, p->vstride, p->d.ndim,
-                                      (float)(p->d.gamma - 1.0), p->d.bc, p->mlp, p->stream);
+                                      (float)(p->d.gamma - 1.0), p->d.bc, p->mlpimg, p->stream);
         if (e != hipSuccess) return e;
     }
     const int k = stage - 1;
@@ -287,6 +290,7 @@ hy_status hy_init_patch(const hy_patch_desc *desc, void *dev_workspace, size_t b
     p->ctl = (hy::DevCtl *)(base + L.ctl);
     p->partials = (double *)(base + L.partials);
     p->mlp = (hy::MlpDevice *)(base + L.mlp);
+    p->mlpimg = (hy::MlpImage *)(base + L.mlpimg);
     p->A = base + L.A;
     p->B = base + L.B;
     p->slopes = desc->limiter == HY_LIM_LEARNED ? (float *)(base + L.slopes) : nullptr;
@@ -441,6 +445,7 @@ hy_status hy_set_mlp(hy_patch *p, const float *w, size_t n)
     hy::MlpDevice host;
     hy::mlp_pack(w, &host);
     hipError_t e = hipMemcpyAsync(p->mlp, &host, sizeof(host), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hy::launch_mlp_image(p->mlp, p->mlpimg, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(e, "weight upload");
     p->mlp_set = true;
@@ -893,7 +898,7 @@ hy_status hy_lim_slopes(hy_patch *p, float *out_dev)
     if (!p || !out_dev) return fail(HY_EINVAL, "null argument");
     if (p->d.limiter != HY_LIM_LEARNED || !p->mlp_set) return fail(HY_EINVAL, "patch has no learned limiter weights");
     hipError_t e = hy::launch_learned_slopes((const float *)p->A, out_dev, p->d.n, p->vstride, p->ncell, p->d.ndim,
-                                             (float)(p->d.gamma - 1.0), p->d.bc, p->mlp, p->stream);
+                                             (float)(p->d.gamma - 1.0), p->d.bc, p->mlpimg, p->stream);
     if (e != hipSuccess) return hip_fail(e, "slope kernel");
     return HY_OK;
 }

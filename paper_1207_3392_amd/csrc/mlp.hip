@@ -138,6 +138,8 @@ __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, 
     for (int j = 0; j < 4; ++j) R.c3[j] = m->b3;
 }
 
+static_assert(sizeof(MlpRegs) == sizeof(uint4) * 12, "lane image layout");
+
 // Network output for the lane's own input x[0..3] (all 64 lanes must be active,
 // and every lane's input finite: 0 x inf in a zero block of an operand would
 // spread a NaN to the other lanes of the same column).
@@ -232,7 +234,7 @@ struct LsTile {
 template <int ND, int Q>
 __global__ void __launch_bounds__(ND == 1 ? 64 : 256)
     k_learned_slopes(const float *__restrict__ u, float *__restrict__ slopes, int nx, int ny, int nz, int64_t vs,
-                     int64_t svs, float gm1, Bc bc, const MlpDevice *__restrict__ mlp)
+                     int64_t svs, float gm1, Bc bc, const MlpImage *__restrict__ img)
 {
     using G = LsTile<ND, Q>;
     constexpr int NP = G::NP, R = G::R, NT = 64 * G::NW, RA = G::RA, CA = G::CA;
@@ -244,6 +246,8 @@ __global__ void __launch_bounds__(ND == 1 ? 64 : 256)
     const int cf = blockIdx.z;      // fixed coordinate (z for Q = 1, y for Q = 2)
     const int nq = Q == 0 ? nx : (Q == 1 ? ny : nz);
     const int nrow = Q == 0 ? ny * nz : nq;
+    MlpRegs M;
+    __builtin_memcpy(&M, &img->lane[lane][0], sizeof(M));
 
     for (int i = tid; i < RA * CA; i += NT) {
         const int r = i / CA, c = i % CA;
@@ -277,8 +281,6 @@ __global__ void __launch_bounds__(ND == 1 ? 64 : 256)
 #pragma unroll
         for (int v = 0; v < NP; ++v) sW[v][r][c] = w[v];
     }
-    MlpRegs M;
-    load_regs(mlp, grp, col, M);
     __syncthreads();
 
     const int x = x0 + lane;
@@ -301,14 +303,22 @@ __global__ void __launch_bounds__(ND == 1 ? 64 : 256)
 
 template <int ND, int Q>
 void ls_launch(const float *u, float *slopes, int nx, int ny, int nz, int64_t vs, int64_t svs, float gm1, const Bc &b,
-               const MlpDevice *mlp, hipStream_t s)
+               const MlpImage *img, hipStream_t s)
 {
     using G = LsTile<ND, Q>;
     const unsigned gx = (unsigned)((nx + 63) / 64);
     const unsigned gy = (unsigned)(Q == 0 ? (ny * nz + G::R - 1) / G::R : ((Q == 1 ? ny : nz) + G::R - 1) / G::R);
     const unsigned gz = (unsigned)(Q == 0 ? 1 : (Q == 1 ? nz : ny));
     hipLaunchKernelGGL((k_learned_slopes<ND, Q>), dim3(gx, gy, gz), dim3(64 * G::NW), 0, s, u, slopes, nx, ny, nz, vs,
-                       svs, gm1, b, mlp);
+                       svs, gm1, b, img);
+}
+
+__global__ void __launch_bounds__(64) k_mlp_image(const MlpDevice *__restrict__ mlp, MlpImage *__restrict__ img)
+{
+    const int lane = threadIdx.x, grp = lane >> 4, col = lane & 15;
+    MlpRegs R;
+    load_regs(mlp, grp, col, R);
+    __builtin_memcpy(&img->lane[lane][0], &R, sizeof(R));
 }
 
 __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDevice *__restrict__ mlp, const float *__restrict__ x,
@@ -327,7 +337,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDevice *__restrict
 }  // namespace
 
 hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[3], int64_t vstride, int64_t svs,
-                                 int ndim, float gm1, const int bc[3][2], const MlpDevice *mlp, hipStream_t s)
+                                 int ndim, float gm1, const int bc[3][2], const MlpImage *img, hipStream_t s)
 {
     Bc b;
     for (int q = 0; q < 3; ++q) {
@@ -336,17 +346,23 @@ hipError_t launch_learned_slopes(const float *u, float *slopes, const int64_t n[
     }
     const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
     switch (ndim) {
-    case 1: ls_launch<1, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s); break;
+    case 1: ls_launch<1, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, img, s); break;
     case 2:
-        ls_launch<2, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
-        ls_launch<2, 1>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        ls_launch<2, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, img, s);
+        ls_launch<2, 1>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, img, s);
         break;
     default:
-        ls_launch<3, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
-        ls_launch<3, 1>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
-        ls_launch<3, 2>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, mlp, s);
+        ls_launch<3, 0>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, img, s);
+        ls_launch<3, 1>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, img, s);
+        ls_launch<3, 2>(u, slopes, nx, ny, nz, vstride, svs, gm1, b, img, s);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_image(const MlpDevice *mlp, MlpImage *img, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_image, dim3(1), dim3(64), 0, s, mlp, img);
     return hipGetLastError();
 }
 
