@@ -86,6 +86,8 @@ def train(x, t, steps: int = 3000, batch: int = 65536, lr: float = 1e-3, seed: i
     gen = torch.Generator(device=x.device)
     gen.manual_seed(seed)
     n = x.shape[0]
+    if n >= 2 ** 31:
+        raise ValueError(f"{n} samples: minibatch indices are int32, at most 2^31 - 1 samples")
     losses = []
     for k in range(steps):
         idx = torch.randint(0, n, (batch,), device=x.device, dtype=torch.int32, generator=gen)

@@ -38,15 +38,18 @@ HELD_OUT_SEED = 4242
 # training
 
 
-def training_set(n_fine: int, runs, times, cfl: float = 0.4):
+def training_set(n_fine: int, runs, times, cfl: float = 0.4, log=None):
     """Samples (x, t) on the device from fine KH runs, one per (seed, width)."""
     import torch
 
     xs, ts = [], []
     for seed, width in runs:
+        t0 = time.perf_counter()
         x, t = limiter.fine_samples(n_fine, times=times, seed=seed, cfl=cfl, width=width)
         xs.append(x)
         ts.append(t)
+        if log:
+            log(f"run seed {seed} width {width}: {x.shape[0]} samples at {n_fine}^2 ({time.perf_counter() - t0:.1f} s)")
     return torch.cat(xs), torch.cat(ts)
 
 
@@ -101,12 +104,12 @@ TRAIN_RUNS = ((1207, 0.0), (1208, 0.0), (1209, 0.0), (1207, 0.01), (1208, 0.05))
 EVAL_WIDTH = 0.025
 
 
-def train_limiter(n_fine: int = 2048, runs=TRAIN_RUNS, times=(0.25, 0.5, 0.75, 1.0),
+def train_limiter(n_fine: int = 8192, runs=TRAIN_RUNS, times=(0.25, 0.5, 1.0),
                   steps: int = 40000, batch: int = 65536, lr: float = 1e-3, log=print):
     """Runs are (seed, shear-layer half-width) pairs; the held-out validation
     run is the sharp setup with another seed."""
     t0 = time.perf_counter()
-    x, t = training_set(n_fine, runs, times)
+    x, t = training_set(n_fine, runs, times, log=log)
     x, t = limiter.augment(x, t)
     log(f"training samples: {x.shape[0]} from {len(runs)} runs at {n_fine}^2 ({time.perf_counter() - t0:.1f} s)")
     t1 = time.perf_counter()
@@ -114,7 +117,7 @@ def train_limiter(n_fine: int = 2048, runs=TRAIN_RUNS, times=(0.25, 0.5, 0.75, 1
                                    cosine=True)
     log(f"trained {steps} steps in {time.perf_counter() - t1:.1f} s; loss {losses[0][1]:.4g} -> {losses[-1][1]:.4g}")
     del x, t
-    xv, tv = training_set(n_fine, ((HELD_OUT_SEED, 0.0),), times)
+    xv, tv = training_set(n_fine, ((HELD_OUT_SEED, 0.0),), times, log=log)
     val = a_priori(params, xv, tv)
     log(f"held-out seed {HELD_OUT_SEED}: " + json.dumps(val))
     info = {"n_fine": n_fine, "runs": [list(r) for r in runs], "times": list(times), "steps": steps,
@@ -221,10 +224,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--n-fine", type=int, default=2048)
+    t.add_argument("--n-fine", type=int, default=8192)
     t.add_argument("--runs", default=",".join(f"{s}:{w}" for s, w in TRAIN_RUNS),
                    help="seed:width pairs of the training runs")
-    t.add_argument("--times", default="0.25,0.5,0.75,1.0")
+    t.add_argument("--times", default="0.25,0.5,1.0")
     t.add_argument("--steps", type=int, default=40000)
     t.add_argument("--batch", type=int, default=65536)
     t.add_argument("--lr", type=float, default=1e-3)
