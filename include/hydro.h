@@ -144,6 +144,34 @@ hy_status hy_kernel_times(hy_patch *p, double ms[2], int64_t launches[2]);
 /* Name of the stage kernel configuration in use (for profiles). */
 hy_status hy_kernel_config(hy_patch *p, char *buf, size_t len);
 
+/* Launch shape of the stage kernels: a workgroup of bx x by threads owns a
+ * bx x by tile of the x-y plane and marches along z over zchunk planes (3D;
+ * zchunk = 1 otherwise).  The launch shape changes no result: every shape
+ * computes the same cells with the same arithmetic.  Supported tiles:
+ * 64x8, 64x4, 32x8 and (FP32) 32x16 in 2D and 3D, 64x1 in 1D; a patch starts
+ * with a shape picked from its size (64x8, at least ~512 workgroups, at most
+ * 64 planes per chunk). */
+typedef struct {
+    int bx, by, zchunk;
+} hy_launch_cfg;
+hy_status hy_get_launch_cfg(hy_patch *p, hy_launch_cfg *out);
+/* HY_EINVAL for an unsupported tile or a chunk outside 1..n_z (1 below 3D). */
+hy_status hy_set_launch_cfg(hy_patch *p, const hy_launch_cfg *cfg);
+/* Autotuner: times every supported tile (and in 3D the z chunks 8, 16, 32,
+ * 64, 128 that fit, plus the starting one) over reps trials of both
+ * Runge-Kutta stage kernels on the patch's current state with dt = 0 (each
+ * stage reading U^n and writing the scratch stage state), on the patch
+ * stream with HIP events (after a few settling trials of the starting
+ * shape; two passes, each candidate's faster one counting), and keeps the
+ * fastest shape unless the starting one is within 2 %; best and best_ms
+ * (mean milliseconds per trial) may be NULL.  U^n, the time and the CFL
+ * rate of U^n are unchanged; the scratch stage state is overwritten.  A
+ * learned-limiter patch needs its weights (its slopes kernel has a fixed
+ * shape and is not part of the trial).  Different z chunks may round
+ * differently in the last place (the z faces at chunk starts are formed by
+ * the chunk's entry code); tiles never change a result.  Synchronising. */
+hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, double *best_ms);
+
 hy_status hy_destroy(hy_patch *p);
 
 const char *hy_last_error(void);
@@ -168,6 +196,18 @@ hy_status hy_batch_init(const hy_patch_desc *descs, int count, void *dev_workspa
 hy_status hy_batch_set_state(hy_batch *b, int i, int kind, const double *host_soa);
 /* Advance every tube from t = 0 to t_end; asynchronous (one graph launch). */
 hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver);
+/* Workgroup size of the batched kernel: 256, 512 or 1024 threads (a tube's
+ * cells are dealt round-robin, 24, 12 or 6 register slots per thread); the
+ * default is 1024.  The size changes no result.  HY_EINVAL otherwise. */
+hy_status hy_batch_set_block(hy_batch *b, int threads);
+hy_status hy_batch_get_block(hy_batch *b, int *threads);
+/* Autotuner: runs the whole batch from its current state to t_end with each
+ * workgroup size (the queue order and every tube's dt loop as in
+ * hy_batch_run_to), times each launch with HIP events, keeps the fastest
+ * (the current size unless another is at least 2 % faster) and restores
+ * the state and the per-tube status as they were before; best
+ * and best_ms may be NULL.  Synchronising. */
+hy_status hy_batch_autotune(hy_batch *b, double t_end, double cfl, int solver, int *best_threads, double *best_ms);
 /* Milliseconds of the last hy_batch_run_to launch (HIP events); synchronising. */
 hy_status hy_batch_last_ms(hy_batch *b, double *ms);
 /* State of tube i; synchronising; HY_ESTATE if that tube met a bad state. */

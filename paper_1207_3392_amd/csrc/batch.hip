@@ -19,7 +19,6 @@
 namespace hy {
 namespace {
 
-constexpr int BT = 1024;  // threads per workgroup
 
 __device__ __forceinline__ float rcpf_(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -87,6 +86,8 @@ __global__ void k_batch_reset(BatchCtl *ctl)
     ctl->next = 0u;
 }
 
+// BT threads per workgroup, BATCH_NMAX / BT cells per thread
+template <int BT>
 __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes, const int *__restrict__ order,
                                               float *__restrict__ U, int64_t ntot, BatchCtl *ctl,
                                               TubeStatus *__restrict__ status, int ntubes, int nmax)
@@ -257,27 +258,59 @@ hipError_t launch_batch_reset(BatchCtl *ctl, hipStream_t s)
     return hipGetLastError();
 }
 
+namespace {
+const void *batch_kernel(int bt)
+{
+    switch (bt) {
+    case 256: return (const void *)k_batch<256>;
+    case 512: return (const void *)k_batch<512>;
+    default: return (const void *)k_batch<1024>;
+    }
+}
+}  // namespace
+
+bool batch_bt_supported(int bt) { return bt == 256 || bt == 512 || bt == 1024; }
+
 hipError_t prepare_batch(int nmax)
 {
     // dynamic LDS above the 64 KiB default must be allowed explicitly
-    return hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)batch_lds_bytes(nmax));
+    hipError_t e = hipSuccess;
+    for (int bt : {256, 512, 1024})
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(batch_kernel(bt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)batch_lds_bytes(nmax));
+    return e;
 }
 
 hipError_t launch_batch(const TubeDesc *tubes, const int *order, float *U, int64_t ntot, BatchCtl *ctl,
-                        TubeStatus *status, int ntubes, int nmax, int nblocks, hipStream_t s)
+                        TubeStatus *status, int ntubes, int nmax, int nblocks, int bt, hipStream_t s)
 {
     const size_t lds = batch_lds_bytes(nmax);
-    hipLaunchKernelGGL(k_batch, dim3(nblocks), dim3(BT), lds, s, tubes, order, U, ntot, ctl, status, ntubes, nmax);
+    switch (bt) {
+    case 256:
+        hipLaunchKernelGGL(k_batch<256>, dim3(nblocks), dim3(256), lds, s, tubes, order, U, ntot, ctl, status, ntubes,
+                           nmax);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_batch<512>, dim3(nblocks), dim3(512), lds, s, tubes, order, U, ntot, ctl, status, ntubes,
+                           nmax);
+        break;
+    default:
+        hipLaunchKernelGGL(k_batch<1024>, dim3(nblocks), dim3(1024), lds, s, tubes, order, U, ntot, ctl, status,
+                           ntubes, nmax);
+        break;
+    }
     return hipGetLastError();
 }
 
 size_t batch_lds_bytes(int nmax) { return sizeof(float) * (3 * (size_t)(nmax + 4) + 3 * (size_t)(nmax + 1)); }
 
-int batch_blocks_per_cu(int nmax)
+int batch_blocks_per_cu(int nmax, int bt)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, BT, batch_lds_bytes(nmax)) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel(bt), bt, batch_lds_bytes(nmax)) !=
+        hipSuccess)
+        return 1;
     return nb > 0 ? nb : 1;
 }
 

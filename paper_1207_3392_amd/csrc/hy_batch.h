@@ -6,7 +6,7 @@
 
 namespace hy {
 
-constexpr int BATCH_NMAX = 6144;  // cells per tube: 6 per thread of a 1024-thread workgroup, LDS-resident
+constexpr int BATCH_NMAX = 6144;  // cells per tube (LDS-resident); 6, 12 or 24 per thread
 
 struct TubeDesc {
     int n;
@@ -33,10 +33,12 @@ struct BatchCtl {
 };
 
 hipError_t launch_batch_reset(BatchCtl *ctl, hipStream_t s);
+// bt = threads per workgroup: 256, 512 or 1024 (BATCH_NMAX / bt cells per thread)
+bool batch_bt_supported(int bt);
 hipError_t launch_batch(const TubeDesc *tubes, const int *order, float *U, int64_t ntot, BatchCtl *ctl,
-                        TubeStatus *status, int ntubes, int nmax, int nblocks, hipStream_t s);
+                        TubeStatus *status, int ntubes, int nmax, int nblocks, int bt, hipStream_t s);
 size_t batch_lds_bytes(int nmax);
 hipError_t prepare_batch(int nmax);
-int batch_blocks_per_cu(int nmax);
+int batch_blocks_per_cu(int nmax, int bt);
 
 }  // namespace hy

@@ -224,6 +224,13 @@ hy_status compute_rate(hy_patch *p)
     return HY_OK;
 }
 
+// Plane tiles the stage kernels are instantiated for (BX x BY threads).
+bool tile_supported(const hy_patch_desc &d, int bx, int by)
+{
+    if (d.ndim == 1) return bx == 64 && by == 1;
+    return (bx == 64 && (by == 8 || by == 4)) || (bx == 32 && (by == 8 || (by == 16 && d.precision == 32)));
+}
+
 void pick_config(hy_patch *p)
 {
     // plane tile and z chunk: at least ~512 workgroups (two per CU) and at
@@ -234,8 +241,7 @@ void pick_config(hy_patch *p)
 
     if (const char *e = std::getenv("HY_TILE")) {  // "BXxBY", for tuning runs
         int bx = 0, by = 0;
-        if (d.ndim > 1 && std::sscanf(e, "%dx%d", &bx, &by) == 2 &&
-            ((bx == 64 && (by == 8 || by == 4)) || (bx == 32 && (by == 8 || (by == 16 && d.precision == 32))))) {
+        if (d.ndim > 1 && std::sscanf(e, "%dx%d", &bx, &by) == 2 && tile_supported(d, bx, by)) {
             p->cfg.bx = bx;
             p->cfg.by = by;
         }
@@ -498,6 +504,129 @@ hy_status hy_kernel_config(hy_patch *p, char *buf, size_t len)
     return HY_OK;
 }
 
+hy_status hy_get_launch_cfg(hy_patch *p, hy_launch_cfg *out)
+{
+    if (!p || !out) return fail(HY_EINVAL, "null argument");
+    out->bx = p->cfg.bx;
+    out->by = p->cfg.by;
+    out->zchunk = p->cfg.zchunk;
+    return HY_OK;
+}
+
+hy_status hy_set_launch_cfg(hy_patch *p, const hy_launch_cfg *cfg)
+{
+    if (!p || !cfg) return fail(HY_EINVAL, "null argument");
+    if (!tile_supported(p->d, cfg->bx, cfg->by)) return fail(HY_EINVAL, "unsupported plane tile");
+    const int64_t zmax = p->d.ndim == 3 ? p->d.n[2] : 1;
+    if (cfg->zchunk < 1 || cfg->zchunk > zmax || (p->d.ndim < 3 && cfg->zchunk != 1))
+        return fail(HY_EINVAL, "z chunk out of range");
+    p->cfg.bx = cfg->bx;
+    p->cfg.by = cfg->by;
+    p->cfg.zchunk = cfg->zchunk;
+    return HY_OK;
+}
+
+hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, double *best_ms)
+{
+    if (!p) return fail(HY_EINVAL, "null patch");
+    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "solver must be HY_HLL or HY_HLLC");
+    if (reps < 1 || reps > 1000) return fail(HY_EINVAL, "reps must be in 1..1000");
+    if (p->d.limiter == HY_LIM_LEARNED && !p->mlp_set) return fail(HY_EINVAL, "learned limiter without weights");
+    const hy_patch_desc &d = p->d;
+    // candidates: every supported tile, and for 3D the z chunks 8..128 that
+    // fit plus the default rule's own choice
+    std::vector<hy::LaunchCfg> cand;
+    const int tiles[4][2] = {{64, 8}, {64, 4}, {32, 8}, {32, 16}};
+    const hy::LaunchCfg dflt = p->cfg;
+    for (const auto &t : tiles) {
+        const int bx = d.ndim == 1 ? 64 : t[0], by = d.ndim == 1 ? 1 : t[1];
+        if (!tile_supported(d, bx, by)) continue;
+        if (d.ndim == 3) {
+            for (int zc : {8, 16, 32, 64, 128})
+                if (zc <= d.n[2]) cand.push_back({bx, by, zc});
+            if (dflt.zchunk != 8 && dflt.zchunk != 16 && dflt.zchunk != 32 && dflt.zchunk != 64 && dflt.zchunk != 128)
+                cand.push_back({bx, by, dflt.zchunk});
+        } else {
+            cand.push_back({bx, by, 1});
+        }
+        if (d.ndim == 1) break;
+    }
+    hipEvent_t ev[2];
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    if (d.limiter == HY_LIM_LEARNED)  // stage 1 reads the slopes of U^n
+        e = hy::launch_learned_slopes((const float *)p->A, p->slopes, d.n, p->vstride, p->vstride, d.ndim,
+                                      (float)(d.gamma - 1.0), d.bc, p->mlpimg, p->stream);
+    // One trial = the two stages of a step with dt = 0, both reading U^n and
+    // writing only the scratch state U^(1) (the second stage with U^n as its
+    // input and as its U^n term, so it does the second stage's full work);
+    // they touch only the control block's slots for the next parity, which
+    // the next step's first stage resets.  U^n, the time and the rate of U^n
+    // are left as they were.
+    auto launch = [&](const hy::LaunchCfg &c) {
+        p->cfg = c;
+        hipError_t r = hipSuccess;
+        for (int stage = 1; stage <= 2 && r == hipSuccess; ++stage) {
+            if (d.precision == 64) {
+                hy::StageArgs<double> a = stage_args<double>(p, stage, hy::DT_HOST, 0.0, 0.0, 0.0);
+                a.uin = a.u0 = (const double *)p->A;
+                a.uout = (double *)p->B;
+                r = hy::launch_stage<double>(d.ndim, solver, stage, d.limiter, c, a, p->stream);
+            } else {
+                hy::StageArgs<float> a = stage_args<float>(p, stage, hy::DT_HOST, 0.0, 0.0, 0.0);
+                a.uin = a.u0 = (const float *)p->A;
+                a.uout = (float *)p->B;
+                r = hy::launch_stage<float>(d.ndim, solver, stage, d.limiter, c, a, p->stream);
+            }
+        }
+        return r;
+    };
+    // the clocks settle on a few trials of the starting shape first; then two
+    // passes over the candidates, each candidate's faster pass counting, and
+    // the starting shape is kept unless another is at least 2 % faster
+    for (int r = 0; r < 4 * reps && e == hipSuccess; ++r) e = launch(dflt);
+    std::vector<double> tms(cand.size(), 1e300);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        for (size_t k = 0; k < cand.size(); ++k) {
+            if (e == hipSuccess) e = launch(cand[k]);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(ev[0], p->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(cand[k]);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess) break;
+            tms[k] = std::min(tms[k], (double)ms / reps);
+        }
+    }
+    double bms = 1e300, dms = 1e300;
+    hy::LaunchCfg bcfg = dflt;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        const auto &c = cand[k];
+        if (c.bx == dflt.bx && c.by == dflt.by && c.zchunk == dflt.zchunk) dms = tms[k];
+        if (tms[k] < bms) {
+            bms = tms[k];
+            bcfg = c;
+        }
+    }
+    if (dms < 1e300 && bms > 0.98 * dms) {
+        bcfg = dflt;
+        bms = dms;
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    p->cfg = e == hipSuccess ? bcfg : dflt;
+    if (e != hipSuccess) return hip_fail(e, "autotune launches");
+    if (best) {
+        best->bx = bcfg.bx;
+        best->by = bcfg.by;
+        best->zchunk = bcfg.zchunk;
+    }
+    if (best_ms) *best_ms = bms;
+    return HY_OK;
+}
+
 hy_status hy_destroy(hy_patch *p)
 {
     if (!p) return HY_OK;
@@ -540,6 +669,8 @@ struct hy_batch {
     hipStream_t capture = nullptr;
     hipGraphExec_t exec = nullptr;
     int nblocks = 0;
+    int bt = 1024;  // threads per workgroup of the batched kernel
+    int cus = 1;
     bool order_set = false;
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
@@ -658,7 +789,8 @@ hy_status hy_batch_init(const hy_patch_desc *descs, int count, void *dev_workspa
         delete b;
         return hip_fail(e, "batch init");
     }
-    b->nblocks = std::min(count, std::max(1, cus) * hy::batch_blocks_per_cu(b->nmax));
+    b->cus = std::max(1, cus);
+    b->nblocks = std::min(count, b->cus * hy::batch_blocks_per_cu(b->nmax, b->bt));
     *out = b;
     return HY_OK;
 }
@@ -701,6 +833,20 @@ hy_status hy_batch_set_state(hy_batch *b, int i, int kind, const double *host)
     return HY_OK;
 }
 
+// queue order: tubes by descending cost estimate (longest first)
+static hy_status batch_order(hy_batch *b)
+{
+    if (b->order_set) return HY_OK;
+    std::vector<int> ord(b->count);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
+    hipError_t e = hipMemcpyAsync(b->order, ord.data(), sizeof(int) * b->count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "queue order upload");
+    b->order_set = true;
+    return HY_OK;
+}
+
 static hy_status batch_capture(hy_batch *b)
 {
     hipError_t e = hipSuccess;
@@ -711,7 +857,7 @@ static hy_status batch_capture(hy_batch *b)
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     hipError_t e1 = hy::launch_batch_reset(b->ctl, b->capture);
     hipError_t e2 = hy::launch_batch(b->tubes, b->order, b->U, b->ntot, b->ctl, b->status, b->count, b->nmax,
-                                     b->nblocks, b->capture);
+                                     b->nblocks, b->bt, b->capture);
     e = hipStreamEndCapture(b->capture, &g);
     if (e1 != hipSuccess) e = e1;
     if (e2 != hipSuccess) e = e2;
@@ -727,16 +873,9 @@ hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver)
     if (!(t_end > 0.0) || !std::isfinite(t_end)) return fail(HY_EINVAL, "t_end must be finite and > 0");
     if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HY_EINVAL, "cfl must be finite and > 0");
     if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    hy_status st0 = batch_order(b);
+    if (st0 != HY_OK) return st0;
     hipError_t e = hipSuccess;
-    if (!b->order_set) {
-        std::vector<int> ord(b->count);
-        std::iota(ord.begin(), ord.end(), 0);
-        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
-        e = hipMemcpyAsync(b->order, ord.data(), sizeof(int) * b->count, hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) return hip_fail(e, "queue order upload");
-        b->order_set = true;
-    }
     if (!b->exec) {
         hy_status st = batch_capture(b);
         if (st != HY_OK) return st;
@@ -751,6 +890,89 @@ hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver)
     if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return HY_OK;
+}
+
+hy_status hy_batch_autotune(hy_batch *b, double t_end, double cfl, int solver, int *best_bt, double *best_ms)
+{
+    if (!b) return fail(HY_EINVAL, "null batch");
+    if (!(t_end > 0.0) || !std::isfinite(t_end)) return fail(HY_EINVAL, "t_end must be finite and > 0");
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HY_EINVAL, "cfl must be finite and > 0");
+    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    hy_status st = batch_order(b);
+    if (st != HY_OK) return st;
+    hy::BatchCtl c{};
+    c.solver = solver;
+    c.max_steps = kBatchMaxSteps;
+    c.t_end = t_end;
+    c.cfl = cfl;
+    const size_t ubytes = sizeof(float) * 3 * (size_t)b->ntot;
+    // the state is kept in the read-back scratch and restored before every
+    // trial and at the end
+    hipError_t e = hipMemcpyAsync(b->W, b->U, ubytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->ctl, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
+    double bms = 1e300;
+    int bbt = b->bt;
+    std::vector<int> bts;
+    bts.push_back(b->bt);  // the current size first, then the others
+    for (int bt : {1024, 512, 256})
+        if (bt != b->bt) bts.push_back(bt);
+    for (int bt : bts) {
+        const int nb = std::min(b->count, b->cus * hy::batch_blocks_per_cu(b->nmax, bt));
+        if (e == hipSuccess) e = hipMemcpyAsync(b->U, b->W, ubytes, hipMemcpyDeviceToDevice, b->stream);
+        if (e == hipSuccess) e = hy::launch_batch_reset(b->ctl, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
+        if (e == hipSuccess)
+            e = hy::launch_batch(b->tubes, b->order, b->U, b->ntot, b->ctl, b->status, b->count, b->nmax, nb, bt,
+                                 b->stream);
+        if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b->ev[1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev[0], b->ev[1]);
+        if (e != hipSuccess) break;
+        if (ms < (bt == b->bt ? bms : 0.98 * bms)) {  // the current size unless another is 2 % faster
+            bms = ms;
+            bbt = bt;
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->U, b->W, ubytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->status, 0, sizeof(hy::TubeStatus) * b->count, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    if (bbt != b->bt) {
+        b->bt = bbt;
+        b->nblocks = std::min(b->count, b->cus * hy::batch_blocks_per_cu(b->nmax, bbt));
+        if (b->exec) {  // recaptured with the new workgroup size at the next run
+            hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+    }
+    if (best_bt) *best_bt = bbt;
+    if (best_ms) *best_ms = bms;
+    return HY_OK;
+}
+
+hy_status hy_batch_set_block(hy_batch *b, int bt)
+{
+    if (!b) return fail(HY_EINVAL, "null batch");
+    if (!hy::batch_bt_supported(bt)) return fail(HY_EINVAL, "workgroup size must be 256, 512 or 1024");
+    if (bt != b->bt) {
+        b->bt = bt;
+        b->nblocks = std::min(b->count, b->cus * hy::batch_blocks_per_cu(b->nmax, bt));
+        if (b->exec) {
+            hipError_t e = hipStreamSynchronize(b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch sync");
+            hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+    }
+    return HY_OK;
+}
+
+hy_status hy_batch_get_block(hy_batch *b, int *bt)
+{
+    if (!b || !bt) return fail(HY_EINVAL, "null argument");
+    *bt = b->bt;
     return HY_OK;
 }
 

@@ -8,6 +8,7 @@ CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import Optional, Sequence
 
@@ -28,6 +29,10 @@ class HydroError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"hydro status {status}: {msg}")
         self.status = status
+
+
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("zchunk", ctypes.c_int)]
 
 
 class PatchDesc(ctypes.Structure):
@@ -64,6 +69,9 @@ SIGNATURES = {
     "hy_set_timing": [_P, ctypes.c_int],
     "hy_kernel_times": [_P, _dp, _i64p],
     "hy_kernel_config": [_P, ctypes.c_char_p, ctypes.c_size_t],
+    "hy_get_launch_cfg": [_P, ctypes.POINTER(LaunchCfg)],
+    "hy_set_launch_cfg": [_P, ctypes.POINTER(LaunchCfg)],
+    "hy_autotune": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(LaunchCfg), _dp],
     "hy_destroy": [_P],
 }
 
@@ -103,6 +111,9 @@ EXTRA_SIGNATURES = {
     "hy_batch_set_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
     "hy_batch_run_to": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int],
     "hy_batch_last_ms": [_P, _dp],
+    "hy_batch_set_block": [_P, ctypes.c_int],
+    "hy_batch_get_block": [_P, ctypes.POINTER(ctypes.c_int)],
+    "hy_batch_autotune": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp],
     "hy_batch_get_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
     "hy_batch_status": [_P, ctypes.c_int, _i64p, _dp],
     "hy_batch_destroy": [_P],
@@ -166,6 +177,7 @@ class Patch:
         self.n = tuple(int(v) for v in problem.n)
         self.nv = self.ndim + 2
         self.ncell = self.n[0] * self.n[1] * self.n[2]
+        self.precision, self.limiter = int(precision), int(limiter)
         self.desc = make_desc(problem.ndim, problem.n, problem.lo, problem.hi, problem.gamma,
                               problem.bc, precision, limiter,
                               problem.theta if theta is None else theta, problem.accel)
@@ -264,6 +276,49 @@ class Patch:
         check(lib().hy_kernel_config(self.handle, buf, 256), "kernel_config")
         return buf.value.decode()
 
+    def launch_cfg(self):
+        """(bx, by, zchunk) of the stage kernels' launch shape."""
+        c = LaunchCfg()
+        check(lib().hy_get_launch_cfg(self.handle, ctypes.byref(c)), "get_launch_cfg")
+        return (c.bx, c.by, c.zchunk)
+
+    def set_launch_cfg(self, bx: int, by: int, zchunk: int):
+        c = LaunchCfg(bx, by, zchunk)
+        check(lib().hy_set_launch_cfg(self.handle, ctypes.byref(c)), "set_launch_cfg")
+
+    def autotune(self, solver: int = HLLC, reps: int = 5, cache: Optional[str] = None):
+        """Pick the fastest launch shape for this patch (see hy_autotune).
+
+        With ``cache`` (a JSON file path) a shape already tuned for the same
+        device architecture, dimensions, precision, limiter, solver and size
+        is applied without timing, and a new result is added to the file.
+        Returns (bx, by, zchunk, ms per first-stage launch or None if cached)."""
+        key = None
+        if cache:
+            import torch
+
+            arch = torch.cuda.get_device_properties(torch.device(self.device)).gcnArchName.split(":")[0]
+            key = (f"{arch}|nd{self.ndim}|fp{self.precision}|lim{self.limiter}|"
+                   f"{'hllc' if solver == HLLC else 'hll'}|{'x'.join(str(int(v)) for v in self.n)}")
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            if key in table:
+                e = table[key]
+                self.set_launch_cfg(e["bx"], e["by"], e["zchunk"])
+                return (e["bx"], e["by"], e["zchunk"], None)
+        best, ms = LaunchCfg(), ctypes.c_double()
+        check(lib().hy_autotune(self.handle, int(solver), int(reps), ctypes.byref(best), ctypes.byref(ms)),
+              "autotune")
+        if key:
+            table[key] = {"bx": best.bx, "by": best.by, "zchunk": best.zchunk, "ms": ms.value}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return (best.bx, best.by, best.zchunk, ms.value)
+
     def close(self):
         if getattr(self, "handle", None):
             lib().hy_destroy(self.handle)
@@ -320,6 +375,23 @@ class Batch:
 
     def run_to(self, t_end: float, cfl: float, solver: int = HLLC):
         check(lib().hy_batch_run_to(self.handle, float(t_end), float(cfl), int(solver)), "batch_run_to")
+
+    def block(self) -> int:
+        """Threads per workgroup of the batched kernel."""
+        v = ctypes.c_int()
+        check(lib().hy_batch_get_block(self.handle, ctypes.byref(v)), "batch_get_block")
+        return v.value
+
+    def set_block(self, threads: int):
+        check(lib().hy_batch_set_block(self.handle, int(threads)), "batch_set_block")
+
+    def autotune(self, t_end: float, cfl: float, solver: int = HLLC):
+        """Time the whole run with each workgroup size, keep the fastest, leave
+        the state as it was; returns (threads, ms)."""
+        bt, ms = ctypes.c_int(), ctypes.c_double()
+        check(lib().hy_batch_autotune(self.handle, float(t_end), float(cfl), int(solver), ctypes.byref(bt),
+                                      ctypes.byref(ms)), "batch_autotune")
+        return bt.value, ms.value
 
     def last_ms(self) -> float:
         out = ctypes.c_double(0.0)

@@ -103,3 +103,40 @@ def test_full_512_tube_configuration_against_exact_solutions():
         assert np.all(l1 < 1e-5), (i, l1)
     print(f"512 tubes in {ms:.1f} ms; median L1(rho) vs exact {np.median(errs):.2e}")
     B.close()
+
+
+def test_workgroup_sizes_identical_and_autotune_restores_state():
+    """Every workgroup size of the batched kernel (256, 512, 1024 threads)
+    gives bitwise the same tubes (the same per-cell arithmetic, a max for the
+    CFL rate); the autotuner picks one of them, leaves the state and the
+    status as they were, and the next run matches."""
+    tubes = wl.batched_tubes(40, seed=8, nmin=128, nmax=6144)
+    probs = [wl.tube_problem(t, t_end=0.004) for t in tubes]
+    B = hydro.Batch(probs)
+    assert B.block() == 1024
+    want = None
+    for bt in (1024, 512, 256):
+        for i, pr in enumerate(probs):
+            B.set_state(i, pr.W)
+        B.set_block(bt)
+        B.run_to(0.004, 0.4, hydro.HLLC)
+        got = [B.get_state(i, hydro.CONSERVED) for i in range(len(probs))]
+        if want is None:
+            want = got
+        else:
+            for i in range(len(probs)):
+                assert np.array_equal(got[i], want[i]), (bt, i)
+    with pytest.raises(hydro.HydroError):
+        B.set_block(128)
+    for i, pr in enumerate(probs):
+        B.set_state(i, pr.W)
+    U0 = [B.get_state(i, hydro.CONSERVED) for i in range(len(probs))]
+    bt, ms = B.autotune(0.004, 0.4, hydro.HLLC)
+    assert bt in (256, 512, 1024) and ms > 0 and B.block() == bt
+    for i in range(len(probs)):
+        assert np.array_equal(B.get_state(i, hydro.CONSERVED), U0[i])
+        assert B.status(i) == (0, 0.0)
+    B.run_to(0.004, 0.4, hydro.HLLC)
+    for i in range(len(probs)):
+        assert np.array_equal(B.get_state(i, hydro.CONSERVED), want[i])
+    B.close()

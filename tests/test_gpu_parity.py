@@ -281,3 +281,69 @@ def test_smooth_periodic_256_sampled_against_oracle(solver):
         ref = oracle.step(d, box0.reshape(5, -1), dt).reshape(5, m, m, m)[:, halo:-halo, halo:-halo, halo:-halo]
         got = _subbox(U1, n, lo, size, 0)
         assert_close(got.reshape(5, -1), ref.reshape(5, -1), 32, tuple(lo))
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_launch_shapes_give_identical_results_and_autotune(nd, tmp_path):
+    """Every supported plane tile computes the same cells with the same
+    arithmetic, so two steps agree bit for bit for a given z chunk; z chunks
+    (down to a single plane, ragged last chunks) enter the z march at other
+    planes, whose entry code may round the z face differently in the last
+    place, so across chunks results agree to FP32 roundoff and each matches
+    the FP64 oracle to the FP32 bar.  The autotuner keeps one of the shapes
+    and leaves U^n, the time and the next step's result unchanged; its JSON
+    cache applies the tuned shape."""
+    n = (70, 37, 29) if nd == 3 else (150, 77, 1)
+    prob = wl.random_smooth_patch(nd, n[:nd], seed=21, bc=wl.BC_REFLECT)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    ref = hydro.Patch(prob, precision=32)
+    U0 = ref.get_state(hydro.CONSERVED)
+    dt = ref.cfl_dt(0.4)
+    ref.step(dt, hydro.HLLC)
+    ref.step(dt, hydro.HLLC)
+    want = ref.get_state(hydro.CONSERVED)
+    ref.close()
+    orc = oracle.step(d, oracle.step(d, U0, dt), dt)
+    tiles = [(64, 8), (64, 4), (32, 8), (32, 16)]
+    chunks = [1, 2, 3, 5, 8, 29] if nd == 3 else [1]
+    for zc in chunks:
+        first = None
+        for bx, by in tiles:
+            p = hydro.Patch(prob, precision=32)
+            p.set_launch_cfg(bx, by, zc)
+            assert p.launch_cfg() == (bx, by, zc)
+            p.step(dt, hydro.HLLC)
+            p.step(dt, hydro.HLLC)
+            got = p.get_state(hydro.CONSERVED)
+            p.close()
+            if first is None:
+                first = got
+                assert_close(got, orc, 32, ("chunk", zc))
+                s = np.max(np.abs(want), axis=1, keepdims=True)
+                s[1:-1] = np.maximum(s[1:-1], np.sqrt(2 * s[0] * s[-1]))
+                assert np.max(np.abs(got - want) / s) < 1e-6, zc
+            else:
+                assert np.array_equal(got, first), (bx, by, zc)
+    p = hydro.Patch(prob, precision=32)
+    with pytest.raises(hydro.HydroError):
+        p.set_launch_cfg(16, 8, 1)
+    with pytest.raises(hydro.HydroError):
+        p.set_launch_cfg(64, 8, n[2] + 1 if nd == 3 else 2)
+    dflt = p.launch_cfg()
+    Ua, t0 = p.get_state(hydro.CONSERVED), p.time()
+    cache = str(tmp_path / "tune.json")
+    bx, by, zc, ms = p.autotune(hydro.HLLC, reps=2, cache=cache)
+    assert (bx, by) in tiles and ms > 0 and p.launch_cfg() == (bx, by, zc)
+    assert np.array_equal(p.get_state(hydro.CONSERVED), Ua) and p.time() == t0
+    p.set_launch_cfg(*dflt)
+    p.advance(2, 0.4, solver=hydro.HLLC)
+    q = hydro.Patch(prob, precision=32)
+    q.advance(2, 0.4, solver=hydro.HLLC)
+    assert np.array_equal(p.get_state(hydro.CONSERVED), q.get_state(hydro.CONSERVED))
+    assert p.time() == q.time()
+    p.close()
+    q.close()
+    r = hydro.Patch(prob, precision=32)
+    assert r.autotune(hydro.HLLC, reps=2, cache=cache) == (bx, by, zc, None)
+    assert r.launch_cfg() == (bx, by, zc)
+    r.close()
