@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ESTATE = 0, -1, -4
-HLL, HLLC = 0, 1
+HLL, HLLC, HLLC_SWITCH = 0, 1, 2
+SHOCK_EPS = 0.5
 LIM_THETA, LIM_LEARNED = 0, 1
 MLP_IN, MLP_H = 4, 32
 MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
@@ -85,6 +86,7 @@ def lib():
             ("orc_flux", [P, ctypes.c_int, dp, dp, dp], None),
             ("orc_physical", [P, ctypes.c_int, dp, dp, dp, dp, dp], None),
             ("orc_hllc_star", [P, ctypes.c_int, dp, dp, dp], None),
+            ("orc_shock_bits", [P, dp, ctypes.POINTER(ctypes.c_ubyte)], ctypes.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -187,6 +189,17 @@ def rhs(desc: Desc, U) -> np.ndarray:
     if st != OK:
         raise OracleError(st, "rhs")
     return L
+
+
+def shock_bits(desc: Desc, U) -> np.ndarray:
+    """Per interior cell, bit q set where the switch's detector flags a shock
+    moving along q (see orc_shock_bits)."""
+    U = _flat(desc, U)
+    out = np.zeros(U.shape[1], dtype=np.uint8)
+    st = lib().orc_shock_bits(ctypes.byref(desc.c()), _dp(U), out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    if st not in (OK, ESTATE):
+        raise OracleError(st, "shock_bits")
+    return out
 
 
 def step(desc: Desc, U, dt: float) -> np.ndarray:

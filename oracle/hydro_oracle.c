@@ -384,6 +384,53 @@ static int fill_primitives(const orc_desc *d, const double *U, const ghost_geom 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Shock detector for the HLLC -> HLL switch.  Sec. 3.2 says HLL replaces    */
+/* HLLC in the immediate vicinity of a shock, in the directions transverse  */
+/* to its propagation, against odd-even decoupling, without giving the      */
+/* detector.  Reading: a cell is in a shock moving along q when the         */
+/* pressures on its two sides along q differ by more than ORC_SHOCK_EPS of  */
+/* the smaller one and the flow converges there; a face normal to r is in   */
+/* the vicinity of a shock transverse to it when one of its two cells is    */
+/* flagged along a direction q != r.                                        */
+/* ------------------------------------------------------------------------ */
+
+/* flag bits of the cell at ghosted coordinates (i, j, k); every neighbour
+ * along an active dimension must lie inside the ghosted array */
+static unsigned cell_shock_bits(const orc_desc *d, const ghost_geom *G, const double *Wg, int64_t i, int64_t j,
+                                int64_t k)
+{
+    int nd = d->ndim;
+    int64_t M = G->m[0] * G->m[1] * G->m[2];
+    unsigned bits = 0;
+    for (int q = 0; q < nd; ++q) {
+        int64_t lo3[3] = {i, j, k}, hi3[3] = {i, j, k};
+        lo3[q] -= 1;
+        hi3[q] += 1;
+        int64_t a = gidx(G, lo3[0], lo3[1], lo3[2]), b = gidx(G, hi3[0], hi3[1], hi3[2]);
+        double pa = Wg[(nd + 1) * M + a], pb = Wg[(nd + 1) * M + b];
+        double va = Wg[(1 + q) * M + a], vb = Wg[(1 + q) * M + b];
+        if (fabs(pb - pa) > ORC_SHOCK_EPS * fmin(pa, pb) && vb - va < 0.0) bits |= 1u << q;
+    }
+    return bits;
+}
+
+int orc_shock_bits(const orc_desc *d, const double *U, unsigned char *bits)
+{
+    if (!valid_desc(d) || !bits) return ORC_EINVAL;
+    ghost_geom G = make_geom(d);
+    int64_t M = G.m[0] * G.m[1] * G.m[2];
+    double *Wg = (double *)malloc(sizeof(double) * nvars(d) * M);
+    if (!Wg) return ORC_EINVAL;
+    int status = fill_primitives(d, U, &G, Wg);
+    for (int64_t k = 0; k < d->n[2]; ++k)
+        for (int64_t j = 0; j < d->n[1]; ++j)
+            for (int64_t i = 0; i < d->n[0]; ++i)
+                bits[(k * d->n[1] + j) * d->n[0] + i] = (unsigned char)cell_shock_bits(d, &G, Wg, i, j, k);
+    free(Wg);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The semi-discrete right-hand side, eq. BalanceEquationAverage on a        */
 /* Cartesian grid: L = -sum_q (F_{i+1/2} - F_{i-1/2}) / dq + S.              */
 /* ------------------------------------------------------------------------ */
@@ -464,7 +511,21 @@ int orc_rhs(const orc_desc *d, const double *U, double *L)
                         wlft[v] = line[f - 1] + 0.5 * sig[v * (nq + 2) + f];
                         wrgt[v] = line[f] - 0.5 * sig[v * (nq + 2) + f + 1];
                     }
-                    orc_flux(d, q, wlft, wrgt, flx);
+                    if (d->solver == ORC_HLLC_SWITCH) {
+                        /* cells f-1 and f along q, at the line's transverse position */
+                        int64_t cl[3], cr[3];
+                        cl[q] = f - 1;
+                        cr[q] = f;
+                        cl[(q + 1) % 3] = cr[(q + 1) % 3] = a;
+                        cl[(q + 2) % 3] = cr[(q + 2) % 3] = b;
+                        unsigned fl_bits = cell_shock_bits(d, &G, Wg, cl[0], cl[1], cl[2]);
+                        unsigned fr_bits = cell_shock_bits(d, &G, Wg, cr[0], cr[1], cr[2]);
+                        orc_desc dd = *d;
+                        dd.solver = ((fl_bits | fr_bits) & ~(1u << q)) ? ORC_HLL : ORC_HLLC;
+                        orc_flux(&dd, q, wlft, wrgt, flx);
+                    } else {
+                        orc_flux(d, q, wlft, wrgt, flx);
+                    }
                     for (int v = 0; v < nv; ++v) F[v * (nq + 1) + f] = flx[v];
                 }
                 for (int64_t s = 0; s < nq; ++s) {

@@ -35,6 +35,11 @@ extern "C" {
 
 #define ORC_HLL 0
 #define ORC_HLLC 1
+/* HLLC with HLL at faces transverse to a detected shock (Sec. 3.2 states the
+ * switch; the detector is this oracle's reading, see orc_shock_bits) */
+#define ORC_HLLC_SWITCH 2
+/* shock detector threshold on the relative pressure jump across a cell */
+#define ORC_SHOCK_EPS 0.5
 
 #define ORC_LIM_THETA 0
 #define ORC_LIM_LEARNED 1
@@ -51,7 +56,7 @@ typedef struct {
     double hi[3];
     double gamma;      /* ideal gas p = (gamma - 1) e */
     int bc[3][2];      /* per dimension, low / high face */
-    int solver;        /* ORC_HLL or ORC_HLLC */
+    int solver;        /* ORC_HLL, ORC_HLLC or ORC_HLLC_SWITCH */
     int limiter;       /* ORC_LIM_THETA or ORC_LIM_LEARNED */
     double theta;      /* generalised-minmod parameter, 1 <= theta <= 2 */
     double accel[3];   /* uniform acceleration a = -grad(Phi) */
@@ -91,6 +96,15 @@ void orc_flux(const orc_desc *d, int q, const double *wl, const double *wr, doub
  * two outer wave speeds v_q -/+ c. */
 void orc_physical(const orc_desc *d, int q, const double *w, double *U, double *F,
                   double *lam_minus, double *lam_plus);
+
+/* Shock flags of every interior cell of U (nz, ny, nx): bit q is set when
+ * the pressures of the cell's two neighbours along q (ghost cells by the
+ * boundary conditions) differ by more than ORC_SHOCK_EPS times the smaller
+ * one and the normal velocity decreases across the cell,
+ * v_q(c + e_q) - v_q(c - e_q) < 0 (a compressive jump).  With
+ * ORC_HLLC_SWITCH a face normal to r takes the HLL flux when either adjacent
+ * cell has a bit q != r set, HLLC otherwise. */
+int orc_shock_bits(const orc_desc *d, const double *U, unsigned char *bits);
 
 /* HLLC middle-wave data for the pins: out[0] = alpha_m, out[1] = p*L,
  * out[2] = p*R, then U*L (nv), U*R (nv), F*L (nv), F*R (nv) where the star

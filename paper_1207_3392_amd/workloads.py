@@ -201,6 +201,38 @@ def implosion(n: int = 64) -> Problem:
                    name="implosion")
 
 
+def planar_shock(nx: int = 200, ny: int = 20, mach: float = 6.0, gamma: float = 1.4, x0: float = 0.1,
+                 amp: float = 1e-3, ndim: int = 2) -> Problem:
+    """A grid-aligned shock of Mach number ``mach`` moving along +x into gas at
+    rest (rho = 1, p = 1/gamma, so c = 1), the post-shock state behind it from
+    the Rankine-Hugoniot relations, in a channel [0, 1] x [0, ny/nx] (and the
+    same depth in z for ndim = 3): outflow at both x ends (the inflow behind
+    the shock is supersonic), reflecting side walls.  The pre-shock density of
+    the middle row of cells is raised by the relative amount ``amp``, the seed
+    of odd-even decoupling (Sec. 3.2)."""
+    r1, p1 = 1.0, 1.0 / gamma
+    m2 = mach * mach
+    r2 = r1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (2.0 * gamma * m2 - (gamma - 1.0)) / (gamma + 1.0)
+    u2 = mach * (1.0 - r1 / r2)  # shock speed mach * c1 = mach
+    x = _cell_centres(nx, 0.0, 1.0)
+    nz = ny if ndim == 3 else 1
+    post = np.broadcast_to(x[None, None, :] < x0, (nz, ny, nx))
+    nv = ndim + 2
+    W = np.zeros((nv, nz, ny, nx))
+    W[0] = np.where(post, r2, r1)
+    W[1] = np.where(post, u2, 0.0)
+    W[nv - 1] = np.where(post, p2, p1)
+    W[0][:, ny // 2, :] *= np.where(post[0, 0], 1.0, 1.0 + amp)
+    depth = ny / nx
+    bc = ((BC_OUTFLOW, BC_OUTFLOW), (BC_REFLECT, BC_REFLECT),
+          (BC_REFLECT, BC_REFLECT) if ndim == 3 else (BC_PERIODIC, BC_PERIODIC))
+    if ndim == 2:
+        W = W[:, 0]
+    return Problem(ndim, (nx, ny, nz), (0.0, 0.0, 0.0), (1.0, depth, depth if ndim == 3 else 1.0), gamma,
+                   bc, W, theta=2.0, cfl=0.4, t_end=0.1, name="planar_shock")
+
+
 def _mode_set(dim: int, kmax: int = 4) -> np.ndarray:
     """All integer wave vectors k with 1 <= |k| <= kmax in ``dim`` dimensions."""
     r = range(-kmax, kmax + 1)

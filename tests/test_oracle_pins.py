@@ -442,3 +442,81 @@ def test_courant_04_in_3d_amplifies_roundoff_and_03_does_not():
         growth[C] = (np.sum(np.abs(A - B), axis=1) / np.sum(np.abs(A), axis=1)) / e0
     assert np.max(growth[0.4][1:4]) > 100, growth
     assert np.max(growth[0.3]) < 10, growth
+
+
+# ---- HLLC -> HLL switch at shocks (Sec. 3.2; the detector is a reading) ----
+
+
+def test_switch_suppresses_odd_even_decoupling():
+    """A Mach 6 grid-aligned shock in a channel with a 1e-3 density bump on the
+    middle row: with HLLC everywhere the shock front decouples row by row
+    (transverse velocities of order 0.1 by t = 0.1), with HLL it stays planar,
+    and with the switch (HLL only at faces transverse to the shock) it stays
+    planar too.  Applying HLL to the faces normal to the shock instead, or a
+    detector that never fires, leaves the decoupling in place."""
+    prob = wl.planar_shock(200, 20)
+    out = {}
+    for solver in (oracle.HLL, oracle.HLLC, oracle.HLLC_SWITCH):
+        d = oracle.Desc.from_problem(prob, solver=solver)
+        U, _ = oracle.run(d, oracle.prim_to_cons(d, prob.flat()), 0.1, 0.4)
+        W = oracle.cons_to_prim(d, U).reshape(4, 20, 200)
+        out[solver] = (np.abs(W[2]).max(), np.std(W[0], axis=0).max())
+    assert out[oracle.HLLC][0] > 0.05 and out[oracle.HLLC][1] > 0.05, out
+    for solver in (oracle.HLL, oracle.HLLC_SWITCH):
+        assert out[solver][0] < 2e-3 and out[solver][1] < 2e-3, (solver, out)
+
+
+def test_shock_detector_flags_only_the_cells_at_a_shock():
+    """The exact Sod solution laid along x (uniform in y): only the two cells
+    that straddle the shock carry a flag, along x; the contact (no pressure
+    jump) and the rarefaction (expanding, pressure varying over many cells)
+    carry none, and nothing is flagged along y.  The same profile reversed in
+    x with the velocity negated (a shock moving left) flags the mirrored
+    cells; the profile with the velocity negated alone (an expanding jump) is
+    not flagged."""
+    n = 200
+    r, u, p = er.sample_cells((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, n, 0.5, 0.2)
+    W = np.zeros((4, 4, n))
+    W[0], W[1], W[3] = r, u, p
+    prob = wl.Problem(2, (n, 4, 1), (0, 0, 0), (1.0, 0.02, 1.0), 1.4, ((1, 1), (0, 0), (0, 0)), W)
+    d = oracle.Desc.from_problem(prob)
+    bits = oracle.shock_bits(d, oracle.prim_to_cons(d, prob.flat())).reshape(4, n)
+    m = np.nonzero(r != 0.125)[0].max() + 1  # first pre-shock cell
+    cells = np.nonzero(bits[0])[0]
+    assert np.all(bits == bits[0][None, :]) and np.all(bits < 2)
+    assert list(cells) == [m - 1, m]
+    Wr = W[:, :, ::-1].copy()
+    Wr[1] = -Wr[1]
+    dr = oracle.Desc.from_problem(wl.Problem(2, (n, 4, 1), (0, 0, 0), (1.0, 0.02, 1.0), 1.4,
+                                             ((1, 1), (0, 0), (0, 0)), Wr))
+    bits_r = oracle.shock_bits(dr, oracle.prim_to_cons(dr, Wr.reshape(4, -1))).reshape(4, n)
+    assert np.array_equal(bits_r[0], bits[0][::-1])
+    We = W.copy()
+    We[1] = -We[1]
+    be = oracle.shock_bits(d, oracle.prim_to_cons(d, We.reshape(4, -1)))
+    assert not be[np.nonzero(bits.ravel())[0]].any()
+
+
+def test_switch_equals_hllc_without_shocks_and_on_planar_shocks():
+    """No flags on a smooth flow: the switch is HLLC exactly.  A planar shock
+    with no transverse variation: the transverse faces see equal left and
+    right states, where HLL and HLLC both give the physical flux, so the
+    switch changes the result only by rounding."""
+    prob = wl.smooth_periodic_3d(12)
+    for solver in (oracle.HLLC, oracle.HLLC_SWITCH):
+        d = oracle.Desc.from_problem(prob, solver=solver)
+        U = oracle.prim_to_cons(d, prob.flat())
+        if solver == oracle.HLLC:
+            ref = oracle.rhs(d, U)
+        else:
+            assert not oracle.shock_bits(d, U).any()
+            assert np.array_equal(oracle.rhs(d, U), ref)
+    prob = wl.planar_shock(64, 8, amp=0.0)
+    d1 = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    d2 = oracle.Desc.from_problem(prob, solver=oracle.HLLC_SWITCH)
+    U = oracle.prim_to_cons(d1, prob.flat())
+    for _ in range(5):
+        U1, U2 = oracle.step(d1, U, 1e-3), oracle.step(d2, U, 1e-3)
+        assert np.allclose(U1, U2, rtol=1e-13, atol=1e-13 * np.abs(U).max())
+        U = U1
+    assert oracle.shock_bits(d2, U).any()
