@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
-                                                   "rt_512_plain", "rt_512_learned", "matched_l1"],
+                                                   "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -102,7 +102,7 @@ def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4):
     prob = wl.smooth_periodic_3d(n)
     p = hydro.Patch(prob, precision=32)
     cfg = p.kernel_config()
-    sv = hydro.HLLC if solver == "hllc" else hydro.HLL
+    sv = {"hll": hydro.HLL, "hllc": hydro.HLLC, "hllc_switch": hydro.HLLC_SWITCH}[solver]
     p.advance(warmup, cfl, solver=sv)
     torch.cuda.synchronize()
     p.set_timing(timing)
@@ -314,7 +314,9 @@ def main():
     if args.only:
         run = {"batched_tubes": time_batch, "kh_2048_plain": lambda: time_kh(learned=False),
                "kh_2048_learned": lambda: time_kh(learned=True), "rt_512_plain": lambda: time_rt(learned=False),
-               "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1}[args.only]
+               "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1,
+               "hllc_switch": lambda: {k: v for k, v in time_patch(args.n, "hllc_switch", args.steps,
+                                                                    args.warmup).items() if k != "kernel"}}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -346,6 +348,16 @@ def main():
 
         guarded(f"{'hll' if args.solver == 'hllc' else 'hllc'}_{args.n}", other_solver)
         guarded(f"{args.solver}_512", big)
+
+        def switch():
+            # HLLC with HLL at faces transverse to shocks: the shock-flag pass
+            # runs before each stage (this flow has no shocks, so every face
+            # still takes HLLC; the cost is the flags and the switch kernels)
+            r = time_patch(args.n, "hllc_switch", args.steps, args.warmup)
+            return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
+                    "stage_ms": r["stage_ms"]}
+
+        guarded(f"hllc_switch_{args.n}", switch)
         guarded("batched_tubes", time_batch)
         guarded("kh_2048_plain", lambda: time_kh(learned=False))
         guarded("kh_2048_learned", lambda: time_kh(learned=True))

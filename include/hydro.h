@@ -44,7 +44,16 @@ typedef enum {
 } hy_status;
 
 typedef enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1, HY_BC_REFLECT = 2 } hy_bc;
-typedef enum { HY_HLL = 0, HY_HLLC = 1 } hy_solver;
+/* HY_HLLC_SWITCH: HLLC, with HLL at the faces next to a shock that are
+ * transverse to its direction of motion (Sec. 3.2, against odd-even
+ * decoupling; the paper names no detector).  Detector: a cell is in a shock
+ * moving along q when the pressures of its two neighbours along q differ by
+ * more than 0.5 of the smaller one and the velocity along q decreases across
+ * it; a face normal to r takes HLL when either adjacent cell is flagged
+ * along some q != r.  The flags are recomputed from each stage's input (one
+ * extra pass, one byte per cell in the workspace).  In 1D (and for batched
+ * tubes) it is HLLC. */
+typedef enum { HY_HLL = 0, HY_HLLC = 1, HY_HLLC_SWITCH = 2 } hy_solver;
 typedef enum { HY_LIM_THETA = 0, HY_LIM_LEARNED = 1 } hy_limiter;
 typedef enum { HY_PRIMITIVE = 0, HY_CONSERVED = 1 } hy_kind;
 
@@ -104,7 +113,7 @@ hy_status hy_set_state(hy_patch *p, int kind, const double *host_soa);
 hy_status hy_get_state(hy_patch *p, int kind, double *host_soa_out);
 
 /* One full two-stage Runge-Kutta step (eqs. Update, RungeKutta1-3) of size dt
- * with the HLL (eq. FluxHLL) or HLLC (eq. FluxHLLC) flux.  dt must be finite
+ * with the HLL (eq. FluxHLL) or HLLC (eq. FluxHLLC) flux, or the switch.  dt must be finite
  * and > 0 (HY_EINVAL otherwise).  Asynchronous.  The second stage also
  * computes the CFL rate of the new state, so a following hy_cfl_dt launches
  * nothing. */

@@ -23,6 +23,8 @@ struct DevCtl {
 };
 
 enum { LIM_THETA = 0, LIM_LEARNED = 1 };
+// Riemann solvers; the switch is HLLC with HLL at faces transverse to a shock
+enum { SOLVER_HLL = 0, SOLVER_HLLC = 1, SOLVER_HLLC_SWITCH = 2 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
 
 // How a stage obtains dt: from the host argument, or from the device control
@@ -35,6 +37,7 @@ struct StageArgs {
     T *uout;          // output (U^(1) in stage 1; U^{n+1} over U^n in stage 2)
     const T *u0;      // stage 2: U^n, read only at the thread's own cell (aliases uout)
     const float *slopes;  // learned limiter: (ndim * nv, ncell) slopes of the stage input
+    const uint8_t *flags; // HLLC switch: per cell of the stage input, bit q = shock moving along q
     int64_t n[3];
     int64_t vstride;  // elements between variables
     T idx[3];         // 1 / dq
@@ -59,6 +62,15 @@ struct LaunchCfg {
 template <typename T>
 hipError_t launch_stage(int ndim, int solver, int stage, int limiter, const LaunchCfg &cfg,
                         const StageArgs<T> &a, hipStream_t s);
+
+// Shock flags of the state u for the HLLC switch (defined in shock.hip): per
+// cell, bit q is set when the pressures of the two neighbours along q
+// (ghosts by the boundary conditions) differ by more than eps times the
+// smaller one and the normal velocity decreases across the cell.
+template <typename T>
+hipError_t launch_shock_flags(const T *u, uint8_t *flags, const int64_t n[3], int64_t vstride, int ndim,
+                              const int bc[3][2], T gm1, T eps, hipStream_t s);
+constexpr double SHOCK_EPS = 0.5;
 
 // Device-side helpers (defined in reduce.hip).
 template <typename T>

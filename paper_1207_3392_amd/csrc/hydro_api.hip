@@ -45,6 +45,7 @@ struct hy_patch {
     void *A = nullptr;  // U^n (and U^{n+1}, written in place by stage 2)
     void *B = nullptr;  // U^(1)
     float *slopes = nullptr;
+    uint8_t *flags = nullptr;  // shock flags of the stage input (HLLC switch)
     hy::MlpDevice *mlp = nullptr;
     hy::MlpImage *mlpimg = nullptr;
     bool mlp_set = false;
@@ -98,7 +99,7 @@ hy_status check_desc(const hy_patch_desc *d)
 }
 
 struct Layout {
-    size_t ctl, partials, A, B, slopes, mlp, mlpimg, total;
+    size_t ctl, partials, A, B, slopes, flags, mlp, mlpimg, total;
     int64_t vstride;
 };
 
@@ -123,6 +124,8 @@ Layout layout(const hy_patch_desc &d)
     o = align_up(o + es * nv * (size_t)L.vstride, 256);
     L.slopes = o;
     if (d.limiter == HY_LIM_LEARNED) o = align_up(o + sizeof(float) * d.ndim * nv * (size_t)L.vstride, 256);
+    L.flags = o;
+    o = align_up(o + (size_t)ncells(d), 256);
     L.total = o + 256;  // slack for aligning the caller's base pointer
     return L;
 }
@@ -137,6 +140,7 @@ hy::StageArgs<T> stage_args(hy_patch *p, int stage, int dt_mode, double dt, doub
     a.uout = stage == 1 ? B : A;
     a.u0 = A;
     a.slopes = p->slopes;
+    a.flags = p->flags;
     for (int q = 0; q < 3; ++q) {
         a.n[q] = d.n[q];
         a.idx[q] = q < d.ndim ? (T)((double)d.n[q] / (d.hi[q] - d.lo[q])) : T(0);
@@ -167,6 +171,12 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
         const T *uin = (const T *)(stage == 1 ? p->A : p->B);
         e = hy::launch_learned_slopes((const float *)uin, p->slopes, p->d.n, p->vstride, p->vstride, p->d.ndim,
                                       (float)(p->d.gamma - 1.0), p->d.bc, p->mlpimg, p->stream);
+        if (e != hipSuccess) return e;
+    }
+    if (solver == HY_HLLC_SWITCH && p->d.ndim >= 2) {
+        const T *uin = (const T *)(stage == 1 ? p->A : p->B);
+        e = hy::launch_shock_flags<T>(uin, p->flags, p->d.n, p->vstride, p->d.ndim, p->d.bc, (T)(p->d.gamma - 1.0),
+                                      (T)hy::SHOCK_EPS, p->stream);
         if (e != hipSuccess) return e;
     }
     const int k = stage - 1;
@@ -300,6 +310,7 @@ hy_status hy_init_patch(const hy_patch_desc *desc, void *dev_workspace, size_t b
     p->A = base + L.A;
     p->B = base + L.B;
     p->slopes = desc->limiter == HY_LIM_LEARNED ? (float *)(base + L.slopes) : nullptr;
+    p->flags = (uint8_t *)(base + L.flags);
     p->stream = (hipStream_t)hip_stream;
     pick_config(p);
     hipError_t e = hy::launch_ctl_init(p->ctl, p->stream);
@@ -377,7 +388,7 @@ hy_status hy_step(hy_patch *p, double dt, int solver)
 {
     if (!p) return fail(HY_EINVAL, "null patch");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HY_EINVAL, "dt must be finite and > 0");
-    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
     if (p->d.limiter == HY_LIM_LEARNED && !p->mlp_set) return fail(HY_EINVAL, "learned limiter without weights");
     hipError_t e = one_step(p, solver, hy::DT_HOST, dt, 0.0, 0.0);
     if (e != hipSuccess) return hip_fail(e, "stage launch");
@@ -389,7 +400,7 @@ hy_status hy_advance(hy_patch *p, int nsteps, double cfl, double t_end, int solv
     if (!p) return fail(HY_EINVAL, "null patch");
     if (nsteps < 0) return fail(HY_EINVAL, "nsteps must be >= 0");
     if (!(cfl > 0.0) || !std::isfinite(cfl) || std::isnan(t_end)) return fail(HY_EINVAL, "bad cfl or t_end");
-    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
     if (p->d.limiter == HY_LIM_LEARNED && !p->mlp_set) return fail(HY_EINVAL, "learned limiter without weights");
     for (int i = 0; i < nsteps; ++i) {
         hipError_t e = one_step(p, solver, hy::DT_DEVICE, 0.0, cfl, t_end);
@@ -529,7 +540,7 @@ hy_status hy_set_launch_cfg(hy_patch *p, const hy_launch_cfg *cfg)
 hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, double *best_ms)
 {
     if (!p) return fail(HY_EINVAL, "null patch");
-    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "solver must be HY_HLL or HY_HLLC");
+    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
     if (reps < 1 || reps > 1000) return fail(HY_EINVAL, "reps must be in 1..1000");
     if (p->d.limiter == HY_LIM_LEARNED && !p->mlp_set) return fail(HY_EINVAL, "learned limiter without weights");
     const hy_patch_desc &d = p->d;
@@ -558,6 +569,14 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
     if (d.limiter == HY_LIM_LEARNED)  // stage 1 reads the slopes of U^n
         e = hy::launch_learned_slopes((const float *)p->A, p->slopes, d.n, p->vstride, p->vstride, d.ndim,
                                       (float)(d.gamma - 1.0), d.bc, p->mlpimg, p->stream);
+    if (e == hipSuccess && solver == HY_HLLC_SWITCH && d.ndim >= 2) {  // and the switch the shock flags of U^n
+        if (d.precision == 64)
+            e = hy::launch_shock_flags<double>((const double *)p->A, p->flags, d.n, p->vstride, d.ndim, d.bc,
+                                               d.gamma - 1.0, hy::SHOCK_EPS, p->stream);
+        else
+            e = hy::launch_shock_flags<float>((const float *)p->A, p->flags, d.n, p->vstride, d.ndim, d.bc,
+                                              (float)(d.gamma - 1.0), (float)hy::SHOCK_EPS, p->stream);
+    }
     // One trial = the two stages of a step with dt = 0, both reading U^n and
     // writing only the scratch state U^(1) (the second stage with U^n as its
     // input and as its U^n term, so it does the second stage's full work);
@@ -872,7 +891,7 @@ hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver)
     if (!b) return fail(HY_EINVAL, "null batch");
     if (!(t_end > 0.0) || !std::isfinite(t_end)) return fail(HY_EINVAL, "t_end must be finite and > 0");
     if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HY_EINVAL, "cfl must be finite and > 0");
-    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
     hy_status st0 = batch_order(b);
     if (st0 != HY_OK) return st0;
     hipError_t e = hipSuccess;
@@ -881,7 +900,7 @@ hy_status hy_batch_run_to(hy_batch *b, double t_end, double cfl, int solver)
         if (st != HY_OK) return st;
     }
     hy::BatchCtl c{};
-    c.solver = solver;
+    c.solver = solver == HY_HLLC_SWITCH ? HY_HLLC : solver;  // no transverse faces in 1D
     c.max_steps = kBatchMaxSteps;
     c.t_end = t_end;
     c.cfl = cfl;
@@ -898,11 +917,11 @@ hy_status hy_batch_autotune(hy_batch *b, double t_end, double cfl, int solver, i
     if (!b) return fail(HY_EINVAL, "null batch");
     if (!(t_end > 0.0) || !std::isfinite(t_end)) return fail(HY_EINVAL, "t_end must be finite and > 0");
     if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HY_EINVAL, "cfl must be finite and > 0");
-    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "unknown solver");
+    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
     hy_status st = batch_order(b);
     if (st != HY_OK) return st;
     hy::BatchCtl c{};
-    c.solver = solver;
+    c.solver = solver == HY_HLLC_SWITCH ? HY_HLLC : solver;  // no transverse faces in 1D
     c.max_steps = kBatchMaxSteps;
     c.t_end = t_end;
     c.cfl = cfl;

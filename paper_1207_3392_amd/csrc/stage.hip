@@ -167,6 +167,30 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
     }
 }
 
+// Face flux for the kernel's solver: the HLLC switch takes HLL where hll is
+// set (a shock flagged along a direction transverse to this face), HLLC
+// elsewhere; the other solvers ignore hll.
+template <int ND, int Q, int SOLVER, typename T>
+__device__ __forceinline__ void face_flux(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2], T gamma,
+                                          T inv_gm1, bool hll)
+{
+    if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+        if (hll) riemann<ND, Q, SOLVER_HLL>(wl, wr, f, gamma, inv_gm1);
+        else riemann<ND, Q, SOLVER_HLLC>(wl, wr, f, gamma, inv_gm1);
+    } else {
+        (void)hll;
+        riemann<ND, Q, SOLVER>(wl, wr, f, gamma, inv_gm1);
+    }
+}
+
+// HLL at a face normal to Q when either adjacent cell is flagged along
+// another direction
+template <int Q>
+__device__ __forceinline__ bool transverse_shock(unsigned fa, unsigned fb)
+{
+    return ((fa | fb) & ~(1u << Q) & 7u) != 0u;
+}
+
 // ------------------------------------------------------------ kernel ----
 
 template <int ND, typename T>
@@ -407,7 +431,12 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         T fl[NP], fr[NP];
         face_state(wm1, sm1, HS, fl);
         face_state(WA, SA, -HS, fr);
-        riemann<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1);
+        bool hll = false;
+        if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+            bool fd = false;
+            hll = transverse_shock<2>(a.flags[zoff(z0 - 1, fd) + colo], a.flags[zoff(z0, fd) + colo]);
+        }
+        face_flux<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1, hll);
     } else {
         load(colo, UA);
         to_w(UA, WA, fxo, fyo, false);
@@ -548,7 +577,12 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 wl[v] = sW[v][row + OY][col + 1] + HS * sSx[v][row][col];
                 wr[v] = sW[v][row + OY][col + 2] - HS * sSx[v][row][col + 1];
             }
-            riemann<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1);
+            bool hll = false;
+            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+                const unsigned yo = zko + (unsigned)((sMap[WX + row + 2] & IDX) * nx);
+                hll = transverse_shock<0>(a.flags[yo + (sMap[col + 1] & IDX)], a.flags[yo + (sMap[col + 2] & IDX)]);
+            }
+            face_flux<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1, hll);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFx[v][row][col] = fl[v];
         };
@@ -559,7 +593,13 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 wl[v] = sW[v][row + 1][col + 2] + HS * sSy[v][row][col];
                 wr[v] = sW[v][row + 2][col + 2] - HS * sSy[v][row + 1][col];
             }
-            riemann<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1);
+            bool hll = false;
+            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+                const unsigned xo = zko + (unsigned)(sMap[col + 2] & IDX);
+                hll = transverse_shock<1>(a.flags[xo + (unsigned)((sMap[WX + row + 1] & IDX) * nx)],
+                                          a.flags[xo + (unsigned)((sMap[WX + row + 2] & IDX) * nx)]);
+            }
+            face_flux<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1, hll);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
         };
@@ -573,7 +613,12 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             T fl[NP], fr[NP];
             face_state(Wk, Sk, HS, fl);
             face_state(Wk1, Sk1, -HS, fr);
-            riemann<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1);
+            bool hll = false;
+            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+                bool fd = false;
+                hll = transverse_shock<2>(a.flags[zko + colo], a.flags[zoff(kz + 1, fd) + colo]);
+            }
+            face_flux<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1, hll);
         }
         if constexpr (ND >= 2) {
             if (tid < BX) face_y(BY, tid);
@@ -700,8 +745,12 @@ template <int ND, typename T>
 hipError_t launch_nd(int solver, int stage, int limiter, const LaunchCfg &cfg, const StageArgs<T> &a,
                      hipStream_t s)
 {
-    if (solver == 0) {
+    if (solver == SOLVER_HLL) {
         return stage == 1 ? launch_lim<ND, T, 0, 1>(limiter, cfg, a, s) : launch_lim<ND, T, 0, 2>(limiter, cfg, a, s);
+    }
+    if constexpr (ND >= 2) {  // in 1D no face is transverse to anything: the switch is HLLC
+        if (solver == SOLVER_HLLC_SWITCH)
+            return stage == 1 ? launch_lim<ND, T, 2, 1>(limiter, cfg, a, s) : launch_lim<ND, T, 2, 2>(limiter, cfg, a, s);
     }
     return stage == 1 ? launch_lim<ND, T, 1, 1>(limiter, cfg, a, s) : launch_lim<ND, T, 1, 2>(limiter, cfg, a, s);
 }

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhydro.so")
 
 HY_OK, HY_EINVAL, HY_ENOMEM, HY_EDEVICE, HY_ESTATE, HY_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-HLL, HLLC = 0, 1
+HLL, HLLC, HLLC_SWITCH = 0, 1, 2
 LIM_THETA, LIM_LEARNED = 0, 1
 PRIMITIVE, CONSERVED = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2

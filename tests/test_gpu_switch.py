@@ -1,0 +1,111 @@
+"""The HLLC -> HLL switch at shocks (Sec. 3.2) on the GPU: parity with the FP64
+oracle's switch on shocked 2D and 3D patches, and the behaviour the switch
+exists for: a grid-aligned Mach 6 shock decouples row by row with HLLC and
+stays planar with the switch."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1207_3392_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+hydro = pytest.importorskip("paper_1207_3392_amd.hydro")
+
+
+def _gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+if not _gpu():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def scale(ref):
+    s = np.max(np.abs(ref), axis=1, keepdims=True)
+    s[1:-1] = np.maximum(s[1:-1], np.sqrt(2 * s[0] * s[-1]))
+    return s
+
+
+def flags_not_marginal(d, U, seed=0):
+    """The detector's decisions on U do not change when U is perturbed by a
+    few FP32 roundings, so FP32 and FP64 evaluations of the detector agree."""
+    b = oracle.shock_bits(d, U)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        Up = U * (1.0 + 2e-6 * rng.uniform(-1, 1, size=U.shape))
+        if not np.array_equal(oracle.shock_bits(d, Up), b):
+            return False
+    return True
+
+
+def run_parity(prob, steps, prec=32, cfl=0.4):
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC_SWITCH)
+    p = hydro.Patch(prob, precision=prec)
+    U = p.get_state(hydro.CONSERVED)
+    nflag = 0
+    for k in range(steps):
+        dt = oracle.cfl_dt(d, U, cfl)
+        assert flags_not_marginal(d, U, k), k
+        nflag += int(np.count_nonzero(oracle.shock_bits(d, U)))
+        ref = oracle.step(d, U, dt)
+        p.set_state(U, hydro.CONSERVED)
+        p.step(dt, hydro.HLLC_SWITCH)
+        G = p.get_state(hydro.CONSERVED)
+        err = np.abs(G - ref) / scale(ref)
+        if prec == 64:
+            assert err.max() < 1e-12, (k, err.max())
+        else:
+            assert err.max() < 2e-5 and np.all(err.mean(axis=1) < 2e-6), (k, err.max(axis=1))
+        U = ref
+    p.close()
+    return nflag
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_switch_parity_planar_shock_2d(prec):
+    prob = wl.planar_shock(120, 24, amp=0.05)
+    assert run_parity(prob, 6, prec) > 0
+
+
+def test_switch_parity_implosion_and_3d_shock():
+    assert run_parity(wl.implosion(48), 4) > 0
+    prob = wl.planar_shock(40, 12, amp=0.05, ndim=3)
+    assert run_parity(prob, 4) > 0
+
+
+def test_switch_without_shocks_is_hllc():
+    """No shock anywhere: every face takes HLLC, so the switch matches the
+    HLLC kernels to FP32 rounding (a separate build of the same arithmetic,
+    whose instruction selection may round differently in the last place)."""
+    prob = wl.smooth_periodic_3d(32)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC_SWITCH)
+    a = hydro.Patch(prob, precision=32)
+    b = hydro.Patch(prob, precision=32)
+    assert not oracle.shock_bits(d, a.get_state(hydro.CONSERVED)).any()
+    a.advance(3, 0.3, solver=hydro.HLLC)
+    b.advance(3, 0.3, solver=hydro.HLLC_SWITCH)
+    A, B = a.get_state(hydro.CONSERVED), b.get_state(hydro.CONSERVED)
+    assert np.max(np.abs(A - B) / scale(A)) < 1e-6
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("ndim,n", [(2, (400, 40)), (3, (160, 16))])
+def test_switch_keeps_a_grid_aligned_shock_planar(ndim, n):
+    """Mach 6 shock to t = 0.1 on the device: HLLC decouples the rows
+    (transverse velocity of order 0.1), the switch keeps it planar."""
+    prob = wl.planar_shock(n[0], n[1], ndim=ndim)
+    res = {}
+    for solver in (hydro.HLLC, hydro.HLLC_SWITCH, hydro.HLL):
+        p = hydro.Patch(prob, precision=32)
+        p.advance(2000, 0.4, t_end=0.1, solver=solver)
+        assert p.time() == pytest.approx(0.1, rel=1e-9)
+        W = p.get_state(hydro.PRIMITIVE)
+        p.close()
+        res[solver] = float(np.max(np.abs(W[2:ndim + 1])))
+    assert res[hydro.HLLC] > 0.05, res
+    assert res[hydro.HLLC_SWITCH] < 5e-3 and res[hydro.HLL] < 5e-3, res
