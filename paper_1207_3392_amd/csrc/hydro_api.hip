@@ -45,7 +45,8 @@ struct hy_patch {
     void *A = nullptr;  // U^n (and U^{n+1}, written in place by stage 2)
     void *B = nullptr;  // U^(1)
     float *slopes = nullptr;
-    uint8_t *flags = nullptr;  // shock flags of the stage input (HLLC switch)
+    uint8_t *det = nullptr;    // HLLC switch: detector bits of the stage input
+    uint8_t *flags = nullptr;  // HLLC switch: face decisions of the stage input
     hy::MlpDevice *mlp = nullptr;
     hy::MlpImage *mlpimg = nullptr;
     bool mlp_set = false;
@@ -99,7 +100,7 @@ hy_status check_desc(const hy_patch_desc *d)
 }
 
 struct Layout {
-    size_t ctl, partials, A, B, slopes, flags, mlp, mlpimg, total;
+    size_t ctl, partials, A, B, slopes, det, flags, mlp, mlpimg, total;
     int64_t vstride;
 };
 
@@ -124,6 +125,8 @@ Layout layout(const hy_patch_desc &d)
     o = align_up(o + es * nv * (size_t)L.vstride, 256);
     L.slopes = o;
     if (d.limiter == HY_LIM_LEARNED) o = align_up(o + sizeof(float) * d.ndim * nv * (size_t)L.vstride, 256);
+    L.det = o;
+    o = align_up(o + (size_t)ncells(d), 256);
     L.flags = o;
     o = align_up(o + (size_t)ncells(d), 256);
     L.total = o + 256;  // slack for aligning the caller's base pointer
@@ -175,7 +178,7 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
     }
     if (solver == HY_HLLC_SWITCH && p->d.ndim >= 2) {
         const T *uin = (const T *)(stage == 1 ? p->A : p->B);
-        e = hy::launch_shock_flags<T>(uin, p->flags, p->d.n, p->vstride, p->d.ndim, p->d.bc, (T)(p->d.gamma - 1.0),
+        e = hy::launch_shock_flags<T>(uin, p->det, p->flags, p->d.n, p->vstride, p->d.ndim, p->d.bc, (T)(p->d.gamma - 1.0),
                                       (T)hy::SHOCK_EPS, p->stream);
         if (e != hipSuccess) return e;
     }
@@ -310,6 +313,7 @@ hy_status hy_init_patch(const hy_patch_desc *desc, void *dev_workspace, size_t b
     p->A = base + L.A;
     p->B = base + L.B;
     p->slopes = desc->limiter == HY_LIM_LEARNED ? (float *)(base + L.slopes) : nullptr;
+    p->det = (uint8_t *)(base + L.det);
     p->flags = (uint8_t *)(base + L.flags);
     p->stream = (hipStream_t)hip_stream;
     pick_config(p);
@@ -571,10 +575,10 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
                                       (float)(d.gamma - 1.0), d.bc, p->mlpimg, p->stream);
     if (e == hipSuccess && solver == HY_HLLC_SWITCH && d.ndim >= 2) {  // and the switch the shock flags of U^n
         if (d.precision == 64)
-            e = hy::launch_shock_flags<double>((const double *)p->A, p->flags, d.n, p->vstride, d.ndim, d.bc,
+            e = hy::launch_shock_flags<double>((const double *)p->A, p->det, p->flags, d.n, p->vstride, d.ndim, d.bc,
                                                d.gamma - 1.0, hy::SHOCK_EPS, p->stream);
         else
-            e = hy::launch_shock_flags<float>((const float *)p->A, p->flags, d.n, p->vstride, d.ndim, d.bc,
+            e = hy::launch_shock_flags<float>((const float *)p->A, p->det, p->flags, d.n, p->vstride, d.ndim, d.bc,
                                               (float)(d.gamma - 1.0), (float)hy::SHOCK_EPS, p->stream);
     }
     // One trial = the two stages of a step with dt = 0, both reading U^n and

@@ -183,13 +183,6 @@ __device__ __forceinline__ void face_flux(const T (&wl)[ND + 2], const T (&wr)[N
     }
 }
 
-// HLL at a face normal to Q when either adjacent cell is flagged along
-// another direction
-template <int Q>
-__device__ __forceinline__ bool transverse_shock(unsigned fa, unsigned fb)
-{
-    return ((fa | fb) & ~(1u << Q) & 7u) != 0u;
-}
 
 // ------------------------------------------------------------ kernel ----
 
@@ -432,10 +425,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         face_state(wm1, sm1, HS, fl);
         face_state(WA, SA, -HS, fr);
         bool hll = false;
-        if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-            bool fd = false;
-            hll = transverse_shock<2>(a.flags[zoff(z0 - 1, fd) + colo], a.flags[zoff(z0, fd) + colo]);
-        }
+        if constexpr (SOLVER == SOLVER_HLLC_SWITCH) hll = (a.flags[(unsigned)(z0 * plane) + colo] >> 2) & 1u;
         face_flux<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1, hll);
     } else {
         load(colo, UA);
@@ -451,7 +441,10 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         for (int j = 0; j < HPT; ++j)
             if (hlds[j] >= 0) load(zo + hoff[j], h[j]);
     };
-    load_halo(z0, hnext);
+    // (the switch kernels hold both flux forms; to stay within the register
+    // budget they load the halo and the second stage's U^n when they are
+    // used instead of ahead)
+    if constexpr (SOLVER != SOLVER_HLLC_SWITCH) load_halo(z0, hnext);
 
     T *sWf = &sW[0][0][0];
     // one plane: Wk/Uk/Sk/Flo hold plane kz, Wk1/Uk1 plane kz+1; the body
@@ -464,7 +457,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         bool fz2 = false;
         if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
         T u0[NP];  // U^n of the own cell (second stage), issued early, used in phase 3
-        if constexpr (STAGE == 2) {
+        if constexpr (STAGE == 2 && SOLVER != SOLVER_HLLC_SWITCH) {
 #pragma unroll
             for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
         }
@@ -486,11 +479,15 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
         for (int v = 0; v < NP; ++v) sW[v][ty + OY][tx + 2] = Wk[v];
         T hcur[HPT][NP];
+        if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+            load_halo(kz, hcur);
+        } else {
 #pragma unroll
-        for (int j = 0; j < HPT; ++j)
+            for (int j = 0; j < HPT; ++j)
 #pragma unroll
-            for (int v = 0; v < NP; ++v) hcur[j][v] = hnext[j][v];
-        if constexpr (ND == 3) load_halo(kz + 1, hnext);
+                for (int v = 0; v < NP; ++v) hcur[j][v] = hnext[j][v];
+            if constexpr (ND == 3) load_halo(kz + 1, hnext);
+        }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (hlds[j] >= 0) {
@@ -577,10 +574,13 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 wl[v] = sW[v][row + OY][col + 1] + HS * sSx[v][row][col];
                 wr[v] = sW[v][row + OY][col + 2] - HS * sSx[v][row][col + 1];
             }
+            // switch: the decision stored with the face's high cell (at a
+            // non-periodic high wall, with the last cell)
             bool hll = false;
             if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-                const unsigned yo = zko + (unsigned)((sMap[WX + row + 2] & IDX) * nx);
-                hll = transverse_shock<0>(a.flags[yo + (sMap[col + 1] & IDX)], a.flags[yo + (sMap[col + 2] & IDX)]);
+                const unsigned b = a.flags[zko + (unsigned)((sMap[WX + row + 2] & IDX) * nx + (sMap[col + 2] & IDX))];
+                const bool wall = x0 + col >= nx && a.bc[0][1] != BC_PERIODIC;
+                hll = (b >> (wall ? 3 : 0)) & 1u;
             }
             face_flux<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1, hll);
 #pragma unroll
@@ -595,9 +595,9 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             }
             bool hll = false;
             if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-                const unsigned xo = zko + (unsigned)(sMap[col + 2] & IDX);
-                hll = transverse_shock<1>(a.flags[xo + (unsigned)((sMap[WX + row + 1] & IDX) * nx)],
-                                          a.flags[xo + (unsigned)((sMap[WX + row + 2] & IDX) * nx)]);
+                const unsigned b = a.flags[zko + (unsigned)((sMap[WX + row + 2] & IDX) * nx + (sMap[col + 2] & IDX))];
+                const bool wall = y0 + row >= ny && a.bc[1][1] != BC_PERIODIC;
+                hll = (b >> (wall ? 4 : 1)) & 1u;
             }
             face_flux<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1, hll);
 #pragma unroll
@@ -615,8 +615,10 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             face_state(Wk1, Sk1, -HS, fr);
             bool hll = false;
             if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+                const bool wall = kz + 1 >= nz && a.bc[2][1] != BC_PERIODIC;
                 bool fd = false;
-                hll = transverse_shock<2>(a.flags[zko + colo], a.flags[zoff(kz + 1, fd) + colo]);
+                const unsigned b = a.flags[(wall ? zko : zoff(kz + 1, fd)) + colo];
+                hll = (b >> (wall ? 5 : 2)) & 1u;
             }
             face_flux<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1, hll);
         }
@@ -657,6 +659,10 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
             for (int v = 0; v < NP; ++v) out[v] = Uk[v] + dt * L[v];
         } else {
+            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+#pragma unroll
+                for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
+            }
 #pragma unroll
             for (int v = 0; v < NP; ++v) out[v] = T(0.5) * (u0[v] + Uk[v] + dt * L[v]);
         }

@@ -77,6 +77,27 @@ def test_switch_parity_implosion_and_3d_shock():
     assert run_parity(prob, 4) > 0
 
 
+@pytest.mark.parametrize("bcs", [((0, 0), (0, 0), (0, 0)), ((2, 1), (1, 2), (0, 0))])
+def test_switch_parity_boundaries_and_ragged_tiles_2d(bcs):
+    """Periodic wrap and mixed walls with ragged detector and stage tiles
+    (70 x 22 cells); the wrap puts a second jump at the x boundary."""
+    prob = wl.planar_shock(70, 22, amp=0.05)
+    prob.bc = bcs
+    assert run_parity(prob, 4) > 0
+
+
+@pytest.mark.parametrize("zbc", [(0, 0), (2, 2), (1, 2)])
+def test_switch_parity_3d_z_boundaries(zbc):
+    """A shock running along z (the channel rotated), z chunks of the detector
+    and stage kernels ragged (21 planes), every z boundary kind."""
+    base = wl.planar_shock(21, 10, amp=0.05, ndim=3)
+    W = np.ascontiguousarray(base.W.transpose(0, 3, 2, 1))  # (v, nz, ny, nx) -> x becomes z
+    W[[1, 3]] = W[[3, 1]]
+    prob = wl.Problem(3, (10, 10, 21), (0, 0, 0), (0.5, 0.5, 1.0), base.gamma, ((2, 2), (1, 1), zbc), W,
+                      theta=2.0, cfl=0.4, name="planar_shock_z")
+    assert run_parity(prob, 3) > 0
+
+
 def test_switch_without_shocks_is_hllc():
     """No shock anywhere: every face takes HLLC, so the switch matches the
     HLLC kernels to FP32 rounding (a separate build of the same arithmetic,
