@@ -59,7 +59,9 @@ typedef enum { HY_PRIMITIVE = 0, HY_CONSERVED = 1 } hy_kind;
 
 /*
  * Patch description.
- *  ndim        1, 2 or 3; n[q] >= 2 cells on active dimensions, 1 elsewhere.
+ *  ndim        1, 2 or 3; n[q] >= 2 cells on active dimensions, 1 elsewhere;
+ *              n[0] <= 2^20, n[1] and n[2] <= 65535, and one variable's array
+ *              below 4 GiB (HY_EINVAL otherwise).
  *  lo, hi      box corners; cell width (hi - lo) / n (uniform grid, Sec. 3).
  *  gamma       ideal-gas index, p = (gamma - 1) e (Sec. 3.4, polytropic closure).
  *  bc[q][s]    boundary kind on the low (s = 0) / high (s = 1) face of

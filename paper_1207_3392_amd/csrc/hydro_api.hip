@@ -89,8 +89,8 @@ hy_status check_desc(const hy_patch_desc *d)
         }
         if (!std::isfinite(d->accel[q])) return fail(HY_EINVAL, "accel must be finite");
     }
-    if (d->n[0] > (int64_t)1 << 20 || d->n[1] > (int64_t)1 << 20 || d->n[2] > (int64_t)1 << 20)
-        return fail(HY_EINVAL, "dimension too large");
+    if (d->n[0] > (int64_t)1 << 20 || d->n[1] > 65535 || d->n[2] > 65535)
+        return fail(HY_EINVAL, "dimension too large (n_x <= 2^20, n_y and n_z <= 65535)");
     const int64_t N = ncells(*d);
     // kernels address cells with 32-bit offsets within one variable's array
     const int64_t es = d->precision == 64 ? 8 : 4;

@@ -196,30 +196,36 @@ __global__ void __launch_bounds__(DT_X * DT_Y) k_shock_flags(const T *__restrict
     }
 }
 
+// Face decisions: one thread per cell (grid: x blocks by y by z).  The low
+// neighbour along q is the cell itself shifted by one, a ghost only at a low
+// wall.
 template <int ND>
 __global__ void __launch_bounds__(256) k_face_decisions(const uint8_t *__restrict__ det, uint8_t *__restrict__ faces,
                                                         int nx, int ny, int nz, Bc3 bc)
 {
     const int x = (int)(blockIdx.x * 256 + threadIdx.x);
     if (x >= nx) return;
+    const int pos[3] = {x, (int)blockIdx.y, (int)blockIdx.z};
     const int ext[3] = {nx, ny, nz};
-    const int stride[3] = {1, nx, nx * ny};
-    for (unsigned yz = blockIdx.y; yz < (unsigned)ny * (unsigned)nz; yz += gridDim.y) {
-        const int pos[3] = {x, (int)(yz % (unsigned)ny), (int)(yz / (unsigned)ny)};
-        const unsigned c = yz * (unsigned)nx + (unsigned)x;
-        const unsigned own = det[c];
-        unsigned out = 0;
+    const unsigned stride[3] = {1u, (unsigned)nx, (unsigned)nx * (unsigned)ny};
+    const unsigned c = ((unsigned)pos[2] * (unsigned)ny + (unsigned)pos[1]) * (unsigned)nx + (unsigned)x;
+    const unsigned own = det[c];
+    unsigned out = 0;
 #pragma unroll
-        for (int q = 0; q < ND; ++q) {
-            const unsigned mask = ~(1u << q) & 7u;
+    for (int q = 0; q < ND; ++q) {
+        const unsigned mask = ~(1u << q) & 7u;
+        unsigned lo;
+        if (pos[q] > 0) {
+            lo = det[c - stride[q]];
+        } else {
             bool flip = false;
-            const int m = map_nb(pos[q] - 1, ext[q], bc.v[q][0], bc.v[q][1], flip);
-            const unsigned lo = det[c + (unsigned)((m - pos[q]) * stride[q])];
-            if ((own | lo) & mask) out |= 1u << q;
-            if (pos[q] == ext[q] - 1 && bc.v[q][1] != BC_PERIODIC && (own & mask)) out |= 8u << q;
+            const int m = map_nb(-1, ext[q], bc.v[q][0], bc.v[q][1], flip);
+            lo = det[c + (unsigned)m * stride[q]];
         }
-        faces[c] = (uint8_t)out;
+        if ((own | lo) & mask) out |= 1u << q;
+        if (pos[q] == ext[q] - 1 && bc.v[q][1] != BC_PERIODIC && (own & mask)) out |= 8u << q;
     }
+    faces[c] = (uint8_t)out;
 }
 
 }  // namespace
@@ -234,8 +240,7 @@ hipError_t launch_shock_flags(const T *u, uint8_t *det, uint8_t *flags, const in
         b.v[q][1] = bc[q][1];
     }
     const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
-    const int64_t lines = n[1] * n[2];
-    const dim3 grid((unsigned)((n[0] + 255) / 256), (unsigned)(lines < 65535 ? lines : 65535));
+    const dim3 grid((unsigned)((n[0] + 255) / 256), (unsigned)n[1], (unsigned)n[2]);
     const int tx = (nx + DT_X - 1) / DT_X, ty = (ny + DT_Y - 1) / DT_Y, tz = (nz + DT_Z - 1) / DT_Z;
     const dim3 tgrid((unsigned)((int64_t)tx * ty * tz));
     switch (ndim) {
