@@ -60,6 +60,7 @@ class _Desc(ctypes.Structure):
         ("accel", ctypes.c_double * 3),
         ("mlp", ctypes.POINTER(ctypes.c_double)),
         ("mlp_bf16", ctypes.c_int),
+        ("shock_fp32", ctypes.c_int),
     ]
 
 
@@ -105,7 +106,7 @@ class Desc:
 
     def __init__(self, ndim, n, lo, hi, gamma, bc, solver=HLLC, theta=2.0,
                  limiter=LIM_THETA, accel=(0.0, 0.0, 0.0), mlp: Optional[np.ndarray] = None,
-                 mlp_bf16: bool = False):
+                 mlp_bf16: bool = False, shock_fp32: bool = False):
         self.ndim = ndim
         self.n = tuple(int(v) for v in n)
         self.lo, self.hi = tuple(lo), tuple(hi)
@@ -119,12 +120,13 @@ class Desc:
         if self.mlp is not None:
             assert self.mlp.size == MLP_NPARAM
         self.mlp_bf16 = bool(mlp_bf16)
+        self.shock_fp32 = bool(shock_fp32)
 
     @classmethod
     def from_problem(cls, prob, solver=HLLC, theta=None, limiter=LIM_THETA, mlp=None,
-                     mlp_bf16=False):
+                     mlp_bf16=False, shock_fp32=False):
         return cls(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.bc, solver,
-                   prob.theta if theta is None else theta, limiter, prob.accel, mlp, mlp_bf16)
+                   prob.theta if theta is None else theta, limiter, prob.accel, mlp, mlp_bf16, shock_fp32)
 
     @property
     def nv(self):
@@ -156,6 +158,7 @@ class Desc:
         d.theta = self.theta
         d.mlp = _dp(self.mlp) if self.mlp is not None else ctypes.POINTER(ctypes.c_double)()
         d.mlp_bf16 = int(self.mlp_bf16)
+        d.shock_fp32 = int(self.shock_fp32)
         self._keep = d
         return d
 

@@ -409,7 +409,13 @@ static unsigned cell_shock_bits(const orc_desc *d, const ghost_geom *G, const do
         int64_t a = gidx(G, lo3[0], lo3[1], lo3[2]), b = gidx(G, hi3[0], hi3[1], hi3[2]);
         double pa = Wg[(nd + 1) * M + a], pb = Wg[(nd + 1) * M + b];
         double va = Wg[(1 + q) * M + a], vb = Wg[(1 + q) * M + b];
-        if (fabs(pb - pa) > ORC_SHOCK_EPS * fmin(pa, pb) && vb - va < 0.0) bits |= 1u << q;
+        if (d->shock_fp32) {
+            /* the decision in the precision an FP32 kernel takes it */
+            float fpa = (float)pa, fpb = (float)pb, fva = (float)va, fvb = (float)vb;
+            if (fabsf(fpb - fpa) > (float)ORC_SHOCK_EPS * fminf(fpa, fpb) && fvb - fva < 0.0f) bits |= 1u << q;
+        } else if (fabs(pb - pa) > ORC_SHOCK_EPS * fmin(pa, pb) && vb - va < 0.0) {
+            bits |= 1u << q;
+        }
     }
     return bits;
 }

@@ -62,6 +62,8 @@ typedef struct {
     double accel[3];   /* uniform acceleration a = -grad(Phi) */
     const double *mlp; /* ORC_MLP_NPARAM parameters when limiter == learned */
     int mlp_bf16;      /* 1: round network operands to bfloat16 first */
+    int shock_fp32;    /* 1: the switch's detector compares in FP32 (the
+                          precision of an FP32 kernel's decision) */
 } orc_desc;
 
 /* Primitive <-> conserved, nv x ncell each.  cons_to_prim returns ORC_ESTATE

@@ -441,10 +441,11 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         for (int j = 0; j < HPT; ++j)
             if (hlds[j] >= 0) load(zo + hoff[j], h[j]);
     };
-    // (the switch kernels hold both flux forms; to stay within the register
-    // budget they load the halo and the second stage's U^n when they are
-    // used instead of ahead)
-    if constexpr (SOLVER != SOLVER_HLLC_SWITCH) load_halo(z0, hnext);
+    // (the switch kernels hold both flux forms and the learned-limiter ones
+    // the prefetched slopes; to stay within the register budget they load the
+    // halo and the second stage's U^n when they are used instead of ahead)
+    constexpr bool LATE = SOLVER == SOLVER_HLLC_SWITCH || LIM == LIM_LEARNED;
+    if constexpr (!LATE) load_halo(z0, hnext);
 
     T *sWf = &sW[0][0][0];
     // one plane: Wk/Uk/Sk/Flo hold plane kz, Wk1/Uk1 plane kz+1; the body
@@ -457,29 +458,61 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         bool fz2 = false;
         if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
         T u0[NP];  // U^n of the own cell (second stage), issued early, used in phase 3
-        if constexpr (STAGE == 2 && SOLVER != SOLVER_HLLC_SWITCH) {
+        if constexpr (STAGE == 2 && !LATE) {
 #pragma unroll
             for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
         }
 
         // learned limiter: the own cell's x and y slopes (and the z slope of
-        // plane kz+1) are loaded here and stored in phase 1, so their latency
-        // overlaps phase 0 and its barrier
-        T lsx[NP], lsy[NP], lsz[NP];
+        // plane kz+1) and this thread's ring slope are loaded here and stored
+        // in phase 1, so their latency overlaps phase 0 and its barrier
+        T lsx[NP], lsy[NP], lsz[NP], lry[NP], lrx[NP];
+        const int ering = tid - (NT - 2 * BY);  // x ring item of the last threads
         if constexpr (LIM == LIM_LEARNED) {
+            if (own_valid) {
+                // an interior cell: the slopes sit at its own offset (and one
+                // plane up for z, unless that plane is past the last one)
+                const unsigned o = zko + colv;
+                const bool ztop = ND == 3 && kz + 1 >= nz;
 #pragma unroll
-            for (int v = 0; v < NP; ++v) {
-                lsx[v] = learned_slope<ND>(a, 0, v, gx, gy, kz);
-                if constexpr (ND >= 2) lsy[v] = learned_slope<ND>(a, 1, v, gx, gy, kz);
-                if constexpr (ND == 3) lsz[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+                for (int v = 0; v < NP; ++v) {
+                    lsx[v] = (T)at(a.slopes + (int64_t)v * a.vstride, o);
+                    if constexpr (ND >= 2) lsy[v] = (T)at(a.slopes + (int64_t)(NP + v) * a.vstride, o);
+                    if constexpr (ND == 3)
+                        lsz[v] = ztop ? learned_slope<ND>(a, 2, v, gx, gy, kz + 1)
+                                      : (T)at(a.slopes + (int64_t)(2 * NP + v) * a.vstride, o + (unsigned)plane);
+                }
+            } else {  // a ghost column of a partial tile: boundary-mapped slopes
+#pragma unroll
+                for (int v = 0; v < NP; ++v) {
+                    lsx[v] = learned_slope<ND>(a, 0, v, gx, gy, kz);
+                    if constexpr (ND >= 2) lsy[v] = learned_slope<ND>(a, 1, v, gx, gy, kz);
+                    if constexpr (ND == 3) lsz[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
+                }
             }
+            // ring slope of cell (rx, ry): direct inside the domain, boundary
+            // mapped for a ghost
+            auto ring_slope = [&](int q, int rx, int ry, T (&out)[NP]) {
+                if (rx >= 0 && rx < nx && ry >= 0 && ry < ny) {
+                    const unsigned o = zko + (unsigned)(ry * nx + rx);
+#pragma unroll
+                    for (int v = 0; v < NP; ++v) out[v] = (T)at(a.slopes + (int64_t)(q * NP + v) * a.vstride, o);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NP; ++v) out[v] = learned_slope<ND>(a, q, v, rx, ry, kz);
+                }
+            };
+            if constexpr (ND >= 2) {
+                if (tid < 2 * BX) ring_slope(1, x0 + (tid < BX ? tid : tid - BX), y0 + (tid < BX ? -1 : BY), lry);
+            }
+            if (ering >= 0) ring_slope(0, x0 + ((ering & 1) ? BX : -1), y0 + (ering >> 1), lrx);
         }
 
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
 #pragma unroll
         for (int v = 0; v < NP; ++v) sW[v][ty + OY][tx + 2] = Wk[v];
         T hcur[HPT][NP];
-        if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+        if constexpr (LATE) {
             load_halo(kz, hcur);
         } else {
 #pragma unroll
@@ -552,12 +585,22 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 else Sk1[v] = lsz[v];
             }
         }
-        if constexpr (ND >= 2) {
-            if (tid < 2 * BX) slope_y(tid < BX ? -1 : BY, tid < BX ? tid : tid - BX);
-        }
-        {
-            const int e = tid - (NT - 2 * BY);
-            if (e >= 0) slope_x(e >> 1, (e & 1) ? BX : -1);
+        if constexpr (LIM == LIM_THETA) {
+            if constexpr (ND >= 2) {
+                if (tid < 2 * BX) slope_y(tid < BX ? -1 : BY, tid < BX ? tid : tid - BX);
+            }
+            if (ering >= 0) slope_x(ering >> 1, (ering & 1) ? BX : -1);
+        } else {
+            if constexpr (ND >= 2) {
+                if (tid < 2 * BX) {
+#pragma unroll
+                    for (int v = 0; v < NP; ++v) sSy[v][tid < BX ? 0 : BY + 1][tid < BX ? tid : tid - BX] = lry[v];
+                }
+            }
+            if (ering >= 0) {
+#pragma unroll
+                for (int v = 0; v < NP; ++v) sSx[v][ering >> 1][(ering & 1) ? BX + 1 : 0] = lrx[v];
+            }
         }
         if (ring1) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
@@ -659,7 +702,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
             for (int v = 0; v < NP; ++v) out[v] = Uk[v] + dt * L[v];
         } else {
-            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
+            if constexpr (LATE) {
 #pragma unroll
                 for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
             }

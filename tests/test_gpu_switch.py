@@ -32,7 +32,8 @@ def scale(ref):
 
 def flags_not_marginal(d, U, seed=0):
     """The detector's decisions on U do not change when U is perturbed by a
-    few FP32 roundings, so FP32 and FP64 evaluations of the detector agree."""
+    few FP32 roundings, so the kernel's primitives (rounded differently from
+    the oracle's) cannot tip a decision."""
     b = oracle.shock_bits(d, U)
     rng = np.random.default_rng(seed)
     for _ in range(3):
@@ -43,7 +44,8 @@ def flags_not_marginal(d, U, seed=0):
 
 
 def run_parity(prob, steps, prec=32, cfl=0.4):
-    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC_SWITCH)
+    # the detector's threshold decision in the kernel's precision
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC_SWITCH, shock_fp32=prec == 32)
     p = hydro.Patch(prob, precision=prec)
     U = p.get_state(hydro.CONSERVED)
     nflag = 0
