@@ -491,9 +491,10 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 }
             }
             // ring slope of cell (rx, ry): direct inside the domain, boundary
-            // mapped for a ghost
+            // mapped for a ghost (in 3D the extra code path costs more
+            // registers than the index arithmetic it saves: measured)
             auto ring_slope = [&](int q, int rx, int ry, T (&out)[NP]) {
-                if (rx >= 0 && rx < nx && ry >= 0 && ry < ny) {
+                if (ND < 3 && rx >= 0 && rx < nx && ry >= 0 && ry < ny) {
                     const unsigned o = zko + (unsigned)(ry * nx + rx);
 #pragma unroll
                     for (int v = 0; v < NP; ++v) out[v] = (T)at(a.slopes + (int64_t)(q * NP + v) * a.vstride, o);
