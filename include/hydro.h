@@ -140,6 +140,12 @@ hy_status hy_get_time(hy_patch *p, double *t_out);
  * Synchronising. */
 hy_status hy_conserved_totals(hy_patch *p, double out[5]);
 
+/* Kinetic energy per component, out[q] = integral of rho v_q^2 / 2 over the
+ * patch (the y component is the E_kin,y of the Kelvin-Helmholtz analysis,
+ * Sec. 4.3.1), as dV times an FP64 fixed-order sum of S_q^2 / (2 D) over the
+ * cells (bitwise reproducible); zeros for absent components.  Synchronising. */
+hy_status hy_kinetic_energy(hy_patch *p, double out[3]);
+
 /* Learned limiter weights: n = 1249 FP32 values, W1[32][4], b1[32],
  * W2[32][32], b2[32], w3[32], b3.  Copied to the device (W1, W2 and w3 in
  * bfloat16, biases in FP32).  Required before stepping with HY_LIM_LEARNED.  Synchronising. */

@@ -194,6 +194,17 @@ def rhs(desc: Desc, U) -> np.ndarray:
     return L
 
 
+def kinetic_energy(desc: Desc, U) -> np.ndarray:
+    """Integral of rho v_q^2 / 2 over the patch per component q (Sec. 4.3.1,
+    the y component is E_kin,y): dV times the exactly rounded sum over cells
+    of S_q^2 / (2 D)."""
+    U = _flat(desc, U)
+    out = np.zeros(3)
+    for q in range(desc.ndim):
+        out[q] = math.fsum(0.5 * U[1 + q] ** 2 / U[0]) * desc.dV()
+    return out
+
+
 def shock_bits(desc: Desc, U) -> np.ndarray:
     """Per interior cell, bit q set where the switch's detector flags a shock
     moving along q (see orc_shock_bits)."""

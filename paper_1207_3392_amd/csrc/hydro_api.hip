@@ -3,6 +3,7 @@
 // per-kernel event timing.
 #include "hydro.h"
 #include "hy_internal.h"
+#include "hy_diag.h"
 #include "hy_mlp.h"
 
 #include <algorithm>
@@ -456,6 +457,26 @@ hy_status hy_conserved_totals(hy_patch *p, double out[5])
     hy_status st = read_ctl(p, &c);
     if (st != HY_OK) return st;
     for (int k = 0; k < 5; ++k) out[k] = c.totals[k];
+    return c.err ? fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value") : HY_OK;
+}
+
+hy_status hy_kinetic_energy(hy_patch *p, double out[3])
+{
+    if (!p || !out) return fail(HY_EINVAL, "null argument");
+    double dv = 1.0;
+    for (int q = 0; q < p->d.ndim; ++q) dv *= (p->d.hi[q] - p->d.lo[q]) / (double)p->d.n[q];
+    hipError_t e;
+    if (p->d.precision == 64)
+        e = hy::launch_kinetic<double>((const double *)p->A, p->ncell, p->vstride, p->d.ndim, dv, p->partials,
+                                       hy::TOTALS_BLOCKS, p->ctl, p->stream);
+    else
+        e = hy::launch_kinetic<float>((const float *)p->A, p->ncell, p->vstride, p->d.ndim, dv, p->partials,
+                                      hy::TOTALS_BLOCKS, p->ctl, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "kinetic energy launch");
+    hy::DevCtl c;
+    hy_status st = read_ctl(p, &c);
+    if (st != HY_OK) return st;
+    for (int q = 0; q < 3; ++q) out[q] = c.totals[5 + q];
     return c.err ? fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value") : HY_OK;
 }
 

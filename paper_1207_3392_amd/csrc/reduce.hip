@@ -2,6 +2,7 @@
 // (Sec. 3.4), the CFL rate reduction (eq. courantTimeStep) and the FP64
 // conserved totals.
 #include "hy_internal.h"
+#include "hy_diag.h"
 
 #include <math.h>
 
@@ -126,6 +127,54 @@ __global__ void __launch_bounds__(RB) k_totals_final(const double *partials, int
         for (int d = ndim; d < 3; ++d) ctl->totals[1 + d] = 0.0;
 }
 
+// Kinetic energy per component, sum over cells of D v_q^2 / 2 = S_q^2 / (2 D),
+// in the same fixed chunks and trees as the totals (each cell's term formed
+// in FP64 from the stored values); results in totals[5 + q].
+template <typename T>
+__global__ void __launch_bounds__(RB) k_kinetic_partial(const T *u, int64_t ncell, int64_t vs, int ndim,
+                                                        double *partials)
+{
+    __shared__ double red[RB];
+    const int64_t C = (ncell + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * C;
+    const int64_t end = beg + C < ncell ? beg + C : ncell;
+    for (int q = 0; q < ndim; ++q) {
+        double s = 0.0;
+        for (int64_t c = beg + threadIdx.x; c < end; c += RB) {
+            const double S = (double)u[c + (1 + q) * vs];
+            s += 0.5 * S * S / (double)u[c];
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = RB / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partials[q * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_kinetic_final(const double *partials, int nblocks, int ndim, double dv,
+                                                      DevCtl *ctl)
+{
+    __shared__ double red[RB];
+    for (int q = 0; q < ndim; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += RB) s += partials[q * nblocks + b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = RB / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ctl->totals[5 + q] = red[0] * dv;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = ndim; q < 3; ++q) ctl->totals[5 + q] = 0.0;
+}
+
 __global__ void k_ctl_reset_rate(DevCtl *ctl, int slot)
 {
     if (threadIdx.x < RATE_SLOTS) ctl->rate[slot][threadIdx.x] = 0ull;
@@ -187,6 +236,15 @@ hipError_t launch_totals(const T *u, int64_t ncell, int64_t vstride, int ndim, d
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_kinetic(const T *u, int64_t ncell, int64_t vstride, int ndim, double dv, double *partials,
+                          int nblocks, DevCtl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kinetic_partial<T>, dim3(nblocks), dim3(RB), 0, s, u, ncell, vstride, ndim, partials);
+    hipLaunchKernelGGL(k_kinetic_final, dim3(1), dim3(RB), 0, s, partials, nblocks, ndim, dv, ctl);
+    return hipGetLastError();
+}
+
 hipError_t launch_ctl_reset_rate(DevCtl *ctl, int slot, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ctl_reset_rate, dim3(1), dim3(64), 0, s, ctl, slot);
@@ -205,7 +263,9 @@ hipError_t launch_ctl_init(DevCtl *ctl, hipStream_t s)
     template hipError_t launch_cfl_rate<T>(const T *, int64_t, int64_t, int64_t, int64_t, int, T, T,            \
                                            const double *, DevCtl *, int, hipStream_t);                         \
     template hipError_t launch_totals<T>(const T *, int64_t, int64_t, int, double, double *, int, DevCtl *,     \
-                                         hipStream_t);
+                                         hipStream_t);                                                          \
+    template hipError_t launch_kinetic<T>(const T *, int64_t, int64_t, int, double, double *, int, DevCtl *,    \
+                                          hipStream_t);
 HY_INST(float)
 HY_INST(double)
 

@@ -65,6 +65,7 @@ SIGNATURES = {
     "hy_advance": [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int],
     "hy_get_time": [_P, _dp],
     "hy_conserved_totals": [_P, _dp],
+    "hy_kinetic_energy": [_P, _dp],
     "hy_set_mlp": [_P, _fp, ctypes.c_size_t],
     "hy_set_timing": [_P, ctypes.c_int],
     "hy_kernel_times": [_P, _dp, _i64p],
@@ -227,6 +228,12 @@ class Patch:
     def totals(self) -> np.ndarray:
         out = np.zeros(5)
         check(lib().hy_conserved_totals(self.handle, _dptr(out)), "conserved_totals")
+        return out
+
+    def kinetic_energy(self) -> np.ndarray:
+        """Integral of rho v_q^2 / 2 per component q (FP64 reduction)."""
+        out = np.zeros(3)
+        check(lib().hy_kinetic_energy(self.handle, _dptr(out)), "kinetic_energy")
         return out
 
     def set_mlp(self, params):

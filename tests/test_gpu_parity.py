@@ -347,3 +347,21 @@ def test_launch_shapes_give_identical_results_and_autotune(nd, tmp_path):
     assert r.autotune(hydro.HLLC, reps=2, cache=cache) == (bx, by, zc, None)
     assert r.launch_cfg() == (bx, by, zc)
     r.close()
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_kinetic_energy_matches_oracle(prec):
+    """E_kin per component (the FP64 fixed-order reduction) against the
+    oracle's exactly rounded sum over the same stored state; bitwise
+    reproducible."""
+    for nd, n in ((1, (300,)), (2, (70, 33)), (3, (40, 21, 13))):
+        prob = wl.random_smooth_patch(nd, n, seed=40 + nd)
+        d = oracle.Desc.from_problem(prob)
+        p = hydro.Patch(prob, precision=prec)
+        U = p.get_state(hydro.CONSERVED)
+        got = p.kinetic_energy()
+        want = oracle.kinetic_energy(d, U)
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-16), (nd, got, want)
+        assert np.all(got[nd:] == 0.0)
+        assert np.array_equal(got, p.kinetic_energy())
+        p.close()
