@@ -28,7 +28,7 @@ import time
 
 import numpy as np
 
-from . import hydro, limiter
+from . import diagnostics, hydro, limiter
 from . import workloads as wl
 
 HELD_OUT_SEED = 4242
@@ -137,9 +137,12 @@ def restrict(a: np.ndarray, n: int) -> np.ndarray:
     return a.reshape(n, r, n, r).mean(axis=(1, 3))
 
 
-def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64):
+def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64, diag=None):
     """Density at each requested time (plain limiter if params is None),
-    with the wall time of the whole run."""
+    with the wall time of the whole run.  With a dict ``diag`` (2D), also
+    E_kin,y at each time (diag["ekin_y"]) and the kinetic-energy spectrum at
+    the last time (diag["spectrum"] = (k, e)); their cost is outside the wall
+    time."""
     import torch
 
     cfl = prob.cfl if cfl is None else cfl
@@ -149,15 +152,21 @@ def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64):
         p.set_mlp(params)
         p.set_state(prob.W)
     out = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    wall = 0.0
     for T in times:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         while p.time() < T * (1 - 1e-12):
             p.advance(chunk, cfl, t_end=T, solver=hydro.HLLC)
         U = p.get_state(hydro.CONSERVED)
+        wall += time.perf_counter() - t0
         shape = (prob.n[1], prob.n[0]) if prob.ndim == 2 else (prob.n[0],)
         out[T] = U[0].reshape(shape).copy()
-    wall = time.perf_counter() - t0
+        if diag is not None:
+            diag.setdefault("ekin_y", []).append(float(p.kinetic_energy()[1]))
+            if T == times[-1]:
+                W = p.get_state(hydro.PRIMITIVE).reshape((prob.ndim + 2,) + shape)
+                diag["spectrum"] = diagnostics.kinetic_spectrum(W, prob.hi[0] - prob.lo[0])
     p.close()
     return out, wall
 
@@ -179,18 +188,46 @@ def loglog_resolution(ns, errs, target):
     return float(math.exp(ln[i] + (lt - le[i]) / slope))
 
 
-def ladder(name, make, ns, n_ref, times, params, log=print):
-    """L1 of plain and learned runs at each N against the restricted fine plain run."""
-    ref, ref_wall = run_to_times(make(n_ref), times)
+def spectral_error(k, e, kr, er, n, level: float = 1e-9):
+    """Mean |ln(e / e_ref)| over the shells 1 .. n/4 (the well-resolved part of
+    an n-cell run's spectrum) on which the reference carries more than
+    ``level`` (below it the reference spectrum is roundoff)."""
+    m = max(1, n // 4)
+    keep = np.nonzero(er[1:m + 1] > level)[0] + 1
+    if keep.size == 0:
+        return float("nan")
+    return float(np.mean(np.abs(np.log(e[keep] / er[keep]))))
+
+
+def ladder(name, make, ns, n_ref, times, params, log=print, diagnose=False):
+    """L1 of plain and learned runs at each N against the restricted fine plain
+    run; with ``diagnose`` (2D) also E_kin,y(t) of every run and the kinetic
+    energy spectra at the last time (Sec. 4.3.1's yardsticks)."""
+    dref = {} if diagnose else None
+    ref, ref_wall = run_to_times(make(n_ref), times, diag=dref)
     log(f"{name}: reference {n_ref} in {ref_wall:.1f} s")
     rows = []
+    spectra = {}
     for n in ns:
-        pl, wp = run_to_times(make(n), times)
-        le, wlr = run_to_times(make(n), times, params=params)
-        for T in times:
+        dp = {} if diagnose else None
+        dl = {} if diagnose else None
+        pl, wp = run_to_times(make(n), times, diag=dp)
+        le, wlr = run_to_times(make(n), times, params=params, diag=dl)
+        if diagnose:
+            kr, er = dref["spectrum"]
+            spectra[n] = {
+                "spectral_error_plain": spectral_error(*dp["spectrum"], kr, er, n),
+                "spectral_error_learned": spectral_error(*dl["spectrum"], kr, er, n),
+                "cutoff_1e-9_plain": diagnostics.spectral_cutoff(*dp["spectrum"], 1e-9),
+                "cutoff_1e-9_learned": diagnostics.spectral_cutoff(*dl["spectrum"], 1e-9)}
+        for i, T in enumerate(times):
             r = restrict(ref[T], n)
-            rows.append({"n": n, "t": T, "l1_plain": float(np.mean(np.abs(pl[T] - r))),
-                         "l1_learned": float(np.mean(np.abs(le[T] - r))), "wall_plain": wp, "wall_learned": wlr})
+            row = {"n": n, "t": T, "l1_plain": float(np.mean(np.abs(pl[T] - r))),
+                   "l1_learned": float(np.mean(np.abs(le[T] - r))), "wall_plain": wp, "wall_learned": wlr}
+            if diagnose:
+                row.update({"ekin_y_plain": dp["ekin_y"][i], "ekin_y_learned": dl["ekin_y"][i],
+                            "ekin_y_reference": dref["ekin_y"][i]})
+            rows.append(row)
         log(f"{name}: N={n} " + " ".join(f"t={r['t']}: plain {r['l1_plain']:.3e} learned {r['l1_learned']:.3e}"
                                              for r in rows[-len(times):]))
     matched = []
@@ -202,7 +239,11 @@ def ladder(name, make, ns, n_ref, times, params, log=print):
             n_eq = loglog_resolution(nsub, lp, r["l1_learned"])
             matched.append({"t": T, "n_learned": r["n"], "l1_learned": r["l1_learned"],
                             "plain_n_for_same_l1": n_eq, "resolution_gain": n_eq / r["n"]})
-    return {"problem": name, "n_ref": n_ref, "times": list(times), "rows": rows, "matched": matched}
+    out = {"problem": name, "n_ref": n_ref, "times": list(times), "rows": rows, "matched": matched}
+    if diagnose:
+        out["spectra_at_last_time"] = {str(n): v for n, v in spectra.items()}
+        out["cutoff_1e-9_reference"] = diagnostics.spectral_cutoff(*dref["spectrum"], 1e-9)
+    return out
 
 
 def evaluate(params, kh_ns=(128, 256, 512, 1024), kh_ref=4096, kh_times=(0.5, 1.0, 1.5), seed=HELD_OUT_SEED,
@@ -212,7 +253,7 @@ def evaluate(params, kh_ns=(128, 256, 512, 1024), kh_ref=4096, kh_times=(0.5, 1.
     tube and the smooth density wave."""
     res = {"kelvin_helmholtz": ladder("kelvin_helmholtz",
                                       lambda n: wl.kelvin_helmholtz(n, seed=seed, width=EVAL_WIDTH, random_amp=0.0),
-                                      kh_ns, kh_ref, kh_times, params, log)}
+                                      kh_ns, kh_ref, kh_times, params, log, diagnose=True)}
     res["sod"] = ladder("sod", lambda n: wl.sod(n, theta=2.0, cfl=0.4, t_end=0.2), (128, 256, 512, 1024),
                         16384, (0.2,), params, log)
     res["advection_1d"] = ladder("advection_1d", lambda n: wl.advection_1d(n, theta=2.0),
