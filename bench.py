@@ -224,7 +224,8 @@ def matched_l1(cost_ratio_2d=None):
     a ladder of N against a fine plain run restricted to each N (well-posed
     Kelvin-Helmholtz with tanh shear layers at t = 1.5, Sod at t = 0.2), the
     resolution the plain method needs for the learned limiter's L1 (log-log
-    interpolation) and, from the measured cost per zone-update of the two
+    interpolation), for KH also the spectral error of both against the fine
+    run's kinetic-energy spectrum, and, from the measured cost per zone-update of the two
     paths at 2048^2, the wall-time ratio learned / plain at equal L1 for the 2D
     problem, whose cost scales as N^3."""
     from paper_1207_3392_amd import limiter, limiter_study as ls
@@ -237,11 +238,15 @@ def matched_l1(cost_ratio_2d=None):
             ("kelvin_helmholtz_t1.5", lambda n: wl.kelvin_helmholtz(n, seed=ls.HELD_OUT_SEED, width=ls.EVAL_WIDTH,
                                                                     random_amp=0.0), (128, 256, 512), 2048, 1.5, 2),
             ("sod_t0.2", lambda n: wl.sod(n, theta=2.0, cfl=0.4, t_end=0.2), (128, 256, 512, 1024), 16384, 0.2, 1)):
-        r = ls.ladder(key, make, ns, nref, (T,), P, log=quiet)
+        r = ls.ladder(key, make, ns, nref, (T,), P, log=quiet, diagnose=d == 2)
         gains = [m["resolution_gain"] for m in r["matched"]]
         entry = {"n": list(ns), "n_reference": nref,
                  "l1_plain": [x["l1_plain"] for x in r["rows"]], "l1_learned": [x["l1_learned"] for x in r["rows"]],
                  "resolution_gain": gains}
+        if d == 2:  # the kinetic-energy spectrum yardstick (mean |ln(e / e_ref)| over resolved shells)
+            sp = r["spectra_at_last_time"]
+            entry["spectral_error_plain"] = [sp[str(n)]["spectral_error_plain"] for n in ns]
+            entry["spectral_error_learned"] = [sp[str(n)]["spectral_error_learned"] for n in ns]
         if cost_ratio_2d is not None and d == 2:
             entry["time_ratio_learned_over_plain"] = [cost_ratio_2d / g ** (d + 1) for g in gains]
         out[key] = entry
