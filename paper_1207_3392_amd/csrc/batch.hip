@@ -126,9 +126,12 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
         }
 
         bool bad = false;
-        float rate = 0.f;  // max (|v| + c) / dx of the current state, this thread
-        // stage input -> primitives in LDS (+ ghosts)
-        auto fill = [&](const float (&S)[CPT][3], bool want_rate) {
+        // stage input -> primitives in LDS, the ghosts written by the threads
+        // that own their source cells (one barrier); with want_rate the
+        // block max of (|v| + c) / dx of the state is returned (each wave's
+        // max goes to LDS before the barrier)
+        auto fill = [&](const float (&S)[CPT][3], bool want_rate) -> float {
+            float rate = 0.f;
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
                 const int i = tid + k * BT;
@@ -141,24 +144,38 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                     sW[1 * SW + i + 2] = v;
                     sW[2 * SW + i + 2] = p;
                     if (want_rate) rate = fmaxf(rate, (fabsf(v) + soundf(g, p, D)) * idx);
+                    if (i < 2 || i >= n - 2) {
+                        // ghosts -2, -1, n, n+1 whose source is this cell
+#pragma unroll
+                        for (int gk = 0; gk < 4; ++gk) {
+                            const int gi = gk < 2 ? gk - 2 : n + gk - 2;
+                            const int bc = gk < 2 ? d.bclo : d.bchi;
+                            int src;
+                            bool flip = false;
+                            if (bc == BC_PERIODIC) src = gk < 2 ? gi + n : gi - n;
+                            else if (bc == BC_OUTFLOW) src = gk < 2 ? 0 : n - 1;
+                            else { src = gk < 2 ? -1 - gi : 2 * n - 1 - gi; flip = true; }
+                            if (src == i) {
+                                sW[0 * SW + gi + 2] = D;
+                                sW[1 * SW + gi + 2] = flip ? -v : v;
+                                sW[2 * SW + gi + 2] = p;
+                            }
+                        }
+                    }
                 }
             }
-            __syncthreads();
-            if (tid < 4) {
-                // ghosts -2, -1 (tid 0, 1) and n, n+1 (tid 2, 3)
-                const int gi = tid < 2 ? tid - 2 : n + tid - 2;
-                const int side = tid < 2 ? 0 : 1;
-                const int bc = side == 0 ? d.bclo : d.bchi;
-                int src;
-                bool flip = false;
-                if (bc == BC_PERIODIC) src = side == 0 ? gi + n : gi - n;
-                else if (bc == BC_OUTFLOW) src = side == 0 ? 0 : n - 1;
-                else { src = side == 0 ? -1 - gi : 2 * n - 1 - gi; flip = true; }
-                sW[0 * SW + gi + 2] = sW[0 * SW + src + 2];
-                sW[1 * SW + gi + 2] = flip ? -sW[1 * SW + src + 2] : sW[1 * SW + src + 2];
-                sW[2 * SW + gi + 2] = sW[2 * SW + src + 2];
+            if (want_rate) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) rate = fmaxf(rate, __shfl_xor(rate, off, 64));
+                if ((tid & 63) == 0) sred[tid >> 6] = rate;
             }
             __syncthreads();
+            float m = 0.f;
+            if (want_rate) {
+#pragma unroll
+                for (int w = 0; w < BT / 64; ++w) m = fmaxf(m, sred[w]);
+            }
+            return m;
         };
         auto faces = [&]() {
             for (int f = tid; f <= n; f += BT) {
@@ -175,23 +192,10 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
             }
             __syncthreads();
         };
-        auto block_max = [&](float r) -> float {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
-            if ((tid & 63) == 0) sred[tid >> 6] = r;
-            __syncthreads();
-            float m = 0.f;
-#pragma unroll
-            for (int w = 0; w < BT / 64; ++w) m = fmaxf(m, sred[w]);
-            __syncthreads();
-            return m;
-        };
 
         double t = 0.0;
         int steps = 0;
-        rate = 0.f;
-        fill(U0, true);
-        float r = block_max(rate);
+        float r = fill(U0, true);  // CFL rate of the state
         bool stop = false;
         while (t < t_end && !stop) {
             double dt = fmin(cfl / (double)r, t_end - t);
@@ -209,7 +213,8 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                 for (int v = 0; v < 3; ++v)
                     Us[k][v] = i < n ? U0[k][v] + dtf * (sF[v * SF + i] - sF[v * SF + i + 1]) * idx : 1.f;
             }
-            __syncthreads();
+            // (no barrier: the flux reads above end before any thread passes
+            // the barrier in fill, and only the next faces() writes sF)
             fill(Us, false);
             // stage 2: U^{n+1} = (U^n + U1 + dt L(U1)) / 2
             faces();
@@ -221,10 +226,7 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                     U0[k][v] = i < n ? 0.5f * (U0[k][v] + Us[k][v] + dtf * (sF[v * SF + i] - sF[v * SF + i + 1]) * idx)
                                      : 1.f;
             }
-            __syncthreads();
-            rate = 0.f;
-            fill(U0, true);
-            r = block_max(rate);
+            r = fill(U0, true);
             t += dt;
             ++steps;
         }
