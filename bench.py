@@ -30,7 +30,7 @@ BYTES_PER_CELL = {1: 40.0, 2: 60.0}  # stage 1 reads U^n, writes U1; stage 2 rea
 
 # The stage kernels are bound by vector-ALU issue, not by HBM, so the roofline
 # is the FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed
-# FP32) x 2.4 GHz.  Packed FP32 is switched off in this build, which halves
+# FP32) x 2.4 GHz.  Packed FP32 is switched off in the library, which halves
 # what the kernels can reach (78.6 TFLOP/s).
 ALU_PEAK_TFLOPS = 157.3
 ALU_PEAK_UNPACKED_TFLOPS = 78.6
