@@ -64,6 +64,20 @@ class _Desc(ctypes.Structure):
     ]
 
 
+FMR_MAXLEV = 8
+NG = 2
+
+
+class _FmrDesc(ctypes.Structure):
+    _fields_ = [
+        ("base", _Desc),
+        ("nlev", ctypes.c_int),
+        ("box_lo", (ctypes.c_int64 * 3) * FMR_MAXLEV),
+        ("box_n", (ctypes.c_int64 * 3) * FMR_MAXLEV),
+        ("no_reflux", ctypes.c_int),
+    ]
+
+
 _lib = None
 
 
@@ -88,6 +102,11 @@ def lib():
             ("orc_physical", [P, ctypes.c_int, dp, dp, dp, dp, dp], None),
             ("orc_hllc_star", [P, ctypes.c_int, dp, dp, dp], None),
             ("orc_shock_bits", [P, dp, ctypes.POINTER(ctypes.c_ubyte)], ctypes.c_int),
+            ("orc_fmr_level", [ctypes.POINTER(_FmrDesc), ctypes.c_int, P], ctypes.c_int),
+            ("orc_fmr_prolong", [ctypes.POINTER(_FmrDesc), ctypes.c_int, dp, dp], ctypes.c_int),
+            ("orc_fmr_restrict", [ctypes.POINTER(_FmrDesc), ctypes.c_int, dp, dp], ctypes.c_int),
+            ("orc_fmr_step", [ctypes.POINTER(_FmrDesc), ctypes.POINTER(dp), ctypes.c_double, ctypes.c_double, dp],
+             ctypes.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -329,3 +348,102 @@ def hllc_star(desc: Desc, q: int, wl, wr) -> dict:
         "U_star_L": out[3:3 + nv], "U_star_R": out[3 + nv:3 + 2 * nv],
         "F_star_L": out[3 + 2 * nv:3 + 3 * nv], "F_star_R": out[3 + 3 * nv:3 + 4 * nv],
     }
+
+
+# ---- fixed multilevel refinement (Sec. 2 prolongation / restriction, Sec. 3.5 Algs. Evolve..StepLevel) ----
+
+class FmrDesc:
+    """Nested levels: ``base`` is level 0; ``boxes[l - 1] = (lo, n)`` is the
+    box of level l - 1 cells that level l refines by two (unused dimensions:
+    lo 0, n 1)."""
+
+    def __init__(self, base: Desc, boxes, no_reflux: bool = False):
+        self.base = base
+        self.boxes = [(tuple(int(v) for v in lo), tuple(int(v) for v in n)) for lo, n in boxes]
+        self.nlev = 1 + len(self.boxes)
+        assert self.nlev <= FMR_MAXLEV
+        self.no_reflux = bool(no_reflux)
+        self.levels = [self.level(l) for l in range(self.nlev)]
+
+    def c(self) -> _FmrDesc:
+        f = _FmrDesc()
+        f.base = self.base.c()
+        f.nlev = self.nlev
+        for l, (lo, n) in enumerate(self.boxes, start=1):
+            for q in range(3):
+                f.box_lo[l][q] = lo[q]
+                f.box_n[l][q] = n[q]
+        f.no_reflux = int(self.no_reflux)
+        self._keep = (f, self.base._keep)
+        return f
+
+    def level(self, l: int) -> Desc:
+        out = _Desc()
+        st = lib().orc_fmr_level(ctypes.byref(self.c()), int(l), ctypes.byref(out))
+        if st != OK:
+            raise OracleError(st, "fmr_level")
+        b = self.base
+        return Desc(b.ndim, tuple(out.n), tuple(out.lo), tuple(out.hi), b.gamma,
+                    tuple((out.bc[q][0], out.bc[q][1]) for q in range(3)), b.solver, b.theta, b.limiter, b.accel)
+
+    def ghosted_shape(self, l: int):
+        d = self.levels[l]
+        return tuple(d.n[q] + (2 * NG if q < d.ndim else 0) for q in range(3))
+
+    def covered(self, l: int) -> np.ndarray:
+        """Boolean (ncell,) of level l: True where level l + 1 covers the cell."""
+        d = self.levels[l]
+        m = np.zeros((d.n[2], d.n[1], d.n[0]), dtype=bool)
+        if l + 1 < self.nlev:
+            lo, n = self.boxes[l]
+            m[lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]] = True
+        return m.ravel()
+
+
+def fmr_prolong(f: FmrDesc, l: int, Uparent) -> np.ndarray:
+    """Level l's exterior from its parent: (nv, ghosted cells) with NaN in
+    the interior cells, which prolongation does not write."""
+    Up = _flat(f.levels[l - 1], Uparent)
+    m = f.ghosted_shape(l)
+    ext = np.full((f.base.nv, m[0] * m[1] * m[2]), np.nan)
+    st = lib().orc_fmr_prolong(ctypes.byref(f.c()), int(l), _dp(Up), _dp(ext))
+    if st != OK:
+        raise OracleError(st, "fmr_prolong")
+    return ext
+
+
+def fmr_restrict(f: FmrDesc, l: int, Uchild, Uparent) -> np.ndarray:
+    Uc = _flat(f.levels[l], Uchild)
+    Up = _flat(f.levels[l - 1], Uparent).copy()
+    st = lib().orc_fmr_restrict(ctypes.byref(f.c()), int(l), _dp(Uc), _dp(Up))
+    if st != OK:
+        raise OracleError(st, "fmr_restrict")
+    return Up
+
+
+def fmr_step(f: FmrDesc, Us, cfl: float = 0.4, dt_fixed: float = 0.0):
+    """One global step of every level; returns (new level states, coarse dt)."""
+    Us = [_flat(f.levels[l], U).copy() for l, U in enumerate(Us)]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * f.nlev)(*[_dp(U) for U in Us])
+    out = np.zeros(1)
+    st = lib().orc_fmr_step(ctypes.byref(f.c()), ptrs, float(cfl), float(dt_fixed), _dp(out))
+    if st != OK:
+        raise OracleError(st, "fmr_step")
+    return Us, float(out[0])
+
+
+def fmr_totals(f: FmrDesc, Us) -> np.ndarray:
+    """Conserved totals over the leaf cells (cells no finer level covers),
+    each level's cells weighted by its cell volume; exactly rounded sums."""
+    nd = f.base.ndim
+    parts = [[] for _ in range(5)]
+    for l, U in enumerate(Us):
+        d = f.levels[l]
+        U = _flat(d, U)
+        leaf = ~f.covered(l)
+        dv = d.dV()
+        comps = [0] + [1 + r for r in range(nd)] + [nd + 1]
+        slots = [0] + [1 + r for r in range(nd)] + [4]
+        for c, s in zip(comps, slots):
+            parts[s].extend((U[c][leaf] * dv).tolist())
+    return np.array([math.fsum(p) for p in parts])

@@ -350,8 +350,10 @@ static int64_t gidx(const ghost_geom *G, int64_t i, int64_t j, int64_t k)
 }
 
 /* Interior primitives into the ghosted array, then every ghost cell from its
- * mapped interior source. */
-static int fill_primitives(const orc_desc *d, const double *U, const ghost_geom *G, double *Wg)
+ * mapped interior source, or, when Uext is given (a refined level, whose
+ * exterior comes from the next coarser level), from the conserved values Uext
+ * holds at that ghost cell (ghosted layout). */
+static int fill_primitives(const orc_desc *d, const double *U, const double *Uext, const ghost_geom *G, double *Wg)
 {
     int nd = d->ndim, nv = nvars(d);
     int64_t N = ncells(d), M = G->m[0] * G->m[1] * G->m[2];
@@ -371,6 +373,13 @@ static int fill_primitives(const orc_desc *d, const double *U, const ghost_geom 
             for (int64_t i = -G->g[0]; i < d->n[0] + G->g[0]; ++i) {
                 int inside = i >= 0 && i < d->n[0] && j >= 0 && j < d->n[1] && k >= 0 && k < d->n[2];
                 if (inside) continue;
+                if (Uext) {
+                    int64_t g = gidx(G, i, j, k);
+                    for (int v = 0; v < nv; ++v) u[v] = Uext[v * M + g];
+                    if (!cons_to_prim_1(nd, d->gamma, u, w)) status = ORC_ESTATE;
+                    for (int v = 0; v < nv; ++v) Wg[v * M + g] = w[v];
+                    continue;
+                }
                 int flip[3] = {0, 0, 0};
                 int64_t si = map_coord(i, d->n[0], d->bc[0], &flip[0]);
                 int64_t sj = nd > 1 ? map_coord(j, d->n[1], d->bc[1], &flip[1]) : 0;
@@ -427,7 +436,7 @@ int orc_shock_bits(const orc_desc *d, const double *U, unsigned char *bits)
     int64_t M = G.m[0] * G.m[1] * G.m[2];
     double *Wg = (double *)malloc(sizeof(double) * nvars(d) * M);
     if (!Wg) return ORC_EINVAL;
-    int status = fill_primitives(d, U, &G, Wg);
+    int status = fill_primitives(d, U, NULL, &G, Wg);
     for (int64_t k = 0; k < d->n[2]; ++k)
         for (int64_t j = 0; j < d->n[1]; ++j)
             for (int64_t i = 0; i < d->n[0]; ++i)
@@ -441,7 +450,19 @@ int orc_shock_bits(const orc_desc *d, const double *U, unsigned char *bits)
 /* Cartesian grid: L = -sum_q (F_{i+1/2} - F_{i-1/2}) / dq + S.              */
 /* ------------------------------------------------------------------------ */
 
-int orc_rhs(const orc_desc *d, const double *U, double *L)
+/* Face fluxes a multilevel step needs (Alg. StepLevel): own[q][s] receives
+ * the fluxes through the level's own low (s = 0) and high (s = 1) boundary
+ * faces normal to q, child[q][s] those through the faces of the box of cells
+ * the next finer level covers.  Layout nv x (t2, t1), t1 the index along
+ * dimension (q + 1) % 3 and t2 along (q + 2) % 3, over the level's cells
+ * (own) or the box's cells (child).  NULL pointers are skipped. */
+typedef struct {
+    double *own[3][2];
+    double *child[3][2];
+    int64_t clo[3], cn[3]; /* the child box, in this level's cells */
+} face_rec;
+
+static int rhs_core(const orc_desc *d, const double *U, const double *Uext, double *L, face_rec *rec)
 {
     if (!valid_desc(d)) return ORC_EINVAL;
     int nd = d->ndim, nv = nvars(d);
@@ -450,7 +471,7 @@ int orc_rhs(const orc_desc *d, const double *U, double *L)
     int64_t M = G.m[0] * G.m[1] * G.m[2];
     double *Wg = (double *)malloc(sizeof(double) * nv * M);
     if (!Wg) return ORC_EINVAL;
-    int status = fill_primitives(d, U, &G, Wg);
+    int status = fill_primitives(d, U, Uext, &G, Wg);
 
     /* sources: S = (0, rho a, rho v . a) for a uniform acceleration a */
     for (int64_t c = 0; c < N; ++c) {
@@ -534,6 +555,22 @@ int orc_rhs(const orc_desc *d, const double *U, double *L)
                     }
                     for (int v = 0; v < nv; ++v) F[v * (nq + 1) + f] = flx[v];
                 }
+                if (rec) {
+                    int64_t t = b * t1n + a;
+                    for (int v = 0; v < nv; ++v) {
+                        if (rec->own[q][0]) rec->own[q][0][v * t1n * t2n + t] = F[v * (nq + 1) + 0];
+                        if (rec->own[q][1]) rec->own[q][1][v * t1n * t2n + t] = F[v * (nq + 1) + nq];
+                    }
+                    int r1 = (q + 1) % 3, r2 = (q + 2) % 3;
+                    int64_t ca = a - rec->clo[r1], cb = b - rec->clo[r2];
+                    if (rec->child[q][0] && ca >= 0 && ca < rec->cn[r1] && cb >= 0 && cb < rec->cn[r2]) {
+                        int64_t ct = cb * rec->cn[r1] + ca, cnt = rec->cn[r1] * rec->cn[r2];
+                        for (int v = 0; v < nv; ++v) {
+                            rec->child[q][0][v * cnt + ct] = F[v * (nq + 1) + rec->clo[q]];
+                            rec->child[q][1][v * cnt + ct] = F[v * (nq + 1) + rec->clo[q] + rec->cn[q]];
+                        }
+                    }
+                }
                 for (int64_t s = 0; s < nq; ++s) {
                     idx3[q] = s;
                     idx3[(q + 1) % 3] = a;
@@ -550,6 +587,8 @@ int orc_rhs(const orc_desc *d, const double *U, double *L)
     free(Wg);
     return status;
 }
+
+int orc_rhs(const orc_desc *d, const double *U, double *L) { return rhs_core(d, U, NULL, L, NULL); }
 
 /* eqs. Update and RungeKutta1-3: K1 = dt L(U^n), U1 = U^n + K1,
  * K2 = dt L(U1), U^{n+1} = U^n + (K1 + K2) / 2. */
@@ -598,4 +637,361 @@ int orc_cfl_dt(const orc_desc *d, const double *U, double cfl, double *dt)
     }
     *dt = cfl * m;
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed multilevel refinement: nested levels, each a box of cells of the   */
+/* next coarser level refined by two in every active dimension (Sec. 2, the */
+/* refinable mesh), stepped with subcycling and conservative coarse/fine    */
+/* flux replacement (Sec. 3.5, Algs. Evolve, EvolveLevel and StepLevel).   */
+/* Readings where the paper leaves the detail open:                         */
+/*  - prolongation only ever fills a level's exterior, so it need not      */
+/*    conserve: it is linear in the primitive variables with minmod-limited */
+/*    per-dimension differences of the parent (the limited option of the    */
+/*    paper's footnote), which keeps density and pressure positive next to  */
+/*    strong shocks; a child at offset +-1/4 of the parent width along q    */
+/*    takes W_p +- sigma_q / 4.  Restriction is the mean of the children's  */
+/*    conserved variables.                                                  */
+/*  - a refined level's exterior (ng cells around it) is prolonged once per */
+/*    step and held fixed through both Runge-Kutta stages;                  */
+/*  - before the provisional step of a refined coarse level its exterior is */
+/*    prolonged from its own parent as it stands (the same data the full   */
+/*    step then uses);                                                      */
+/*  - the coarse/fine replacement acts on the step's net update: the coarse */
+/*    cell outside the child box gets the difference between the fine       */
+/*    fluxes, integrated over both fine steps and averaged over the fine    */
+/*    faces of the coarse face, and its own flux integrated over the step.  */
+/* ------------------------------------------------------------------------ */
+
+static int fmr_valid(const orc_fmr_desc *f)
+{
+    if (!f || f->nlev < 1 || f->nlev > ORC_FMR_MAXLEV || !valid_desc(&f->base)) return 0;
+    if (f->base.solver != ORC_HLL && f->base.solver != ORC_HLLC) return 0;
+    if (f->base.limiter != ORC_LIM_THETA) return 0;
+    int64_t n[3] = {f->base.n[0], f->base.n[1], f->base.n[2]};
+    for (int l = 1; l < f->nlev; ++l)
+        for (int q = 0; q < 3; ++q) {
+            if (q < f->base.ndim) {
+                if (f->box_n[l][q] < 1 || f->box_lo[l][q] < NG || f->box_lo[l][q] + f->box_n[l][q] > n[q] - NG)
+                    return 0;
+                n[q] = 2 * f->box_n[l][q];
+            } else if (f->box_lo[l][q] != 0 || f->box_n[l][q] != 1) {
+                return 0;
+            }
+        }
+    return 1;
+}
+
+int orc_fmr_level(const orc_fmr_desc *f, int l, orc_desc *out)
+{
+    if (!fmr_valid(f) || l < 0 || l >= f->nlev || !out) return ORC_EINVAL;
+    orc_desc d = f->base;
+    for (int k = 1; k <= l; ++k)
+        for (int q = 0; q < d.ndim; ++q) {
+            double dq = cell_width(&d, q);
+            d.lo[q] = d.lo[q] + (double)f->box_lo[k][q] * dq;
+            d.hi[q] = d.lo[q] + (double)f->box_n[k][q] * dq;
+            d.n[q] = 2 * f->box_n[k][q];
+            /* the exterior is supplied by prolongation; the kinds are unused */
+            d.bc[q][0] = d.bc[q][1] = ORC_BC_OUTFLOW;
+        }
+    *out = d;
+    return ORC_OK;
+}
+
+static int64_t floor_half(int64_t i) { return i >= 0 ? i / 2 : -((-i + 1) / 2); }
+
+int orc_fmr_prolong(const orc_fmr_desc *f, int l, const double *Uparent, double *Uext)
+{
+    if (!fmr_valid(f) || l < 1 || l >= f->nlev || !Uparent || !Uext) return ORC_EINVAL;
+    orc_desc pd, cd;
+    orc_fmr_level(f, l - 1, &pd);
+    orc_fmr_level(f, l, &cd);
+    int nd = cd.ndim, nv = nvars(&cd);
+    int64_t NP = ncells(&pd);
+    ghost_geom G = make_geom(&cd);
+    int64_t M = G.m[0] * G.m[1] * G.m[2];
+    int status = ORC_OK;
+    for (int64_t k = -G.g[2]; k < cd.n[2] + G.g[2]; ++k)
+        for (int64_t j = -G.g[1]; j < cd.n[1] + G.g[1]; ++j)
+            for (int64_t i = -G.g[0]; i < cd.n[0] + G.g[0]; ++i) {
+                int inside = i >= 0 && i < cd.n[0] && j >= 0 && j < cd.n[1] && k >= 0 && k < cd.n[2];
+                if (inside) continue;
+                int64_t c3[3] = {i, j, k}, p3[3], s3[3];
+                for (int q = 0; q < 3; ++q) {
+                    if (q < nd) {
+                        p3[q] = f->box_lo[l][q] + floor_half(c3[q]);
+                        s3[q] = c3[q] - 2 * floor_half(c3[q]);
+                    } else {
+                        p3[q] = 0;
+                        s3[q] = 0;
+                    }
+                }
+                /* the parent and its two neighbours along each active q, in
+                 * primitive variables */
+                double w0[5], wm[3][5], wp[3][5], u[5], wc[5];
+                int64_t pc = (p3[2] * pd.n[1] + p3[1]) * pd.n[0] + p3[0];
+                for (int v = 0; v < nv; ++v) u[v] = Uparent[v * NP + pc];
+                if (!cons_to_prim_1(nd, cd.gamma, u, w0)) status = ORC_ESTATE;
+                for (int q = 0; q < nd; ++q) {
+                    int64_t lo3[3] = {p3[0], p3[1], p3[2]}, hi3[3] = {p3[0], p3[1], p3[2]};
+                    lo3[q] -= 1;
+                    hi3[q] += 1;
+                    int64_t cm = (lo3[2] * pd.n[1] + lo3[1]) * pd.n[0] + lo3[0];
+                    int64_t cp = (hi3[2] * pd.n[1] + hi3[1]) * pd.n[0] + hi3[0];
+                    for (int v = 0; v < nv; ++v) u[v] = Uparent[v * NP + cm];
+                    if (!cons_to_prim_1(nd, cd.gamma, u, wm[q])) status = ORC_ESTATE;
+                    for (int v = 0; v < nv; ++v) u[v] = Uparent[v * NP + cp];
+                    if (!cons_to_prim_1(nd, cd.gamma, u, wp[q])) status = ORC_ESTATE;
+                }
+                for (int v = 0; v < nv; ++v) {
+                    double val = w0[v];
+                    for (int q = 0; q < nd; ++q) {
+                        double sigma = orc_limiter_theta(w0[v] - wm[q][v], wp[q][v] - w0[v], 1.0);
+                        val += (s3[q] ? 0.25 : -0.25) * sigma;
+                    }
+                    wc[v] = val;
+                }
+                prim_to_cons_1(nd, cd.gamma, wc, u);
+                int64_t g = gidx(&G, i, j, k);
+                for (int v = 0; v < nv; ++v) Uext[v * M + g] = u[v];
+            }
+    return status;
+}
+
+int orc_fmr_restrict(const orc_fmr_desc *f, int l, const double *Uchild, double *Uparent)
+{
+    if (!fmr_valid(f) || l < 1 || l >= f->nlev || !Uparent || !Uchild) return ORC_EINVAL;
+    orc_desc pd, cd;
+    orc_fmr_level(f, l - 1, &pd);
+    orc_fmr_level(f, l, &cd);
+    int nd = cd.ndim, nv = nvars(&cd);
+    int64_t NP = ncells(&pd), NC = ncells(&cd);
+    int nchild = 1 << nd;
+    for (int64_t k = 0; k < f->box_n[l][2]; ++k)
+        for (int64_t j = 0; j < f->box_n[l][1]; ++j)
+            for (int64_t i = 0; i < f->box_n[l][0]; ++i) {
+                int64_t pc = ((f->box_lo[l][2] + k) * pd.n[1] + f->box_lo[l][1] + j) * pd.n[0] + f->box_lo[l][0] + i;
+                for (int v = 0; v < nv; ++v) {
+                    double sum = 0.0;
+                    for (int o = 0; o < nchild; ++o) {
+                        int64_t ci = nd > 0 ? 2 * i + (o & 1) : i;
+                        int64_t cj = nd > 1 ? 2 * j + ((o >> 1) & 1) : j;
+                        int64_t ck = nd > 2 ? 2 * k + ((o >> 2) & 1) : k;
+                        sum += Uchild[v * NC + (ck * cd.n[1] + cj) * cd.n[0] + ci];
+                    }
+                    Uparent[v * NP + pc] = sum / (double)nchild;
+                }
+            }
+    return ORC_OK;
+}
+
+typedef struct {
+    const orc_fmr_desc *f;
+    orc_desc lev[ORC_FMR_MAXLEV];
+    double *const *U;
+    double *ext[ORC_FMR_MAXLEV];
+    double T[ORC_FMR_MAXLEV];
+    double *from_children[ORC_FMR_MAXLEV][3][2];
+    double cfl, dt_fixed;
+    int status;
+} fmr_ctx;
+
+/* number of faces normal to q of an (n0, n1, n2) block of cells: one per
+ * transverse position */
+static int64_t face_count(const int64_t n[3], int q) { return n[(q + 1) % 3] * n[(q + 2) % 3]; }
+
+static void note(fmr_ctx *c, int st)
+{
+    if (st != ORC_OK && c->status == ORC_OK) c->status = st;
+}
+
+/* Stepper(l)%Step: one two-stage step of level l with its exterior held in
+ * ext[l].  provisional: the first stage alone (the coarse half-step of Alg.
+ * EvolveLevel), no replacement.  acc, when given, accumulates the level's
+ * own boundary fluxes integrated over the step (ForParents). */
+static void level_step(fmr_ctx *c, int l, double dt, int provisional, double *acc[3][2])
+{
+    const orc_desc *d = &c->lev[l];
+    int nd = d->ndim, nv = nvars(d);
+    int64_t N = ncells(d), T = nv * N;
+    double *U = c->U[l];
+    const double *Uext = l > 0 ? c->ext[l] : NULL;
+    double *L = (double *)malloc(sizeof(double) * T);
+    if (provisional) {
+        note(c, rhs_core(d, U, Uext, L, NULL));
+        for (int64_t i = 0; i < T; ++i) U[i] = U[i] + dt * L[i];
+        free(L);
+        return;
+    }
+    int child = l + 1 < c->f->nlev;
+    face_rec r[2];
+    memset(r, 0, sizeof(r));
+    int64_t cn[3] = {1, 1, 1};
+    if (child)
+        for (int q = 0; q < 3; ++q) cn[q] = c->f->box_n[l + 1][q];
+    for (int s = 0; s < 2; ++s) {
+        for (int q = 0; q < nd; ++q)
+            for (int side = 0; side < 2; ++side) {
+                if (acc) r[s].own[q][side] = (double *)malloc(sizeof(double) * nv * face_count(d->n, q));
+                if (child) r[s].child[q][side] = (double *)malloc(sizeof(double) * nv * face_count(cn, q));
+            }
+        for (int q = 0; q < 3; ++q) {
+            r[s].clo[q] = child ? c->f->box_lo[l + 1][q] : 0;
+            r[s].cn[q] = cn[q];
+        }
+    }
+    double *K1 = (double *)malloc(sizeof(double) * T);
+    double *U1 = (double *)malloc(sizeof(double) * T);
+    note(c, rhs_core(d, U, Uext, L, &r[0]));
+    for (int64_t i = 0; i < T; ++i) {
+        K1[i] = dt * L[i];
+        U1[i] = U[i] + K1[i];
+    }
+    note(c, rhs_core(d, U1, Uext, L, &r[1]));
+    for (int64_t i = 0; i < T; ++i) U[i] = U[i] + 0.5 * (K1[i] + dt * L[i]);
+
+    if (child && !c->f->no_reflux) {
+        for (int q = 0; q < nd; ++q) {
+            int r1 = (q + 1) % 3, r2 = (q + 2) % 3;
+            double dq = cell_width(d, q);
+            int64_t nf = face_count(cn, q);
+            for (int side = 0; side < 2; ++side)
+                for (int64_t t2 = 0; t2 < cn[r2]; ++t2)
+                    for (int64_t t1 = 0; t1 < cn[r1]; ++t1) {
+                        int64_t t = t2 * cn[r1] + t1, x[3];
+                        x[q] = side == 0 ? r[0].clo[q] - 1 : r[0].clo[q] + cn[q];
+                        x[r1] = r[0].clo[r1] + t1;
+                        x[r2] = r[0].clo[r2] + t2;
+                        int64_t cell = (x[2] * d->n[1] + x[1]) * d->n[0] + x[0];
+                        for (int v = 0; v < nv; ++v) {
+                            double phi_c = 0.5 * dt * (r[0].child[q][side][v * nf + t] + r[1].child[q][side][v * nf + t]);
+                            double phi_f = c->from_children[l][q][side][v * nf + t];
+                            double corr = side == 0 ? phi_c - phi_f : phi_f - phi_c;
+                            U[v * N + cell] += corr / dq;
+                        }
+                    }
+        }
+    }
+    if (acc)
+        for (int q = 0; q < nd; ++q)
+            for (int side = 0; side < 2; ++side) {
+                int64_t m = nv * face_count(d->n, q);
+                for (int64_t i = 0; i < m; ++i)
+                    acc[q][side][i] += 0.5 * dt * (r[0].own[q][side][i] + r[1].own[q][side][i]);
+            }
+    for (int s = 0; s < 2; ++s)
+        for (int q = 0; q < 3; ++q)
+            for (int side = 0; side < 2; ++side) {
+                free(r[s].own[q][side]);
+                free(r[s].child[q][side]);
+            }
+    free(K1);
+    free(U1);
+    free(L);
+}
+
+static void evolve_level(fmr_ctx *c, int l, double *acc[3][2]);
+
+/* Alg. StepLevel */
+static void step_level(fmr_ctx *c, int l, double *acc[3][2])
+{
+    const orc_fmr_desc *f = c->f;
+    int nv = nvars(&f->base), nd = f->base.ndim;
+    if (l + 1 < f->nlev) {
+        /* the child's boundary fluxes over its two steps (ForParentsNext) */
+        const orc_desc *cd = &c->lev[l + 1];
+        double *next[3][2];
+        memset(next, 0, sizeof(next));
+        for (int q = 0; q < nd; ++q)
+            for (int s = 0; s < 2; ++s) next[q][s] = (double *)calloc((size_t)(nv * face_count(cd->n, q)), sizeof(double));
+        evolve_level(c, l + 1, next);
+        /* restricted to this level's faces of the child box: mean over the
+         * 2^(d-1) fine faces of each coarse face */
+        int64_t cn[3] = {f->box_n[l + 1][0], f->box_n[l + 1][1], f->box_n[l + 1][2]};
+        for (int q = 0; q < nd; ++q) {
+            int r1 = (q + 1) % 3, r2 = (q + 2) % 3;
+            int64_t nf = face_count(cn, q), nff = face_count(cd->n, q);
+            int a1 = r1 < nd ? 2 : 1, a2 = r2 < nd ? 2 : 1;
+            for (int s = 0; s < 2; ++s)
+                for (int v = 0; v < nv; ++v)
+                    for (int64_t t2 = 0; t2 < cn[r2]; ++t2)
+                        for (int64_t t1 = 0; t1 < cn[r1]; ++t1) {
+                            double sum = 0.0;
+                            for (int o2 = 0; o2 < a2; ++o2)
+                                for (int o1 = 0; o1 < a1; ++o1)
+                                    sum += next[q][s][v * nff + (a2 * t2 + o2) * cd->n[r1] + a1 * t1 + o1];
+                            c->from_children[l][q][s][v * nf + t2 * cn[r1] + t1] = sum / (double)(a1 * a2);
+                        }
+        }
+        for (int q = 0; q < nd; ++q)
+            for (int s = 0; s < 2; ++s) free(next[q][s]);
+    }
+    if (l > 0) note(c, orc_fmr_prolong(f, l, c->U[l - 1], c->ext[l]));
+    double dt;
+    if (l == f->nlev - 1) {
+        if (c->dt_fixed > 0.0) {
+            dt = c->dt_fixed;
+        } else {
+            note(c, orc_cfl_dt(&c->lev[l], c->U[l], c->cfl, &dt));
+        }
+    } else {
+        dt = c->T[l + 1] - c->T[l];
+    }
+    level_step(c, l, dt, 0, acc);
+    if (l + 1 < f->nlev) note(c, orc_fmr_restrict(f, l + 1, c->U[l + 1], c->U[l]));
+    c->T[l] += dt;
+}
+
+/* Alg. EvolveLevel */
+static void evolve_level(fmr_ctx *c, int l, double *acc[3][2])
+{
+    if (l >= c->f->nlev) return;
+    step_level(c, l, acc);
+    if (l == 0) return;
+    const orc_desc *pd = &c->lev[l - 1];
+    int64_t T = nvars(pd) * ncells(pd);
+    double *old = (double *)malloc(sizeof(double) * T);
+    memcpy(old, c->U[l - 1], sizeof(double) * T);
+    if (l - 1 > 0) note(c, orc_fmr_prolong(c->f, l - 1, c->U[l - 2], c->ext[l - 1]));
+    level_step(c, l - 1, c->T[l] - c->T[l - 1], 1, NULL);
+    step_level(c, l, acc);
+    memcpy(c->U[l - 1], old, sizeof(double) * T);
+    free(old);
+}
+
+/* Alg. Evolve, one pass of its loop: every level advances to the same time. */
+int orc_fmr_step(const orc_fmr_desc *f, double *const *U, double cfl, double dt_fixed, double *dt_out)
+{
+    if (!fmr_valid(f) || !U || !dt_out) return ORC_EINVAL;
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return ORC_EINVAL;
+    fmr_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.f = f;
+    c.U = U;
+    c.cfl = cfl;
+    c.dt_fixed = dt_fixed;
+    int nv = nvars(&f->base), nd = f->base.ndim;
+    for (int l = 0; l < f->nlev; ++l) {
+        orc_fmr_level(f, l, &c.lev[l]);
+        if (l > 0) {
+            ghost_geom G = make_geom(&c.lev[l]);
+            c.ext[l] = (double *)calloc((size_t)(nv * G.m[0] * G.m[1] * G.m[2]), sizeof(double));
+        }
+        if (l + 1 < f->nlev)
+            for (int q = 0; q < nd; ++q)
+                for (int s = 0; s < 2; ++s)
+                    c.from_children[l][q][s] =
+                        (double *)calloc((size_t)(nv * face_count(f->box_n[l + 1], q)), sizeof(double));
+    }
+    evolve_level(&c, 0, NULL);
+    for (int l = 1; l < f->nlev; ++l)
+        if (c.T[l] != c.T[0]) note(&c, ORC_EINVAL);
+    *dt_out = c.T[0];
+    for (int l = 0; l < f->nlev; ++l) {
+        free(c.ext[l]);
+        for (int q = 0; q < 3; ++q)
+            for (int s = 0; s < 2; ++s) free(c.from_children[l][q][s]);
+    }
+    return c.status;
 }

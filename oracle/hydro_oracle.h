@@ -113,6 +113,44 @@ int orc_shock_bits(const orc_desc *d, const double *U, unsigned char *bits);
  * fluxes come from the jump conditions F* = F_K + s_K (U*_K - U_K). */
 void orc_hllc_star(const orc_desc *d, int q, const double *wl, const double *wr, double *out);
 
+/* ---- fixed multilevel refinement (Sec. 2 and Sec. 3.5) ---- */
+
+#define ORC_FMR_MAXLEV 8
+
+/* Level 0 is base (the whole box, its boundary conditions); level l >= 1
+ * covers cells box_lo[l] .. box_lo[l] + box_n[l] - 1 of level l - 1, refined
+ * by two along every active dimension (unused dimensions: box_lo 0, box_n 1).
+ * Each box keeps at least NG = 2 parent cells between itself and the parent
+ * level's edge.  HLL or HLLC with the generalised-minmod limiter only. */
+typedef struct {
+    orc_desc base;
+    int nlev;
+    int64_t box_lo[ORC_FMR_MAXLEV][3];
+    int64_t box_n[ORC_FMR_MAXLEV][3];
+    int no_reflux; /* test hook: 1 drops the coarse/fine flux replacement */
+} orc_fmr_desc;
+
+/* The descriptor of level l (cells, box corners). */
+int orc_fmr_level(const orc_fmr_desc *f, int l, orc_desc *out);
+
+/* Prolongation of the parent level's state into the exterior of level l,
+ * linear in the primitive variables with minmod-limited parent differences,
+ * stored as conserved variables: Uext has level l's ghosted layout,
+ * nv x (n2 + 2NG, n1 + 2NG, n0 + 2NG) over active dimensions; only its ghost
+ * cells are written. */
+int orc_fmr_prolong(const orc_fmr_desc *f, int l, const double *Uparent, double *Uext);
+
+/* Restriction: every parent cell under level l becomes the mean of its
+ * children. */
+int orc_fmr_restrict(const orc_fmr_desc *f, int l, const double *Uchild, double *Uparent);
+
+/* One global step (Algs. Evolve / EvolveLevel / StepLevel): U[l] are the
+ * levels' interior states, advanced in place to a common time; the deepest
+ * level steps by cfl * its CFL time step (or by dt_fixed when > 0), every
+ * coarser level by the sum of its child's two steps.  *dt_out receives the
+ * coarse step. */
+int orc_fmr_step(const orc_fmr_desc *f, double *const *U, double cfl, double dt_fixed, double *dt_out);
+
 #ifdef __cplusplus
 }
 #endif

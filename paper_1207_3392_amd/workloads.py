@@ -415,3 +415,139 @@ def random_smooth_patch(ndim: int, n: Sequence[int], seed: int = DEFAULT_SEED,
     bcs = tuple((bc, bc) if q < ndim else (0, 0) for q in range(3))
     return Problem(ndim, n3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), gamma, bcs, W,
                    theta=theta, name="random_smooth")
+
+
+@dataclasses.dataclass
+class Levels:
+    """A nested multilevel configuration: ``base`` is level 0 (box, boundary
+    kinds, its initial fields in ``base.W``); ``boxes[l - 1] = (lo, n)`` names
+    the cells of level l - 1 that level l refines by two per active dimension
+    (unused dimensions: lo 0, n 1); ``W[l]`` are level l's initial primitive
+    fields, point values at its own cell centres."""
+
+    base: Problem
+    boxes: List[Tuple[Tuple[int, int, int], Tuple[int, int, int]]]
+    W: List[np.ndarray]
+
+    @property
+    def nlev(self) -> int:
+        return 1 + len(self.boxes)
+
+    def level_geometry(self, l: int):
+        """(n, lo, hi) of level l."""
+        n = list(self.base.n)
+        lo = list(self.base.lo)
+        hi = list(self.base.hi)
+        for k in range(1, l + 1):
+            blo, bn = self.boxes[k - 1]
+            for q in range(self.base.ndim):
+                dq = (hi[q] - lo[q]) / n[q]
+                lo[q] = lo[q] + blo[q] * dq
+                hi[q] = lo[q] + bn[q] * dq
+                n[q] = 2 * bn[q]
+        return tuple(n), tuple(lo), tuple(hi)
+
+
+def _nested_boxes(ndim: int, n0: int, nlev: int):
+    """Each level covers the central half of its parent: box lo n/4, n/2."""
+    boxes = []
+    for _ in range(1, nlev):
+        lo = tuple(n0 // 4 if q < ndim else 0 for q in range(3))
+        n = tuple(n0 // 2 if q < ndim else 1 for q in range(3))
+        boxes.append((lo, n))
+    return boxes
+
+
+def _level_fields(lv: Levels, fn) -> List[np.ndarray]:
+    out = []
+    for l in range(lv.nlev):
+        n, lo, hi = lv.level_geometry(l)
+        out.append(fn(n, lo, hi))
+    return out
+
+
+def sedov_levels(ndim: int = 2, n0: int = 64, nlev: int = 3, gamma: float = 1.4, rho0: float = 1.0,
+                 p0: float = 1e-5, e_d: float = 1.0, r_cells: float = 3.5, sub: int = 20,
+                 bc: int = BC_OUTFLOW, theta: float = 2.0, cfl: float = 0.4) -> Levels:
+    """Sedov-Taylor blast (Sec. 4.2): fluid at rest, density rho0, pressure p0
+    on [-0.5, 0.5]^d, with the energy e_d released as the pressure
+    3 (gamma - 1) e_d / ((alpha + 1) pi R_d^alpha) inside r <= R_d (alpha = d;
+    in 1D the slab |x| <= R_d holds e_d as (gamma - 1) e_d / (2 R_d)).  R_d is
+    r_cells finest-level cells; every cell cut by the sphere takes the volume
+    average of the pressure over a sub^d subgrid.  Levels: nested boxes, each
+    the central half of its parent, n0 cells per dimension on every level."""
+    lo3 = tuple(-0.5 if q < ndim else 0.0 for q in range(3))
+    hi3 = tuple(0.5 if q < ndim else 1.0 for q in range(3))
+    n3 = tuple(n0 if q < ndim else 1 for q in range(3))
+    bcs = tuple((bc, bc) if q < ndim else (0, 0) for q in range(3))
+    dx_fine = 1.0 / (n0 * 2 ** (nlev - 1))
+    r_d = r_cells * dx_fine
+    if ndim == 1:
+        p_d = (gamma - 1.0) * e_d / (2.0 * r_d)
+    else:
+        p_d = 3.0 * (gamma - 1.0) * e_d / ((ndim + 1) * math.pi * r_d ** ndim)
+
+    def fields(n, lo, hi):
+        axes = [_cell_centres(n[q], lo[q], hi[q]) for q in range(ndim)]
+        widths = [(hi[q] - lo[q]) / n[q] for q in range(ndim)]
+        grids = np.meshgrid(*reversed(axes), indexing="ij")  # (z, y, x) order
+        r = np.sqrt(sum(g ** 2 for g in grids))
+        half_diag = 0.5 * math.sqrt(sum(w ** 2 for w in widths))
+        frac = (r <= r_d).astype(np.float64)
+        cut = np.abs(r - r_d) <= half_diag
+        if np.any(cut):
+            offs = (np.arange(sub) + 0.5) / sub - 0.5
+            sg = np.meshgrid(*([offs] * ndim), indexing="ij")
+            for idx in zip(*np.nonzero(cut)):
+                rr2 = 0.0
+                for a, g in enumerate(grids):
+                    w = widths[ndim - 1 - a]
+                    rr2 = rr2 + (g[idx] + sg[a] * w) ** 2
+                frac[idx] = float(np.mean(np.sqrt(rr2) <= r_d))
+        W = np.empty((ndim + 2,) + r.shape)
+        W[0] = rho0
+        W[1:ndim + 1] = 0.0
+        W[ndim + 1] = p0 + (p_d - p0) * frac
+        return W
+
+    base = Problem(ndim, n3, lo3, hi3, gamma, bcs, None, theta=theta, cfl=cfl, name="sedov_levels")
+    lv = Levels(base, _nested_boxes(ndim, n0, nlev), [])
+    lv.W = _level_fields(lv, fields)
+    base.W = lv.W[0]
+    return lv
+
+
+def smooth_levels(ndim: int = 2, n0: int = 32, nlev: int = 2, seed: int = DEFAULT_SEED, amp: float = 0.2,
+                  vel=(0.6, 0.3, 0.2), gamma: float = 1.4, theta: float = 2.0, cfl: float = 0.4,
+                  uniform: bool = False, t: float = 0.0) -> Levels:
+    """Periodic unit box with a smooth density wave (random phases, modes 1 and
+    2 per dimension) carried by a uniform velocity at uniform pressure; with
+    ``uniform`` the density is 1 everywhere.  ``t`` > 0 gives the exact
+    solution at time t (the wave translated by vel * t).  Levels as in
+    sedov_levels."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=(ndim, 2))
+    n3 = tuple(n0 if q < ndim else 1 for q in range(3))
+    bcs = tuple((BC_PERIODIC, BC_PERIODIC) for _ in range(3))
+
+    def fields(n, lo, hi):
+        axes = [_cell_centres(n[q], lo[q], hi[q]) - vel[q] * t for q in range(ndim)]
+        grids = list(reversed(np.meshgrid(*reversed(axes), indexing="ij")))  # grids[q] varies along q
+        rho = np.ones(grids[0].shape)
+        if not uniform:
+            for q in range(ndim):
+                rho = rho + amp / ndim * (np.sin(2 * math.pi * grids[q] + ph[q, 0])
+                                          + 0.5 * np.sin(4 * math.pi * grids[q] + ph[q, 1]))
+        W = np.empty((ndim + 2,) + rho.shape)
+        W[0] = rho
+        for q in range(ndim):
+            W[1 + q] = vel[q]
+        W[ndim + 1] = 1.0
+        return W
+
+    base = Problem(ndim, n3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), gamma, bcs, None, theta=theta, cfl=cfl,
+                   name="smooth_levels")
+    lv = Levels(base, _nested_boxes(ndim, n0, nlev), [])
+    lv.W = _level_fields(lv, fields)
+    base.W = lv.W[0]
+    return lv
