@@ -54,12 +54,13 @@ FLOPS_PER_CELL = {"hllc": {1: 478, 2: 524}, "hll": {1: 448, 2: 494}}
 # kernel source and launch configuration they were taken on (the source is
 # identified by its digest); after any change the traffic is reported as null
 # until the counters are retaken.
-TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h")
+TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h",
+                   "paper_1207_3392_amd/csrc/hy_face.h")
 TRAFFIC = {
-    "digest": "d9318a3f380da15bf0f4735b56383930272bc697d78f5bbad577c42928651a82",
+    "digest": "70f6381b4c49ebe98916af3870f7d953bf5389120fdbb0ad8ca980dfde63243a",
     "ncell": 256 ** 3,
     "kernel": "k_stage<nd=3,f32,tile=64x8> zchunk=64",
-    "bytes_per_launch": {1: 703638811, 2: 1102254891},
+    "bytes_per_launch": {1: 703673307, 2: 1100950699},
 }
 
 
@@ -74,7 +75,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
-                                                   "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch"],
+                                                   "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch",
+                                                   "fmr_sedov3d"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -175,6 +177,40 @@ def time_kh(n=2048, steps=20, learned=False):
     p.cfl_dt(0.4)
     p.close()
     return {"zone_updates_per_s": n * n * steps / wall, "ms_per_step": 1e3 * wall / steps}
+
+
+def time_fmr(nd=3, n0=128, nlev=4, steps=4, warmup=1):
+    """Multilevel Sedov-Taylor blast (Sec. 4.2; Algs. Evolve..StepLevel):
+    nested boxes, each the central half of its parent, n0^d cells per level,
+    FP32, HLL, theta 1.4, C_CFL 0.4.  A global step advances every level to a
+    common time (the deepest level takes 2^(nlev-1) steps).  Leaf zone-updates
+    count each level's cells that no finer level covers, times its steps."""
+    import numpy as np
+    import torch
+
+    from paper_1207_3392_amd import hydro
+    from paper_1207_3392_amd import workloads as wl
+
+    lv = wl.sedov_levels(nd, n0, nlev)
+    F = hydro.Fmr(lv, precision=32)
+    T0 = F.totals()
+    for _ in range(warmup):
+        F.step(0.4, solver=hydro.HLL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.step(0.4, solver=hydro.HLL)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    T1 = F.totals()
+    F.close()
+    leaf = 0
+    for l in range(nlev):
+        covered = int(np.prod(lv.boxes[l][1])) if l + 1 < nlev else 0
+        leaf += (F.ncell[l] - covered) * 2 ** l
+    return {"levels": nlev, "cells_per_level": F.ncell[0], "leaf_zone_updates_per_global_step": leaf,
+            "ms_per_global_step": 1e3 * wall / steps, "leaf_zone_updates_per_s": leaf * steps / wall,
+            "mass_drift": float((T1[0] - T0[0]) / T0[0]), "energy_drift": float((T1[4] - T0[4]) / T0[4])}
 
 
 def source_digest():
@@ -320,6 +356,7 @@ def main():
         run = {"batched_tubes": time_batch, "kh_2048_plain": lambda: time_kh(learned=False),
                "kh_2048_learned": lambda: time_kh(learned=True), "rt_512_plain": lambda: time_rt(learned=False),
                "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1,
+               "fmr_sedov3d": time_fmr,
                "hllc_switch": lambda: {k: v for k, v in time_patch(args.n, "hllc_switch", args.steps,
                                                                     args.warmup).items() if k != "kernel"}}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
@@ -364,6 +401,7 @@ def main():
 
         guarded(f"hllc_switch_{args.n}", switch)
         guarded("batched_tubes", time_batch)
+        guarded("fmr_sedov3d", time_fmr)
         guarded("kh_2048_plain", lambda: time_kh(learned=False))
         guarded("kh_2048_learned", lambda: time_kh(learned=True))
         guarded("rt_512_plain", lambda: time_rt(learned=False))

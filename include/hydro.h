@@ -283,6 +283,53 @@ hy_status hy_trainer_get_params(hy_trainer *tr, float *params_host);
 hy_status hy_mlp_eval(hy_trainer *tr, const float *x_dev, float *y_dev, int64_t batch);
 hy_status hy_trainer_destroy(hy_trainer *tr);
 
+/* ---------------------------------------------------------------------
+ * Fixed multilevel refinement (Sec. 2, the refinable mesh with its
+ * prolongation and restriction; Sec. 3.5, Algs. Evolve, EvolveLevel and
+ * StepLevel).  Level 0 is `base` (the whole box, its boundary kinds,
+ * precision, gamma, theta; limiter must be HY_LIM_THETA, and the solver of
+ * hy_fmr_step HY_HLL or HY_HLLC).  Level l >= 1 refines by two along every
+ * active dimension the cells box_lo[l] .. box_lo[l] + box_n[l] - 1 of level
+ * l - 1 (unused dimensions: box_lo 0, box_n 1); every box keeps at least two
+ * parent cells between itself and its parent's edge (HY_EINVAL otherwise).
+ * One global step (hy_fmr_step) runs the recursion of the three algorithms:
+ * the deepest level steps first, by cfl times its own CFL time step (or by
+ * dt_fixed when > 0); every coarser level then steps by the sum of its
+ * child's two steps, after a provisional forward-Euler half-step that feeds
+ * the child's second step.  Each refined level's exterior (two cells around
+ * it) is prolonged from its parent before each step and held through both
+ * stages: linear in the primitive variables with minmod-limited parent
+ * differences.  After a coarse step the cells just outside the child take the
+ * child's fluxes through the shared faces (integrated over its two steps,
+ * averaged over the 2^(d-1) fine faces of each coarse face) in place of their
+ * own, and the cells under the child become the mean of their children, so
+ * mass, momentum and energy summed over the leaf cells change only through
+ * the outer boundary.  Device memory: the caller's workspace holds every
+ * level (a refined level padded by its exterior) and the flux accumulators. */
+#define HY_FMR_MAXLEV 8
+typedef struct {
+    hy_patch_desc base;
+    int nlev;                          /* 1 .. HY_FMR_MAXLEV */
+    int64_t box_lo[HY_FMR_MAXLEV][3];  /* entry 0 unused */
+    int64_t box_n[HY_FMR_MAXLEV][3];
+} hy_fmr_desc;
+typedef struct hy_fmr hy_fmr;
+
+hy_status hy_fmr_workspace_bytes(const hy_fmr_desc *d, size_t *bytes);
+hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, void *hip_stream, hy_fmr **out);
+/* Interior state of one level (nv x that level's cells, FP64 SoA);
+ * synchronising. */
+hy_status hy_fmr_set_state(hy_fmr *f, int level, int kind, const double *host_soa);
+hy_status hy_fmr_get_state(hy_fmr *f, int level, int kind, double *host_soa_out);
+/* One global step; *dt_out (may be NULL) receives the coarse step.
+ * Synchronising (one device read per deepest-level step for its time step,
+ * unless dt_fixed > 0, and one at the end for the error latch). */
+hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double *dt_out);
+/* FP64 sums of D, S_x, S_y, S_z, G times the cell volume over the leaf
+ * cells of all levels (cells no finer level covers); synchronising. */
+hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5]);
+hy_status hy_fmr_destroy(hy_fmr *f);
+
 #ifdef __cplusplus
 }
 #endif

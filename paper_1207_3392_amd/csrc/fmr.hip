@@ -1,0 +1,422 @@
+// fmr.hip -- kernels of fixed multilevel refinement (Sec. 2, prolongation and
+// restriction; Sec. 3.5, Algs. EvolveLevel and StepLevel): the exterior of a
+// refined level by prolongation, the boundary fluxes a level hands to its
+// parent and the fluxes the parent computed at the same faces, the
+// coarse/fine flux replacement, restriction, and the CFL rate and conserved
+// totals over part of an array.  These are thin passes over faces or over a
+// level's two-cell shell; the cell update itself is the stage kernel's.
+#include "hy_fmr.h"
+#include "hy_face.h"
+
+namespace hy {
+namespace {
+
+constexpr int FB = 64;   // threads per block of the shell and face kernels
+constexpr int TB = 256;  // threads per block of the reductions
+
+__device__ __forceinline__ int64_t at(const Grid &g, int i, int j, int k)
+{
+    return ((int64_t)k * g.m[1] + j) * g.m[0] + i;
+}
+
+// The exterior cells of row (j, k) of a padded array: every cell when the row
+// itself lies in the exterior along y or z, else the NG cells at each x end.
+template <int ND>
+__device__ __forceinline__ bool shell_row(const Grid &g, int j, int k)
+{
+    bool row = false;
+    if constexpr (ND >= 2) row = row || j < FMR_NG || j >= g.m[1] - FMR_NG;
+    if constexpr (ND >= 3) row = row || k < FMR_NG || k >= g.m[2] - FMR_NG;
+    return row;
+}
+
+template <int ND>
+__device__ __forceinline__ int shell_count(const Grid &g, bool row)
+{
+    return row ? g.m[0] : 2 * FMR_NG;
+}
+
+template <int ND>
+__device__ __forceinline__ int shell_x(const Grid &g, bool row, int t)
+{
+    return row ? t : (t < FMR_NG ? t : g.m[0] - 2 * FMR_NG + t);
+}
+
+template <int ND, typename T>
+__device__ __forceinline__ void load_prim(const T *u, const Grid &g, int64_t c, T gm1, T (&w)[ND + 2])
+{
+    T uu[ND + 2];
+#pragma unroll
+    for (int v = 0; v < ND + 2; ++v) uu[v] = u[v * g.vs + c];
+    (void)to_prim<ND>(uu, w, gm1);
+}
+
+template <int ND, typename T>
+__global__ void __launch_bounds__(FB) k_prolong(T *fine, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
+                                                 T inv_gm1)
+{
+    const int j = blockIdx.x, k = blockIdx.y;
+    const bool row = shell_row<ND>(fg, j, k);
+    const int cnt = shell_count<ND>(fg, row);
+    for (int t = threadIdx.x; t < cnt; t += FB) {
+        const int c3[3] = {shell_x<ND>(fg, row, t), j, k};
+        int p3[3], s3[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q < ND) {
+                const int r = c3[q] - FMR_NG;  // offset from the first interior cell
+                p3[q] = pb.lo[q] + (r >> 1);   // floor(r / 2)
+                s3[q] = r & 1;                 // 0: low child, 1: high child
+            } else {
+                p3[q] = 0;
+                s3[q] = 0;
+            }
+        }
+        T w0[ND + 2], wc[ND + 2];
+        load_prim<ND>(parent, pg, at(pg, p3[0], p3[1], p3[2]), gm1, w0);
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) wc[v] = w0[v];
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            int lo3[3] = {p3[0], p3[1], p3[2]}, hi3[3] = {p3[0], p3[1], p3[2]};
+            lo3[q] -= 1;
+            hi3[q] += 1;
+            T wm[ND + 2], wp[ND + 2];
+            load_prim<ND>(parent, pg, at(pg, lo3[0], lo3[1], lo3[2]), gm1, wm);
+            load_prim<ND>(parent, pg, at(pg, hi3[0], hi3[1], hi3[2]), gm1, wp);
+            // minmod (theta = 1) as twice the slope; the child sits at +/- 1/4
+            // of the parent width, so it moves by +/- slope2 / 8
+            const T h = s3[q] ? T(0.125) : T(-0.125);
+#pragma unroll
+            for (int v = 0; v < ND + 2; ++v) wc[v] += h * slope2_mm(wm[v], w0[v], wp[v], T(2));
+        }
+        const int64_t c = at(fg, c3[0], c3[1], c3[2]);
+        T ke = T(0);
+        fine[c] = wc[0];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            fine[(1 + d) * fg.vs + c] = wc[0] * wc[1 + d];
+            ke += wc[1 + d] * wc[1 + d];
+        }
+        fine[(ND + 1) * fg.vs + c] = wc[ND + 1] * inv_gm1 + T(0.5) * wc[0] * ke;
+    }
+}
+
+template <int ND, typename T>
+__global__ void __launch_bounds__(FB) k_exterior_copy(const T *src, T *dst, Grid g)
+{
+    const int j = blockIdx.x, k = blockIdx.y;
+    const bool row = shell_row<ND>(g, j, k);
+    const int cnt = shell_count<ND>(g, row);
+    for (int t = threadIdx.x; t < cnt; t += FB) {
+        const int64_t c = at(g, shell_x<ND>(g, row, t), j, k);
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) dst[v * g.vs + c] = src[v * g.vs + c];
+    }
+}
+
+// One thread per face position transverse to Q: both faces (low and high
+// side of the box) along the line through it.
+template <int ND, int Q, int SOLVER, typename T>
+__global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, Box b, T gamma, T gm1, T inv_gm1, T theta2,
+                                                  double w, double *acc_lo, double *acc_hi)
+{
+    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    const int faces = b.n[R1] * b.n[R2];
+    const int t = blockIdx.x * FB + threadIdx.x;
+    if (t >= faces) return;
+    const int t1 = t % b.n[R1], t2 = t / b.n[R1];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int f = side == 0 ? b.lo[Q] : b.lo[Q] + b.n[Q];  // face between cells f - 1 and f
+        T w4[4][ND + 2];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            int c3[3];
+            c3[Q] = f - 2 + s;
+            c3[R1] = b.lo[R1] + t1;
+            c3[R2] = b.lo[R2] + t2;
+            load_prim<ND>(u, g, at(g, c3[0], c3[1], c3[2]), gm1, w4[s]);
+        }
+        T wl[ND + 2], wr[ND + 2], fl[ND + 2];
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) {
+            wl[v] = w4[1][v] + T(0.25) * slope2_mm(w4[0][v], w4[1][v], w4[2][v], theta2);
+            wr[v] = w4[2][v] - T(0.25) * slope2_mm(w4[1][v], w4[2][v], w4[3][v], theta2);
+        }
+        face_flux<ND, Q, SOLVER>(wl, wr, fl, gamma, inv_gm1, false);
+        double *acc = side == 0 ? acc_lo : acc_hi;
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) acc[(int64_t)v * faces + t] += w * (double)fl[v];
+    }
+}
+
+// One thread per coarse face of the child box normal to Q (both sides).
+template <int ND, int Q, typename T>
+__global__ void __launch_bounds__(FB) k_reflux(T *u, Grid g, Box b, const double *c_lo, const double *c_hi,
+                                                const double *f_lo, const double *f_hi, double idq)
+{
+    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    constexpr int A1 = R1 < ND ? 2 : 1, A2 = R2 < ND ? 2 : 1;
+    const int faces = b.n[R1] * b.n[R2];
+    const int ffaces = faces * A1 * A2, fn1 = b.n[R1] * A1;
+    const int t = blockIdx.x * FB + threadIdx.x;
+    if (t >= faces) return;
+    const int t1 = t % b.n[R1], t2 = t / b.n[R1];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const double *cf = side == 0 ? c_lo : c_hi;
+        const double *ff = side == 0 ? f_lo : f_hi;
+        int c3[3];
+        c3[Q] = side == 0 ? b.lo[Q] - 1 : b.lo[Q] + b.n[Q];
+        c3[R1] = b.lo[R1] + t1;
+        c3[R2] = b.lo[R2] + t2;
+        const int64_t c = at(g, c3[0], c3[1], c3[2]);
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) {
+            double sum = 0.0;
+#pragma unroll
+            for (int o2 = 0; o2 < A2; ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < A1; ++o1)
+                    sum += ff[(int64_t)v * ffaces + (A2 * t2 + o2) * fn1 + A1 * t1 + o1];
+            const double phi_f = sum / (double)(A1 * A2);
+            const double phi_c = cf[(int64_t)v * faces + t];
+            const double corr = side == 0 ? phi_c - phi_f : phi_f - phi_c;
+            T &x = u[v * g.vs + c];
+            x = (T)((double)x + corr * idq);
+        }
+    }
+}
+
+template <int ND, typename T>
+__global__ void __launch_bounds__(FB) k_restrict(T *parent, Grid pg, Box b, const T *child, Grid cg)
+{
+    const int i = blockIdx.x * FB + threadIdx.x;
+    const int j = blockIdx.y, k = blockIdx.z;
+    if (i >= b.n[0]) return;
+    const int64_t pc = at(pg, b.lo[0] + i, b.lo[1] + j, b.lo[2] + k);
+    constexpr int NC = 1 << ND;
+#pragma unroll
+    for (int v = 0; v < ND + 2; ++v) {
+        double sum = 0.0;
+#pragma unroll
+        for (int o = 0; o < NC; ++o) {
+            const int ci = FMR_NG + 2 * i + (o & 1);
+            const int cj = ND > 1 ? FMR_NG + 2 * j + ((o >> 1) & 1) : 0;
+            const int ck = ND > 2 ? FMR_NG + 2 * k + ((o >> 2) & 1) : 0;
+            sum += (double)child[v * cg.vs + at(cg, ci, cj, ck)];
+        }
+        parent[v * pg.vs + pc] = (T)(sum / (double)NC);
+    }
+}
+
+template <int ND, typename T>
+__global__ void __launch_bounds__(TB) k_box_rate(const T *u, Grid g, Box b, T gamma, T gm1, double idq0, double idq1,
+                                                  double idq2, unsigned long long *rate_bits)
+{
+    __shared__ double red[TB];
+    const int j = blockIdx.x, k = blockIdx.y;
+    const double idq[3] = {idq0, idq1, idq2};
+    double m = 0.0;
+    for (int i = threadIdx.x; i < b.n[0]; i += TB) {
+        T w[ND + 2];
+        load_prim<ND>(u, g, at(g, b.lo[0] + i, b.lo[1] + j, b.lo[2] + k), gm1, w);
+        const double cs = (double)sound_(gamma, w[ND + 1], w[0]);
+#pragma unroll
+        for (int q = 0; q < ND; ++q) m = fmax(m, (fabs((double)w[1 + q]) + cs) * idq[q]);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = TB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(rate_bits, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+template <int ND, typename T>
+__global__ void __launch_bounds__(TB) k_leaf_totals(const T *u, Grid g, Box b, Box hole, double dv, double *partials)
+{
+    __shared__ double red[TB];
+    const int j = blockIdx.x, k = blockIdx.y;
+    const int row = k * b.n[1] + j;
+    const int y = b.lo[1] + j, z = b.lo[2] + k;
+    const bool row_in_hole = hole.n[0] > 0 && y >= hole.lo[1] && y < hole.lo[1] + hole.n[1] && z >= hole.lo[2] &&
+                             z < hole.lo[2] + hole.n[2];
+    double s[ND + 2];
+#pragma unroll
+    for (int v = 0; v < ND + 2; ++v) s[v] = 0.0;
+    for (int i = threadIdx.x; i < b.n[0]; i += TB) {
+        const int x = b.lo[0] + i;
+        if (row_in_hole && x >= hole.lo[0] && x < hole.lo[0] + hole.n[0]) continue;
+        const int64_t c = at(g, x, y, z);
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) s[v] += (double)u[v * g.vs + c];
+    }
+#pragma unroll
+    for (int v = 0; v < ND + 2; ++v) {
+        red[threadIdx.x] = s[v];
+        __syncthreads();
+        for (int st = TB / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int slot = v == 0 ? 0 : (v == ND + 1 ? 4 : v);
+            partials[row * 5 + slot] = red[0] * dv;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) {
+        // slots of absent momentum components
+        const int slot = threadIdx.x;
+        if (slot > ND && slot < 4) partials[row * 5 + slot] = 0.0;
+    }
+}
+
+template <int ND, int Q, typename T>
+hipError_t box_flux_q(const T *u, const Grid &g, const Box &b, int solver, T gamma, T gm1, T inv_gm1, T theta2,
+                      double w, double *lo, double *hi, hipStream_t s)
+{
+    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    const int faces = b.n[R1] * b.n[R2];
+    const dim3 grid((faces + FB - 1) / FB);
+    if (solver == SOLVER_HLL)
+        hipLaunchKernelGGL((k_box_flux<ND, Q, SOLVER_HLL, T>), grid, dim3(FB), 0, s, u, g, b, gamma, gm1, inv_gm1,
+                           theta2, w, lo, hi);
+    else
+        hipLaunchKernelGGL((k_box_flux<ND, Q, SOLVER_HLLC, T>), grid, dim3(FB), 0, s, u, g, b, gamma, gm1, inv_gm1,
+                           theta2, w, lo, hi);
+    return hipGetLastError();
+}
+
+template <int ND, typename T>
+hipError_t box_flux_nd(const T *u, const Grid &g, const Box &b, int solver, T gamma, T gm1, T inv_gm1, T theta2,
+                       double w, double *const acc[3][2], hipStream_t s)
+{
+    hipError_t e = box_flux_q<ND, 0>(u, g, b, solver, gamma, gm1, inv_gm1, theta2, w, acc[0][0], acc[0][1], s);
+    if constexpr (ND >= 2)
+        if (e == hipSuccess)
+            e = box_flux_q<ND, 1>(u, g, b, solver, gamma, gm1, inv_gm1, theta2, w, acc[1][0], acc[1][1], s);
+    if constexpr (ND >= 3)
+        if (e == hipSuccess)
+            e = box_flux_q<ND, 2>(u, g, b, solver, gamma, gm1, inv_gm1, theta2, w, acc[2][0], acc[2][1], s);
+    return e;
+}
+
+template <int ND, int Q, typename T>
+hipError_t reflux_q(T *u, const Grid &g, const Box &b, const double *const c[3][2], const double *const f[3][2],
+                    double idq, hipStream_t s)
+{
+    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    const int faces = b.n[R1] * b.n[R2];
+    hipLaunchKernelGGL((k_reflux<ND, Q, T>), dim3((faces + FB - 1) / FB), dim3(FB), 0, s, u, g, b, c[Q][0], c[Q][1],
+                       f[Q][0], f[Q][1], idq);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box, int ndim,
+                          T gamma, T gm1, hipStream_t s)
+{
+    (void)gamma;
+    const dim3 grid(fg.m[1], fg.m[2]);
+    const T inv_gm1 = T(1) / gm1;
+    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(FB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
+    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(FB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
+    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(FB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, hipStream_t s)
+{
+    const dim3 grid(g.m[1], g.m[2]);
+    if (ndim == 1) hipLaunchKernelGGL((k_exterior_copy<1, T>), grid, dim3(FB), 0, s, src, dst, g);
+    else if (ndim == 2) hipLaunchKernelGGL((k_exterior_copy<2, T>), grid, dim3(FB), 0, s, src, dst, g);
+    else hipLaunchKernelGGL((k_exterior_copy<3, T>), grid, dim3(FB), 0, s, src, dst, g);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_box_flux(const T *u, const Grid &g, const Box &box, int ndim, int solver, T gamma, T gm1,
+                           T inv_gm1, T theta, double w, double *const acc[3][2], hipStream_t s)
+{
+    const T theta2 = T(2) * theta;
+    if (ndim == 1) return box_flux_nd<1>(u, g, box, solver, gamma, gm1, inv_gm1, theta2, w, acc, s);
+    if (ndim == 2) return box_flux_nd<2>(u, g, box, solver, gamma, gm1, inv_gm1, theta2, w, acc, s);
+    return box_flux_nd<3>(u, g, box, solver, gamma, gm1, inv_gm1, theta2, w, acc, s);
+}
+
+template <typename T>
+hipError_t launch_reflux(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
+                         const double *const fine[3][2], const double idq[3], hipStream_t s)
+{
+    hipError_t e;
+    if (ndim == 1) return reflux_q<1, 0>(u, g, child_box, coarse, fine, idq[0], s);
+    if (ndim == 2) {
+        e = reflux_q<2, 0>(u, g, child_box, coarse, fine, idq[0], s);
+        return e == hipSuccess ? reflux_q<2, 1>(u, g, child_box, coarse, fine, idq[1], s) : e;
+    }
+    e = reflux_q<3, 0>(u, g, child_box, coarse, fine, idq[0], s);
+    if (e == hipSuccess) e = reflux_q<3, 1>(u, g, child_box, coarse, fine, idq[1], s);
+    return e == hipSuccess ? reflux_q<3, 2>(u, g, child_box, coarse, fine, idq[2], s) : e;
+}
+
+template <typename T>
+hipError_t launch_restrict(T *parent, const Grid &pg, const Box &child_box, const T *child, const Grid &cg, int ndim,
+                           hipStream_t s)
+{
+    const dim3 grid((child_box.n[0] + FB - 1) / FB, child_box.n[1], child_box.n[2]);
+    if (ndim == 1) hipLaunchKernelGGL((k_restrict<1, T>), grid, dim3(FB), 0, s, parent, pg, child_box, child, cg);
+    else if (ndim == 2) hipLaunchKernelGGL((k_restrict<2, T>), grid, dim3(FB), 0, s, parent, pg, child_box, child, cg);
+    else hipLaunchKernelGGL((k_restrict<3, T>), grid, dim3(FB), 0, s, parent, pg, child_box, child, cg);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_box_rate(const T *u, const Grid &g, const Box &box, int ndim, T gamma, T gm1, const double idq[3],
+                           unsigned long long *rate_bits, hipStream_t s)
+{
+    const dim3 grid(box.n[1], box.n[2]);
+    if (ndim == 1)
+        hipLaunchKernelGGL((k_box_rate<1, T>), grid, dim3(TB), 0, s, u, g, box, gamma, gm1, idq[0], idq[1], idq[2], rate_bits);
+    else if (ndim == 2)
+        hipLaunchKernelGGL((k_box_rate<2, T>), grid, dim3(TB), 0, s, u, g, box, gamma, gm1, idq[0], idq[1], idq[2], rate_bits);
+    else
+        hipLaunchKernelGGL((k_box_rate<3, T>), grid, dim3(TB), 0, s, u, g, box, gamma, gm1, idq[0], idq[1], idq[2], rate_bits);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const Box &hole, int ndim, double dv,
+                              double *partials, hipStream_t s)
+{
+    const dim3 grid(box.n[1], box.n[2]);
+    if (ndim == 1) hipLaunchKernelGGL((k_leaf_totals<1, T>), grid, dim3(TB), 0, s, u, g, box, hole, dv, partials);
+    else if (ndim == 2) hipLaunchKernelGGL((k_leaf_totals<2, T>), grid, dim3(TB), 0, s, u, g, box, hole, dv, partials);
+    else hipLaunchKernelGGL((k_leaf_totals<3, T>), grid, dim3(TB), 0, s, u, g, box, hole, dv, partials);
+    return hipGetLastError();
+}
+
+#define HY_FMR_INST(T)                                                                                               \
+    template hipError_t launch_prolong<T>(T *, const Grid &, const T *, const Grid &, const Box &, int, T, T,        \
+                                          hipStream_t);                                                              \
+    template hipError_t launch_exterior_copy<T>(const T *, T *, const Grid &, int, hipStream_t);                     \
+    template hipError_t launch_box_flux<T>(const T *, const Grid &, const Box &, int, int, T, T, T, T, double,       \
+                                           double *const[3][2], hipStream_t);                                        \
+    template hipError_t launch_reflux<T>(T *, const Grid &, const Box &, int, const double *const[3][2],             \
+                                         const double *const[3][2], const double[3], hipStream_t);                   \
+    template hipError_t launch_restrict<T>(T *, const Grid &, const Box &, const T *, const Grid &, int, hipStream_t); \
+    template hipError_t launch_box_rate<T>(const T *, const Grid &, const Box &, int, T, T, const double[3],         \
+                                           unsigned long long *, hipStream_t);                                       \
+    template hipError_t launch_leaf_totals<T>(const T *, const Grid &, const Box &, const Box &, int, double,        \
+                                              double *, hipStream_t);
+HY_FMR_INST(float)
+HY_FMR_INST(double)
+#undef HY_FMR_INST
+
+}  // namespace hy

@@ -1,0 +1,78 @@
+// Fixed multilevel refinement: device kernels' launchers (internal).
+//
+// Levels are nested boxes refined by two along every active dimension.  A
+// refined level lives in a padded array: its n cells per active dimension
+// plus NG = 2 exterior cells on each side, so the stage kernels run over the
+// padded extent unchanged while the exterior holds values prolonged from the
+// next coarser level.  All arrays are SoA (variable stride vs), x fastest;
+// "box" arguments are cell ranges in the coordinates of the array they index.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hy {
+
+constexpr int FMR_NG = 2;
+
+struct Box {
+    int lo[3];  // first cell, array coordinates
+    int n[3];   // cells per dimension (1 along unused dimensions)
+};
+
+// Dense array extents and variable stride.
+struct Grid {
+    int m[3];
+    int64_t vs;
+};
+
+// Exterior of the padded level (fine) from its parent: each exterior cell at
+// fine offset r from the level's first interior cell takes its parent
+// cell's primitives plus +/- 1/4 of the parent's minmod-limited differences
+// along each active dimension, stored as conserved variables.  parent_box
+// names the parent cells the level refines.
+template <typename T>
+hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box, int ndim,
+                          T gamma, T gm1, hipStream_t s);
+
+// Copies the exterior cells of a padded level from src to dst.
+template <typename T>
+hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, hipStream_t s);
+
+// Fluxes through the low and high faces of box along every active q, from
+// the generalised-minmod face states of the array u (the box needs two cells
+// of u beyond each face): acc[q][side][v * faces + t] += w * F, t running over
+// the box's cells transverse to q ((q + 1) % 3 fastest).
+template <typename T>
+hipError_t launch_box_flux(const T *u, const Grid &g, const Box &box, int ndim, int solver, T gamma, T gm1,
+                           T inv_gm1, T theta, double w, double *const acc[3][2], hipStream_t s);
+
+// Coarse/fine replacement: every parent cell just outside the child box takes
+// (fine - coarse) / dq of the flux through its face into the box (sign by
+// side), the fine value being the mean over the 2^(d-1) child faces of the
+// child's accumulated boundary fluxes (layout of launch_box_flux over the
+// child's interior).
+template <typename T>
+hipError_t launch_reflux(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
+                         const double *const fine[3][2], const double idq[3], hipStream_t s);
+
+// Every parent cell of child_box becomes the mean of its 2^d children, the
+// child being a padded level (interior at offset NG).
+template <typename T>
+hipError_t launch_restrict(T *parent, const Grid &pg, const Box &child_box, const T *child, const Grid &cg, int ndim,
+                           hipStream_t s);
+
+// max over the cells of box of (|v_q| + c_s) / dq into *rate_bits (the bits of
+// a positive double; unsigned atomic max).
+template <typename T>
+hipError_t launch_box_rate(const T *u, const Grid &g, const Box &box, int ndim, T gamma, T gm1, const double idq[3],
+                           unsigned long long *rate_bits, hipStream_t s);
+
+// Per row (j, k) of box, dv times the sums of D, S_q and G over the row's
+// cells outside hole (hole.n[0] == 0: no hole) into partials[row * 5 + slot]
+// (slots D, S_x, S_y, S_z, G).
+template <typename T>
+hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const Box &hole, int ndim, double dv,
+                              double *partials, hipStream_t s);
+
+}  // namespace hy

@@ -1272,3 +1272,441 @@ hy_status hy_trainer_destroy(hy_trainer *tr)
 }
 
 }  // extern "C"
+
+// ================================================ fixed multilevel refinement
+//
+// Host recursion of Algs. Evolve / EvolveLevel / StepLevel over nested levels.
+// Level 0 is an ordinary patch with the physical boundaries; a refined level
+// is a patch over its cells plus a two-cell exterior (outflow kinds, never
+// used for the interior: the exterior is rewritten by prolongation before
+// each step and restored into the stage-1 output before stage 2).  Every
+// launch goes to the one stream; the host waits only for the deepest level's
+// CFL rate and for the error latch at the end of a step.
+#include "hy_fmr.h"
+
+struct hy_fmr {
+    hy_fmr_desc d;
+    int nlev = 0, nv = 0;
+    hipStream_t stream = nullptr;
+    struct Level {
+        hy_patch *p = nullptr;
+        int64_t n[3] = {1, 1, 1};  // interior cells
+        int off = 0;               // interior offset per active dimension (0 or NG)
+        hy::Grid g{};
+        hy::Box own{};             // interior, array coordinates
+        hy::Box child{};           // cells the next level refines, array coordinates (n[0] = 0: none)
+        double idq[3] = {0, 0, 0};
+        double dv = 1.0;
+        double *own_acc[3][2] = {};     // boundary fluxes over the last two steps (for the parent)
+        double *coarse_acc[3][2] = {};  // this level's fluxes at the child's faces over one step
+        size_t own_bytes[3] = {0, 0, 0}, coarse_bytes[3] = {0, 0, 0};  // per side; the two sides are adjacent
+        double *partials = nullptr;     // leaf totals, rows x 5
+        int64_t rows = 0;
+        bool prov = false;  // the provisional half-step result sits in the patch's stage buffer
+        double T = 0.0;
+    } lev[HY_FMR_MAXLEV];
+    unsigned long long *rate = nullptr;
+    int solver = HY_HLLC;
+    double cfl = 0.4, dt_fixed = 0.0;
+};
+
+namespace {
+
+struct FmrLayout {
+    hy_patch_desc desc[HY_FMR_MAXLEV];
+    size_t patch[HY_FMR_MAXLEV], own[HY_FMR_MAXLEV][3], coarse[HY_FMR_MAXLEV][3], partials[HY_FMR_MAXLEV];
+    size_t patch_bytes[HY_FMR_MAXLEV], own_bytes[HY_FMR_MAXLEV][3], coarse_bytes[HY_FMR_MAXLEV][3];
+    size_t rate, total;
+};
+
+int64_t transverse(const int64_t n[3], int q) { return n[(q + 1) % 3] * n[(q + 2) % 3]; }
+
+hy_status fmr_layout(const hy_fmr_desc *d, FmrLayout *L)
+{
+    if (!d) return fail(HY_EINVAL, "null descriptor");
+    hy_status st = check_desc(&d->base);
+    if (st != HY_OK) return st;
+    if (d->nlev < 1 || d->nlev > HY_FMR_MAXLEV) return fail(HY_EINVAL, "nlev must lie in 1 .. HY_FMR_MAXLEV");
+    if (d->base.limiter != HY_LIM_THETA) return fail(HY_EUNSUPPORTED, "multilevel runs take the theta limiter");
+    const int nd = d->base.ndim, nv = nd + 2;
+    int64_t n[3] = {d->base.n[0], d->base.n[1], d->base.n[2]};
+    size_t o = 0;
+    for (int l = 0; l < d->nlev; ++l) {
+        hy_patch_desc pd = d->base;
+        if (l > 0) {
+            const hy_patch_desc &pp = L->desc[l - 1];
+            const int poff = l > 1 ? hy::FMR_NG : 0;
+            for (int q = 0; q < 3; ++q) {
+                const int64_t lo = d->box_lo[l][q], bn = d->box_n[l][q];
+                if (q < nd) {
+                    if (bn < 1 || lo < hy::FMR_NG || lo + bn > n[q] - hy::FMR_NG)
+                        return fail(HY_EINVAL, "a refined box must keep two parent cells from its parent's edge");
+                    const double dqp = (pp.hi[q] - pp.lo[q]) / (double)pp.n[q];
+                    const double dq = 0.5 * dqp;
+                    n[q] = 2 * bn;
+                    pd.n[q] = n[q] + 2 * hy::FMR_NG;
+                    pd.lo[q] = pp.lo[q] + (double)(lo + poff) * dqp - hy::FMR_NG * dq;
+                    pd.hi[q] = pd.lo[q] + (double)pd.n[q] * dq;
+                    pd.bc[q][0] = pd.bc[q][1] = HY_BC_OUTFLOW;
+                } else if (lo != 0 || bn != 1) {
+                    return fail(HY_EINVAL, "unused dimensions take box_lo 0 and box_n 1");
+                }
+            }
+            st = check_desc(&pd);
+            if (st != HY_OK) return st;
+        }
+        L->desc[l] = pd;
+        L->patch[l] = o;
+        L->patch_bytes[l] = layout(pd).total;
+        o = align_up(o + L->patch_bytes[l], 256);
+        for (int q = 0; q < 3; ++q) {
+            L->own_bytes[l][q] = 0;
+            L->coarse_bytes[l][q] = 0;
+            if (q >= nd) continue;
+            if (l > 0) {
+                L->own[l][q] = o;
+                L->own_bytes[l][q] = sizeof(double) * nv * (size_t)transverse(n, q);
+                o = align_up(o + 2 * L->own_bytes[l][q], 256);
+            }
+            if (l + 1 < d->nlev) {
+                L->coarse[l][q] = o;
+                L->coarse_bytes[l][q] = sizeof(double) * nv * (size_t)transverse(d->box_n[l + 1], q);
+                o = align_up(o + 2 * L->coarse_bytes[l][q], 256);
+            }
+        }
+        L->partials[l] = o;
+        o = align_up(o + sizeof(double) * 5 * (size_t)(n[1] * n[2]), 256);
+    }
+    L->rate = o;
+    o = align_up(o + sizeof(unsigned long long), 256);
+    L->total = o + 256;
+    return HY_OK;
+}
+
+template <typename T> T *arrA(hy_fmr::Level &L) { return (T *)L.p->A; }
+template <typename T> T *arrB(hy_fmr::Level &L) { return (T *)L.p->B; }
+
+template <typename T>
+hipError_t fmr_prolong(hy_fmr *f, int l)
+{
+    hy_fmr::Level &L = f->lev[l], &P = f->lev[l - 1];
+    hy::Box pb{};
+    for (int q = 0; q < 3; ++q) {
+        pb.lo[q] = (int)(f->d.box_lo[l][q] + (q < f->d.base.ndim ? P.off : 0));
+        pb.n[q] = (int)f->d.box_n[l][q];
+    }
+    const T *src = P.prov ? arrB<T>(P) : arrA<T>(P);
+    const double g = f->d.base.gamma;
+    return hy::launch_prolong<T>(arrA<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0), f->stream);
+}
+
+template <typename T>
+hipError_t fmr_level_step(hy_fmr *f, int l, double dt, bool provisional)
+{
+    hy_fmr::Level &L = f->lev[l];
+    hy_patch *p = L.p;
+    hipError_t e;
+    if (provisional) {
+        e = run_stage<T>(p, f->solver, 1, hy::DT_HOST, dt, 0.0, 0.0);
+        L.prov = true;
+        return e;
+    }
+    const int nd = f->d.base.ndim;
+    const bool child = l + 1 < f->nlev;
+    const double g = f->d.base.gamma, w = 0.5 * dt;
+    const T gamma = (T)g, gm1 = (T)(g - 1.0), igm1 = (T)(1.0 / (g - 1.0)), theta = (T)f->d.base.theta;
+    if (child)
+        for (int q = 0; q < nd; ++q) {
+            e = hipMemsetAsync(L.coarse_acc[q][0], 0, 2 * L.coarse_bytes[q], f->stream);
+            if (e != hipSuccess) return e;
+        }
+    for (int stage = 1; stage <= 2; ++stage) {
+        const T *u = stage == 1 ? arrA<T>(L) : arrB<T>(L);
+        if (child) {
+            e = hy::launch_box_flux<T>(u, L.g, L.child, nd, f->solver, gamma, gm1, igm1, theta, w, L.coarse_acc,
+                                       f->stream);
+            if (e != hipSuccess) return e;
+        }
+        if (l > 0) {
+            e = hy::launch_box_flux<T>(u, L.g, L.own, nd, f->solver, gamma, gm1, igm1, theta, w, L.own_acc,
+                                       f->stream);
+            if (e != hipSuccess) return e;
+        }
+        e = run_stage<T>(p, f->solver, stage, hy::DT_HOST, dt, 0.0, 0.0);
+        if (e != hipSuccess) return e;
+        if (stage == 1 && l > 0) {
+            e = hy::launch_exterior_copy<T>(arrA<T>(L), arrB<T>(L), L.g, nd, f->stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    p->parity ^= 1;
+    if (child) {
+        const double *c[3][2], *fa[3][2];
+        for (int q = 0; q < 3; ++q)
+            for (int s = 0; s < 2; ++s) {
+                c[q][s] = L.coarse_acc[q][s];
+                fa[q][s] = f->lev[l + 1].own_acc[q][s];
+            }
+        e = hy::launch_reflux<T>(arrA<T>(L), L.g, L.child, nd, c, fa, L.idq, f->stream);
+    }
+    return e;
+}
+
+template <typename T>
+hy_status fmr_step_level(hy_fmr *f, int l);
+
+template <typename T>
+hy_status fmr_evolve_level(hy_fmr *f, int l)
+{
+    if (l >= f->nlev) return HY_OK;
+    hy_status st = fmr_step_level<T>(f, l);
+    if (st != HY_OK || l == 0) return st;
+    hipError_t e = hipSuccess;
+    if (l - 1 > 0) e = fmr_prolong<T>(f, l - 1);
+    if (e == hipSuccess) e = fmr_level_step<T>(f, l - 1, f->lev[l].T - f->lev[l - 1].T, true);
+    if (e != hipSuccess) return hip_fail(e, "provisional coarse step");
+    st = fmr_step_level<T>(f, l);
+    f->lev[l - 1].prov = false;
+    return st;
+}
+
+template <typename T>
+hy_status fmr_step_level(hy_fmr *f, int l)
+{
+    hy_fmr::Level &L = f->lev[l];
+    const int nd = f->d.base.ndim;
+    hipError_t e;
+    if (l + 1 < f->nlev) {
+        hy_fmr::Level &C = f->lev[l + 1];
+        for (int q = 0; q < nd; ++q) {
+            e = hipMemsetAsync(C.own_acc[q][0], 0, 2 * C.own_bytes[q], f->stream);
+            if (e != hipSuccess) return hip_fail(e, "flux accumulator clear");
+        }
+        hy_status st = fmr_evolve_level<T>(f, l + 1);
+        if (st != HY_OK) return st;
+    }
+    if (l > 0) {
+        e = fmr_prolong<T>(f, l);
+        if (e != hipSuccess) return hip_fail(e, "prolongation");
+    }
+    double dt;
+    if (l == f->nlev - 1) {
+        if (f->dt_fixed > 0.0) {
+            dt = f->dt_fixed;
+        } else {
+            e = hipMemsetAsync(f->rate, 0, sizeof(unsigned long long), f->stream);
+            const double g = f->d.base.gamma;
+            if (e == hipSuccess)
+                e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
+            unsigned long long rb = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&rb, f->rate, sizeof(rb), hipMemcpyDeviceToHost, f->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+            if (e != hipSuccess) return hip_fail(e, "deepest-level CFL rate");
+            const double rate = __builtin_bit_cast(double, rb);
+            if (!(rate > 0.0) || !std::isfinite(rate))
+                return fail(HY_ESTATE, "the deepest level holds rho <= 0, p <= 0 or a non-finite value");
+            dt = f->cfl / rate;
+        }
+    } else {
+        dt = f->lev[l + 1].T - L.T;
+    }
+    e = fmr_level_step<T>(f, l, dt, false);
+    if (e == hipSuccess && l + 1 < f->nlev) {
+        hy_fmr::Level &C = f->lev[l + 1];
+        e = hy::launch_restrict<T>(arrA<T>(L), L.g, L.child, arrA<T>(C), C.g, nd, f->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "level step");
+    L.T += dt;
+    return HY_OK;
+}
+
+hy_status fmr_check_level(hy_fmr *f, int level)
+{
+    if (!f) return fail(HY_EINVAL, "null handle");
+    if (level < 0 || level >= f->nlev) return fail(HY_EINVAL, "no such level");
+    return HY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hy_status hy_fmr_workspace_bytes(const hy_fmr_desc *d, size_t *bytes)
+{
+    if (!bytes) return fail(HY_EINVAL, "null output");
+    FmrLayout L;
+    hy_status st = fmr_layout(d, &L);
+    if (st != HY_OK) return st;
+    *bytes = L.total;
+    return HY_OK;
+}
+
+hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, void *hip_stream, hy_fmr **out)
+{
+    FmrLayout L;
+    hy_status st = fmr_layout(d, &L);
+    if (st != HY_OK) return st;
+    if (!out || !dev_workspace) return fail(HY_EINVAL, "null workspace or output handle");
+    if (bytes < L.total) return fail(HY_ENOMEM, "workspace too small");
+    hy_fmr *f = new (std::nothrow) hy_fmr();
+    if (!f) return fail(HY_ENOMEM, "host allocation failed");
+    f->d = *d;
+    f->nlev = d->nlev;
+    f->nv = d->base.ndim + 2;
+    f->stream = (hipStream_t)hip_stream;
+    const int nd = d->base.ndim;
+    char *base = (char *)(((uintptr_t)dev_workspace + 255) & ~(uintptr_t)255);
+    for (int l = 0; l < f->nlev; ++l) {
+        hy_fmr::Level &V = f->lev[l];
+        st = hy_init_patch(&L.desc[l], base + L.patch[l], L.patch_bytes[l], hip_stream, &V.p);
+        if (st != HY_OK) {
+            hy_fmr_destroy(f);
+            return st;
+        }
+        V.off = l > 0 ? hy::FMR_NG : 0;
+        V.g.vs = V.p->vstride;
+        V.dv = 1.0;
+        for (int q = 0; q < 3; ++q) {
+            const bool act = q < nd;
+            V.g.m[q] = (int)L.desc[l].n[q];
+            V.n[q] = act ? L.desc[l].n[q] - 2 * V.off : 1;
+            V.own.lo[q] = act ? V.off : 0;
+            V.own.n[q] = (int)V.n[q];
+            V.idq[q] = act ? (double)L.desc[l].n[q] / (L.desc[l].hi[q] - L.desc[l].lo[q]) : 0.0;
+            if (act) V.dv /= V.idq[q];
+            if (l + 1 < f->nlev) {
+                V.child.lo[q] = (int)(d->box_lo[l + 1][q] + (act ? V.off : 0));
+                V.child.n[q] = (int)d->box_n[l + 1][q];
+            }
+            if (act) {
+                if (l > 0) {
+                    V.own_acc[q][0] = (double *)(base + L.own[l][q]);
+                    V.own_acc[q][1] = (double *)(base + L.own[l][q] + L.own_bytes[l][q]);
+                    V.own_bytes[q] = L.own_bytes[l][q];
+                }
+                if (l + 1 < f->nlev) {
+                    V.coarse_acc[q][0] = (double *)(base + L.coarse[l][q]);
+                    V.coarse_acc[q][1] = (double *)(base + L.coarse[l][q] + L.coarse_bytes[l][q]);
+                    V.coarse_bytes[q] = L.coarse_bytes[l][q];
+                }
+            }
+        }
+        V.partials = (double *)(base + L.partials[l]);
+        V.rows = V.n[1] * V.n[2];
+    }
+    f->rate = (unsigned long long *)(base + L.rate);
+    *out = f;
+    return HY_OK;
+}
+
+hy_status hy_fmr_set_state(hy_fmr *f, int level, int kind, const double *host)
+{
+    hy_status st = fmr_check_level(f, level);
+    if (st != HY_OK) return st;
+    if (!host) return fail(HY_EINVAL, "null argument");
+    hy_fmr::Level &V = f->lev[level];
+    if (V.off == 0) return hy_set_state(V.p, kind, host);
+    // a refined level's array is padded: the exterior starts as a copy of the
+    // nearest interior cell (prolongation replaces it before it is used)
+    const int nd = f->d.base.ndim;
+    const int64_t N = V.n[0] * V.n[1] * V.n[2];
+    const int64_t M = (int64_t)V.g.m[0] * V.g.m[1] * V.g.m[2];
+    std::vector<double> pad((size_t)(f->nv * M));
+    for (int64_t k = 0; k < V.g.m[2]; ++k)
+        for (int64_t j = 0; j < V.g.m[1]; ++j)
+            for (int64_t i = 0; i < V.g.m[0]; ++i) {
+                const int64_t c3[3] = {i, j, k};
+                int64_t s3[3];
+                for (int q = 0; q < 3; ++q)
+                    s3[q] = q < nd ? std::min(std::max(c3[q] - V.off, (int64_t)0), V.n[q] - 1) : 0;
+                const int64_t src = (s3[2] * V.n[1] + s3[1]) * V.n[0] + s3[0];
+                const int64_t dst = (k * V.g.m[1] + j) * V.g.m[0] + i;
+                for (int v = 0; v < f->nv; ++v) pad[(size_t)(v * M + dst)] = host[v * N + src];
+            }
+    return hy_set_state(V.p, kind, pad.data());
+}
+
+hy_status hy_fmr_get_state(hy_fmr *f, int level, int kind, double *out)
+{
+    hy_status st = fmr_check_level(f, level);
+    if (st != HY_OK) return st;
+    if (!out) return fail(HY_EINVAL, "null argument");
+    hy_fmr::Level &V = f->lev[level];
+    if (V.off == 0) return hy_get_state(V.p, kind, out);
+    const int nd = f->d.base.ndim;
+    const int64_t N = V.n[0] * V.n[1] * V.n[2];
+    const int64_t M = (int64_t)V.g.m[0] * V.g.m[1] * V.g.m[2];
+    std::vector<double> pad((size_t)(f->nv * M));
+    st = hy_get_state(V.p, kind, pad.data());
+    if (st != HY_OK && st != HY_ESTATE) return st;
+    for (int64_t k = 0; k < V.n[2]; ++k)
+        for (int64_t j = 0; j < V.n[1]; ++j)
+            for (int64_t i = 0; i < V.n[0]; ++i) {
+                const int64_t src = ((k + (nd > 2 ? V.off : 0)) * V.g.m[1] + j + (nd > 1 ? V.off : 0)) * V.g.m[0] + i + V.off;
+                const int64_t dst = (k * V.n[1] + j) * V.n[0] + i;
+                for (int v = 0; v < f->nv; ++v) out[v * N + dst] = pad[(size_t)(v * M + src)];
+            }
+    return st;
+}
+
+hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double *dt_out)
+{
+    if (!f) return fail(HY_EINVAL, "null handle");
+    if (solver != HY_HLL && solver != HY_HLLC) return fail(HY_EINVAL, "multilevel steps take HY_HLL or HY_HLLC");
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0 && std::isfinite(cfl))) return fail(HY_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    if (dt_fixed > 0.0 && !std::isfinite(dt_fixed)) return fail(HY_EINVAL, "dt_fixed must be finite");
+    f->solver = solver;
+    f->cfl = cfl;
+    f->dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+    for (int l = 0; l < f->nlev; ++l) {
+        f->lev[l].T = 0.0;
+        f->lev[l].prov = false;
+    }
+    hy_status st = f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
+    if (st != HY_OK) return st;
+    for (int l = 0; l < f->nlev; ++l) {
+        hy::DevCtl c;
+        st = read_ctl(f->lev[l].p, &c);
+        if (st != HY_OK) return st;
+        if (c.err) return fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value");
+    }
+    if (dt_out) *dt_out = f->lev[0].T;
+    return HY_OK;
+}
+
+hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5])
+{
+    if (!f || !out) return fail(HY_EINVAL, "null argument");
+    for (int k = 0; k < 5; ++k) out[k] = 0.0;
+    const int nd = f->d.base.ndim;
+    for (int l = 0; l < f->nlev; ++l) {
+        hy_fmr::Level &V = f->lev[l];
+        hy::Box hole{};
+        if (l + 1 < f->nlev) hole = V.child;
+        hipError_t e;
+        if (f->d.base.precision == 64)
+            e = hy::launch_leaf_totals<double>((const double *)V.p->A, V.g, V.own, hole, nd, V.dv, V.partials, f->stream);
+        else
+            e = hy::launch_leaf_totals<float>((const float *)V.p->A, V.g, V.own, hole, nd, V.dv, V.partials, f->stream);
+        std::vector<double> host((size_t)(V.rows * 5));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host.data(), V.partials, sizeof(double) * host.size(), hipMemcpyDeviceToHost, f->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+        if (e != hipSuccess) return hip_fail(e, "leaf totals");
+        for (int64_t r = 0; r < V.rows; ++r)
+            for (int k = 0; k < 5; ++k) out[k] += host[(size_t)(r * 5 + k)];
+    }
+    return HY_OK;
+}
+
+hy_status hy_fmr_destroy(hy_fmr *f)
+{
+    if (!f) return HY_OK;
+    hipStreamSynchronize(f->stream);
+    for (int l = 0; l < f->nlev; ++l)
+        if (f->lev[l].p) hy_destroy(f->lev[l].p);
+    delete f;
+    return HY_OK;
+}
+
+}  // extern "C"

@@ -22,167 +22,12 @@
 // to their interior source (periodic wrap, outflow clamp, reflecting mirror
 // with the normal velocity negated).
 #include "hy_internal.h"
+#include "hy_face.h"
 
 #include <math.h>
 
 namespace hy {
 namespace {
-
-
-// ---------------------------------------------------------------- math ----
-
-template <typename T> __device__ __forceinline__ T rcp_(T x);
-template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double rcp_<double>(double x) { return 1.0 / x; }
-
-// c_s = sqrt(gamma p / rho), evaluated as (gamma p) rsqrt(gamma p rho)
-template <typename T> __device__ __forceinline__ T sound_(T gamma, T p, T rho);
-template <> __device__ __forceinline__ float sound_<float>(float g, float p, float r)
-{
-    float gp = g * p;
-    return gp * __builtin_amdgcn_rsqf(gp * r);
-}
-template <> __device__ __forceinline__ double sound_<double>(double g, double p, double r)
-{
-    return sqrt(g * p / r);
-}
-
-template <typename T> __device__ __forceinline__ T max3_(T a, T b, T c) { return fmax(a, fmax(b, c)); }
-
-// ------------------------------------------------------- index mapping ----
-
-// ------------------------------------------------------ fluid variables ----
-
-// primitives (rho, v, p) from conserved (D, S, G), m = 1; returns false on
-// rho <= 0, p <= 0 or a non-finite value
-template <int ND, typename T>
-__device__ __forceinline__ bool to_prim(const T (&u)[ND + 2], T (&w)[ND + 2], T gm1)
-{
-    const T ir = rcp_(u[0]);
-    T ke = T(0);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        w[1 + d] = u[1 + d] * ir;
-        ke += u[1 + d] * w[1 + d];
-    }
-    w[0] = u[0];
-    w[ND + 1] = gm1 * (u[ND + 1] - T(0.5) * ke);
-    const T big = T(3.0e38);
-    return (w[0] > T(0)) & (w[ND + 1] > T(0)) & (w[0] < big) & (w[ND + 1] < big);
-}
-
-template <typename T> __device__ __forceinline__ T med3_(T a, T b, T c);
-template <> __device__ __forceinline__ float med3_<float>(float a, float b, float c)
-{
-    return __builtin_amdgcn_fmed3f(a, b, c);
-}
-template <> __device__ __forceinline__ double med3_<double>(double a, double b, double c)
-{
-    return fmax(fmin(a, b), fmin(fmax(a, b), c));
-}
-
-// Twice the generalised-minmod slope of eq. MinMod as a per-cell difference:
-// with a = 2 theta dm, b = dm + dp, c = 2 theta dp, MM(a, b, c) (the argument
-// of least magnitude when all share a sign, else 0) equals
-// med3(min(a, b, c), max(a, b, c), 0), and MM(a, b, c) = 2 MM(theta dm,
-// (dm + dp) / 2, theta dp) exactly.  Face values are then w +/- slope / 4.
-template <typename T>
-__device__ __forceinline__ T slope2_mm(T wm, T w0, T wp, T theta2)
-{
-    const T dm = w0 - wm, dp = wp - w0;
-    const T a = theta2 * dm, b = dm + dp, c = theta2 * dp;
-    return med3_(fmin(a, fmin(b, c)), fmax(a, fmax(b, c)), T(0));
-}
-
-// ------------------------------------------------------ Riemann solvers ----
-
-// Flux normal to Q from the primitive face states wl (left), wr (right).
-template <int ND, int Q, int SOLVER, typename T>
-__device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2],
-                                        T gamma, T inv_gm1)
-{
-    constexpr int IP = ND + 1;
-    const T rl = wl[0], vl = wl[1 + Q], pl = wl[IP];
-    const T rr = wr[0], vr = wr[1 + Q], pr = wr[IP];
-    const T cl = sound_(gamma, pl, rl), cr = sound_(gamma, pr, rr);
-    // outer speed estimates alpha_+/- = max(0, +/-lambda_+/-(L), +/-lambda_+/-(R))
-    const T ap = max3_(T(0), vl + cl, vr + cr);
-    const T am = max3_(T(0), cl - vl, cr - vr);
-    if constexpr (SOLVER == 0) {
-        T kl = T(0), kr = T(0);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            kl += wl[1 + d] * wl[1 + d];
-            kr += wr[1 + d] * wr[1 + d];
-        }
-        const T El = pl * inv_gm1 + T(0.5) * rl * kl;
-        const T Er = pr * inv_gm1 + T(0.5) * rr * kr;
-        const T ml = rl * vl, mr = rr * vr;  // mass fluxes
-        // F = (a+ F_L + a- F_R - a+ a- (U_R - U_L)) / (a+ + a-), formed one
-        // variable at a time with the weights folded; a+ + a- = 0 (both sides
-        // at rest with c = 0) gives the mean of the two fluxes
-        const T den = ap + am;
-        const bool pos = den > T(0);
-        const T inv = pos ? rcp_(den) : T(0);
-        const T wL = pos ? ap * inv : T(0.5), wR = pos ? am * inv : T(0.5), wD = ap * am * inv;
-        f[0] = wL * ml + wR * mr - wD * (rr - rl);
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-            f[1 + d] = wL * (ml * wl[1 + d] + (d == Q ? pl : T(0))) + wR * (mr * wr[1 + d] + (d == Q ? pr : T(0))) -
-                       wD * (rr * wr[1 + d] - rl * wl[1 + d]);
-        f[IP] = wL * ((El + pl) * vl) + wR * ((Er + pr) * vr) - wD * (Er - El);
-    } else {
-        // Batten's middle-wave speed (eq. MiddleWaveSpeed)
-        const T ql = am + vl, qr = ap - vr;
-        const T am_ = (rr * vr * qr + rl * vl * ql - (pr - pl)) * rcp_(rr * qr + rl * ql);
-        // eq. FluxHLLC: alpha_- = 0 selects L, then alpha_+ = 0 selects R,
-        // then the sign of alpha_m selects the middle state on its side
-        const bool sup = (am == T(0)) | (ap == T(0));
-        const bool useL = (am == T(0)) | ((ap != T(0)) & (am_ >= T(0)));
-        T wk[ND + 2];
-#pragma unroll
-        for (int v = 0; v < ND + 2; ++v) wk[v] = useL ? wl[v] : wr[v];
-        const T sK = useL ? -am : ap;
-        const T rK = wk[0], vK = wk[1 + Q], pK = wk[IP];
-        T kk = T(0);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) kk += wk[1 + d] * wk[1 + d];
-        const T EK = pK * inv_gm1 + T(0.5) * rK * kk;
-        const T mK = rK * vK;
-        // middle state from the jump conditions across the K-side outer wave
-        const T qk = sK - vK;
-        const T inv = sup ? T(0) : rcp_(sup ? T(1) : sK - am_);
-        const T rs = rK * qk * inv;
-        const T ps = pK + rK * qk * (am_ - vK);
-        const T Gs = (qk * EK - pK * vK + ps * am_) * inv;
-        // F = F_K + s_K (U*_K - U_K); s_K = 0 in the supersonic cases
-        const T fd = mK + sK * (rs - rK);
-        f[0] = fd;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            if (d == Q) f[1 + d] = mK * vK + pK + sK * (rs * am_ - mK);
-            else f[1 + d] = fd * wk[1 + d];
-        }
-        f[IP] = (EK + pK) * vK + sK * (Gs - EK);
-    }
-}
-
-// Face flux for the kernel's solver: the HLLC switch takes HLL where hll is
-// set (a shock flagged along a direction transverse to this face), HLLC
-// elsewhere; the other solvers ignore hll.
-template <int ND, int Q, int SOLVER, typename T>
-__device__ __forceinline__ void face_flux(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2], T gamma,
-                                          T inv_gm1, bool hll)
-{
-    if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-        if (hll) riemann<ND, Q, SOLVER_HLL>(wl, wr, f, gamma, inv_gm1);
-        else riemann<ND, Q, SOLVER_HLLC>(wl, wr, f, gamma, inv_gm1);
-    } else {
-        (void)hll;
-        riemann<ND, Q, SOLVER>(wl, wr, f, gamma, inv_gm1);
-    }
-}
-
 
 // ------------------------------------------------------------ kernel ----
 

@@ -50,6 +50,18 @@ class PatchDesc(ctypes.Structure):
     ]
 
 
+FMR_MAXLEV = 8
+
+
+class FmrDesc(ctypes.Structure):
+    _fields_ = [
+        ("base", PatchDesc),
+        ("nlev", ctypes.c_int),
+        ("box_lo", (ctypes.c_int64 * 3) * FMR_MAXLEV),
+        ("box_n", (ctypes.c_int64 * 3) * FMR_MAXLEV),
+    ]
+
+
 _P = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -130,6 +142,13 @@ EXTRA_SIGNATURES = {
     "hy_trainer_get_params": [_P, _fp],
     "hy_mlp_eval": [_P, _P, _P, ctypes.c_int64],
     "hy_trainer_destroy": [_P],
+    "hy_fmr_workspace_bytes": [ctypes.POINTER(FmrDesc), ctypes.POINTER(ctypes.c_size_t)],
+    "hy_fmr_init": [ctypes.POINTER(FmrDesc), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "hy_fmr_set_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
+    "hy_fmr_get_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
+    "hy_fmr_step": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp],
+    "hy_fmr_conserved_totals": [_P, _dp],
+    "hy_fmr_destroy": [_P],
 }
 
 
@@ -484,6 +503,75 @@ class Trainer:
     def close(self):
         if getattr(self, "handle", None):
             lib().hy_trainer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fmr:
+    """Nested levels stepped with subcycling and coarse/fine flux replacement
+    (include/hydro.h, hy_fmr_*).  ``levels`` is a workloads.Levels (base
+    problem, boxes, per-level initial primitive fields)."""
+
+    def __init__(self, levels, precision: int = 32, theta: Optional[float] = None, device: str = "cuda",
+                 set_initial: bool = True):
+        import torch
+
+        b = levels.base
+        self.levels = levels
+        self.nlev = levels.nlev
+        self.ndim = b.ndim
+        self.nv = b.ndim + 2
+        self.desc = FmrDesc()
+        self.desc.base = make_desc(b.ndim, b.n, b.lo, b.hi, b.gamma, b.bc, precision, LIM_THETA,
+                                   b.theta if theta is None else theta, b.accel)
+        self.desc.nlev = self.nlev
+        for l, (lo, n) in enumerate(levels.boxes, start=1):
+            for q in range(3):
+                self.desc.box_lo[l][q] = int(lo[q])
+                self.desc.box_n[l][q] = int(n[q])
+        self.ncell = [int(np.prod(levels.level_geometry(l)[0])) for l in range(self.nlev)]
+        nbytes = ctypes.c_size_t(0)
+        check(lib().hy_fmr_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)), "fmr_workspace_bytes")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _P()
+        check(lib().hy_fmr_init(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "fmr_init")
+        self.handle = h
+        if set_initial:
+            for l, W in enumerate(levels.W):
+                self.set_state(l, W, PRIMITIVE)
+
+    def set_state(self, level: int, arr, kind: int = PRIMITIVE):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(self.nv, self.ncell[level]))
+        check(lib().hy_fmr_set_state(self.handle, int(level), int(kind), _dptr(a)), "fmr_set_state")
+
+    def get_state(self, level: int, kind: int = CONSERVED) -> np.ndarray:
+        out = np.empty((self.nv, self.ncell[level]), dtype=np.float64)
+        check(lib().hy_fmr_get_state(self.handle, int(level), int(kind), _dptr(out)), "fmr_get_state")
+        return out
+
+    def step(self, cfl: float = 0.4, dt_fixed: float = 0.0, solver: int = HLLC) -> float:
+        """One global step; returns the coarse time step."""
+        out = ctypes.c_double(0.0)
+        check(lib().hy_fmr_step(self.handle, float(cfl), float(dt_fixed), int(solver), ctypes.byref(out)),
+              "fmr_step")
+        return out.value
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(5)
+        check(lib().hy_fmr_conserved_totals(self.handle, _dptr(out)), "fmr_conserved_totals")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hy_fmr_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -468,18 +468,21 @@ def _level_fields(lv: Levels, fn) -> List[np.ndarray]:
 
 def sedov_levels(ndim: int = 2, n0: int = 64, nlev: int = 3, gamma: float = 1.4, rho0: float = 1.0,
                  p0: float = 1e-5, e_d: float = 1.0, r_cells: float = 3.5, sub: int = 20,
-                 bc: int = BC_OUTFLOW, theta: float = 2.0, cfl: float = 0.4) -> Levels:
+                 bc: int = BC_OUTFLOW, theta: float = 1.4, cfl: float = 0.4, boxes=None) -> Levels:
     """Sedov-Taylor blast (Sec. 4.2): fluid at rest, density rho0, pressure p0
     on [-0.5, 0.5]^d, with the energy e_d released as the pressure
     3 (gamma - 1) e_d / ((alpha + 1) pi R_d^alpha) inside r <= R_d (alpha = d;
     in 1D the slab |x| <= R_d holds e_d as (gamma - 1) e_d / (2 R_d)).  R_d is
     r_cells finest-level cells; every cell cut by the sphere takes the volume
     average of the pressure over a sub^d subgrid.  Levels: nested boxes, each
-    the central half of its parent, n0 cells per dimension on every level."""
+    the central half of its parent, n0 cells per dimension on every level, or
+    the given ``boxes``.  theta = 1.4, the value the paper often uses."""
     lo3 = tuple(-0.5 if q < ndim else 0.0 for q in range(3))
     hi3 = tuple(0.5 if q < ndim else 1.0 for q in range(3))
     n3 = tuple(n0 if q < ndim else 1 for q in range(3))
     bcs = tuple((bc, bc) if q < ndim else (0, 0) for q in range(3))
+    if boxes is not None:
+        nlev = 1 + len(boxes)
     dx_fine = 1.0 / (n0 * 2 ** (nlev - 1))
     r_d = r_cells * dx_fine
     if ndim == 1:
@@ -511,7 +514,7 @@ def sedov_levels(ndim: int = 2, n0: int = 64, nlev: int = 3, gamma: float = 1.4,
         return W
 
     base = Problem(ndim, n3, lo3, hi3, gamma, bcs, None, theta=theta, cfl=cfl, name="sedov_levels")
-    lv = Levels(base, _nested_boxes(ndim, n0, nlev), [])
+    lv = Levels(base, _nested_boxes(ndim, n0, nlev) if boxes is None else list(boxes), [])
     lv.W = _level_fields(lv, fields)
     base.W = lv.W[0]
     return lv
@@ -519,15 +522,15 @@ def sedov_levels(ndim: int = 2, n0: int = 64, nlev: int = 3, gamma: float = 1.4,
 
 def smooth_levels(ndim: int = 2, n0: int = 32, nlev: int = 2, seed: int = DEFAULT_SEED, amp: float = 0.2,
                   vel=(0.6, 0.3, 0.2), gamma: float = 1.4, theta: float = 2.0, cfl: float = 0.4,
-                  uniform: bool = False, t: float = 0.0) -> Levels:
+                  uniform: bool = False, t: float = 0.0, boxes=None, n=None) -> Levels:
     """Periodic unit box with a smooth density wave (random phases, modes 1 and
     2 per dimension) carried by a uniform velocity at uniform pressure; with
     ``uniform`` the density is 1 everywhere.  ``t`` > 0 gives the exact
     solution at time t (the wave translated by vel * t).  Levels as in
-    sedov_levels."""
+    sedov_levels; ``n`` (cells per dimension of level 0) overrides n0."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ph = rng.uniform(0.0, 2.0 * math.pi, size=(ndim, 2))
-    n3 = tuple(n0 if q < ndim else 1 for q in range(3))
+    n3 = tuple((n0 if n is None else n[q]) if q < ndim else 1 for q in range(3))
     bcs = tuple((BC_PERIODIC, BC_PERIODIC) for _ in range(3))
 
     def fields(n, lo, hi):
@@ -547,7 +550,7 @@ def smooth_levels(ndim: int = 2, n0: int = 32, nlev: int = 2, seed: int = DEFAUL
 
     base = Problem(ndim, n3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), gamma, bcs, None, theta=theta, cfl=cfl,
                    name="smooth_levels")
-    lv = Levels(base, _nested_boxes(ndim, n0, nlev), [])
+    lv = Levels(base, _nested_boxes(ndim, n0, nlev) if boxes is None else list(boxes), [])
     lv.W = _level_fields(lv, fields)
     base.W = lv.W[0]
     return lv
