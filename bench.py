@@ -193,6 +193,7 @@ def time_fmr(nd=3, n0=128, nlev=4, steps=4, warmup=1):
 
     lv = wl.sedov_levels(nd, n0, nlev)
     F = hydro.Fmr(lv, precision=32)
+    shapes = F.autotune(hydro.HLL, 3)
     T0 = F.totals()
     for _ in range(warmup):
         F.step(0.4, solver=hydro.HLL)
@@ -210,7 +211,8 @@ def time_fmr(nd=3, n0=128, nlev=4, steps=4, warmup=1):
         leaf += (F.ncell[l] - covered) * 2 ** l
     return {"levels": nlev, "cells_per_level": F.ncell[0], "leaf_zone_updates_per_global_step": leaf,
             "ms_per_global_step": 1e3 * wall / steps, "leaf_zone_updates_per_s": leaf * steps / wall,
-            "mass_drift": float((T1[0] - T0[0]) / T0[0]), "energy_drift": float((T1[4] - T0[4]) / T0[4])}
+            "mass_drift": float((T1[0] - T0[0]) / T0[0]), "energy_drift": float((T1[4] - T0[4]) / T0[4]),
+            "launch_shapes": shapes}
 
 
 def source_digest():

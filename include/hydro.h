@@ -328,6 +328,10 @@ hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double
 /* FP64 sums of D, S_x, S_y, S_z, G times the cell volume over the leaf
  * cells of all levels (cells no finer level covers); synchronising. */
 hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5]);
+/* hy_autotune on every level (its padded extent, its current state); best,
+ * when not NULL, receives nlev shapes.  Results do not change.
+ * Synchronising. */
+hy_status hy_fmr_autotune(hy_fmr *f, int solver, int reps, hy_launch_cfg *best);
 hy_status hy_fmr_destroy(hy_fmr *f);
 
 #ifdef __cplusplus

@@ -8,6 +8,8 @@
 #include "hy_fmr.h"
 #include "hy_face.h"
 
+#include <algorithm>
+
 namespace hy {
 namespace {
 
@@ -19,27 +21,61 @@ __device__ __forceinline__ int64_t at(const Grid &g, int i, int j, int k)
     return ((int64_t)k * g.m[1] + j) * g.m[0] + i;
 }
 
-// The exterior cells of row (j, k) of a padded array: every cell when the row
-// itself lies in the exterior along y or z, else the NG cells at each x end.
+constexpr int SB = 256;  // threads per block of the exterior-shell kernels
+
+// The exterior cells of a padded array, enumerated flat: first the rows that
+// lie wholly in the exterior (every x), then the NG cells at each x end of
+// the remaining rows.
 template <int ND>
-__device__ __forceinline__ bool shell_row(const Grid &g, int j, int k)
+__host__ __device__ inline int shell_full_rows(const Grid &g)
 {
-    bool row = false;
-    if constexpr (ND >= 2) row = row || j < FMR_NG || j >= g.m[1] - FMR_NG;
-    if constexpr (ND >= 3) row = row || k < FMR_NG || k >= g.m[2] - FMR_NG;
-    return row;
+    if constexpr (ND == 1) return 0;
+    if constexpr (ND == 2) return 2 * FMR_NG;
+    return 2 * FMR_NG * g.m[1] + (g.m[2] - 2 * FMR_NG) * 2 * FMR_NG;
 }
 
 template <int ND>
-__device__ __forceinline__ int shell_count(const Grid &g, bool row)
+__host__ __device__ inline int shell_cells(const Grid &g)
 {
-    return row ? g.m[0] : 2 * FMR_NG;
+    int part = 1;
+    if constexpr (ND >= 2) part *= g.m[1] - 2 * FMR_NG;
+    if constexpr (ND >= 3) part *= g.m[2] - 2 * FMR_NG;
+    return shell_full_rows<ND>(g) * g.m[0] + part * 2 * FMR_NG;
 }
 
 template <int ND>
-__device__ __forceinline__ int shell_x(const Grid &g, bool row, int t)
+__device__ __forceinline__ void shell_cell(const Grid &g, int s, int (&c)[3])
 {
-    return row ? t : (t < FMR_NG ? t : g.m[0] - 2 * FMR_NG + t);
+    const int full = shell_full_rows<ND>(g) * g.m[0];
+    c[1] = 0;
+    c[2] = 0;
+    if (s < full) {
+        const int r = s / g.m[0];
+        c[0] = s - r * g.m[0];
+        if constexpr (ND == 2) {
+            c[1] = r < FMR_NG ? r : g.m[1] - 2 * FMR_NG + r;
+        } else if constexpr (ND == 3) {
+            const int slab = FMR_NG * g.m[1];  // rows of the low (or high) z exterior
+            if (r < 2 * slab) {
+                const int h = r / slab, rr = r - h * slab;
+                c[2] = (h ? g.m[2] - FMR_NG : 0) + rr / g.m[1];
+                c[1] = rr % g.m[1];
+            } else {
+                const int rr = r - 2 * slab, jj = rr % (2 * FMR_NG);
+                c[2] = FMR_NG + rr / (2 * FMR_NG);
+                c[1] = jj < FMR_NG ? jj : g.m[1] - 2 * FMR_NG + jj;
+            }
+        }
+    } else {
+        const int p = s - full, row = p / (2 * FMR_NG), x = p - row * 2 * FMR_NG;
+        c[0] = x < FMR_NG ? x : g.m[0] - 2 * FMR_NG + x;
+        if constexpr (ND == 2) c[1] = FMR_NG + row;
+        if constexpr (ND == 3) {
+            const int ny = g.m[1] - 2 * FMR_NG;
+            c[2] = FMR_NG + row / ny;
+            c[1] = FMR_NG + row % ny;
+        }
+    }
 }
 
 template <int ND, typename T>
@@ -52,14 +88,13 @@ __device__ __forceinline__ void load_prim(const T *u, const Grid &g, int64_t c, 
 }
 
 template <int ND, typename T>
-__global__ void __launch_bounds__(FB) k_prolong(T *fine, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
+__global__ void __launch_bounds__(SB) k_prolong(T *fine, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
                                                  T inv_gm1)
 {
-    const int j = blockIdx.x, k = blockIdx.y;
-    const bool row = shell_row<ND>(fg, j, k);
-    const int cnt = shell_count<ND>(fg, row);
-    for (int t = threadIdx.x; t < cnt; t += FB) {
-        const int c3[3] = {shell_x<ND>(fg, row, t), j, k};
+    const int sc = blockIdx.x * SB + threadIdx.x;
+    if (sc < shell_cells<ND>(fg)) {
+        int c3[3];
+        shell_cell<ND>(fg, sc, c3);
         int p3[3], s3[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -103,27 +138,26 @@ __global__ void __launch_bounds__(FB) k_prolong(T *fine, Grid fg, const T *paren
 }
 
 template <int ND, typename T>
-__global__ void __launch_bounds__(FB) k_exterior_copy(const T *src, T *dst, Grid g)
+__global__ void __launch_bounds__(SB) k_exterior_copy(const T *src, T *dst, Grid g)
 {
-    const int j = blockIdx.x, k = blockIdx.y;
-    const bool row = shell_row<ND>(g, j, k);
-    const int cnt = shell_count<ND>(g, row);
-    for (int t = threadIdx.x; t < cnt; t += FB) {
-        const int64_t c = at(g, shell_x<ND>(g, row, t), j, k);
+    const int sc = blockIdx.x * SB + threadIdx.x;
+    if (sc >= shell_cells<ND>(g)) return;
+    int c3[3];
+    shell_cell<ND>(g, sc, c3);
+    const int64_t c = at(g, c3[0], c3[1], c3[2]);
 #pragma unroll
-        for (int v = 0; v < ND + 2; ++v) dst[v * g.vs + c] = src[v * g.vs + c];
-    }
+    for (int v = 0; v < ND + 2; ++v) dst[v * g.vs + c] = src[v * g.vs + c];
 }
 
-// One thread per face position transverse to Q: both faces (low and high
-// side of the box) along the line through it.
+// The faces of one box normal to Q: one thread per face position
+// transverse to Q, both faces (low and high side of the box) along the line
+// through it.
 template <int ND, int Q, int SOLVER, typename T>
-__global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, Box b, T gamma, T gm1, T inv_gm1, T theta2,
-                                                  double w, double *acc_lo, double *acc_hi)
+__device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &b, int t, T gamma, T gm1, T inv_gm1,
+                                          T theta2, double w, bool assign, double *acc_lo, double *acc_hi)
 {
     constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
     const int faces = b.n[R1] * b.n[R2];
-    const int t = blockIdx.x * FB + threadIdx.x;
     if (t >= faces) return;
     const int t1 = t % b.n[R1], t2 = t / b.n[R1];
 #pragma unroll
@@ -147,8 +181,39 @@ __global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, Box b, T ga
         face_flux<ND, Q, SOLVER>(wl, wr, fl, gamma, inv_gm1, false);
         double *acc = side == 0 ? acc_lo : acc_hi;
 #pragma unroll
-        for (int v = 0; v < ND + 2; ++v) acc[(int64_t)v * faces + t] += w * (double)fl[v];
+        for (int v = 0; v < ND + 2; ++v) {
+            double &a = acc[(int64_t)v * faces + t];
+            a = (assign ? 0.0 : a) + w * (double)fl[v];
+        }
     }
+}
+
+// Up to two boxes of one array in one launch: blockIdx.y = box * ND + Q.
+// assign[k]: box k's accumulators are overwritten, not added to.
+struct FluxSet {
+    Box b[2];
+    double *acc[2][3][2];
+    int assign[2];
+};
+
+template <int ND, int SOLVER, typename T>
+__global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs, T gamma, T gm1, T inv_gm1, T theta2,
+                                                  double w)
+{
+    const int bx = blockIdx.y / ND, q = blockIdx.y - bx * ND;
+    const int t = blockIdx.x * FB + threadIdx.x;
+    const Box &b = fs.b[bx];
+    if (q == 0)
+        box_faces<ND, 0, SOLVER>(u, g, b, t, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+                                     fs.acc[bx][0][0], fs.acc[bx][0][1]);
+    if constexpr (ND >= 2)
+        if (q == 1)
+            box_faces<ND, 1, SOLVER>(u, g, b, t, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+                                     fs.acc[bx][1][0], fs.acc[bx][1][1]);
+    if constexpr (ND >= 3)
+        if (q == 2)
+            box_faces<ND, 2, SOLVER>(u, g, b, t, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+                                     fs.acc[bx][2][0], fs.acc[bx][2][1]);
 }
 
 // One thread per coarse face of the child box normal to Q (both sides).
@@ -211,15 +276,17 @@ __global__ void __launch_bounds__(FB) k_restrict(T *parent, Grid pg, Box b, cons
     }
 }
 
+// Grid-stride over the box's cells; one atomic per block.
 template <int ND, typename T>
 __global__ void __launch_bounds__(TB) k_box_rate(const T *u, Grid g, Box b, T gamma, T gm1, double idq0, double idq1,
                                                   double idq2, unsigned long long *rate_bits)
 {
     __shared__ double red[TB];
-    const int j = blockIdx.x, k = blockIdx.y;
     const double idq[3] = {idq0, idq1, idq2};
+    const int nx = b.n[0], nxy = b.n[0] * b.n[1], cells = nxy * b.n[2];
     double m = 0.0;
-    for (int i = threadIdx.x; i < b.n[0]; i += TB) {
+    for (int c = blockIdx.x * TB + threadIdx.x; c < cells; c += gridDim.x * TB) {
+        const int k = c / nxy, r = c - k * nxy, j = r / nx, i = r - j * nx;
         T w[ND + 2];
         load_prim<ND>(u, g, at(g, b.lo[0] + i, b.lo[1] + j, b.lo[2] + k), gm1, w);
         const double cs = (double)sound_(gamma, w[ND + 1], w[0]);
@@ -275,34 +342,19 @@ __global__ void __launch_bounds__(TB) k_leaf_totals(const T *u, Grid g, Box b, B
     }
 }
 
-template <int ND, int Q, typename T>
-hipError_t box_flux_q(const T *u, const Grid &g, const Box &b, int solver, T gamma, T gm1, T inv_gm1, T theta2,
-                      double w, double *lo, double *hi, hipStream_t s)
-{
-    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
-    const int faces = b.n[R1] * b.n[R2];
-    const dim3 grid((faces + FB - 1) / FB);
-    if (solver == SOLVER_HLL)
-        hipLaunchKernelGGL((k_box_flux<ND, Q, SOLVER_HLL, T>), grid, dim3(FB), 0, s, u, g, b, gamma, gm1, inv_gm1,
-                           theta2, w, lo, hi);
-    else
-        hipLaunchKernelGGL((k_box_flux<ND, Q, SOLVER_HLLC, T>), grid, dim3(FB), 0, s, u, g, b, gamma, gm1, inv_gm1,
-                           theta2, w, lo, hi);
-    return hipGetLastError();
-}
-
 template <int ND, typename T>
-hipError_t box_flux_nd(const T *u, const Grid &g, const Box &b, int solver, T gamma, T gm1, T inv_gm1, T theta2,
-                       double w, double *const acc[3][2], hipStream_t s)
+hipError_t box_flux_nd(const T *u, const Grid &g, const FluxSet &fs, int nbox, int solver, T gamma, T gm1, T inv_gm1,
+                       T theta2, double w, hipStream_t s)
 {
-    hipError_t e = box_flux_q<ND, 0>(u, g, b, solver, gamma, gm1, inv_gm1, theta2, w, acc[0][0], acc[0][1], s);
-    if constexpr (ND >= 2)
-        if (e == hipSuccess)
-            e = box_flux_q<ND, 1>(u, g, b, solver, gamma, gm1, inv_gm1, theta2, w, acc[1][0], acc[1][1], s);
-    if constexpr (ND >= 3)
-        if (e == hipSuccess)
-            e = box_flux_q<ND, 2>(u, g, b, solver, gamma, gm1, inv_gm1, theta2, w, acc[2][0], acc[2][1], s);
-    return e;
+    int most = 0;
+    for (int k = 0; k < nbox; ++k)
+        for (int q = 0; q < ND; ++q) most = std::max(most, fs.b[k].n[(q + 1) % 3] * fs.b[k].n[(q + 2) % 3]);
+    const dim3 grid((most + FB - 1) / FB, nbox * ND);
+    if (solver == SOLVER_HLL)
+        hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLL, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta2, w);
+    else
+        hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLLC, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta2, w);
+    return hipGetLastError();
 }
 
 template <int ND, int Q, typename T>
@@ -323,32 +375,43 @@ hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &
                           T gamma, T gm1, hipStream_t s)
 {
     (void)gamma;
-    const dim3 grid(fg.m[1], fg.m[2]);
     const T inv_gm1 = T(1) / gm1;
-    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(FB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
-    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(FB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
-    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(FB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
+    const int cells = ndim == 1 ? shell_cells<1>(fg) : ndim == 2 ? shell_cells<2>(fg) : shell_cells<3>(fg);
+    const dim3 grid((cells + SB - 1) / SB);
+    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(SB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
+    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(SB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
+    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(SB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, hipStream_t s)
 {
-    const dim3 grid(g.m[1], g.m[2]);
-    if (ndim == 1) hipLaunchKernelGGL((k_exterior_copy<1, T>), grid, dim3(FB), 0, s, src, dst, g);
-    else if (ndim == 2) hipLaunchKernelGGL((k_exterior_copy<2, T>), grid, dim3(FB), 0, s, src, dst, g);
-    else hipLaunchKernelGGL((k_exterior_copy<3, T>), grid, dim3(FB), 0, s, src, dst, g);
+    const int cells = ndim == 1 ? shell_cells<1>(g) : ndim == 2 ? shell_cells<2>(g) : shell_cells<3>(g);
+    const dim3 grid((cells + SB - 1) / SB);
+    if (ndim == 1) hipLaunchKernelGGL((k_exterior_copy<1, T>), grid, dim3(SB), 0, s, src, dst, g);
+    else if (ndim == 2) hipLaunchKernelGGL((k_exterior_copy<2, T>), grid, dim3(SB), 0, s, src, dst, g);
+    else hipLaunchKernelGGL((k_exterior_copy<3, T>), grid, dim3(SB), 0, s, src, dst, g);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_box_flux(const T *u, const Grid &g, const Box &box, int ndim, int solver, T gamma, T gm1,
-                           T inv_gm1, T theta, double w, double *const acc[3][2], hipStream_t s)
+hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes, double *const (*acc)[3][2],
+                           const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta, double w,
+                           hipStream_t s)
 {
+    if (nbox < 1 || nbox > 2) return hipErrorInvalidValue;
+    FluxSet fs{};
+    for (int k = 0; k < nbox; ++k) {
+        fs.b[k] = boxes[k];
+        fs.assign[k] = assign[k];
+        for (int q = 0; q < 3; ++q)
+            for (int side = 0; side < 2; ++side) fs.acc[k][q][side] = acc[k][q][side];
+    }
     const T theta2 = T(2) * theta;
-    if (ndim == 1) return box_flux_nd<1>(u, g, box, solver, gamma, gm1, inv_gm1, theta2, w, acc, s);
-    if (ndim == 2) return box_flux_nd<2>(u, g, box, solver, gamma, gm1, inv_gm1, theta2, w, acc, s);
-    return box_flux_nd<3>(u, g, box, solver, gamma, gm1, inv_gm1, theta2, w, acc, s);
+    if (ndim == 1) return box_flux_nd<1>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta2, w, s);
+    if (ndim == 2) return box_flux_nd<2>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta2, w, s);
+    return box_flux_nd<3>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta2, w, s);
 }
 
 template <typename T>
@@ -381,7 +444,8 @@ template <typename T>
 hipError_t launch_box_rate(const T *u, const Grid &g, const Box &box, int ndim, T gamma, T gm1, const double idq[3],
                            unsigned long long *rate_bits, hipStream_t s)
 {
-    const dim3 grid(box.n[1], box.n[2]);
+    const int64_t cells = (int64_t)box.n[0] * box.n[1] * box.n[2];
+    const dim3 grid((unsigned)std::min<int64_t>((cells + TB - 1) / TB, 1024));
     if (ndim == 1)
         hipLaunchKernelGGL((k_box_rate<1, T>), grid, dim3(TB), 0, s, u, g, box, gamma, gm1, idq[0], idq[1], idq[2], rate_bits);
     else if (ndim == 2)
@@ -406,8 +470,8 @@ hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const B
     template hipError_t launch_prolong<T>(T *, const Grid &, const T *, const Grid &, const Box &, int, T, T,        \
                                           hipStream_t);                                                              \
     template hipError_t launch_exterior_copy<T>(const T *, T *, const Grid &, int, hipStream_t);                     \
-    template hipError_t launch_box_flux<T>(const T *, const Grid &, const Box &, int, int, T, T, T, T, double,       \
-                                           double *const[3][2], hipStream_t);                                        \
+    template hipError_t launch_box_flux<T>(const T *, const Grid &, int, const Box *, double *const(*)[3][2],        \
+                                           const int *, int, int, T, T, T, T, double, hipStream_t);                  \
     template hipError_t launch_reflux<T>(T *, const Grid &, const Box &, int, const double *const[3][2],             \
                                          const double *const[3][2], const double[3], hipStream_t);                   \
     template hipError_t launch_restrict<T>(T *, const Grid &, const Box &, const T *, const Grid &, int, hipStream_t); \

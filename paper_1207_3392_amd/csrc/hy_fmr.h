@@ -39,13 +39,16 @@ hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &
 template <typename T>
 hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, hipStream_t s);
 
-// Fluxes through the low and high faces of box along every active q, from
-// the generalised-minmod face states of the array u (the box needs two cells
-// of u beyond each face): acc[q][side][v * faces + t] += w * F, t running over
-// the box's cells transverse to q ((q + 1) % 3 fastest).
+// Fluxes through the low and high faces of each of nbox (1 or 2) boxes of
+// the array u along every active q, from its generalised-minmod face states
+// (a box needs two cells of u beyond each face), in one launch:
+// acc[k][q][side][v * faces + t] += w * F for box k (= w * F when
+// assign[k] != 0), t running over the box's cells transverse to q
+// ((q + 1) % 3 fastest).
 template <typename T>
-hipError_t launch_box_flux(const T *u, const Grid &g, const Box &box, int ndim, int solver, T gamma, T gm1,
-                           T inv_gm1, T theta, double w, double *const acc[3][2], hipStream_t s);
+hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes, double *const (*acc)[3][2],
+                           const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta, double w,
+                           hipStream_t s);
 
 // Coarse/fine replacement: every parent cell just outside the child box takes
 // (fine - coarse) / dq of the flux through its face into the box (sign by

@@ -1299,10 +1299,10 @@ struct hy_fmr {
         double dv = 1.0;
         double *own_acc[3][2] = {};     // boundary fluxes over the last two steps (for the parent)
         double *coarse_acc[3][2] = {};  // this level's fluxes at the child's faces over one step
-        size_t own_bytes[3] = {0, 0, 0}, coarse_bytes[3] = {0, 0, 0};  // per side; the two sides are adjacent
         double *partials = nullptr;     // leaf totals, rows x 5
         int64_t rows = 0;
-        bool prov = false;  // the provisional half-step result sits in the patch's stage buffer
+        bool prov = false;       // the provisional half-step result sits in the patch's stage buffer
+        bool own_fresh = false;  // own_acc holds nothing yet: the next write assigns
         double T = 0.0;
     } lev[HY_FMR_MAXLEV];
     unsigned long long *rate = nullptr;
@@ -1415,22 +1415,36 @@ hipError_t fmr_level_step(hy_fmr *f, int l, double dt, bool provisional)
     const bool child = l + 1 < f->nlev;
     const double g = f->d.base.gamma, w = 0.5 * dt;
     const T gamma = (T)g, gm1 = (T)(g - 1.0), igm1 = (T)(1.0 / (g - 1.0)), theta = (T)f->d.base.theta;
-    if (child)
-        for (int q = 0; q < nd; ++q) {
-            e = hipMemsetAsync(L.coarse_acc[q][0], 0, 2 * L.coarse_bytes[q], f->stream);
-            if (e != hipSuccess) return e;
-        }
+    // the fluxes through the child's faces (replaced later) and through this
+    // level's own boundary (handed to the parent), from each stage's input
+    hy::Box boxes[2];
+    double *const(*accs[2])[2] = {nullptr, nullptr};
+    int nbox = 0, assign[2] = {0, 0}, kc = -1, ko = -1;
+    if (child) {
+        boxes[nbox] = L.child;
+        kc = nbox;
+        accs[nbox++] = L.coarse_acc;
+    }
+    if (l > 0) {
+        boxes[nbox] = L.own;
+        ko = nbox;
+        accs[nbox++] = L.own_acc;
+    }
+    double *acc[2][3][2];
+    for (int k = 0; k < nbox; ++k)
+        for (int q = 0; q < 3; ++q)
+            for (int s = 0; s < 2; ++s) acc[k][q][s] = accs[k][q][s];
     for (int stage = 1; stage <= 2; ++stage) {
         const T *u = stage == 1 ? arrA<T>(L) : arrB<T>(L);
-        if (child) {
-            e = hy::launch_box_flux<T>(u, L.g, L.child, nd, f->solver, gamma, gm1, igm1, theta, w, L.coarse_acc,
+        if (nbox > 0) {
+            // the child-face fluxes start afresh each step; the boundary
+            // fluxes afresh after the parent has consumed them
+            if (kc >= 0) assign[kc] = stage == 1;
+            if (ko >= 0) assign[ko] = stage == 1 && L.own_fresh;
+            e = hy::launch_box_flux<T>(u, L.g, nbox, boxes, acc, assign, nd, f->solver, gamma, gm1, igm1, theta, w,
                                        f->stream);
             if (e != hipSuccess) return e;
-        }
-        if (l > 0) {
-            e = hy::launch_box_flux<T>(u, L.g, L.own, nd, f->solver, gamma, gm1, igm1, theta, w, L.own_acc,
-                                       f->stream);
-            if (e != hipSuccess) return e;
+            L.own_fresh = false;
         }
         e = run_stage<T>(p, f->solver, stage, hy::DT_HOST, dt, 0.0, 0.0);
         if (e != hipSuccess) return e;
@@ -1477,11 +1491,7 @@ hy_status fmr_step_level(hy_fmr *f, int l)
     const int nd = f->d.base.ndim;
     hipError_t e;
     if (l + 1 < f->nlev) {
-        hy_fmr::Level &C = f->lev[l + 1];
-        for (int q = 0; q < nd; ++q) {
-            e = hipMemsetAsync(C.own_acc[q][0], 0, 2 * C.own_bytes[q], f->stream);
-            if (e != hipSuccess) return hip_fail(e, "flux accumulator clear");
-        }
+        f->lev[l + 1].own_fresh = true;  // the child's boundary fluxes over its next two steps
         hy_status st = fmr_evolve_level<T>(f, l + 1);
         if (st != HY_OK) return st;
     }
@@ -1582,12 +1592,10 @@ hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, v
                 if (l > 0) {
                     V.own_acc[q][0] = (double *)(base + L.own[l][q]);
                     V.own_acc[q][1] = (double *)(base + L.own[l][q] + L.own_bytes[l][q]);
-                    V.own_bytes[q] = L.own_bytes[l][q];
                 }
                 if (l + 1 < f->nlev) {
                     V.coarse_acc[q][0] = (double *)(base + L.coarse[l][q]);
                     V.coarse_acc[q][1] = (double *)(base + L.coarse[l][q] + L.coarse_bytes[l][q]);
-                    V.coarse_bytes[q] = L.coarse_bytes[l][q];
                 }
             }
         }
@@ -1695,6 +1703,16 @@ hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5])
         if (e != hipSuccess) return hip_fail(e, "leaf totals");
         for (int64_t r = 0; r < V.rows; ++r)
             for (int k = 0; k < 5; ++k) out[k] += host[(size_t)(r * 5 + k)];
+    }
+    return HY_OK;
+}
+
+hy_status hy_fmr_autotune(hy_fmr *f, int solver, int reps, hy_launch_cfg *best)
+{
+    if (!f) return fail(HY_EINVAL, "null handle");
+    for (int l = 0; l < f->nlev; ++l) {
+        hy_status st = hy_autotune(f->lev[l].p, solver, reps, best ? &best[l] : nullptr, nullptr);
+        if (st != HY_OK) return st;
     }
     return HY_OK;
 }

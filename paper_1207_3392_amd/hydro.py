@@ -148,6 +148,7 @@ EXTRA_SIGNATURES = {
     "hy_fmr_get_state": [_P, ctypes.c_int, ctypes.c_int, _dp],
     "hy_fmr_step": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp],
     "hy_fmr_conserved_totals": [_P, _dp],
+    "hy_fmr_autotune": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(LaunchCfg)],
     "hy_fmr_destroy": [_P],
 }
 
@@ -568,6 +569,12 @@ class Fmr:
         out = np.zeros(5)
         check(lib().hy_fmr_conserved_totals(self.handle, _dptr(out)), "fmr_conserved_totals")
         return out
+
+    def autotune(self, solver: int = HLLC, reps: int = 3):
+        """Tune every level's stage launch shape; returns [(bx, by, zchunk)] per level."""
+        best = (LaunchCfg * self.nlev)()
+        check(lib().hy_fmr_autotune(self.handle, int(solver), int(reps), best), "fmr_autotune")
+        return [(c.bx, c.by, c.zchunk) for c in best]
 
     def close(self):
         if getattr(self, "handle", None):

@@ -136,6 +136,24 @@ def test_single_level_equals_patch_step():
     P.close()
 
 
+def test_autotune_changes_no_result():
+    """Tiles never change a result; the tuned shapes are among the supported
+    ones, and a step after tuning matches a step without it."""
+    lv = wl.sedov_levels(3, 16, 2)
+    A = hydro.Fmr(lv, precision=32)
+    B = hydro.Fmr(lv, precision=32)
+    shapes = B.autotune(hydro.HLL, 2)
+    assert len(shapes) == 2 and all(s[0] in (32, 64) for s in shapes)
+    for F in (A, B):
+        F.step(dt_fixed=1e-3, solver=hydro.HLL)
+    for l in range(2):
+        a, b = A.get_state(l), B.get_state(l)
+        s = scale(a)
+        assert np.max(np.abs(a - b) / s) < 1e-6
+    A.close()
+    B.close()
+
+
 def test_blast_symmetry_fp64():
     lv = wl.sedov_levels(2, 32, 3)
     F = hydro.Fmr(lv, precision=64)
