@@ -57,10 +57,10 @@ FLOPS_PER_CELL = {"hllc": {1: 478, 2: 524}, "hll": {1: 448, 2: 494}}
 TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h",
                    "paper_1207_3392_amd/csrc/hy_face.h")
 TRAFFIC = {
-    "digest": "70f6381b4c49ebe98916af3870f7d953bf5389120fdbb0ad8ca980dfde63243a",
+    "digest": "17e5314d9f1795336b8546149fba6766f009e746faf55448ee1b2942280741f3",
     "ncell": 256 ** 3,
     "kernel": "k_stage<nd=3,f32,tile=64x8> zchunk=64",
-    "bytes_per_launch": {1: 703673307, 2: 1100950699},
+    "bytes_per_launch": {1: 703416432, 2: 1107725184},
 }
 
 
@@ -180,7 +180,7 @@ def time_kh(n=2048, steps=20, learned=False):
 
 
 def time_fmr(nd=3, n0=128, nlev=4, steps=4, warmup=1):
-    """Multilevel Sedov-Taylor blast (Sec. 4.2; Algs. Evolve..StepLevel):
+    """Multilevel Sedov-Taylor blast (Sec. 4.2.3; Algs. Evolve..StepLevel):
     nested boxes, each the central half of its parent, n0^d cells per level,
     FP32, HLL, theta 1.4, C_CFL 0.4.  A global step advances every level to a
     common time (the deepest level takes 2^(nlev-1) steps).  Leaf zone-updates

@@ -8,7 +8,7 @@
  *  - Every function returns hy_status (0 = HY_OK, negative = error) and never
  *    throws; hy_last_error() gives a thread-local message for the last error.
  *  - Host arrays are structure-of-arrays (nv, nz, ny, nx), x fastest, over
- *    interior cells only, FP64.  nv = ndim + 2.  Conserved order (Sec. 3.4):
+ *    interior cells only, FP64.  nv = ndim + 2.  Conserved order (Sec. 3.5):
  *    D, S_1..S_ndim, G.  Primitive order: rho, v_1..v_ndim, p.  The baryon
  *    mass m is 1, so rho = D.  Unused dimensions have n = 1.
  *  - Device memory is owned by the caller: the library carves everything it
@@ -63,7 +63,7 @@ typedef enum { HY_PRIMITIVE = 0, HY_CONSERVED = 1 } hy_kind;
  *              n[0] <= 2^20, n[1] and n[2] <= 65535, and one variable's array
  *              below 4 GiB (HY_EINVAL otherwise).
  *  lo, hi      box corners; cell width (hi - lo) / n (uniform grid, Sec. 3).
- *  gamma       ideal-gas index, p = (gamma - 1) e (Sec. 3.4, polytropic closure).
+ *  gamma       ideal-gas index, p = (gamma - 1) e (Sec. 3.5, polytropic closure).
  *  bc[q][s]    boundary kind on the low (s = 0) / high (s = 1) face of
  *              dimension q.  Ghost cells are filled from cell-centre
  *              primitives: periodic wraps, outflow copies the nearest interior
@@ -285,7 +285,7 @@ hy_status hy_trainer_destroy(hy_trainer *tr);
 
 /* ---------------------------------------------------------------------
  * Fixed multilevel refinement (Sec. 2, the refinable mesh with its
- * prolongation and restriction; Sec. 3.5, Algs. Evolve, EvolveLevel and
+ * prolongation and restriction; Sec. 3.6, Algs. Evolve, EvolveLevel and
  * StepLevel).  Level 0 is `base` (the whole box, its boundary kinds,
  * precision, gamma, theta; limiter must be HY_LIM_THETA, and the solver of
  * hy_fmr_step HY_HLL or HY_HLLC).  Level l >= 1 refines by two along every

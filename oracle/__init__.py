@@ -350,7 +350,7 @@ def hllc_star(desc: Desc, q: int, wl, wr) -> dict:
     }
 
 
-# ---- fixed multilevel refinement (Sec. 2 prolongation / restriction, Sec. 3.5 Algs. Evolve..StepLevel) ----
+# ---- fixed multilevel refinement (Sec. 2 prolongation / restriction, Sec. 3.6 Algs. Evolve..StepLevel) ----
 
 class FmrDesc:
     """Nested levels: ``base`` is level 0; ``boxes[l - 1] = (lo, n)`` is the

@@ -37,7 +37,7 @@ static int valid_desc(const orc_desc *d)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Fluid variables (Sec. 3.4): D = n, S = m n v, G = e + m n |v|^2 / 2,     */
+/* Fluid variables (Sec. 3.5): D = n, S = m n v, G = e + m n |v|^2 / 2,     */
 /* p = (gamma - 1) e from the polytropic closure; m = 1.                    */
 /* ------------------------------------------------------------------------ */
 
@@ -111,7 +111,7 @@ void orc_physical(const orc_desc *d, int q, const double *w, double *U, double *
 }
 
 /* ------------------------------------------------------------------------ */
-/* Riemann solvers (Sec. 3.2 and 3.4)                                       */
+/* Riemann solvers (Sec. 3.2 and 3.5)                                       */
 /* ------------------------------------------------------------------------ */
 
 static double max3(double a, double b, double c) { return fmax(a, fmax(b, c)); }
@@ -643,7 +643,7 @@ int orc_cfl_dt(const orc_desc *d, const double *U, double cfl, double *dt)
 /* Fixed multilevel refinement: nested levels, each a box of cells of the   */
 /* next coarser level refined by two in every active dimension (Sec. 2, the */
 /* refinable mesh), stepped with subcycling and conservative coarse/fine    */
-/* flux replacement (Sec. 3.5, Algs. Evolve, EvolveLevel and StepLevel).   */
+/* flux replacement (Sec. 3.6, Algs. Evolve, EvolveLevel and StepLevel).   */
 /* Readings where the paper leaves the detail open:                         */
 /*  - prolongation only ever fills a level's exterior, so it need not      */
 /*    conserve: it is linear in the primitive variables with minmod-limited */

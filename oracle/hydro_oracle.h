@@ -113,7 +113,7 @@ int orc_shock_bits(const orc_desc *d, const double *U, unsigned char *bits);
  * fluxes come from the jump conditions F* = F_K + s_K (U*_K - U_K). */
 void orc_hllc_star(const orc_desc *d, int q, const double *wl, const double *wr, double *out);
 
-/* ---- fixed multilevel refinement (Sec. 2 and Sec. 3.5) ---- */
+/* ---- fixed multilevel refinement (Sec. 2 and Sec. 3.6) ---- */
 
 #define ORC_FMR_MAXLEV 8
 

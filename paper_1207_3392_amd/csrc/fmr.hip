@@ -1,5 +1,5 @@
 // fmr.hip -- kernels of fixed multilevel refinement (Sec. 2, prolongation and
-// restriction; Sec. 3.5, Algs. EvolveLevel and StepLevel): the exterior of a
+// restriction; Sec. 3.6, Algs. EvolveLevel and StepLevel): the exterior of a
 // refined level by prolongation, the boundary fluxes a level hands to its
 // parent and the fluxes the parent computed at the same faces, the
 // coarse/fine flux replacement, restriction, and the CFL rate and conserved
@@ -198,8 +198,9 @@ struct FluxSet {
 
 template <int ND, int SOLVER, typename T>
 __global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs, T gamma, T gm1, T inv_gm1, T theta2,
-                                                  double w)
+                                                  const double *dt)
 {
+    const double w = 0.5 * *dt;
     const int bx = blockIdx.y / ND, q = blockIdx.y - bx * ND;
     const int t = blockIdx.x * FB + threadIdx.x;
     const Box &b = fs.b[bx];
@@ -344,7 +345,7 @@ __global__ void __launch_bounds__(TB) k_leaf_totals(const T *u, Grid g, Box b, B
 
 template <int ND, typename T>
 hipError_t box_flux_nd(const T *u, const Grid &g, const FluxSet &fs, int nbox, int solver, T gamma, T gm1, T inv_gm1,
-                       T theta2, double w, hipStream_t s)
+                       T theta2, const double *w, hipStream_t s)
 {
     int most = 0;
     for (int k = 0; k < nbox; ++k)
@@ -368,7 +369,33 @@ hipError_t reflux_q(T *u, const Grid &g, const Box &b, const double *const c[3][
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(64) k_clock(FmrClock *c, int op, int l, int nlev, unsigned long long *rate_bits,
+                                               double cfl, double dt_fixed)
+{
+    if (threadIdx.x != 0) return;
+    switch (op) {
+    case CLOCK_RESET:
+        for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
+        *rate_bits = 0ull;
+        break;
+    case CLOCK_DEEPEST:
+        c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)*rate_bits);
+        *rate_bits = 0ull;
+        break;
+    case CLOCK_COARSE: c[l].dt = c[l + 1].t - c[l].t; break;
+    case CLOCK_PROVISIONAL: c[l].dtp = c[l + 1].t - c[l].t; break;
+    default: c[l].t += c[l].dt; break;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_clock(FmrClock *clock, int op, int l, int nlev, unsigned long long *rate_bits, double cfl,
+                        double dt_fixed, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, clock, op, l, nlev, rate_bits, cfl, dt_fixed);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box, int ndim,
@@ -397,8 +424,8 @@ hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, h
 
 template <typename T>
 hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes, double *const (*acc)[3][2],
-                           const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta, double w,
-                           hipStream_t s)
+                           const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta,
+                           const double *w, hipStream_t s)
 {
     if (nbox < 1 || nbox > 2) return hipErrorInvalidValue;
     FluxSet fs{};
@@ -471,7 +498,7 @@ hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const B
                                           hipStream_t);                                                              \
     template hipError_t launch_exterior_copy<T>(const T *, T *, const Grid &, int, hipStream_t);                     \
     template hipError_t launch_box_flux<T>(const T *, const Grid &, int, const Box *, double *const(*)[3][2],        \
-                                           const int *, int, int, T, T, T, T, double, hipStream_t);                  \
+                                           const int *, int, int, T, T, T, T, const double *, hipStream_t);          \
     template hipError_t launch_reflux<T>(T *, const Grid &, const Box &, int, const double *const[3][2],             \
                                          const double *const[3][2], const double[3], hipStream_t);                   \
     template hipError_t launch_restrict<T>(T *, const Grid &, const Box &, const T *, const Grid &, int, hipStream_t); \

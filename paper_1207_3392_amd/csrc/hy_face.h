@@ -1,6 +1,6 @@
 // Pointwise device math of the finite-volume update, shared by the stage
 // kernels and the multilevel kernels so that both compute the same face
-// fluxes: primitive recovery (Sec. 3.4), the generalised-minmod slope (eq.
+// fluxes: primitive recovery (Sec. 3.5), the generalised-minmod slope (eq.
 // MinMod) and the HLL / HLLC fluxes (eqs. FluxHLL, FluxHLLC and the middle
 // wave of eq. MiddleWaveSpeed).  Internal; every user gets its own copy.
 #pragma once

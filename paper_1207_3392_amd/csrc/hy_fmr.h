@@ -20,6 +20,25 @@ struct Box {
     int n[3];   // cells per dimension (1 along unused dimensions)
 };
 
+// A level's clock in device memory: its time, the step of its next full
+// step and of its next provisional half-step.  Kernels read their steps from
+// here, so a global step needs no host round trip.
+struct FmrClock {
+    double t, dt, dtp, pad;
+};
+
+enum { CLOCK_RESET = 0, CLOCK_DEEPEST = 1, CLOCK_COARSE = 2, CLOCK_PROVISIONAL = 3, CLOCK_ADVANCE = 4 };
+
+// One clock update (a single thread):
+//  RESET        every level's time to 0 and *rate_bits to 0;
+//  DEEPEST      dt of level l = dt_fixed if > 0, else cfl / (the rate in
+//               *rate_bits), which is then cleared;
+//  COARSE       dt of level l = t(l + 1) - t(l) (the child's two steps);
+//  PROVISIONAL  dtp of level l = t(l + 1) - t(l) (the child's first step);
+//  ADVANCE      t(l) += dt(l).
+hipError_t launch_clock(FmrClock *clock, int op, int l, int nlev, unsigned long long *rate_bits, double cfl,
+                        double dt_fixed, hipStream_t s);
+
 // Dense array extents and variable stride.
 struct Grid {
     int m[3];
@@ -43,12 +62,12 @@ hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, h
 // the array u along every active q, from its generalised-minmod face states
 // (a box needs two cells of u beyond each face), in one launch:
 // acc[k][q][side][v * faces + t] += w * F for box k (= w * F when
-// assign[k] != 0), t running over the box's cells transverse to q
-// ((q + 1) % 3 fastest).
+// assign[k] != 0), w = *dt / 2 (a stage's share of the step), t running
+// over the box's cells transverse to q ((q + 1) % 3 fastest).
 template <typename T>
 hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes, double *const (*acc)[3][2],
-                           const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta, double w,
-                           hipStream_t s);
+                           const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta,
+                           const double *dt, hipStream_t s);
 
 // Coarse/fine replacement: every parent cell just outside the child box takes
 // (fine - coarse) / dq of the flux through its face into the box (sign by

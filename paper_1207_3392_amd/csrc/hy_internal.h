@@ -27,9 +27,10 @@ enum { LIM_THETA = 0, LIM_LEARNED = 1 };
 enum { SOLVER_HLL = 0, SOLVER_HLLC = 1, SOLVER_HLLC_SWITCH = 2 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
 
-// How a stage obtains dt: from the host argument, or from the device control
-// block (dt = min(cfl / rate, t_end - t)).
-enum { DT_HOST = 0, DT_DEVICE = 1 };
+// How a stage obtains dt: from the host argument, from the device control
+// block (dt = min(cfl / rate, t_end - t)), or from a double in device memory
+// (dt_dev; the multilevel driver keeps each level's step there).
+enum { DT_HOST = 0, DT_DEVICE = 1, DT_PTR = 2 };
 
 template <typename T>
 struct StageArgs {
@@ -50,6 +51,7 @@ struct StageArgs {
     int parity;       // slot of the input state's time / rate
     int dt_mode;
     double dt_host, cfl, t_end;
+    const double *dt_dev;  // DT_PTR: the step
 };
 
 struct LaunchCfg {

@@ -53,6 +53,7 @@ struct hy_patch {
     bool mlp_set = false;
     hipStream_t stream = nullptr;
     int parity = 0;
+    const double *dt_dev = nullptr;  // the step of DT_PTR stages (set by the multilevel driver)
     hy::LaunchCfg cfg{64, 8, 32};
     // timing
     bool timing = false;
@@ -164,6 +165,7 @@ hy::StageArgs<T> stage_args(hy_patch *p, int stage, int dt_mode, double dt, doub
     a.dt_host = dt;
     a.cfl = cfl;
     a.t_end = t_end;
+    a.dt_dev = p->dt_dev;
     return a;
 }
 
@@ -1303,9 +1305,9 @@ struct hy_fmr {
         int64_t rows = 0;
         bool prov = false;       // the provisional half-step result sits in the patch's stage buffer
         bool own_fresh = false;  // own_acc holds nothing yet: the next write assigns
-        double T = 0.0;
     } lev[HY_FMR_MAXLEV];
     unsigned long long *rate = nullptr;
+    hy::FmrClock *clock = nullptr;
     int solver = HY_HLLC;
     double cfl = 0.4, dt_fixed = 0.0;
 };
@@ -1316,7 +1318,7 @@ struct FmrLayout {
     hy_patch_desc desc[HY_FMR_MAXLEV];
     size_t patch[HY_FMR_MAXLEV], own[HY_FMR_MAXLEV][3], coarse[HY_FMR_MAXLEV][3], partials[HY_FMR_MAXLEV];
     size_t patch_bytes[HY_FMR_MAXLEV], own_bytes[HY_FMR_MAXLEV][3], coarse_bytes[HY_FMR_MAXLEV][3];
-    size_t rate, total;
+    size_t rate, clock, total;
 };
 
 int64_t transverse(const int64_t n[3], int q) { return n[(q + 1) % 3] * n[(q + 2) % 3]; }
@@ -1379,6 +1381,8 @@ hy_status fmr_layout(const hy_fmr_desc *d, FmrLayout *L)
     }
     L->rate = o;
     o = align_up(o + sizeof(unsigned long long), 256);
+    L->clock = o;
+    o = align_up(o + sizeof(hy::FmrClock) * HY_FMR_MAXLEV, 256);
     L->total = o + 256;
     return HY_OK;
 }
@@ -1400,20 +1404,25 @@ hipError_t fmr_prolong(hy_fmr *f, int l)
     return hy::launch_prolong<T>(arrA<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0), f->stream);
 }
 
+// Stepper(l)%Step with the level's step from its device clock (dt, or dtp for
+// the provisional half-step).
 template <typename T>
-hipError_t fmr_level_step(hy_fmr *f, int l, double dt, bool provisional)
+hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
 {
     hy_fmr::Level &L = f->lev[l];
     hy_patch *p = L.p;
     hipError_t e;
     if (provisional) {
-        e = run_stage<T>(p, f->solver, 1, hy::DT_HOST, dt, 0.0, 0.0);
+        p->dt_dev = &f->clock[l].dtp;
+        e = run_stage<T>(p, f->solver, 1, hy::DT_PTR, 0.0, 0.0, 0.0);
         L.prov = true;
         return e;
     }
     const int nd = f->d.base.ndim;
     const bool child = l + 1 < f->nlev;
-    const double g = f->d.base.gamma, w = 0.5 * dt;
+    const double g = f->d.base.gamma;
+    const double *dt = &f->clock[l].dt;
+    p->dt_dev = dt;
     const T gamma = (T)g, gm1 = (T)(g - 1.0), igm1 = (T)(1.0 / (g - 1.0)), theta = (T)f->d.base.theta;
     // the fluxes through the child's faces (replaced later) and through this
     // level's own boundary (handed to the parent), from each stage's input
@@ -1441,12 +1450,12 @@ hipError_t fmr_level_step(hy_fmr *f, int l, double dt, bool provisional)
             // fluxes afresh after the parent has consumed them
             if (kc >= 0) assign[kc] = stage == 1;
             if (ko >= 0) assign[ko] = stage == 1 && L.own_fresh;
-            e = hy::launch_box_flux<T>(u, L.g, nbox, boxes, acc, assign, nd, f->solver, gamma, gm1, igm1, theta, w,
+            e = hy::launch_box_flux<T>(u, L.g, nbox, boxes, acc, assign, nd, f->solver, gamma, gm1, igm1, theta, dt,
                                        f->stream);
             if (e != hipSuccess) return e;
             L.own_fresh = false;
         }
-        e = run_stage<T>(p, f->solver, stage, hy::DT_HOST, dt, 0.0, 0.0);
+        e = run_stage<T>(p, f->solver, stage, hy::DT_PTR, 0.0, 0.0, 0.0);
         if (e != hipSuccess) return e;
         if (stage == 1 && l > 0) {
             e = hy::launch_exterior_copy<T>(arrA<T>(L), arrB<T>(L), L.g, nd, f->stream);
@@ -1477,7 +1486,9 @@ hy_status fmr_evolve_level(hy_fmr *f, int l)
     if (st != HY_OK || l == 0) return st;
     hipError_t e = hipSuccess;
     if (l - 1 > 0) e = fmr_prolong<T>(f, l - 1);
-    if (e == hipSuccess) e = fmr_level_step<T>(f, l - 1, f->lev[l].T - f->lev[l - 1].T, true);
+    if (e == hipSuccess)
+        e = hy::launch_clock(f->clock, hy::CLOCK_PROVISIONAL, l - 1, f->nlev, f->rate, 0.0, 0.0, f->stream);
+    if (e == hipSuccess) e = fmr_level_step<T>(f, l - 1, true);
     if (e != hipSuccess) return hip_fail(e, "provisional coarse step");
     st = fmr_step_level<T>(f, l);
     f->lev[l - 1].prov = false;
@@ -1499,34 +1510,26 @@ hy_status fmr_step_level(hy_fmr *f, int l)
         e = fmr_prolong<T>(f, l);
         if (e != hipSuccess) return hip_fail(e, "prolongation");
     }
-    double dt;
+    // Alg. StepLevel's time step: the CFL step at the deepest level, else
+    // the span of the child's two steps
     if (l == f->nlev - 1) {
-        if (f->dt_fixed > 0.0) {
-            dt = f->dt_fixed;
-        } else {
-            e = hipMemsetAsync(f->rate, 0, sizeof(unsigned long long), f->stream);
+        e = hipSuccess;
+        if (!(f->dt_fixed > 0.0)) {
             const double g = f->d.base.gamma;
-            if (e == hipSuccess)
-                e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
-            unsigned long long rb = 0;
-            if (e == hipSuccess) e = hipMemcpyAsync(&rb, f->rate, sizeof(rb), hipMemcpyDeviceToHost, f->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
-            if (e != hipSuccess) return hip_fail(e, "deepest-level CFL rate");
-            const double rate = __builtin_bit_cast(double, rb);
-            if (!(rate > 0.0) || !std::isfinite(rate))
-                return fail(HY_ESTATE, "the deepest level holds rho <= 0, p <= 0 or a non-finite value");
-            dt = f->cfl / rate;
+            e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
         }
+        if (e == hipSuccess)
+            e = hy::launch_clock(f->clock, hy::CLOCK_DEEPEST, l, f->nlev, f->rate, f->cfl, f->dt_fixed, f->stream);
     } else {
-        dt = f->lev[l + 1].T - L.T;
+        e = hy::launch_clock(f->clock, hy::CLOCK_COARSE, l, f->nlev, f->rate, 0.0, 0.0, f->stream);
     }
-    e = fmr_level_step<T>(f, l, dt, false);
+    if (e == hipSuccess) e = fmr_level_step<T>(f, l, false);
     if (e == hipSuccess && l + 1 < f->nlev) {
         hy_fmr::Level &C = f->lev[l + 1];
         e = hy::launch_restrict<T>(arrA<T>(L), L.g, L.child, arrA<T>(C), C.g, nd, f->stream);
     }
+    if (e == hipSuccess) e = hy::launch_clock(f->clock, hy::CLOCK_ADVANCE, l, f->nlev, f->rate, 0.0, 0.0, f->stream);
     if (e != hipSuccess) return hip_fail(e, "level step");
-    L.T += dt;
     return HY_OK;
 }
 
@@ -1603,6 +1606,7 @@ hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, v
         V.rows = V.n[1] * V.n[2];
     }
     f->rate = (unsigned long long *)(base + L.rate);
+    f->clock = (hy::FmrClock *)(base + L.clock);
     *out = f;
     return HY_OK;
 }
@@ -1666,19 +1670,23 @@ hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double
     f->solver = solver;
     f->cfl = cfl;
     f->dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
-    for (int l = 0; l < f->nlev; ++l) {
-        f->lev[l].T = 0.0;
-        f->lev[l].prov = false;
-    }
+    for (int l = 0; l < f->nlev; ++l) f->lev[l].prov = false;
+    hipError_t e = hy::launch_clock(f->clock, hy::CLOCK_RESET, 0, f->nlev, f->rate, 0.0, 0.0, f->stream);
+    if (e != hipSuccess) return hip_fail(e, "clock reset");
     hy_status st = f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
     if (st != HY_OK) return st;
+    hy::FmrClock c0;
+    e = hipMemcpyAsync(&c0, f->clock, sizeof(c0), hipMemcpyDeviceToHost, f->stream);
+    if (e != hipSuccess) return hip_fail(e, "clock read");
     for (int l = 0; l < f->nlev; ++l) {
         hy::DevCtl c;
-        st = read_ctl(f->lev[l].p, &c);
+        st = read_ctl(f->lev[l].p, &c);  // synchronises the stream
         if (st != HY_OK) return st;
         if (c.err) return fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value");
     }
-    if (dt_out) *dt_out = f->lev[0].T;
+    if (!(c0.t > 0.0) || !std::isfinite(c0.t))
+        return fail(HY_ESTATE, "the deepest level's CFL step is not positive and finite");
+    if (dt_out) *dt_out = c0.t;
     return HY_OK;
 }
 

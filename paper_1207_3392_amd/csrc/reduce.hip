@@ -1,5 +1,5 @@
 // reduce.hip -- whole-patch passes: primitive <-> conserved conversion
-// (Sec. 3.4), the CFL rate reduction (eq. courantTimeStep) and the FP64
+// (Sec. 3.5), the CFL rate reduction (eq. courantTimeStep) and the FP64
 // conserved totals.
 #include "hy_internal.h"
 #include "hy_diag.h"

@@ -2,7 +2,7 @@
 // a single gfx950 kernel.
 //
 // Per cell the kernel performs, in the paper's order (Sec. 3, Alg. 1):
-// primitive recovery (Sec. 3.4), ghost values by index mapping (the boundary
+// primitive recovery (Sec. 3.5), ghost values by index mapping (the boundary
 // step), generalised-minmod slopes (eq. MinMod) or learned slopes, face states
 // (eqs. conservedLeft..conservedRight), the HLL or HLLC flux (eqs. FluxHLL,
 // FluxHLLC with eq. MiddleWaveSpeed and the middle states), the flux
@@ -35,6 +35,7 @@ template <int ND, typename T>
 __device__ __forceinline__ double stage_dt(const StageArgs<T> &a)
 {
     if (a.dt_mode == DT_HOST) return a.dt_host;
+    if (a.dt_mode == DT_PTR) return *a.dt_dev;
     unsigned long long rb = 0ull;
 #pragma unroll
     for (int k = 0; k < RATE_SLOTS; ++k) rb = rb > a.ctl->rate[a.parity][k] ? rb : a.ctl->rate[a.parity][k];

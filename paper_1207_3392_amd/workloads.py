@@ -469,7 +469,7 @@ def _level_fields(lv: Levels, fn) -> List[np.ndarray]:
 def sedov_levels(ndim: int = 2, n0: int = 64, nlev: int = 3, gamma: float = 1.4, rho0: float = 1.0,
                  p0: float = 1e-5, e_d: float = 1.0, r_cells: float = 3.5, sub: int = 20,
                  bc: int = BC_OUTFLOW, theta: float = 1.4, cfl: float = 0.4, boxes=None) -> Levels:
-    """Sedov-Taylor blast (Sec. 4.2): fluid at rest, density rho0, pressure p0
+    """Sedov-Taylor blast (Sec. 4.2.3): fluid at rest, density rho0, pressure p0
     on [-0.5, 0.5]^d, with the energy e_d released as the pressure
     3 (gamma - 1) e_d / ((alpha + 1) pi R_d^alpha) inside r <= R_d (alpha = d;
     in 1D the slab |x| <= R_d holds e_d as (gamma - 1) e_d / (2 R_d)).  R_d is

@@ -1,11 +1,11 @@
-"""Fixed multilevel refinement on the GPU (Sec. 3.5, Algs. Evolve,
+"""Fixed multilevel refinement on the GPU (Sec. 3.6, Algs. Evolve,
 EvolveLevel, StepLevel) against the oracle's, through the C ABI.
 
 Both sides start from the GPU's initial level states read back as FP64 and
 take the same deepest-level time step, so a comparison isolates the kernels'
 arithmetic: FP64 within 1e-11 of each variable's scale, FP32 within the
 precision the state is held in.  Leaf-cell totals stay constant to the
-state's precision, as Sec. 4.2 states for the multilevel Sedov runs."""
+state's precision, as Sec. 4.2.3 states for the multilevel Sedov runs."""
 import math
 
 import numpy as np

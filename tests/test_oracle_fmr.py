@@ -1,5 +1,5 @@
 """Pins of the oracle's fixed multilevel refinement (Sec. 2 prolongation and
-restriction; Sec. 3.5, Algs. Evolve, EvolveLevel and StepLevel; Sec. 4.2,
+restriction; Sec. 3.6, Algs. Evolve, EvolveLevel and StepLevel; Sec. 4.2.3,
 conservation of mass, momentum and energy over the leaf cells to numerical
 precision).  Each check comes from outside the oracle: brute-force NumPy
 averages, exact linear data, the single-level step, symmetry of the initial
@@ -183,7 +183,7 @@ def test_subcycling_time_steps():
 @pytest.mark.parametrize("nd,n0,nlev,solver", [(1, 32, 4, O.HLL), (2, 16, 3, O.HLL), (2, 16, 3, O.HLLC),
                                                (3, 8, 2, O.HLLC)])
 def test_leaf_totals_conserved(nd, n0, nlev, solver):
-    """Sec. 4.2: mass, momentum and energy over the leaf cells stay constant
+    """Sec. 4.2.3: mass, momentum and energy over the leaf cells stay constant
     to numerical precision once the blast has crossed level boundaries
     (periodic outer boundary, so nothing leaves the box)."""
     lv = wl.sedov_levels(nd, n0, nlev, bc=wl.BC_PERIODIC)

@@ -106,7 +106,7 @@ def test_supersonic_flux_is_upwind(solver):
 
 
 def test_hllc_middle_pressure_is_continuous():
-    """p*L = p*R follows from the middle-wave jump condition (Sec. 3.4)."""
+    """p*L = p*R follows from the middle-wave jump condition (Sec. 3.5)."""
     d = desc3d(oracle.HLLC)
     WL = wl.random_states(2000, seed=7, ndim=3)
     WR = wl.random_states(2000, seed=8, ndim=3)
