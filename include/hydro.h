@@ -321,10 +321,14 @@ hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, v
  * synchronising. */
 hy_status hy_fmr_set_state(hy_fmr *f, int level, int kind, const double *host_soa);
 hy_status hy_fmr_get_state(hy_fmr *f, int level, int kind, double *host_soa_out);
-/* One global step; *dt_out (may be NULL) receives the coarse step.
- * Synchronising (one device read per deepest-level step for its time step,
- * unless dt_fixed > 0, and one at the end for the error latch). */
+/* One global step; *dt_out (may be NULL) receives the coarse step.  The
+ * levels' times and steps stay in device memory, so the step's launches need
+ * no host round trip: they are captured once into a HIP graph per (solver,
+ * cfl, dt_fixed) and replayed (hy_fmr_set_graph(f, 0) launches them one by
+ * one instead; the results are the same).  Synchronising once, at the end,
+ * for the error latches and the coarse step. */
 hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double *dt_out);
+hy_status hy_fmr_set_graph(hy_fmr *f, int on);
 /* FP64 sums of D, S_x, S_y, S_z, G times the cell volume over the leaf
  * cells of all levels (cells no finer level covers); synchronising. */
 hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5]);

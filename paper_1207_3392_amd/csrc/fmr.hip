@@ -156,7 +156,7 @@ template <int ND, int Q, int SOLVER, typename T>
 __device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &b, int t, T gamma, T gm1, T inv_gm1,
                                           T theta2, double w, bool assign, double *acc_lo, double *acc_hi)
 {
-    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
     const int faces = b.n[R1] * b.n[R2];
     if (t >= faces) return;
     const int t1 = t % b.n[R1], t2 = t / b.n[R1];
@@ -222,7 +222,7 @@ template <int ND, int Q, typename T>
 __global__ void __launch_bounds__(FB) k_reflux(T *u, Grid g, Box b, const double *c_lo, const double *c_hi,
                                                 const double *f_lo, const double *f_hi, double idq)
 {
-    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
     constexpr int A1 = R1 < ND ? 2 : 1, A2 = R2 < ND ? 2 : 1;
     const int faces = b.n[R1] * b.n[R2];
     const int ffaces = faces * A1 * A2, fn1 = b.n[R1] * A1;
@@ -300,7 +300,8 @@ __global__ void __launch_bounds__(TB) k_box_rate(const T *u, Grid g, Box b, T ga
         if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(rate_bits, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0)
+        atomicMax(&rate_bits[blockIdx.x % FMR_RATE_SLOTS], (unsigned long long)__double_as_longlong(red[0]));
 }
 
 template <int ND, typename T>
@@ -362,7 +363,7 @@ template <int ND, int Q, typename T>
 hipError_t reflux_q(T *u, const Grid &g, const Box &b, const double *const c[3][2], const double *const f[3][2],
                     double idq, hipStream_t s)
 {
-    constexpr int R1 = (Q + 1) % 3, R2 = (Q + 2) % 3;
+    constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
     const int faces = b.n[R1] * b.n[R2];
     hipLaunchKernelGGL((k_reflux<ND, Q, T>), dim3((faces + FB - 1) / FB), dim3(FB), 0, s, u, g, b, c[Q][0], c[Q][1],
                        f[Q][0], f[Q][1], idq);
@@ -376,12 +377,17 @@ __global__ void __launch_bounds__(64) k_clock(FmrClock *c, int op, int l, int nl
     switch (op) {
     case CLOCK_RESET:
         for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
-        *rate_bits = 0ull;
+        for (int k = 0; k < FMR_RATE_SLOTS; ++k) rate_bits[k] = 0ull;
         break;
-    case CLOCK_DEEPEST:
-        c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)*rate_bits);
-        *rate_bits = 0ull;
+    case CLOCK_DEEPEST: {
+        unsigned long long rb = 0ull;
+        for (int k = 0; k < FMR_RATE_SLOTS; ++k) {
+            rb = rb > rate_bits[k] ? rb : rate_bits[k];
+            rate_bits[k] = 0ull;
+        }
+        c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)rb);
         break;
+    }
     case CLOCK_COARSE: c[l].dt = c[l + 1].t - c[l].t; break;
     case CLOCK_PROVISIONAL: c[l].dtp = c[l + 1].t - c[l].t; break;
     default: c[l].t += c[l].dt; break;

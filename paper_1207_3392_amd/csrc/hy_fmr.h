@@ -29,10 +29,15 @@ struct FmrClock {
 
 enum { CLOCK_RESET = 0, CLOCK_DEEPEST = 1, CLOCK_COARSE = 2, CLOCK_PROVISIONAL = 3, CLOCK_ADVANCE = 4 };
 
+// The CFL rate is reduced into FMR_RATE_SLOTS words (workgroup b into word
+// b mod FMR_RATE_SLOTS), so the atomics of a reduction never queue on one
+// address; readers take the max over the words.
+constexpr int FMR_RATE_SLOTS = 32;
+
 // One clock update (a single thread):
-//  RESET        every level's time to 0 and *rate_bits to 0;
-//  DEEPEST      dt of level l = dt_fixed if > 0, else cfl / (the rate in
-//               *rate_bits), which is then cleared;
+//  RESET        every level's time to 0 and the rate words to 0;
+//  DEEPEST      dt of level l = dt_fixed if > 0, else cfl / (the max of the
+//               rate words), which are then cleared;
 //  COARSE       dt of level l = t(l + 1) - t(l) (the child's two steps);
 //  PROVISIONAL  dtp of level l = t(l + 1) - t(l) (the child's first step);
 //  ADVANCE      t(l) += dt(l).
@@ -63,7 +68,9 @@ hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, h
 // (a box needs two cells of u beyond each face), in one launch:
 // acc[k][q][side][v * faces + t] += w * F for box k (= w * F when
 // assign[k] != 0), w = *dt / 2 (a stage's share of the step), t running
-// over the box's cells transverse to q ((q + 1) % 3 fastest).
+// over the box's cells transverse to q, the lower transverse dimension
+// fastest (x for faces normal to y or z, so neighbouring threads read
+// neighbouring cells).
 template <typename T>
 hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes, double *const (*acc)[3][2],
                            const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta,
@@ -84,8 +91,8 @@ template <typename T>
 hipError_t launch_restrict(T *parent, const Grid &pg, const Box &child_box, const T *child, const Grid &cg, int ndim,
                            hipStream_t s);
 
-// max over the cells of box of (|v_q| + c_s) / dq into *rate_bits (the bits of
-// a positive double; unsigned atomic max).
+// max over the cells of box of (|v_q| + c_s) / dq into the FMR_RATE_SLOTS
+// words rate_bits (the bits of a positive double; unsigned atomic max).
 template <typename T>
 hipError_t launch_box_rate(const T *u, const Grid &g, const Box &box, int ndim, T gamma, T gm1, const double idq[3],
                            unsigned long long *rate_bits, hipStream_t s);

@@ -1310,6 +1310,13 @@ struct hy_fmr {
     hy::FmrClock *clock = nullptr;
     int solver = HY_HLLC;
     double cfl = 0.4, dt_fixed = 0.0;
+    // the launches of one global step, captured once per (solver, cfl,
+    // dt_fixed) on a private stream and replayed on the caller's
+    bool use_graph = true;
+    hipStream_t capture = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int g_solver = -1;
+    double g_cfl = 0.0, g_dt_fixed = 0.0;
 };
 
 namespace {
@@ -1380,7 +1387,7 @@ hy_status fmr_layout(const hy_fmr_desc *d, FmrLayout *L)
         o = align_up(o + sizeof(double) * 5 * (size_t)(n[1] * n[2]), 256);
     }
     L->rate = o;
-    o = align_up(o + sizeof(unsigned long long), 256);
+    o = align_up(o + sizeof(unsigned long long) * hy::FMR_RATE_SLOTS, 256);
     L->clock = o;
     o = align_up(o + sizeof(hy::FmrClock) * HY_FMR_MAXLEV, 256);
     L->total = o + 256;
@@ -1533,6 +1540,57 @@ hy_status fmr_step_level(hy_fmr *f, int l)
     return HY_OK;
 }
 
+// Enqueues one global step on stream s (every level's launches go there).
+hy_status fmr_enqueue(hy_fmr *f, hipStream_t s)
+{
+    f->stream = s;
+    for (int l = 0; l < f->nlev; ++l) {
+        f->lev[l].p->stream = s;
+        f->lev[l].prov = false;
+    }
+    hipError_t e = hy::launch_clock(f->clock, hy::CLOCK_RESET, 0, f->nlev, f->rate, 0.0, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "clock reset");
+    return f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
+}
+
+void fmr_drop_graph(hy_fmr *f)
+{
+    if (f->exec) (void)hipGraphExecDestroy(f->exec);
+    f->exec = nullptr;
+}
+
+// Captures the global step's launches into f->exec (none of them is a
+// memset or a host wait).
+hy_status fmr_capture(hy_fmr *f, hipStream_t caller)
+{
+    fmr_drop_graph(f);
+    hipError_t e = hipSuccess;
+    if (!f->capture) e = hipStreamCreateWithFlags(&f->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(f->capture, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    hy_status st = fmr_enqueue(f, f->capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(f->capture, &g);
+    // every later launch outside the graph goes to the caller's stream again
+    f->stream = caller;
+    for (int l = 0; l < f->nlev; ++l) f->lev[l].p->stream = caller;
+    if (st != HY_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&f->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        f->exec = nullptr;
+        return hip_fail(e, "graph capture");
+    }
+    f->g_solver = f->solver;
+    f->g_cfl = f->cfl;
+    f->g_dt_fixed = f->dt_fixed;
+    return HY_OK;
+}
+
 hy_status fmr_check_level(hy_fmr *f, int level)
 {
     if (!f) return fail(HY_EINVAL, "null handle");
@@ -1661,6 +1719,14 @@ hy_status hy_fmr_get_state(hy_fmr *f, int level, int kind, double *out)
     return st;
 }
 
+hy_status hy_fmr_set_graph(hy_fmr *f, int on)
+{
+    if (!f) return fail(HY_EINVAL, "null handle");
+    f->use_graph = on != 0;
+    if (!f->use_graph) fmr_drop_graph(f);
+    return HY_OK;
+}
+
 hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double *dt_out)
 {
     if (!f) return fail(HY_EINVAL, "null handle");
@@ -1670,11 +1736,20 @@ hy_status hy_fmr_step(hy_fmr *f, double cfl, double dt_fixed, int solver, double
     f->solver = solver;
     f->cfl = cfl;
     f->dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
-    for (int l = 0; l < f->nlev; ++l) f->lev[l].prov = false;
-    hipError_t e = hy::launch_clock(f->clock, hy::CLOCK_RESET, 0, f->nlev, f->rate, 0.0, 0.0, f->stream);
-    if (e != hipSuccess) return hip_fail(e, "clock reset");
-    hy_status st = f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
-    if (st != HY_OK) return st;
+    hipStream_t caller = f->stream;
+    hy_status st;
+    hipError_t e;
+    if (f->use_graph) {
+        if (!f->exec || f->g_solver != f->solver || f->g_cfl != f->cfl || f->g_dt_fixed != f->dt_fixed) {
+            st = fmr_capture(f, caller);
+            if (st != HY_OK) return st;
+        }
+        e = hipGraphLaunch(f->exec, caller);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+    } else {
+        st = fmr_enqueue(f, caller);
+        if (st != HY_OK) return st;
+    }
     hy::FmrClock c0;
     e = hipMemcpyAsync(&c0, f->clock, sizeof(c0), hipMemcpyDeviceToHost, f->stream);
     if (e != hipSuccess) return hip_fail(e, "clock read");
@@ -1718,6 +1793,7 @@ hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5])
 hy_status hy_fmr_autotune(hy_fmr *f, int solver, int reps, hy_launch_cfg *best)
 {
     if (!f) return fail(HY_EINVAL, "null handle");
+    fmr_drop_graph(f);  // captured with the old launch shapes
     for (int l = 0; l < f->nlev; ++l) {
         hy_status st = hy_autotune(f->lev[l].p, solver, reps, best ? &best[l] : nullptr, nullptr);
         if (st != HY_OK) return st;
@@ -1729,6 +1805,8 @@ hy_status hy_fmr_destroy(hy_fmr *f)
 {
     if (!f) return HY_OK;
     hipStreamSynchronize(f->stream);
+    fmr_drop_graph(f);
+    if (f->capture) (void)hipStreamDestroy(f->capture);
     for (int l = 0; l < f->nlev; ++l)
         if (f->lev[l].p) hy_destroy(f->lev[l].p);
     delete f;

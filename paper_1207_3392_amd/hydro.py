@@ -149,6 +149,7 @@ EXTRA_SIGNATURES = {
     "hy_fmr_step": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp],
     "hy_fmr_conserved_totals": [_P, _dp],
     "hy_fmr_autotune": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(LaunchCfg)],
+    "hy_fmr_set_graph": [_P, ctypes.c_int],
     "hy_fmr_destroy": [_P],
 }
 
@@ -569,6 +570,10 @@ class Fmr:
         out = np.zeros(5)
         check(lib().hy_fmr_conserved_totals(self.handle, _dptr(out)), "fmr_conserved_totals")
         return out
+
+    def set_graph(self, on: bool):
+        """Replay the global step from a captured HIP graph (default) or launch it kernel by kernel."""
+        check(lib().hy_fmr_set_graph(self.handle, int(bool(on))), "fmr_set_graph")
 
     def autotune(self, solver: int = HLLC, reps: int = 3):
         """Tune every level's stage launch shape; returns [(bx, by, zchunk)] per level."""
