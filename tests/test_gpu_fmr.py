@@ -209,3 +209,43 @@ def test_host_checks():
     for level in (-1, 2):
         assert hydro.lib().hy_fmr_get_state(F.handle, level, hydro.CONSERVED, hydro._dptr(out)) == hydro.HY_EINVAL
     F.close()
+
+
+def test_multilevel_blast_tracks_the_single_level_run():
+    """Sec. 4.2.3 compares multilevel Sedov runs with a single level at the
+    finest resolution: the shock positions are similar.  Here the 2D blast on
+    three levels (64^2 each, finest 1/256) runs until its shock has crossed
+    the finest level's boundary; its shock radius along +x (the density
+    maximum in the leaf cells of level 1) lies within two level-1 cells of a
+    single-level 256^2 run's at the same time, both near the dimensional
+    estimate R = (E t^2 / rho)^(1/4)."""
+    lv = wl.sedov_levels(2, 64, 3, bc=wl.BC_OUTFLOW)
+    F = hydro.Fmr(lv, precision=32)
+    T0 = F.totals()
+    t = 0.0
+    while t < 0.03:
+        t += F.step(cfl=0.4, solver=hydro.HLL)
+    T = F.totals()
+    W1 = F.get_state(1, hydro.PRIMITIVE).reshape(4, 64, 64)  # level 1: [-0.25, 0.25]^2, dx 1/128
+    x1 = -0.25 + (np.arange(64) + 0.5) / 128
+    row = W1[0, 31]  # y just below 0
+    leaf = x1 > 0.125  # outside level 2
+    r_fmr = x1[leaf][np.argmax(row[leaf])]
+
+    single = wl.sedov_levels(2, 256, 1, bc=wl.BC_OUTFLOW)  # one level at the finest spacing
+    P = hydro.Patch(single.base, precision=32)
+    while P.time() < t * (1 - 1e-12):
+        P.advance(50, 0.4, t_end=t, solver=hydro.HLL)
+    assert P.time() == pytest.approx(t, rel=1e-9)
+    Ws = P.get_state(hydro.PRIMITIVE).reshape(4, 256, 256)
+    xs = -0.5 + (np.arange(256) + 0.5) / 256
+    rs = Ws[0, 127]
+    r_single = xs[xs > 0][np.argmax(rs[xs > 0])]
+    print(f"t={t:.4f} r_fmr={r_fmr:.4f} r_single={r_single:.4f} estimate={t ** 0.5:.4f}")
+    assert abs(r_fmr - r_single) <= 2.0 / 128
+    for r in (r_fmr, r_single):
+        assert abs(r - t ** 0.5) < 0.15 * t ** 0.5
+    # nothing has reached the outer boundary yet: totals as at the start
+    assert abs(T[0] - T0[0]) < 1e-6 * T0[0] and abs(T[4] - T0[4]) < 1e-5 * T0[4]
+    F.close()
+    P.close()
