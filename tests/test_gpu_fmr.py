@@ -66,6 +66,10 @@ CASES = [
     ("smooth2d_ragged", lambda: wl.smooth_levels(2, 0, boxes=[((5, 3, 0), (13, 9, 1)), ((4, 2, 0), (9, 7, 1))],
                                                  n=(40, 24))),
     ("smooth3d_ragged", lambda: wl.smooth_levels(3, 0, boxes=[((3, 2, 4), (7, 9, 5))], n=(13, 14, 15))),
+    # the smallest boxes the margin rule allows: one or two parent cells
+    ("tiny1d", lambda: wl.smooth_levels(1, 0, boxes=[((2, 0, 0), (1, 1, 1))], n=(5,))),
+    ("tiny2d", lambda: wl.smooth_levels(2, 0, boxes=[((2, 2, 0), (2, 3, 1))], n=(6, 7))),
+    ("tiny3d", lambda: wl.smooth_levels(3, 0, boxes=[((2, 2, 2), (1, 2, 1))], n=(5, 6, 5))),
 ]
 
 
