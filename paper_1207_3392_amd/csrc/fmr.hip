@@ -219,14 +219,13 @@ __global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs,
 
 // One thread per coarse face of the child box normal to Q (both sides).
 template <int ND, int Q, typename T>
-__global__ void __launch_bounds__(FB) k_reflux(T *u, Grid g, Box b, const double *c_lo, const double *c_hi,
-                                                const double *f_lo, const double *f_hi, double idq)
+__device__ __forceinline__ void reflux_faces(T *u, const Grid &g, const Box &b, int t, const double *c_lo,
+                                             const double *c_hi, const double *f_lo, const double *f_hi, double idq)
 {
     constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
     constexpr int A1 = R1 < ND ? 2 : 1, A2 = R2 < ND ? 2 : 1;
     const int faces = b.n[R1] * b.n[R2];
     const int ffaces = faces * A1 * A2, fn1 = b.n[R1] * A1;
-    const int t = blockIdx.x * FB + threadIdx.x;
     if (t >= faces) return;
     const int t1 = t % b.n[R1], t2 = t / b.n[R1];
 #pragma unroll
@@ -253,6 +252,25 @@ __global__ void __launch_bounds__(FB) k_reflux(T *u, Grid g, Box b, const double
             x = (T)((double)x + corr * idq);
         }
     }
+}
+
+struct RefluxSet {
+    const double *c[3][2];
+    const double *f[3][2];
+    double idq[3];
+};
+
+// Every dimension in one launch (blockIdx.y = Q): the cells corrected across
+// different faces of the box are disjoint.
+template <int ND, typename T>
+__global__ void __launch_bounds__(FB) k_reflux(T *u, Grid g, Box b, RefluxSet r)
+{
+    const int q = blockIdx.y, t = blockIdx.x * FB + threadIdx.x;
+    if (q == 0) reflux_faces<ND, 0>(u, g, b, t, r.c[0][0], r.c[0][1], r.f[0][0], r.f[0][1], r.idq[0]);
+    if constexpr (ND >= 2)
+        if (q == 1) reflux_faces<ND, 1>(u, g, b, t, r.c[1][0], r.c[1][1], r.f[1][0], r.f[1][1], r.idq[1]);
+    if constexpr (ND >= 3)
+        if (q == 2) reflux_faces<ND, 2>(u, g, b, t, r.c[2][0], r.c[2][1], r.f[2][0], r.f[2][1], r.idq[2]);
 }
 
 template <int ND, typename T>
@@ -359,21 +377,9 @@ hipError_t box_flux_nd(const T *u, const Grid &g, const FluxSet &fs, int nbox, i
     return hipGetLastError();
 }
 
-template <int ND, int Q, typename T>
-hipError_t reflux_q(T *u, const Grid &g, const Box &b, const double *const c[3][2], const double *const f[3][2],
-                    double idq, hipStream_t s)
+__device__ __forceinline__ void clock_op(FmrClock *c, int op, int l, int nlev, unsigned long long *rate_bits,
+                                         double cfl, double dt_fixed)
 {
-    constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
-    const int faces = b.n[R1] * b.n[R2];
-    hipLaunchKernelGGL((k_reflux<ND, Q, T>), dim3((faces + FB - 1) / FB), dim3(FB), 0, s, u, g, b, c[Q][0], c[Q][1],
-                       f[Q][0], f[Q][1], idq);
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(64) k_clock(FmrClock *c, int op, int l, int nlev, unsigned long long *rate_bits,
-                                               double cfl, double dt_fixed)
-{
-    if (threadIdx.x != 0) return;
     switch (op) {
     case CLOCK_RESET:
         for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
@@ -390,16 +396,26 @@ __global__ void __launch_bounds__(64) k_clock(FmrClock *c, int op, int l, int nl
     }
     case CLOCK_COARSE: c[l].dt = c[l + 1].t - c[l].t; break;
     case CLOCK_PROVISIONAL: c[l].dtp = c[l + 1].t - c[l].t; break;
-    default: c[l].t += c[l].dt; break;
+    case CLOCK_ADVANCE: c[l].t += c[l].dt; break;
+    default: break;
     }
+}
+
+// up to two clock updates in order (op < 0: none)
+__global__ void __launch_bounds__(64) k_clock(FmrClock *c, int op0, int l0, int op1, int l1, int nlev,
+                                               unsigned long long *rate_bits, double cfl, double dt_fixed)
+{
+    if (threadIdx.x != 0) return;
+    clock_op(c, op0, l0, nlev, rate_bits, cfl, dt_fixed);
+    clock_op(c, op1, l1, nlev, rate_bits, cfl, dt_fixed);
 }
 
 }  // namespace
 
-hipError_t launch_clock(FmrClock *clock, int op, int l, int nlev, unsigned long long *rate_bits, double cfl,
-                        double dt_fixed, hipStream_t s)
+hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int nlev, unsigned long long *rate_bits,
+                        double cfl, double dt_fixed, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, clock, op, l, nlev, rate_bits, cfl, dt_fixed);
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, clock, op0, l0, op1, l1, nlev, rate_bits, cfl, dt_fixed);
     return hipGetLastError();
 }
 
@@ -451,15 +467,24 @@ template <typename T>
 hipError_t launch_reflux(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
                          const double *const fine[3][2], const double idq[3], hipStream_t s)
 {
-    hipError_t e;
-    if (ndim == 1) return reflux_q<1, 0>(u, g, child_box, coarse, fine, idq[0], s);
-    if (ndim == 2) {
-        e = reflux_q<2, 0>(u, g, child_box, coarse, fine, idq[0], s);
-        return e == hipSuccess ? reflux_q<2, 1>(u, g, child_box, coarse, fine, idq[1], s) : e;
+    RefluxSet r{};
+    int most = 0;
+    for (int q = 0; q < 3; ++q) {
+        for (int side = 0; side < 2; ++side) {
+            r.c[q][side] = coarse[q][side];
+            r.f[q][side] = fine[q][side];
+        }
+        r.idq[q] = idq[q];
+        if (q < ndim) {
+            const int r1 = q == 0 ? 1 : 0, r2 = q == 2 ? 1 : 2;
+            most = std::max(most, child_box.n[r1] * child_box.n[r2]);
+        }
     }
-    e = reflux_q<3, 0>(u, g, child_box, coarse, fine, idq[0], s);
-    if (e == hipSuccess) e = reflux_q<3, 1>(u, g, child_box, coarse, fine, idq[1], s);
-    return e == hipSuccess ? reflux_q<3, 2>(u, g, child_box, coarse, fine, idq[2], s) : e;
+    const dim3 grid((most + FB - 1) / FB, ndim);
+    if (ndim == 1) hipLaunchKernelGGL((k_reflux<1, T>), grid, dim3(FB), 0, s, u, g, child_box, r);
+    else if (ndim == 2) hipLaunchKernelGGL((k_reflux<2, T>), grid, dim3(FB), 0, s, u, g, child_box, r);
+    else hipLaunchKernelGGL((k_reflux<3, T>), grid, dim3(FB), 0, s, u, g, child_box, r);
+    return hipGetLastError();
 }
 
 template <typename T>

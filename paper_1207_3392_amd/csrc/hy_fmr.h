@@ -34,15 +34,16 @@ enum { CLOCK_RESET = 0, CLOCK_DEEPEST = 1, CLOCK_COARSE = 2, CLOCK_PROVISIONAL =
 // address; readers take the max over the words.
 constexpr int FMR_RATE_SLOTS = 32;
 
-// One clock update (a single thread):
+// One launch applies the clock updates op0 (on level l0), then op1 (on l1),
+// on a single thread; an op < 0 is skipped.  The updates:
 //  RESET        every level's time to 0 and the rate words to 0;
 //  DEEPEST      dt of level l = dt_fixed if > 0, else cfl / (the max of the
 //               rate words), which are then cleared;
 //  COARSE       dt of level l = t(l + 1) - t(l) (the child's two steps);
 //  PROVISIONAL  dtp of level l = t(l + 1) - t(l) (the child's first step);
 //  ADVANCE      t(l) += dt(l).
-hipError_t launch_clock(FmrClock *clock, int op, int l, int nlev, unsigned long long *rate_bits, double cfl,
-                        double dt_fixed, hipStream_t s);
+hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int nlev, unsigned long long *rate_bits,
+                        double cfl, double dt_fixed, hipStream_t s);
 
 // Dense array extents and variable stride.
 struct Grid {

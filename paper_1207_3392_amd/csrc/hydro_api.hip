@@ -1308,6 +1308,7 @@ struct hy_fmr {
     } lev[HY_FMR_MAXLEV];
     unsigned long long *rate = nullptr;
     hy::FmrClock *clock = nullptr;
+    int pending_advance = -1;  // level whose clock advance rides on the next clock launch
     int solver = HY_HLLC;
     double cfl = 0.4, dt_fixed = 0.0;
     // the launches of one global step, captured once per (solver, cfl,
@@ -1392,6 +1393,26 @@ hy_status fmr_layout(const hy_fmr_desc *d, FmrLayout *L)
     o = align_up(o + sizeof(hy::FmrClock) * HY_FMR_MAXLEV, 256);
     L->total = o + 256;
     return HY_OK;
+}
+
+// A clock update on the stream; a pending advance of a level's time goes
+// first in the same launch.
+hipError_t fmr_clock(hy_fmr *f, int op, int l)
+{
+    const int pre = f->pending_advance;
+    f->pending_advance = -1;
+    return hy::launch_clock(f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, l, f->nlev, f->rate, f->cfl,
+                            f->dt_fixed, f->stream);
+}
+
+// Level l's time advances by its step; the update joins the next clock launch
+// (nothing reads the time before then).
+hipError_t fmr_defer_advance(hy_fmr *f, int l)
+{
+    hipError_t e = hipSuccess;
+    if (f->pending_advance >= 0) e = fmr_clock(f, -1, 0);
+    f->pending_advance = l;
+    return e;
 }
 
 template <typename T> T *arrA(hy_fmr::Level &L) { return (T *)L.p->A; }
@@ -1494,7 +1515,7 @@ hy_status fmr_evolve_level(hy_fmr *f, int l)
     hipError_t e = hipSuccess;
     if (l - 1 > 0) e = fmr_prolong<T>(f, l - 1);
     if (e == hipSuccess)
-        e = hy::launch_clock(f->clock, hy::CLOCK_PROVISIONAL, l - 1, f->nlev, f->rate, 0.0, 0.0, f->stream);
+        e = fmr_clock(f, hy::CLOCK_PROVISIONAL, l - 1);
     if (e == hipSuccess) e = fmr_level_step<T>(f, l - 1, true);
     if (e != hipSuccess) return hip_fail(e, "provisional coarse step");
     st = fmr_step_level<T>(f, l);
@@ -1526,16 +1547,16 @@ hy_status fmr_step_level(hy_fmr *f, int l)
             e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
         }
         if (e == hipSuccess)
-            e = hy::launch_clock(f->clock, hy::CLOCK_DEEPEST, l, f->nlev, f->rate, f->cfl, f->dt_fixed, f->stream);
+            e = fmr_clock(f, hy::CLOCK_DEEPEST, l);
     } else {
-        e = hy::launch_clock(f->clock, hy::CLOCK_COARSE, l, f->nlev, f->rate, 0.0, 0.0, f->stream);
+        e = fmr_clock(f, hy::CLOCK_COARSE, l);
     }
     if (e == hipSuccess) e = fmr_level_step<T>(f, l, false);
     if (e == hipSuccess && l + 1 < f->nlev) {
         hy_fmr::Level &C = f->lev[l + 1];
         e = hy::launch_restrict<T>(arrA<T>(L), L.g, L.child, arrA<T>(C), C.g, nd, f->stream);
     }
-    if (e == hipSuccess) e = hy::launch_clock(f->clock, hy::CLOCK_ADVANCE, l, f->nlev, f->rate, 0.0, 0.0, f->stream);
+    if (e == hipSuccess) e = fmr_defer_advance(f, l);
     if (e != hipSuccess) return hip_fail(e, "level step");
     return HY_OK;
 }
@@ -1548,9 +1569,14 @@ hy_status fmr_enqueue(hy_fmr *f, hipStream_t s)
         f->lev[l].p->stream = s;
         f->lev[l].prov = false;
     }
-    hipError_t e = hy::launch_clock(f->clock, hy::CLOCK_RESET, 0, f->nlev, f->rate, 0.0, 0.0, s);
+    f->pending_advance = -1;
+    hipError_t e = fmr_clock(f, hy::CLOCK_RESET, 0);
     if (e != hipSuccess) return hip_fail(e, "clock reset");
-    return f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
+    hy_status st = f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
+    if (st != HY_OK) return st;
+    e = fmr_clock(f, -1, 0);  // the coarse level's final advance
+    if (e != hipSuccess) return hip_fail(e, "clock advance");
+    return HY_OK;
 }
 
 void fmr_drop_graph(hy_fmr *f)
