@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(TB) k_box_rate(const T *u, Grid g, Box b, T ga
     red[threadIdx.x] = m;
     __syncthreads();
     for (int s = TB / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
     if (threadIdx.x == 0)
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(TB) k_leaf_totals(const T *u, Grid g, Box b, B
         red[threadIdx.x] = s[v];
         __syncthreads();
         for (int st = TB / 2; st > 0; st >>= 1) {
-            if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
             __syncthreads();
         }
         if (threadIdx.x == 0) {
