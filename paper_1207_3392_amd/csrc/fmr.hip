@@ -4,7 +4,8 @@
 // parent and the fluxes the parent computed at the same faces, the
 // coarse/fine flux replacement, restriction, and the CFL rate and conserved
 // totals over part of an array.  These are thin passes over faces or over a
-// level's two-cell shell; the cell update itself is the stage kernel's.
+// level's two-cell shell; the cell update itself is the stage kernel's
+// (in its padded mode on refined levels).
 #include "hy_fmr.h"
 #include "hy_face.h"
 
@@ -88,7 +89,7 @@ __device__ __forceinline__ void load_prim(const T *u, const Grid &g, int64_t c, 
 }
 
 template <int ND, typename T>
-__global__ void __launch_bounds__(SB) k_prolong(T *fine, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
+__global__ void __launch_bounds__(SB) k_prolong(T *fine, T *fine2, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
                                                  T inv_gm1)
 {
     const int sc = blockIdx.x * SB + threadIdx.x;
@@ -126,27 +127,20 @@ __global__ void __launch_bounds__(SB) k_prolong(T *fine, Grid fg, const T *paren
             for (int v = 0; v < ND + 2; ++v) wc[v] += h * slope2_mm(wm[v], w0[v], wp[v], T(2));
         }
         const int64_t c = at(fg, c3[0], c3[1], c3[2]);
-        T ke = T(0);
-        fine[c] = wc[0];
+        T uc[ND + 2], ke = T(0);
+        uc[0] = wc[0];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            fine[(1 + d) * fg.vs + c] = wc[0] * wc[1 + d];
+            uc[1 + d] = wc[0] * wc[1 + d];
             ke += wc[1 + d] * wc[1 + d];
         }
-        fine[(ND + 1) * fg.vs + c] = wc[ND + 1] * inv_gm1 + T(0.5) * wc[0] * ke;
-    }
-}
-
-template <int ND, typename T>
-__global__ void __launch_bounds__(SB) k_exterior_copy(const T *src, T *dst, Grid g)
-{
-    const int sc = blockIdx.x * SB + threadIdx.x;
-    if (sc >= shell_cells<ND>(g)) return;
-    int c3[3];
-    shell_cell<ND>(g, sc, c3);
-    const int64_t c = at(g, c3[0], c3[1], c3[2]);
+        uc[ND + 1] = wc[ND + 1] * inv_gm1 + T(0.5) * wc[0] * ke;
 #pragma unroll
-    for (int v = 0; v < ND + 2; ++v) dst[v * g.vs + c] = src[v * g.vs + c];
+        for (int v = 0; v < ND + 2; ++v) {
+            fine[v * fg.vs + c] = uc[v];
+            if (fine2) fine2[v * fg.vs + c] = uc[v];
+        }
+    }
 }
 
 // The faces of one box normal to Q: one thread per face position
@@ -420,27 +414,19 @@ hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int n
 }
 
 template <typename T>
-hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box, int ndim,
-                          T gamma, T gm1, hipStream_t s)
+hipError_t launch_prolong(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
+                          int ndim, T gamma, T gm1, hipStream_t s)
 {
     (void)gamma;
     const T inv_gm1 = T(1) / gm1;
     const int cells = ndim == 1 ? shell_cells<1>(fg) : ndim == 2 ? shell_cells<2>(fg) : shell_cells<3>(fg);
     const dim3 grid((cells + SB - 1) / SB);
-    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(SB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
-    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(SB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
-    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(SB), 0, s, fine, fg, parent, pg, parent_box, gm1, inv_gm1);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, hipStream_t s)
-{
-    const int cells = ndim == 1 ? shell_cells<1>(g) : ndim == 2 ? shell_cells<2>(g) : shell_cells<3>(g);
-    const dim3 grid((cells + SB - 1) / SB);
-    if (ndim == 1) hipLaunchKernelGGL((k_exterior_copy<1, T>), grid, dim3(SB), 0, s, src, dst, g);
-    else if (ndim == 2) hipLaunchKernelGGL((k_exterior_copy<2, T>), grid, dim3(SB), 0, s, src, dst, g);
-    else hipLaunchKernelGGL((k_exterior_copy<3, T>), grid, dim3(SB), 0, s, src, dst, g);
+    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
+                           inv_gm1);
+    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
+                           inv_gm1);
+    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
+                           inv_gm1);
     return hipGetLastError();
 }
 
@@ -525,9 +511,8 @@ hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const B
 }
 
 #define HY_FMR_INST(T)                                                                                               \
-    template hipError_t launch_prolong<T>(T *, const Grid &, const T *, const Grid &, const Box &, int, T, T,        \
+    template hipError_t launch_prolong<T>(T *, T *, const Grid &, const T *, const Grid &, const Box &, int, T, T,   \
                                           hipStream_t);                                                              \
-    template hipError_t launch_exterior_copy<T>(const T *, T *, const Grid &, int, hipStream_t);                     \
     template hipError_t launch_box_flux<T>(const T *, const Grid &, int, const Box *, double *const(*)[3][2],        \
                                            const int *, int, int, T, T, T, T, const double *, hipStream_t);          \
     template hipError_t launch_reflux<T>(T *, const Grid &, const Box &, int, const double *const[3][2],             \

@@ -2,9 +2,9 @@
 //
 // Levels are nested boxes refined by two along every active dimension.  A
 // refined level lives in a padded array: its n cells per active dimension
-// plus NG = 2 exterior cells on each side, so the stage kernels run over the
-// padded extent unchanged while the exterior holds values prolonged from the
-// next coarser level.  All arrays are SoA (variable stride vs), x fastest;
+// plus NG = 2 exterior cells on each side, which hold values prolonged from
+// the next coarser level; the stage kernels (padded mode) update the interior
+// and read the exterior as the stencil's ghost cells.  All arrays are SoA (variable stride vs), x fastest;
 // "box" arguments are cell ranges in the coordinates of the array they index.
 #pragma once
 
@@ -54,15 +54,12 @@ struct Grid {
 // Exterior of the padded level (fine) from its parent: each exterior cell at
 // fine offset r from the level's first interior cell takes its parent
 // cell's primitives plus +/- 1/4 of the parent's minmod-limited differences
-// along each active dimension, stored as conserved variables.  parent_box
-// names the parent cells the level refines.
+// along each active dimension, stored as conserved variables into fine and,
+// when not null, fine2 (the level's stage state).  parent_box names the
+// parent cells the level refines.
 template <typename T>
-hipError_t launch_prolong(T *fine, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box, int ndim,
-                          T gamma, T gm1, hipStream_t s);
-
-// Copies the exterior cells of a padded level from src to dst.
-template <typename T>
-hipError_t launch_exterior_copy(const T *src, T *dst, const Grid &g, int ndim, hipStream_t s);
+hipError_t launch_prolong(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
+                          int ndim, T gamma, T gm1, hipStream_t s);
 
 // Fluxes through the low and high faces of each of nbox (1 or 2) boxes of
 // the array u along every active q, from its generalised-minmod face states

@@ -22,7 +22,11 @@ struct DevCtl {
     double totals[8];
 };
 
-enum { LIM_THETA = 0, LIM_LEARNED = 1 };
+// LIM_THETA_PADDED: the generalised-minmod limiter on a padded array (a
+// refined level): the state holds 2 exterior cells on each side of every
+// active dimension, filled by the caller; n are the interior extents, only
+// interior cells are updated, and no boundary kind applies.
+enum { LIM_THETA = 0, LIM_LEARNED = 1, LIM_THETA_PADDED = 2 };
 // Riemann solvers; the switch is HLLC with HLL at faces transverse to a shock
 enum { SOLVER_HLL = 0, SOLVER_HLLC = 1, SOLVER_HLLC_SWITCH = 2 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };

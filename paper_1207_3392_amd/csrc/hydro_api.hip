@@ -53,7 +53,12 @@ struct hy_patch {
     bool mlp_set = false;
     hipStream_t stream = nullptr;
     int parity = 0;
-    const double *dt_dev = nullptr;  // the step of DT_PTR stages (set by the multilevel driver)
+    const double *dt_dev = nullptr;  // the step of DT_PTR stages (set by the multilevel recursion)
+    // a refined level: the arrays hold `inner` interior cells plus 2 exterior
+    // cells on each side of every active dimension; the stages update the
+    // interior only (LIM_THETA_PADDED)
+    bool padded = false;
+    int64_t inner[3] = {1, 1, 1};
     hy::LaunchCfg cfg{64, 8, 32};
     // timing
     bool timing = false;
@@ -135,6 +140,8 @@ Layout layout(const hy_patch_desc &d)
     return L;
 }
 
+int stage_limiter(const hy_patch *p) { return p->padded ? hy::LIM_THETA_PADDED : p->d.limiter; }
+
 template <typename T>
 hy::StageArgs<T> stage_args(hy_patch *p, int stage, int dt_mode, double dt, double cfl, double t_end)
 {
@@ -147,7 +154,7 @@ hy::StageArgs<T> stage_args(hy_patch *p, int stage, int dt_mode, double dt, doub
     a.slopes = p->slopes;
     a.flags = p->flags;
     for (int q = 0; q < 3; ++q) {
-        a.n[q] = d.n[q];
+        a.n[q] = p->padded ? p->inner[q] : d.n[q];
         a.idx[q] = q < d.ndim ? (T)((double)d.n[q] / (d.hi[q] - d.lo[q])) : T(0);
         a.accel[q] = q < d.ndim ? (T)d.accel[q] : T(0);
         a.bc[q][0] = d.bc[q][0];
@@ -192,7 +199,7 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
         if (e != hipSuccess) return e;
     }
     hy::StageArgs<T> a = stage_args<T>(p, stage, dt_mode, dt, cfl, t_end);
-    e = hy::launch_stage<T>(p->d.ndim, solver, stage, p->d.limiter, p->cfg, a, p->stream);
+    e = hy::launch_stage<T>(p->d.ndim, solver, stage, stage_limiter(p), p->cfg, a, p->stream);
     if (e != hipSuccess) return e;
     if (rec) {
         e = hipEventRecord(p->ev[k][2 * p->nrec[k] + 1], p->stream);
@@ -252,6 +259,7 @@ void pick_config(hy_patch *p)
     // plane tile and z chunk: at least ~512 workgroups (two per CU) and at
     // most 64 planes per workgroup (measured best at 256^3: 64x8 tile, 64 planes)
     const hy_patch_desc &d = p->d;
+    const int64_t *n = p->padded ? p->inner : d.n;  // the extents the stages cover
     p->cfg.bx = 64;
     p->cfg.by = d.ndim == 1 ? 1 : 8;
 
@@ -263,15 +271,15 @@ void pick_config(hy_patch *p)
         }
     }
     if (d.ndim == 3) {
-        const int64_t tiles = ((d.n[0] + p->cfg.bx - 1) / p->cfg.bx) * ((d.n[1] + p->cfg.by - 1) / p->cfg.by);
+        const int64_t tiles = ((n[0] + p->cfg.bx - 1) / p->cfg.bx) * ((n[1] + p->cfg.by - 1) / p->cfg.by);
         int64_t chunks = (512 + tiles - 1) / tiles;
-        chunks = std::max<int64_t>(chunks, (d.n[2] + 63) / 64);
-        if (chunks > d.n[2] / 8) chunks = d.n[2] / 8;
+        chunks = std::max<int64_t>(chunks, (n[2] + 63) / 64);
+        if (chunks > n[2] / 8) chunks = n[2] / 8;
         if (chunks < 1) chunks = 1;
-        p->cfg.zchunk = (int)((d.n[2] + chunks - 1) / chunks);
+        p->cfg.zchunk = (int)((n[2] + chunks - 1) / chunks);
         if (const char *e = std::getenv("HY_ZCHUNK")) {  // planes per workgroup, for tuning runs
             const int zc = std::atoi(e);
-            if (zc >= 1 && zc <= d.n[2]) p->cfg.zchunk = zc;
+            if (zc >= 1 && zc <= n[2]) p->cfg.zchunk = zc;
         }
     } else {
         p->cfg.zchunk = 1;
@@ -618,12 +626,12 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
                 hy::StageArgs<double> a = stage_args<double>(p, stage, hy::DT_HOST, 0.0, 0.0, 0.0);
                 a.uin = a.u0 = (const double *)p->A;
                 a.uout = (double *)p->B;
-                r = hy::launch_stage<double>(d.ndim, solver, stage, d.limiter, c, a, p->stream);
+                r = hy::launch_stage<double>(d.ndim, solver, stage, stage_limiter(p), c, a, p->stream);
             } else {
                 hy::StageArgs<float> a = stage_args<float>(p, stage, hy::DT_HOST, 0.0, 0.0, 0.0);
                 a.uin = a.u0 = (const float *)p->A;
                 a.uout = (float *)p->B;
-                r = hy::launch_stage<float>(d.ndim, solver, stage, d.limiter, c, a, p->stream);
+                r = hy::launch_stage<float>(d.ndim, solver, stage, stage_limiter(p), c, a, p->stream);
             }
         }
         return r;
@@ -1429,7 +1437,10 @@ hipError_t fmr_prolong(hy_fmr *f, int l)
     }
     const T *src = P.prov ? arrB<T>(P) : arrA<T>(P);
     const double g = f->d.base.gamma;
-    return hy::launch_prolong<T>(arrA<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0), f->stream);
+    // the exterior of both the level's state and its stage state: the stages
+    // update interiors only, so the exterior stays fixed through the step
+    return hy::launch_prolong<T>(arrA<T>(L), arrB<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0),
+                                 f->stream);
 }
 
 // Stepper(l)%Step with the level's step from its device clock (dt, or dtp for
@@ -1485,10 +1496,6 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
         }
         e = run_stage<T>(p, f->solver, stage, hy::DT_PTR, 0.0, 0.0, 0.0);
         if (e != hipSuccess) return e;
-        if (stage == 1 && l > 0) {
-            e = hy::launch_exterior_copy<T>(arrA<T>(L), arrB<T>(L), L.g, nd, f->stream);
-            if (e != hipSuccess) return e;
-        }
     }
     p->parity ^= 1;
     if (child) {
@@ -1662,6 +1669,11 @@ hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, v
         }
         V.off = l > 0 ? hy::FMR_NG : 0;
         V.g.vs = V.p->vstride;
+        if (l > 0) {
+            V.p->padded = true;
+            for (int q = 0; q < 3; ++q) V.p->inner[q] = q < nd ? L.desc[l].n[q] - 2 * hy::FMR_NG : 1;
+            pick_config(V.p);
+        }
         V.dv = 1.0;
         for (int q = 0; q < 3; ++q) {
             const bool act = q < nd;

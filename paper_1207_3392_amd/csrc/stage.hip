@@ -124,7 +124,19 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
     const int nx = (int)a.n[0], ny = (int)a.n[1], nz = (int)a.n[2];
-    const int plane = nx * ny;
+    // storage: interior cells only, or (padded) the interior plus 2 exterior
+    // cells on each side of every active dimension
+    constexpr bool PAD = LIM == LIM_THETA_PADDED;
+    static_assert(!PAD || SOLVER != SOLVER_HLLC_SWITCH, "padded arrays take HLL or HLLC");
+    constexpr int OFFY = (PAD && ND >= 2) ? 2 : 0, OFFZ = (PAD && ND == 3) ? 2 : 0;
+    const int sx = PAD ? nx + 4 : nx;
+    const int plane = sx * (ny + 2 * OFFY);
+    // a coordinate's storage index: boundary-mapped, or (padded) shifted into
+    // the exterior and clamped to it (the unused columns of partial tiles)
+    auto smap = [&](int i, int n, int bclo, int bchi, bool &f) -> int {
+        if constexpr (PAD) return (i < -2 ? -2 : (i > n + 1 ? n + 1 : i)) + 2;
+        return map32(i, n, bclo, bchi, f);
+    };
     // XCD-aware tile order: consecutive workgroup ids are dealt round-robin
     // to the 8 XCDs, so hand each XCD a contiguous band of tiles (x fastest,
     // then y, then z chunk); neighbouring tiles then share halo lines in the
@@ -172,8 +184,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     for (int i = tid; i < WX + RY; i += NT) {
         bool f = false;
         int m = 0;
-        if (i < WX) m = map32(x0 + i - 2, nx, a.bc[0][0], a.bc[0][1], f);
-        else if (ND >= 2) m = map32(y0 + (i - WX) - 2, ny, a.bc[1][0], a.bc[1][1], f);
+        if (i < WX) m = smap(x0 + i - 2, nx, a.bc[0][0], a.bc[0][1], f);
+        else if (ND >= 2) m = smap(y0 + (i - WX) - 2, ny, a.bc[1][0], a.bc[1][1], f);
         sMap[i] = m | (f ? FLIP : 0);
     }
 
@@ -191,10 +203,10 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int xm = sMap[tx + 2];
     const int ym = (ND >= 2) ? sMap[WX + ty + 2] : 0;
     const bool fxo = (xm & FLIP) != 0, fyo = (ym & FLIP) != 0;
-    const unsigned colo = (unsigned)((ym & IDX) * nx + (xm & IDX));
+    const unsigned colo = (unsigned)((ym & IDX) * sx + (xm & IDX));
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own_valid = (gx < nx) && (gy < ny);
-    const unsigned colv = (unsigned)(gy * nx + gx);
+    const unsigned colv = (unsigned)((gy + OFFY) * sx + gx + (PAD ? 2 : 0));
 
     // halo cells of this thread: plane offset, LDS slot, mirror flags
     unsigned hoff[HPT];
@@ -219,7 +231,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             }
             const int hx = sMap[col + 2];
             const int hy = (ND >= 2) ? sMap[WX + row + 2] : 0;
-            hoff[j] = (unsigned)((hy & IDX) * nx + (hx & IDX));
+            hoff[j] = (unsigned)((hy & IDX) * sx + (hx & IDX));
             hlds[j] = (row + OY) * WX + col + 2;
             hflg[j] = ((hx & FLIP) ? 1 : 0) | ((hy & FLIP) ? 2 : 0);
         }
@@ -235,7 +247,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         if constexpr (ND == 3) { if (fz) w[3] = -w[3]; }
     };
     auto zoff = [&](int z, bool &fz) -> unsigned {
-        if constexpr (ND == 3) return (unsigned)(map32(z, nz, a.bc[2][0], a.bc[2][1], fz) * plane);
+        if constexpr (ND == 3) return (unsigned)(smap(z, nz, a.bc[2][0], a.bc[2][1], fz) * plane);
         return 0u;
     };
     auto face_state = [&](const T (&w)[NP], const T (&s)[NP], T h, T (&out)[NP]) {
@@ -259,7 +271,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         to_w(UB, WB, fxo, fyo, fp);
 #pragma unroll
         for (int v = 0; v < NP; ++v) {
-            if constexpr (LIM == LIM_THETA) {
+            if constexpr (LIM != LIM_LEARNED) {
                 sm1[v] = slope2_mm(wm2[v], wm1[v], WA[v], theta2);
                 SA[v] = slope2_mm(wm1[v], WA[v], WB[v], theta2);
             } else {
@@ -282,7 +294,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     // is not on the path to the first barrier of the plane
     T hnext[HPT][NP];
     auto load_halo = [&](int z, T (&h)[HPT][NP]) {
-        const unsigned zo = (ND == 3) ? (unsigned)((z < nz ? z : nz - 1) * plane) : 0u;
+        const unsigned zo = (ND == 3) ? (unsigned)(((z < nz ? z : nz - 1) + OFFZ) * plane) : 0u;
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
             if (hlds[j] >= 0) load(zo + hoff[j], h[j]);
@@ -300,7 +312,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                     T (&Sk)[NP], T (&Sk1)[NP], T (&Flo)[NP], T (&Fhi)[NP]) {
         (void)Uk1;
         const int kz = z0 + it;
-        const unsigned zko = (ND == 3) ? (unsigned)(kz * plane) : 0u;
+        const unsigned zko = (ND == 3) ? (unsigned)((kz + OFFZ) * plane) : 0u;
         bool fz2 = false;
         if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
         T u0[NP];  // U^n of the own cell (second stage), issued early, used in phase 3
@@ -389,7 +401,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         auto slope_x = [&](int row, int col) {
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM == LIM_THETA)
+                if constexpr (LIM != LIM_LEARNED)
                     sSx[v][row][col + 1] = slope2_mm(sW[v][row + OY][col + 1], sW[v][row + OY][col + 2],
                                                     sW[v][row + OY][col + 3], theta2);
                 else
@@ -399,7 +411,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         auto slope_y = [&](int row, int col) {
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM == LIM_THETA)
+                if constexpr (LIM != LIM_LEARNED)
                     sSy[v][row + 1][col] = slope2_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
                                                     sW[v][row + 3][col + 2], theta2);
                 else
@@ -414,7 +426,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         const bool ring1 = ND == 3 && (wv < (2 * BX + 63) / 64 || wv >= (NT - 2 * BY) / 64);
         const bool ring2 = ND == 3 && (wv < (BX + 63) / 64 || wv >= (NT - BY) / 64);
         if (ring1) __builtin_amdgcn_s_setprio(2);
-        if constexpr (LIM == LIM_THETA) {
+        if constexpr (LIM != LIM_LEARNED) {
             slope_x(ty, tx);
             if constexpr (ND >= 2) slope_y(ty, tx);
         } else {
@@ -428,11 +440,11 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             to_w(U2, W2, fxo, fyo, fz2);
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM == LIM_THETA) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
+                if constexpr (LIM != LIM_LEARNED) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
                 else Sk1[v] = lsz[v];
             }
         }
-        if constexpr (LIM == LIM_THETA) {
+        if constexpr (LIM != LIM_LEARNED) {
             if constexpr (ND >= 2) {
                 if (tid < 2 * BX) slope_y(tid < BX ? -1 : BY, tid < BX ? tid : tid - BX);
             }
@@ -633,6 +645,11 @@ hipError_t launch_lim(int limiter, const LaunchCfg &cfg, const StageArgs<T> &a, 
 {
     if constexpr (sizeof(T) == 4) {
         if (limiter == LIM_LEARNED) return launch_by<ND, T, SOLVER, STAGE, LIM_LEARNED>(cfg, a, s);
+    }
+    if constexpr (SOLVER != SOLVER_HLLC_SWITCH) {
+        if (limiter == LIM_THETA_PADDED) return launch_by<ND, T, SOLVER, STAGE, LIM_THETA_PADDED>(cfg, a, s);
+    } else {
+        if (limiter == LIM_THETA_PADDED) return hipErrorInvalidValue;
     }
     return launch_by<ND, T, SOLVER, STAGE, LIM_THETA>(cfg, a, s);
 }
