@@ -62,6 +62,8 @@ CASES = [
     ("sedov1d", lambda: wl.sedov_levels(1, 64, 4)),
     ("sedov2d", lambda: wl.sedov_levels(2, 32, 3)),
     ("sedov3d", lambda: wl.sedov_levels(3, 16, 2)),
+    # seven levels, as in the paper's 2D multilevel runs (finest spacing 1/2048)
+    ("sedov2d_7levels", lambda: wl.sedov_levels(2, 32, 7)),
     # uneven boxes and a non-square base: ragged tiles on every level
     ("smooth2d_ragged", lambda: wl.smooth_levels(2, 0, boxes=[((5, 3, 0), (13, 9, 1)), ((4, 2, 0), (9, 7, 1))],
                                                  n=(40, 24))),
