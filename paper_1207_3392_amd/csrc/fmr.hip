@@ -143,19 +143,17 @@ __global__ void __launch_bounds__(SB) k_prolong(T *fine, T *fine2, Grid fg, cons
     }
 }
 
-// The faces of one box normal to Q: one thread per face position
-// transverse to Q, both faces (low and high side of the box) along the line
-// through it.
+// The faces of one box normal to Q on one side (0: low, 1: high): one
+// thread per face position transverse to Q.
 template <int ND, int Q, int SOLVER, typename T>
-__device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &b, int t, T gamma, T gm1, T inv_gm1,
-                                          T theta2, double w, bool assign, double *acc_lo, double *acc_hi)
+__device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &b, int t, int side, T gamma, T gm1,
+                                          T inv_gm1, T theta2, double w, bool assign, double *acc_lo, double *acc_hi)
 {
     constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
     const int faces = b.n[R1] * b.n[R2];
     if (t >= faces) return;
     const int t1 = t % b.n[R1], t2 = t / b.n[R1];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
+    {
         const int f = side == 0 ? b.lo[Q] : b.lo[Q] + b.n[Q];  // face between cells f - 1 and f
         T w4[4][ND + 2];
 #pragma unroll
@@ -182,7 +180,8 @@ __device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &
     }
 }
 
-// Up to two boxes of one array in one launch: blockIdx.y = box * ND + Q.
+// Up to two boxes of one array in one launch: blockIdx.y = (box * ND + Q) * 2
+// + side.
 // assign[k]: box k's accumulators are overwritten, not added to.
 struct FluxSet {
     Box b[2];
@@ -195,19 +194,20 @@ __global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs,
                                                   const double *dt)
 {
     const double w = 0.5 * *dt;
-    const int bx = blockIdx.y / ND, q = blockIdx.y - bx * ND;
+    const int side = blockIdx.y & 1, bq = blockIdx.y >> 1;
+    const int bx = bq / ND, q = bq - bx * ND;
     const int t = blockIdx.x * FB + threadIdx.x;
     const Box &b = fs.b[bx];
     if (q == 0)
-        box_faces<ND, 0, SOLVER>(u, g, b, t, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+        box_faces<ND, 0, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
                                      fs.acc[bx][0][0], fs.acc[bx][0][1]);
     if constexpr (ND >= 2)
         if (q == 1)
-            box_faces<ND, 1, SOLVER>(u, g, b, t, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+            box_faces<ND, 1, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
                                      fs.acc[bx][1][0], fs.acc[bx][1][1]);
     if constexpr (ND >= 3)
         if (q == 2)
-            box_faces<ND, 2, SOLVER>(u, g, b, t, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+            box_faces<ND, 2, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
                                      fs.acc[bx][2][0], fs.acc[bx][2][1]);
 }
 
@@ -363,7 +363,7 @@ hipError_t box_flux_nd(const T *u, const Grid &g, const FluxSet &fs, int nbox, i
     int most = 0;
     for (int k = 0; k < nbox; ++k)
         for (int q = 0; q < ND; ++q) most = std::max(most, fs.b[k].n[(q + 1) % 3] * fs.b[k].n[(q + 2) % 3]);
-    const dim3 grid((most + FB - 1) / FB, nbox * ND);
+    const dim3 grid((most + FB - 1) / FB, nbox * ND * 2);
     if (solver == SOLVER_HLL)
         hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLL, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta2, w);
     else
