@@ -317,11 +317,16 @@ typedef struct hy_fmr hy_fmr;
 
 hy_status hy_fmr_workspace_bytes(const hy_fmr_desc *d, size_t *bytes);
 hy_status hy_fmr_init(const hy_fmr_desc *d, void *dev_workspace, size_t bytes, void *hip_stream, hy_fmr **out);
-/* Interior state of one level (nv x that level's cells, FP64 SoA);
- * synchronising. */
+/* Interior state of one level (nv x that level's cells, FP64 SoA; the
+ * exterior of a refined level is filled by prolongation at the next step);
+ * synchronising.  HY_EINVAL for a level outside 0 .. nlev - 1; HY_ESTATE as
+ * for hy_set_state / hy_get_state. */
 hy_status hy_fmr_set_state(hy_fmr *f, int level, int kind, const double *host_soa);
 hy_status hy_fmr_get_state(hy_fmr *f, int level, int kind, double *host_soa_out);
-/* One global step; *dt_out (may be NULL) receives the coarse step.  The
+/* One global step; *dt_out (may be NULL) receives the coarse step.
+ * HY_EINVAL unless solver is HY_HLL or HY_HLLC and cfl > 0 or dt_fixed > 0
+ * (finite); HY_ESTATE when a kernel met rho <= 0, p <= 0 or a non-finite
+ * value (the levels then hold that step's results).  The
  * levels' times and steps stay in device memory, so the step's launches need
  * no host round trip: they are captured once into a HIP graph per (solver,
  * cfl, dt_fixed) and replayed (hy_fmr_set_graph(f, 0) launches them one by
@@ -332,8 +337,10 @@ hy_status hy_fmr_set_graph(hy_fmr *f, int on);
 /* FP64 sums of D, S_x, S_y, S_z, G times the cell volume over the leaf
  * cells of all levels (cells no finer level covers); synchronising. */
 hy_status hy_fmr_conserved_totals(hy_fmr *f, double out[5]);
-/* hy_autotune on every level (its padded extent, its current state); best,
- * when not NULL, receives nlev shapes.  Results do not change.
+/* hy_autotune on every level (over the cells its stages update: a refined
+ * level's interior, in the stage kernel's padded mode; its current state);
+ * best, when not NULL, receives nlev shapes.  Results do not change beyond
+ * the last-place rounding z chunks can bring.  Drops the captured graph.
  * Synchronising. */
 hy_status hy_fmr_autotune(hy_fmr *f, int solver, int reps, hy_launch_cfg *best);
 hy_status hy_fmr_destroy(hy_fmr *f);
