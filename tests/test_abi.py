@@ -58,6 +58,45 @@ def test_workspace_size_and_host_validation():
     assert b"FP32" in L.hy_last_error()
 
 
+def _fmr_desc(ndim, n, boxes, limiter=0, precision=32):
+    f = hydro.FmrDesc()
+    f.base = hydro.make_desc(ndim, n, (0, 0, 0), (1, 1, 1), 1.4, ((1, 1),) * 3, precision=precision,
+                             limiter=limiter, theta=1.4)
+    f.nlev = 1 + len(boxes)
+    for l, (lo, bn) in enumerate(boxes, start=1):
+        for q in range(3):
+            f.box_lo[l][q] = lo[q]
+            f.box_n[l][q] = bn[q]
+    return f
+
+
+def test_multilevel_workspace_and_host_validation():
+    """Host checks of the multilevel layout: the workspace grows with every
+    level (a refined level is padded by its two-cell exterior), and boxes
+    that break the two-parent-cell margin, unused dimensions with a box, too
+    many levels and the learned limiter are refused before any launch."""
+    L = hydro.lib()
+    nb1, nb2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    one = _fmr_desc(2, (32, 32, 1), [])
+    two = _fmr_desc(2, (32, 32, 1), [((8, 8, 0), (16, 16, 1))])
+    assert L.hy_fmr_workspace_bytes(ctypes.byref(one), ctypes.byref(nb1)) == hydro.HY_OK
+    assert L.hy_fmr_workspace_bytes(ctypes.byref(two), ctypes.byref(nb2)) == hydro.HY_OK
+    # level 1 holds 36 x 36 padded cells, two states of 4 FP32 variables
+    assert nb2.value - nb1.value >= 2 * 4 * 36 * 36 * 4
+    for boxes in ([((1, 8, 0), (16, 16, 1))], [((8, 8, 0), (23, 16, 1))], [((8, 8, 1), (16, 16, 1))],
+                  [((8, 8, 0), (0, 16, 1))], [((8, 8, 0), (16, 16, 1)), ((2, 2, 0), (30, 4, 1))]):
+        bad = _fmr_desc(2, (32, 32, 1), boxes)
+        assert L.hy_fmr_workspace_bytes(ctypes.byref(bad), ctypes.byref(nb1)) == hydro.HY_EINVAL, boxes
+    deep = _fmr_desc(1, (64, 1, 1), [((2, 0, 0), (4, 1, 1))] * 7)
+    deep.nlev = hydro.FMR_MAXLEV + 1
+    assert L.hy_fmr_workspace_bytes(ctypes.byref(deep), ctypes.byref(nb1)) == hydro.HY_EINVAL
+    learned = _fmr_desc(2, (32, 32, 1), [((8, 8, 0), (16, 16, 1))], limiter=hydro.LIM_LEARNED)
+    assert L.hy_fmr_workspace_bytes(ctypes.byref(learned), ctypes.byref(nb1)) == hydro.HY_EUNSUPPORTED
+    h = ctypes.c_void_p()
+    assert L.hy_fmr_init(ctypes.byref(two), ctypes.c_void_p(0x1000), 16, None, ctypes.byref(h)) == hydro.HY_ENOMEM
+    assert L.hy_fmr_step(None, 0.4, 0.0, hydro.HLLC, None) == hydro.HY_EINVAL
+
+
 def test_init_rejects_small_workspace_without_touching_the_device():
     L = hydro.lib()
     d = hydro.make_desc(1, (8, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((1, 1), (0, 0), (0, 0)))
