@@ -379,11 +379,12 @@ __device__ __forceinline__ void clock_op(FmrClock *c, int op, int l, int nlev, u
         for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
         for (int k = 0; k < FMR_RATE_SLOTS; ++k) rate_bits[k] = 0ull;
         break;
-    case CLOCK_DEEPEST: {
+    case CLOCK_DEEPEST:
+    case CLOCK_DEEPEST_KEEP: {
         unsigned long long rb = 0ull;
         for (int k = 0; k < FMR_RATE_SLOTS; ++k) {
             rb = rb > rate_bits[k] ? rb : rate_bits[k];
-            rate_bits[k] = 0ull;
+            if (op == CLOCK_DEEPEST) rate_bits[k] = 0ull;
         }
         c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)rb);
         break;

@@ -27,7 +27,14 @@ struct FmrClock {
     double t, dt, dtp, pad;
 };
 
-enum { CLOCK_RESET = 0, CLOCK_DEEPEST = 1, CLOCK_COARSE = 2, CLOCK_PROVISIONAL = 3, CLOCK_ADVANCE = 4 };
+enum {
+    CLOCK_RESET = 0,
+    CLOCK_DEEPEST = 1,
+    CLOCK_COARSE = 2,
+    CLOCK_PROVISIONAL = 3,
+    CLOCK_ADVANCE = 4,
+    CLOCK_DEEPEST_KEEP = 5
+};
 
 // The CFL rate is reduced into FMR_RATE_SLOTS words (workgroup b into word
 // b mod FMR_RATE_SLOTS), so the atomics of a reduction never queue on one
@@ -39,6 +46,8 @@ constexpr int FMR_RATE_SLOTS = 32;
 //  RESET        every level's time to 0 and the rate words to 0;
 //  DEEPEST      dt of level l = dt_fixed if > 0, else cfl / (the max of the
 //               rate words), which are then cleared;
+//  DEEPEST_KEEP the same from rate words that belong to someone else (a
+//               patch's control block), left as they are;
 //  COARSE       dt of level l = t(l + 1) - t(l) (the child's two steps);
 //  PROVISIONAL  dtp of level l = t(l + 1) - t(l) (the child's first step);
 //  ADVANCE      t(l) += dt(l).

@@ -1405,12 +1405,12 @@ hy_status fmr_layout(const hy_fmr_desc *d, FmrLayout *L)
 
 // A clock update on the stream; a pending advance of a level's time goes
 // first in the same launch.
-hipError_t fmr_clock(hy_fmr *f, int op, int l)
+hipError_t fmr_clock(hy_fmr *f, int op, int l, unsigned long long *rate = nullptr)
 {
     const int pre = f->pending_advance;
     f->pending_advance = -1;
-    return hy::launch_clock(f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, l, f->nlev, f->rate, f->cfl,
-                            f->dt_fixed, f->stream);
+    return hy::launch_clock(f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, l, f->nlev, rate ? rate : f->rate,
+                            f->cfl, f->dt_fixed, f->stream);
 }
 
 // Level l's time advances by its step; the update joins the next clock launch
@@ -1549,12 +1549,22 @@ hy_status fmr_step_level(hy_fmr *f, int l)
     // the span of the child's two steps
     if (l == f->nlev - 1) {
         e = hipSuccess;
-        if (!(f->dt_fixed > 0.0)) {
-            const double g = f->d.base.gamma;
-            e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
+        if (l > 0 && !(f->dt_fixed > 0.0)) {
+            // the rate of the current state, which the level's last second
+            // stage (or hy_set_state) left in its control block: a refined
+            // level's stages cover its interior only, and nothing else
+            // changes the deepest level between its steps.  Its 2^l steps per
+            // global step leave the parity slot where a replay expects it.
+            static_assert(hy::FMR_RATE_SLOTS == hy::RATE_SLOTS, "rate words");
+            e = fmr_clock(f, hy::CLOCK_DEEPEST_KEEP, l, &L.p->ctl->rate[L.p->parity][0]);
+        } else {
+            if (!(f->dt_fixed > 0.0)) {
+                const double g = f->d.base.gamma;
+                e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate,
+                                           f->stream);
+            }
+            if (e == hipSuccess) e = fmr_clock(f, hy::CLOCK_DEEPEST, l);
         }
-        if (e == hipSuccess)
-            e = fmr_clock(f, hy::CLOCK_DEEPEST, l);
     } else {
         e = fmr_clock(f, hy::CLOCK_COARSE, l);
     }
