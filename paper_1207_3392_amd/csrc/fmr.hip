@@ -88,10 +88,41 @@ __device__ __forceinline__ void load_prim(const T *u, const Grid &g, int64_t c, 
     (void)to_prim<ND>(uu, w, gm1);
 }
 
+__device__ __forceinline__ void clock_op(FmrClock *c, int op, int l, int nlev, unsigned long long *rate_bits,
+                                         double cfl, double dt_fixed)
+{
+    switch (op) {
+    case CLOCK_RESET:
+        for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
+        for (int k = 0; k < FMR_RATE_SLOTS; ++k) rate_bits[k] = 0ull;
+        break;
+    case CLOCK_DEEPEST:
+    case CLOCK_DEEPEST_KEEP: {
+        unsigned long long rb = 0ull;
+        for (int k = 0; k < FMR_RATE_SLOTS; ++k) {
+            rb = rb > rate_bits[k] ? rb : rate_bits[k];
+            if (op == CLOCK_DEEPEST) rate_bits[k] = 0ull;
+        }
+        c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)rb);
+        break;
+    }
+    case CLOCK_COARSE: c[l].dt = c[l + 1].t - c[l].t; break;
+    case CLOCK_PROVISIONAL: c[l].dtp = c[l + 1].t - c[l].t; break;
+    case CLOCK_ADVANCE: c[l].t += c[l].dt; break;
+    default: break;
+    }
+}
+
 template <int ND, typename T>
 __global__ void __launch_bounds__(SB) k_prolong(T *fine, T *fine2, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
-                                                 T inv_gm1)
+                                                 T inv_gm1, ClockOps ck)
 {
+    // clock updates that ride on this launch (none of its threads reads the
+    // clocks; the kernels after it do)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ck.c) {
+        clock_op(ck.c, ck.op0, ck.l0, ck.nlev, ck.rate, ck.cfl, ck.dt_fixed);
+        clock_op(ck.c, ck.op1, ck.l1, ck.nlev, ck.rate, ck.cfl, ck.dt_fixed);
+    }
     const int sc = blockIdx.x * SB + threadIdx.x;
     if (sc < shell_cells<ND>(fg)) {
         int c3[3];
@@ -371,30 +402,6 @@ hipError_t box_flux_nd(const T *u, const Grid &g, const FluxSet &fs, int nbox, i
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void clock_op(FmrClock *c, int op, int l, int nlev, unsigned long long *rate_bits,
-                                         double cfl, double dt_fixed)
-{
-    switch (op) {
-    case CLOCK_RESET:
-        for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
-        for (int k = 0; k < FMR_RATE_SLOTS; ++k) rate_bits[k] = 0ull;
-        break;
-    case CLOCK_DEEPEST:
-    case CLOCK_DEEPEST_KEEP: {
-        unsigned long long rb = 0ull;
-        for (int k = 0; k < FMR_RATE_SLOTS; ++k) {
-            rb = rb > rate_bits[k] ? rb : rate_bits[k];
-            if (op == CLOCK_DEEPEST) rate_bits[k] = 0ull;
-        }
-        c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)rb);
-        break;
-    }
-    case CLOCK_COARSE: c[l].dt = c[l + 1].t - c[l].t; break;
-    case CLOCK_PROVISIONAL: c[l].dtp = c[l + 1].t - c[l].t; break;
-    case CLOCK_ADVANCE: c[l].t += c[l].dt; break;
-    default: break;
-    }
-}
 
 // up to two clock updates in order (op < 0: none)
 __global__ void __launch_bounds__(64) k_clock(FmrClock *c, int op0, int l0, int op1, int l1, int nlev,
@@ -416,18 +423,18 @@ hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int n
 
 template <typename T>
 hipError_t launch_prolong(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
-                          int ndim, T gamma, T gm1, hipStream_t s)
+                          int ndim, T gamma, T gm1, const ClockOps &ck, hipStream_t s)
 {
     (void)gamma;
     const T inv_gm1 = T(1) / gm1;
     const int cells = ndim == 1 ? shell_cells<1>(fg) : ndim == 2 ? shell_cells<2>(fg) : shell_cells<3>(fg);
     const dim3 grid((cells + SB - 1) / SB);
     if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
-                           inv_gm1);
+                           inv_gm1, ck);
     else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
-                           inv_gm1);
+                           inv_gm1, ck);
     else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
-                           inv_gm1);
+                           inv_gm1, ck);
     return hipGetLastError();
 }
 
@@ -513,7 +520,7 @@ hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const B
 
 #define HY_FMR_INST(T)                                                                                               \
     template hipError_t launch_prolong<T>(T *, T *, const Grid &, const T *, const Grid &, const Box &, int, T, T,   \
-                                          hipStream_t);                                                              \
+                                          const ClockOps &, hipStream_t);                                            \
     template hipError_t launch_box_flux<T>(const T *, const Grid &, int, const Box *, double *const(*)[3][2],        \
                                            const int *, int, int, T, T, T, T, const double *, hipStream_t);          \
     template hipError_t launch_reflux<T>(T *, const Grid &, const Box &, int, const double *const[3][2],             \

@@ -54,6 +54,14 @@ constexpr int FMR_RATE_SLOTS = 32;
 hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int nlev, unsigned long long *rate_bits,
                         double cfl, double dt_fixed, hipStream_t s);
 
+// Clock updates carried by another launch (c == nullptr: none).
+struct ClockOps {
+    FmrClock *c;
+    int op0, l0, op1, l1, nlev;
+    unsigned long long *rate;
+    double cfl, dt_fixed;
+};
+
 // Dense array extents and variable stride.
 struct Grid {
     int m[3];
@@ -65,10 +73,11 @@ struct Grid {
 // cell's primitives plus +/- 1/4 of the parent's minmod-limited differences
 // along each active dimension, stored as conserved variables into fine and,
 // when not null, fine2 (the level's stage state).  parent_box names the
-// parent cells the level refines.
+// parent cells the level refines.  The clock updates ck (if any) run in the
+// same launch.
 template <typename T>
 hipError_t launch_prolong(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
-                          int ndim, T gamma, T gm1, hipStream_t s);
+                          int ndim, T gamma, T gm1, const ClockOps &ck, hipStream_t s);
 
 // Fluxes through the low and high faces of each of nbox (1 or 2) boxes of
 // the array u along every active q, from its generalised-minmod face states

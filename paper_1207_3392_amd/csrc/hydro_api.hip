@@ -1426,8 +1426,10 @@ hipError_t fmr_defer_advance(hy_fmr *f, int l)
 template <typename T> T *arrA(hy_fmr::Level &L) { return (T *)L.p->A; }
 template <typename T> T *arrB(hy_fmr::Level &L) { return (T *)L.p->B; }
 
+// Prolongation into level l's exterior; the pending clock advance and the
+// clock update op (on level lop; op < 0: none) ride on the same launch.
 template <typename T>
-hipError_t fmr_prolong(hy_fmr *f, int l)
+hipError_t fmr_prolong(hy_fmr *f, int l, int op = -1, int lop = 0, unsigned long long *rate = nullptr)
 {
     hy_fmr::Level &L = f->lev[l], &P = f->lev[l - 1];
     hy::Box pb{};
@@ -1439,7 +1441,13 @@ hipError_t fmr_prolong(hy_fmr *f, int l)
     const double g = f->d.base.gamma;
     // the exterior of both the level's state and its stage state: the stages
     // update interiors only, so the exterior stays fixed through the step
-    return hy::launch_prolong<T>(arrA<T>(L), arrB<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0),
+    hy::ClockOps ck{};
+    const int pre = f->pending_advance;
+    f->pending_advance = -1;
+    if (pre >= 0 || op >= 0)
+        ck = {f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, lop, f->nlev, rate ? rate : f->rate, f->cfl,
+              f->dt_fixed};
+    return hy::launch_prolong<T>(arrA<T>(L), arrB<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0), ck,
                                  f->stream);
 }
 
@@ -1519,10 +1527,10 @@ hy_status fmr_evolve_level(hy_fmr *f, int l)
     if (l >= f->nlev) return HY_OK;
     hy_status st = fmr_step_level<T>(f, l);
     if (st != HY_OK || l == 0) return st;
-    hipError_t e = hipSuccess;
-    if (l - 1 > 0) e = fmr_prolong<T>(f, l - 1);
-    if (e == hipSuccess)
-        e = fmr_clock(f, hy::CLOCK_PROVISIONAL, l - 1);
+    // the provisional step of the parent: its exterior (if it has a parent),
+    // its step (the child's first), then its first stage
+    hipError_t e = l - 1 > 0 ? fmr_prolong<T>(f, l - 1, hy::CLOCK_PROVISIONAL, l - 1)
+                             : fmr_clock(f, hy::CLOCK_PROVISIONAL, l - 1);
     if (e == hipSuccess) e = fmr_level_step<T>(f, l - 1, true);
     if (e != hipSuccess) return hip_fail(e, "provisional coarse step");
     st = fmr_step_level<T>(f, l);
@@ -1541,34 +1549,31 @@ hy_status fmr_step_level(hy_fmr *f, int l)
         hy_status st = fmr_evolve_level<T>(f, l + 1);
         if (st != HY_OK) return st;
     }
-    if (l > 0) {
-        e = fmr_prolong<T>(f, l);
-        if (e != hipSuccess) return hip_fail(e, "prolongation");
-    }
     // Alg. StepLevel's time step: the CFL step at the deepest level, else
-    // the span of the child's two steps
-    if (l == f->nlev - 1) {
+    // the span of the child's two steps; on a refined level the clock update
+    // rides on the prolongation of its exterior
+    const bool deepest = l == f->nlev - 1;
+    if (l > 0) {
+        // the deepest refined level's rate is the one its last second stage
+        // (or hy_set_state) left in its control block: its stages cover its
+        // interior only, and nothing else changes it between its steps; its
+        // 2^l steps per global step leave the parity slot where a replay of
+        // the captured step expects it
+        static_assert(hy::FMR_RATE_SLOTS == hy::RATE_SLOTS, "rate words");
+        e = deepest ? fmr_prolong<T>(f, l, hy::CLOCK_DEEPEST_KEEP, l, &L.p->ctl->rate[L.p->parity][0])
+                    : fmr_prolong<T>(f, l, hy::CLOCK_COARSE, l);
+    } else if (deepest) {  // one level: a rate pass over it
         e = hipSuccess;
-        if (l > 0 && !(f->dt_fixed > 0.0)) {
-            // the rate of the current state, which the level's last second
-            // stage (or hy_set_state) left in its control block: a refined
-            // level's stages cover its interior only, and nothing else
-            // changes the deepest level between its steps.  Its 2^l steps per
-            // global step leave the parity slot where a replay expects it.
-            static_assert(hy::FMR_RATE_SLOTS == hy::RATE_SLOTS, "rate words");
-            e = fmr_clock(f, hy::CLOCK_DEEPEST_KEEP, l, &L.p->ctl->rate[L.p->parity][0]);
-        } else {
-            if (!(f->dt_fixed > 0.0)) {
-                const double g = f->d.base.gamma;
-                e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate,
-                                           f->stream);
-            }
-            if (e == hipSuccess) e = fmr_clock(f, hy::CLOCK_DEEPEST, l);
+        if (!(f->dt_fixed > 0.0)) {
+            const double g = f->d.base.gamma;
+            e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
         }
+        if (e == hipSuccess) e = fmr_clock(f, hy::CLOCK_DEEPEST, l);
     } else {
         e = fmr_clock(f, hy::CLOCK_COARSE, l);
     }
-    if (e == hipSuccess) e = fmr_level_step<T>(f, l, false);
+    if (e != hipSuccess) return hip_fail(e, "prolongation and time step");
+    e = fmr_level_step<T>(f, l, false);
     if (e == hipSuccess && l + 1 < f->nlev) {
         hy_fmr::Level &C = f->lev[l + 1];
         e = hy::launch_restrict<T>(arrA<T>(L), L.g, L.child, arrA<T>(C), C.g, nd, f->stream);
