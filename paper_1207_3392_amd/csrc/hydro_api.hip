@@ -1287,11 +1287,13 @@ hy_status hy_trainer_destroy(hy_trainer *tr)
 //
 // Host recursion of Algs. Evolve / EvolveLevel / StepLevel over nested levels.
 // Level 0 is an ordinary patch with the physical boundaries; a refined level
-// is a patch over its cells plus a two-cell exterior (outflow kinds, never
-// used for the interior: the exterior is rewritten by prolongation before
-// each step and restored into the stage-1 output before stage 2).  Every
-// launch goes to the one stream; the host waits only for the deepest level's
-// CFL rate and for the error latch at the end of a step.
+// is a patch over its cells plus a two-cell exterior, stepped by the stage
+// kernels' padded mode (interior updated, exterior read as ghost cells; its
+// boundary kinds go unused), the exterior written by prolongation into both
+// the state and the stage state before each step.  The levels' times and
+// steps live in device clocks, so a global step is a fixed launch sequence:
+// captured once into a HIP graph and replayed; the host waits once, at the
+// end, for the error latches and the coarse step.
 #include "hy_fmr.h"
 
 struct hy_fmr {
