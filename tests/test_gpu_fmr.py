@@ -158,6 +158,14 @@ def test_graph_replays_match_eager_launches(prec):
         for l in range(3):
             assert np.array_equal(G.get_state(l), E.get_state(l)), (k, l)
         assert np.array_equal(G.totals(), E.totals())
+        if k == 2:
+            # a new state on every level between replays: the captured step
+            # reads whatever the levels hold
+            for l in range(3):
+                W = lv.W[l].reshape(4, -1).copy()
+                W[0] *= 1.1
+                G.set_state(l, W, hydro.PRIMITIVE)
+                E.set_state(l, W, hydro.PRIMITIVE)
     G.close()
     E.close()
 
