@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
                                                    "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch",
-                                                   "fmr_sedov3d"],
+                                                   "fmr_sedov3d", "fmr_sedov2d_7levels"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -359,6 +359,7 @@ def main():
                "kh_2048_learned": lambda: time_kh(learned=True), "rt_512_plain": lambda: time_rt(learned=False),
                "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1,
                "fmr_sedov3d": time_fmr,
+               "fmr_sedov2d_7levels": lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1),
                "hllc_switch": lambda: {k: v for k, v in time_patch(args.n, "hllc_switch", args.steps,
                                                                     args.warmup).items() if k != "kernel"}}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
@@ -404,6 +405,7 @@ def main():
         guarded(f"hllc_switch_{args.n}", switch)
         guarded("batched_tubes", time_batch)
         guarded("fmr_sedov3d", time_fmr)
+        guarded("fmr_sedov2d_7levels", lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1))
         guarded("kh_2048_plain", lambda: time_kh(learned=False))
         guarded("kh_2048_learned", lambda: time_kh(learned=True))
         guarded("rt_512_plain", lambda: time_rt(learned=False))
