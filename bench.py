@@ -57,10 +57,10 @@ FLOPS_PER_CELL = {"hllc": {1: 478, 2: 524}, "hll": {1: 448, 2: 494}}
 TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h",
                    "paper_1207_3392_amd/csrc/hy_face.h")
 TRAFFIC = {
-    "digest": "06309fc392a7402286795dc8509517bfee070840868029d309bff83ffd5bc969",
+    "digest": "c8e7f2acf3f50e539b053825b6254f0589bbe36ad37969735b6d79d1070a4165",
     "ncell": 256 ** 3,
     "kernel": "k_stage<nd=3,f32,tile=64x8> zchunk=64",
-    "bytes_per_launch": {1: 703499205, 2: 1105782400},
+    "bytes_per_launch": {1: 703914715, 2: 1101754368},
 }
 
 

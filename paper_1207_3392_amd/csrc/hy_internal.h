@@ -22,10 +22,11 @@ struct DevCtl {
     double totals[8];
 };
 
-// LIM_THETA_PADDED: the generalised-minmod limiter on a padded array (a
-// refined level): the state holds 2 exterior cells on each side of every
-// active dimension, filled by the caller; n are the interior extents, only
-// interior cells are updated, and no boundary kind applies.
+// LIM_THETA_PADDED: the generalised-minmod limiter on a view of a larger
+// array (a refined level, or part of one): the cells updated are the n cells
+// starting at storage cell voff of an array of extents vm, and the 2 cells
+// around them on each side of every active dimension are read as they are
+// (filled by the caller); no boundary kind applies.
 enum { LIM_THETA = 0, LIM_LEARNED = 1, LIM_THETA_PADDED = 2 };
 // Riemann solvers; the switch is HLLC with HLL at faces transverse to a shock
 enum { SOLVER_HLL = 0, SOLVER_HLLC = 1, SOLVER_HLLC_SWITCH = 2 };
@@ -56,6 +57,7 @@ struct StageArgs {
     int dt_mode;
     double dt_host, cfl, t_end;
     const double *dt_dev;  // DT_PTR: the step
+    int voff[3], vm[3];    // LIM_THETA_PADDED: first updated cell and extents of the storage
 };
 
 struct LaunchCfg {

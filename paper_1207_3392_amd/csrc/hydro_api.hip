@@ -155,6 +155,8 @@ hy::StageArgs<T> stage_args(hy_patch *p, int stage, int dt_mode, double dt, doub
     a.flags = p->flags;
     for (int q = 0; q < 3; ++q) {
         a.n[q] = p->padded ? p->inner[q] : d.n[q];
+        a.voff[q] = p->padded && q < d.ndim ? 2 : 0;  // the interior of a padded level
+        a.vm[q] = (int)d.n[q];
         a.idx[q] = q < d.ndim ? (T)((double)d.n[q] / (d.hi[q] - d.lo[q])) : T(0);
         a.accel[q] = q < d.ndim ? (T)d.accel[q] : T(0);
         a.bc[q][0] = d.bc[q][0];
@@ -1463,7 +1465,20 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
     hipError_t e;
     if (provisional) {
         p->dt_dev = &f->clock[l].dtp;
-        e = run_stage<T>(p, f->solver, 1, hy::DT_PTR, 0.0, 0.0, 0.0);
+        if (l > 0) {
+            // a refined parent updates only the cells the child's
+            // prolongation reads: the child box grown by two cells (a view of
+            // the padded array; the box keeps two cells from the level's edge,
+            // so the view's ghosts lie inside the array)
+            hy::StageArgs<T> a = stage_args<T>(p, 1, hy::DT_PTR, 0.0, 0.0, 0.0);
+            for (int q = 0; q < p->d.ndim; ++q) {
+                a.n[q] = f->d.box_n[l + 1][q] + 4;
+                a.voff[q] = (int)f->d.box_lo[l + 1][q];  // NG + (box_lo - 2) in storage
+            }
+            e = hy::launch_stage<T>(p->d.ndim, f->solver, 1, hy::LIM_THETA_PADDED, p->cfg, a, p->stream);
+        } else {
+            e = run_stage<T>(p, f->solver, 1, hy::DT_PTR, 0.0, 0.0, 0.0);
+        }
         L.prov = true;
         return e;
     }

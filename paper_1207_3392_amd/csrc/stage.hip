@@ -124,17 +124,19 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
     const int nx = (int)a.n[0], ny = (int)a.n[1], nz = (int)a.n[2];
-    // storage: interior cells only, or (padded) the interior plus 2 exterior
-    // cells on each side of every active dimension
+    // storage: interior cells only, or (a view of a padded array) the n cells
+    // from storage cell voff of an array of extents vm, with the 2 cells
+    // around them read as ghosts
     constexpr bool PAD = LIM == LIM_THETA_PADDED;
     static_assert(!PAD || SOLVER != SOLVER_HLLC_SWITCH, "padded arrays take HLL or HLLC");
-    constexpr int OFFY = (PAD && ND >= 2) ? 2 : 0, OFFZ = (PAD && ND == 3) ? 2 : 0;
-    const int sx = PAD ? nx + 4 : nx;
-    const int plane = sx * (ny + 2 * OFFY);
-    // a coordinate's storage index: boundary-mapped, or (padded) shifted into
-    // the exterior and clamped to it (the unused columns of partial tiles)
-    auto smap = [&](int i, int n, int bclo, int bchi, bool &f) -> int {
-        if constexpr (PAD) return (i < -2 ? -2 : (i > n + 1 ? n + 1 : i)) + 2;
+    const int vx = PAD ? a.voff[0] : 0, vy = (PAD && ND >= 2) ? a.voff[1] : 0, vz = (PAD && ND == 3) ? a.voff[2] : 0;
+    const int sx = PAD ? a.vm[0] : nx;
+    const int plane = PAD ? a.vm[0] * a.vm[1] : nx * ny;
+    // a coordinate's storage index: boundary-mapped, or (a view) shifted by
+    // the view offset and clamped to the ghost layers (the unused columns of
+    // partial tiles)
+    auto smap = [&](int i, int n, int off, int bclo, int bchi, bool &f) -> int {
+        if constexpr (PAD) return (i < -2 ? -2 : (i > n + 1 ? n + 1 : i)) + off;
         return map32(i, n, bclo, bchi, f);
     };
     // XCD-aware tile order: consecutive workgroup ids are dealt round-robin
@@ -184,8 +186,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     for (int i = tid; i < WX + RY; i += NT) {
         bool f = false;
         int m = 0;
-        if (i < WX) m = smap(x0 + i - 2, nx, a.bc[0][0], a.bc[0][1], f);
-        else if (ND >= 2) m = smap(y0 + (i - WX) - 2, ny, a.bc[1][0], a.bc[1][1], f);
+        if (i < WX) m = smap(x0 + i - 2, nx, vx, a.bc[0][0], a.bc[0][1], f);
+        else if (ND >= 2) m = smap(y0 + (i - WX) - 2, ny, vy, a.bc[1][0], a.bc[1][1], f);
         sMap[i] = m | (f ? FLIP : 0);
     }
 
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const unsigned colo = (unsigned)((ym & IDX) * sx + (xm & IDX));
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own_valid = (gx < nx) && (gy < ny);
-    const unsigned colv = (unsigned)((gy + OFFY) * sx + gx + (PAD ? 2 : 0));
+    const unsigned colv = (unsigned)((gy + vy) * sx + gx + vx);
 
     // halo cells of this thread: plane offset, LDS slot, mirror flags
     unsigned hoff[HPT];
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         if constexpr (ND == 3) { if (fz) w[3] = -w[3]; }
     };
     auto zoff = [&](int z, bool &fz) -> unsigned {
-        if constexpr (ND == 3) return (unsigned)(smap(z, nz, a.bc[2][0], a.bc[2][1], fz) * plane);
+        if constexpr (ND == 3) return (unsigned)(smap(z, nz, vz, a.bc[2][0], a.bc[2][1], fz) * plane);
         return 0u;
     };
     auto face_state = [&](const T (&w)[NP], const T (&s)[NP], T h, T (&out)[NP]) {
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     // is not on the path to the first barrier of the plane
     T hnext[HPT][NP];
     auto load_halo = [&](int z, T (&h)[HPT][NP]) {
-        const unsigned zo = (ND == 3) ? (unsigned)(((z < nz ? z : nz - 1) + OFFZ) * plane) : 0u;
+        const unsigned zo = (ND == 3) ? (unsigned)(((z < nz ? z : nz - 1) + vz) * plane) : 0u;
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
             if (hlds[j] >= 0) load(zo + hoff[j], h[j]);
@@ -312,7 +314,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                     T (&Sk)[NP], T (&Sk1)[NP], T (&Flo)[NP], T (&Fhi)[NP]) {
         (void)Uk1;
         const int kz = z0 + it;
-        const unsigned zko = (ND == 3) ? (unsigned)((kz + OFFZ) * plane) : 0u;
+        const unsigned zko = (ND == 3) ? (unsigned)((kz + vz) * plane) : 0u;
         bool fz2 = false;
         if constexpr (ND == 3) load(zoff(kz + 2, fz2) + colo, U2);
         T u0[NP];  // U^n of the own cell (second stage), issued early, used in phase 3
