@@ -285,25 +285,12 @@ struct RefluxSet {
     double idq[3];
 };
 
-// Every dimension in one launch (blockIdx.y = Q): the cells corrected across
-// different faces of the box are disjoint.
+// Every parent cell of b (interior cell i, j, k) becomes the mean of its 2^ND
+// children, the child being a padded level (interior at offset NG).
 template <int ND, typename T>
-__global__ void __launch_bounds__(FB) k_reflux(T *u, Grid g, Box b, RefluxSet r)
+__device__ __forceinline__ void restrict_cell(T *parent, const Grid &pg, const Box &b, const T *child, const Grid &cg,
+                                              int i, int j, int k)
 {
-    const int q = blockIdx.y, t = blockIdx.x * FB + threadIdx.x;
-    if (q == 0) reflux_faces<ND, 0>(u, g, b, t, r.c[0][0], r.c[0][1], r.f[0][0], r.f[0][1], r.idq[0]);
-    if constexpr (ND >= 2)
-        if (q == 1) reflux_faces<ND, 1>(u, g, b, t, r.c[1][0], r.c[1][1], r.f[1][0], r.f[1][1], r.idq[1]);
-    if constexpr (ND >= 3)
-        if (q == 2) reflux_faces<ND, 2>(u, g, b, t, r.c[2][0], r.c[2][1], r.f[2][0], r.f[2][1], r.idq[2]);
-}
-
-template <int ND, typename T>
-__global__ void __launch_bounds__(FB) k_restrict(T *parent, Grid pg, Box b, const T *child, Grid cg)
-{
-    const int i = blockIdx.x * FB + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
-    if (i >= b.n[0]) return;
     const int64_t pc = at(pg, b.lo[0] + i, b.lo[1] + j, b.lo[2] + k);
     constexpr int NC = 1 << ND;
 #pragma unroll
@@ -318,6 +305,33 @@ __global__ void __launch_bounds__(FB) k_restrict(T *parent, Grid pg, Box b, cons
         }
         parent[v * pg.vs + pc] = (T)(sum / (double)NC);
     }
+}
+
+// The replacement and the restriction of one child box in one launch: the
+// first ND * rblocks blocks correct the cells just outside the box (rblocks
+// blocks per dimension Q), the rest restrict the cells under it, x fastest.
+// The two sets of cells are disjoint, and neither reads what the other writes.
+template <int ND, typename T>
+__global__ void __launch_bounds__(FB) k_reflux_restrict(T *u, Grid g, Box b, RefluxSet r, const T *child, Grid cg,
+                                                        int rblocks)
+{
+    const int bid = blockIdx.x;
+    if (bid < ND * rblocks) {
+        const int q = bid / rblocks, t = (bid - q * rblocks) * FB + threadIdx.x;
+        if (q == 0) reflux_faces<ND, 0>(u, g, b, t, r.c[0][0], r.c[0][1], r.f[0][0], r.f[0][1], r.idq[0]);
+        if constexpr (ND >= 2)
+            if (q == 1) reflux_faces<ND, 1>(u, g, b, t, r.c[1][0], r.c[1][1], r.f[1][0], r.f[1][1], r.idq[1]);
+        if constexpr (ND >= 3)
+            if (q == 2) reflux_faces<ND, 2>(u, g, b, t, r.c[2][0], r.c[2][1], r.f[2][0], r.f[2][1], r.idq[2]);
+        return;
+    }
+    const int64_t cell = (int64_t)(bid - ND * rblocks) * FB + threadIdx.x;
+    const int64_t nxy = (int64_t)b.n[0] * b.n[1];
+    if (cell >= nxy * b.n[2]) return;
+    const int k = (int)(cell / nxy);
+    const int rem = (int)(cell - (int64_t)k * nxy);
+    const int j = rem / b.n[0], i = rem - j * b.n[0];
+    restrict_cell<ND>(u, g, b, child, cg, i, j, k);
 }
 
 // Grid-stride over the box's cells; one atomic per block.
@@ -458,8 +472,9 @@ hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes
 }
 
 template <typename T>
-hipError_t launch_reflux(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
-                         const double *const fine[3][2], const double idq[3], hipStream_t s)
+hipError_t launch_reflux_restrict(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
+                                  const double *const fine[3][2], const double idq[3], const T *child, const Grid &cg,
+                                  hipStream_t s)
 {
     RefluxSet r{};
     int most = 0;
@@ -474,21 +489,17 @@ hipError_t launch_reflux(T *u, const Grid &g, const Box &child_box, int ndim, co
             most = std::max(most, child_box.n[r1] * child_box.n[r2]);
         }
     }
-    const dim3 grid((most + FB - 1) / FB, ndim);
-    if (ndim == 1) hipLaunchKernelGGL((k_reflux<1, T>), grid, dim3(FB), 0, s, u, g, child_box, r);
-    else if (ndim == 2) hipLaunchKernelGGL((k_reflux<2, T>), grid, dim3(FB), 0, s, u, g, child_box, r);
-    else hipLaunchKernelGGL((k_reflux<3, T>), grid, dim3(FB), 0, s, u, g, child_box, r);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_restrict(T *parent, const Grid &pg, const Box &child_box, const T *child, const Grid &cg, int ndim,
-                           hipStream_t s)
-{
-    const dim3 grid((child_box.n[0] + FB - 1) / FB, child_box.n[1], child_box.n[2]);
-    if (ndim == 1) hipLaunchKernelGGL((k_restrict<1, T>), grid, dim3(FB), 0, s, parent, pg, child_box, child, cg);
-    else if (ndim == 2) hipLaunchKernelGGL((k_restrict<2, T>), grid, dim3(FB), 0, s, parent, pg, child_box, child, cg);
-    else hipLaunchKernelGGL((k_restrict<3, T>), grid, dim3(FB), 0, s, parent, pg, child_box, child, cg);
+    const int rblocks = (most + FB - 1) / FB;
+    const int64_t cells = (int64_t)child_box.n[0] * child_box.n[1] * child_box.n[2];
+    const int64_t blocks = (int64_t)ndim * rblocks + (cells + FB - 1) / FB;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    if (ndim == 1)
+        hipLaunchKernelGGL((k_reflux_restrict<1, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks);
+    else if (ndim == 2)
+        hipLaunchKernelGGL((k_reflux_restrict<2, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks);
+    else
+        hipLaunchKernelGGL((k_reflux_restrict<3, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks);
     return hipGetLastError();
 }
 
@@ -523,9 +534,9 @@ hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const B
                                           const ClockOps &, hipStream_t);                                            \
     template hipError_t launch_box_flux<T>(const T *, const Grid &, int, const Box *, double *const(*)[3][2],        \
                                            const int *, int, int, T, T, T, T, const double *, hipStream_t);          \
-    template hipError_t launch_reflux<T>(T *, const Grid &, const Box &, int, const double *const[3][2],             \
-                                         const double *const[3][2], const double[3], hipStream_t);                   \
-    template hipError_t launch_restrict<T>(T *, const Grid &, const Box &, const T *, const Grid &, int, hipStream_t); \
+    template hipError_t launch_reflux_restrict<T>(T *, const Grid &, const Box &, int, const double *const[3][2],    \
+                                                  const double *const[3][2], const double[3], const T *,             \
+                                                  const Grid &, hipStream_t);                                        \
     template hipError_t launch_box_rate<T>(const T *, const Grid &, const Box &, int, T, T, const double[3],         \
                                            unsigned long long *, hipStream_t);                                       \
     template hipError_t launch_leaf_totals<T>(const T *, const Grid &, const Box &, const Box &, int, double,        \

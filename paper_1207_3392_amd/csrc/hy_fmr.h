@@ -92,20 +92,18 @@ hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes
                            const int *assign, int ndim, int solver, T gamma, T gm1, T inv_gm1, T theta,
                            const double *dt, hipStream_t s);
 
-// Coarse/fine replacement: every parent cell just outside the child box takes
-// (fine - coarse) / dq of the flux through its face into the box (sign by
-// side), the fine value being the mean over the 2^(d-1) child faces of the
-// child's accumulated boundary fluxes (layout of launch_box_flux over the
-// child's interior).
+// After the child's two steps, in one launch: the coarse/fine replacement
+// (every parent cell just outside child_box takes (fine - coarse) / dq of
+// the flux through its face into the box, sign by side, the fine value being
+// the mean over the 2^(d-1) child faces of the child's accumulated boundary
+// fluxes, layout of launch_box_flux over the child's interior) and the
+// restriction (every parent cell of child_box becomes the mean of its 2^d
+// children, the child being a padded level, interior at offset NG).  The two
+// touch disjoint parent cells.
 template <typename T>
-hipError_t launch_reflux(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
-                         const double *const fine[3][2], const double idq[3], hipStream_t s);
-
-// Every parent cell of child_box becomes the mean of its 2^d children, the
-// child being a padded level (interior at offset NG).
-template <typename T>
-hipError_t launch_restrict(T *parent, const Grid &pg, const Box &child_box, const T *child, const Grid &cg, int ndim,
-                           hipStream_t s);
+hipError_t launch_reflux_restrict(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
+                                  const double *const fine[3][2], const double idq[3], const T *child, const Grid &cg,
+                                  hipStream_t s);
 
 // max over the cells of box of (|v_q| + c_s) / dq into the FMR_RATE_SLOTS
 // words rate_bits (the bits of a positive double; unsigned atomic max).

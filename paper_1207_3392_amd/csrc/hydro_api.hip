@@ -1523,15 +1523,6 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
         if (e != hipSuccess) return e;
     }
     p->parity ^= 1;
-    if (child) {
-        const double *c[3][2], *fa[3][2];
-        for (int q = 0; q < 3; ++q)
-            for (int s = 0; s < 2; ++s) {
-                c[q][s] = L.coarse_acc[q][s];
-                fa[q][s] = f->lev[l + 1].own_acc[q][s];
-            }
-        e = hy::launch_reflux<T>(arrA<T>(L), L.g, L.child, nd, c, fa, L.idq, f->stream);
-    }
     return e;
 }
 
@@ -1592,8 +1583,15 @@ hy_status fmr_step_level(hy_fmr *f, int l)
     if (e != hipSuccess) return hip_fail(e, "prolongation and time step");
     e = fmr_level_step<T>(f, l, false);
     if (e == hipSuccess && l + 1 < f->nlev) {
+        // the coarse/fine flux replacement and the restriction of the child
         hy_fmr::Level &C = f->lev[l + 1];
-        e = hy::launch_restrict<T>(arrA<T>(L), L.g, L.child, arrA<T>(C), C.g, nd, f->stream);
+        const double *c[3][2], *fa[3][2];
+        for (int q = 0; q < 3; ++q)
+            for (int s = 0; s < 2; ++s) {
+                c[q][s] = L.coarse_acc[q][s];
+                fa[q][s] = C.own_acc[q][s];
+            }
+        e = hy::launch_reflux_restrict<T>(arrA<T>(L), L.g, L.child, nd, c, fa, L.idq, arrA<T>(C), C.g, f->stream);
     }
     if (e == hipSuccess) e = fmr_defer_advance(f, l);
     if (e != hipSuccess) return hip_fail(e, "level step");
