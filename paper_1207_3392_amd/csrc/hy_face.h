@@ -164,5 +164,58 @@ __device__ __forceinline__ void face_flux(const T (&wl)[ND + 2], const T (&wr)[N
     }
 }
 
+// ------------------------------------------------ box face fluxes ----
+
+__device__ __forceinline__ int64_t at(const Grid &g, int i, int j, int k)
+{
+    return ((int64_t)k * g.m[1] + j) * g.m[0] + i;
+}
+
+template <int ND, typename T>
+__device__ __forceinline__ void load_prim(const T *u, const Grid &g, int64_t c, T gm1, T (&w)[ND + 2])
+{
+    T uu[ND + 2];
+#pragma unroll
+    for (int v = 0; v < ND + 2; ++v) uu[v] = u[v * g.vs + c];
+    (void)to_prim<ND>(uu, w, gm1);
+}
+
+// The faces of one box normal to Q on one side (0: low, 1: high): one
+// thread per face position transverse to Q.
+template <int ND, int Q, int SOLVER, typename T>
+__device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &b, int t, int side, T gamma, T gm1,
+                                          T inv_gm1, T theta2, double w, bool assign, double *acc_lo, double *acc_hi)
+{
+    constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
+    const int faces = b.n[R1] * b.n[R2];
+    if (t >= faces) return;
+    const int t1 = t % b.n[R1], t2 = t / b.n[R1];
+    {
+        const int f = side == 0 ? b.lo[Q] : b.lo[Q] + b.n[Q];  // face between cells f - 1 and f
+        T w4[4][ND + 2];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            int c3[3];
+            c3[Q] = f - 2 + s;
+            c3[R1] = b.lo[R1] + t1;
+            c3[R2] = b.lo[R2] + t2;
+            load_prim<ND>(u, g, at(g, c3[0], c3[1], c3[2]), gm1, w4[s]);
+        }
+        T wl[ND + 2], wr[ND + 2], fl[ND + 2];
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) {
+            wl[v] = w4[1][v] + T(0.25) * slope2_mm(w4[0][v], w4[1][v], w4[2][v], theta2);
+            wr[v] = w4[2][v] - T(0.25) * slope2_mm(w4[1][v], w4[2][v], w4[3][v], theta2);
+        }
+        face_flux<ND, Q, SOLVER>(wl, wr, fl, gamma, inv_gm1, false);
+        double *acc = side == 0 ? acc_lo : acc_hi;
+#pragma unroll
+        for (int v = 0; v < ND + 2; ++v) {
+            double &a = acc[(int64_t)v * faces + t];
+            a = (assign ? 0.0 : a) + w * (double)fl[v];
+        }
+    }
+}
+
 }  // namespace
 }  // namespace hy

@@ -8,17 +8,14 @@
 // "box" arguments are cell ranges in the coordinates of the array they index.
 #pragma once
 
+#include "hy_internal.h"
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace hy {
 
 constexpr int FMR_NG = 2;
-
-struct Box {
-    int lo[3];  // first cell, array coordinates
-    int n[3];   // cells per dimension (1 along unused dimensions)
-};
 
 // A level's clock in device memory: its time, the step of its next full
 // step and of its next provisional half-step.  Kernels read their steps from
@@ -60,12 +57,6 @@ struct ClockOps {
     int op0, l0, op1, l1, nlev;
     unsigned long long *rate;
     double cfl, dt_fixed;
-};
-
-// Dense array extents and variable stride.
-struct Grid {
-    int m[3];
-    int64_t vs;
 };
 
 // Exterior of the padded level (fine) from its parent: each exterior cell at

@@ -37,6 +37,34 @@ enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
 // (dt_dev; the multilevel driver keeps each level's step there).
 enum { DT_HOST = 0, DT_DEVICE = 1, DT_PTR = 2 };
 
+// A box of cells of an array: first cell (array coordinates) and cells per
+// dimension (1 along unused dimensions).
+struct Box {
+    int lo[3];
+    int n[3];
+};
+
+// Dense array extents and variable stride.
+struct Grid {
+    int m[3];
+    int64_t vs;
+};
+
+// Face fluxes that a padded stage launch computes beside its cell update
+// (nbox = 0: none): for each of nbox boxes of the stage input, the fluxes
+// through its low and high faces along every active q from the input's
+// generalised-minmod face states, acc[k][q][side][v * faces + t] += dt / 2 *
+// F (= when assign[k] != 0), t over the box's cells transverse to q, the
+// lower transverse dimension fastest.  The launcher adds blocks workgroups
+// per (box, q, side) after the tile workgroups.
+struct BoxFluxes {
+    Box b[2];
+    double *acc[2][3][2];
+    int assign[2];
+    int nbox;
+    int blocks;
+};
+
 template <typename T>
 struct StageArgs {
     const T *uin;     // state read with the stencil (U^n in stage 1, U^(1) in stage 2)
@@ -58,6 +86,7 @@ struct StageArgs {
     double dt_host, cfl, t_end;
     const double *dt_dev;  // DT_PTR: the step
     int voff[3], vm[3];    // LIM_THETA_PADDED: first updated cell and extents of the storage
+    BoxFluxes bf;          // LIM_THETA_PADDED: face fluxes of the input computed in the same launch
 };
 
 struct LaunchCfg {

@@ -1514,6 +1514,21 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
             // fluxes afresh after the parent has consumed them
             if (kc >= 0) assign[kc] = stage == 1;
             if (ko >= 0) assign[ko] = stage == 1 && L.own_fresh;
+            if (l > 0) {
+                // a padded level's stage launch computes the box fluxes too
+                hy::StageArgs<T> a = stage_args<T>(p, stage, hy::DT_PTR, 0.0, 0.0, 0.0);
+                a.bf.nbox = nbox;
+                for (int k = 0; k < nbox; ++k) {
+                    a.bf.b[k] = boxes[k];
+                    a.bf.assign[k] = assign[k];
+                    for (int q = 0; q < 3; ++q)
+                        for (int sd = 0; sd < 2; ++sd) a.bf.acc[k][q][sd] = acc[k][q][sd];
+                }
+                e = hy::launch_stage<T>(nd, f->solver, stage, hy::LIM_THETA_PADDED, p->cfg, a, p->stream);
+                if (e != hipSuccess) return e;
+                L.own_fresh = false;
+                continue;
+            }
             e = hy::launch_box_flux<T>(u, L.g, nbox, boxes, acc, assign, nd, f->solver, gamma, gm1, igm1, theta, dt,
                                        f->stream);
             if (e != hipSuccess) return e;

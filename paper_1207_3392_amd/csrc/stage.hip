@@ -96,6 +96,32 @@ __device__ __forceinline__ T learned_slope(const StageArgs<T> &a, int q, int v, 
     return sgn * (T)base[c];
 }
 
+// The face-flux workgroups of a padded launch (see BoxFluxes): workgroup fid
+// after the tiles takes (box, q, side) = segment fid / blocks, NT faces of it.
+template <int ND, int SOLVER, int NT, typename T>
+__device__ __forceinline__ void stage_box_faces(const StageArgs<T> &a, int fid, int tid)
+{
+    const int seg = fid / a.bf.blocks;
+    const int t = (fid - seg * a.bf.blocks) * NT + tid;
+    const int side = seg & 1, bq = seg >> 1, k = bq / ND, q = bq - k * ND;
+    const Grid g{{a.vm[0], a.vm[1], a.vm[2]}, a.vstride};
+    const Box &b = a.bf.b[k];
+    const double w = 0.5 * *a.dt_dev;
+    const T theta2 = T(2) * a.theta;
+    const bool as = a.bf.assign[k] != 0;
+    if (q == 0)
+        box_faces<ND, 0, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, theta2, w, as, a.bf.acc[k][0][0],
+                                 a.bf.acc[k][0][1]);
+    if constexpr (ND >= 2)
+        if (q == 1)
+            box_faces<ND, 1, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, theta2, w, as,
+                                     a.bf.acc[k][1][0], a.bf.acc[k][1][1]);
+    if constexpr (ND >= 3)
+        if (q == 2)
+            box_faces<ND, 2, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, theta2, w, as,
+                                     a.bf.acc[k][2][0], a.bf.acc[k][2][1]);
+}
+
 // At least 4 waves per SIMD: the LDS plane tile admits two 512-thread
 // workgroups per CU, so registers beyond 128 per lane would only cost occupancy.
 template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BX, int BY>
@@ -129,6 +155,14 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     // around them read as ghosts
     constexpr bool PAD = LIM == LIM_THETA_PADDED;
     static_assert(!PAD || SOLVER != SOLVER_HLLC_SWITCH, "padded arrays take HLL or HLLC");
+    if constexpr (PAD) {
+        // the workgroups after the tiles compute box face fluxes (whole
+        // workgroups, before any barrier)
+        if ((int)blockIdx.x >= a.ntiles) {
+            stage_box_faces<ND, SOLVER, NT>(a, (int)blockIdx.x - a.ntiles, tid);
+            return;
+        }
+    }
     const int vx = PAD ? a.voff[0] : 0, vy = (PAD && ND >= 2) ? a.voff[1] : 0, vz = (PAD && ND == 3) ? a.voff[2] : 0;
     const int sx = PAD ? a.vm[0] : nx;
     const int plane = PAD ? a.vm[0] * a.vm[1] : nx * ny;
@@ -622,7 +656,22 @@ hipError_t launch_one(const LaunchCfg &cfg, StageArgs<T> a, hipStream_t s)
     a.tiles_y = ND >= 2 ? (int)((a.n[1] + BY - 1) / BY) : 1;
     const int chunks = ND == 3 ? (int)((a.n[2] + cfg.zchunk - 1) / cfg.zchunk) : 1;
     a.ntiles = a.tiles_x * a.tiles_y * chunks;
-    hipLaunchKernelGGL((k_stage<ND, T, SOLVER, STAGE, LIM, BX, BY>), dim3((unsigned)a.ntiles), dim3(BX, BY, 1), 0, s, a);
+    int64_t blocks = a.ntiles;
+    if constexpr (LIM == LIM_THETA_PADDED) {
+        if (a.bf.nbox > 0) {
+            if (a.bf.nbox > 2 || a.dt_mode != DT_PTR || !a.dt_dev) return hipErrorInvalidValue;
+            int most = 0;
+            for (int k = 0; k < a.bf.nbox; ++k)
+                for (int q = 0; q < ND; ++q) {
+                    const int r1 = q == 0 ? 1 : 0, r2 = q == 2 ? 1 : 2;
+                    most = most > a.bf.b[k].n[r1] * a.bf.b[k].n[r2] ? most : a.bf.b[k].n[r1] * a.bf.b[k].n[r2];
+                }
+            a.bf.blocks = (most + BX * BY - 1) / (BX * BY);
+            blocks += (int64_t)a.bf.nbox * ND * 2 * a.bf.blocks;
+        }
+    }
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stage<ND, T, SOLVER, STAGE, LIM, BX, BY>), dim3((unsigned)blocks), dim3(BX, BY, 1), 0, s, a);
     return hipGetLastError();
 }
 
