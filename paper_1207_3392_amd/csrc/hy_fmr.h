@@ -71,7 +71,8 @@ hipError_t launch_prolong(T *fine, T *fine2, const Grid &fg, const T *parent, co
                           int ndim, T gamma, T gm1, const ClockOps &ck, hipStream_t s);
 
 // Fluxes through the low and high faces of each of nbox (1 or 2) boxes of
-// the array u along every active q, from its generalised-minmod face states
+// the array u along every active q (the unpadded coarsest level; a padded
+// level's stage launch computes the same fluxes in workgroups of its own), from its generalised-minmod face states
 // (a box needs two cells of u beyond each face), in one launch:
 // acc[k][q][side][v * faces + t] += w * F for box k (= w * F when
 // assign[k] != 0), w = *dt / 2 (a stage's share of the step), t running
