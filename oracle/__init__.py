@@ -37,10 +37,11 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain -O2, no FP contraction)."""
+    """Compile liboracle.so with gcc (plain -O2, no FP contraction; OpenMP over
+    independent loops, bitwise the same result on any thread count)."""
     src = os.path.join(_HERE, "hydro_oracle.c")
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-shared", "-fPIC",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fopenmp", "-Wall", "-shared", "-fPIC",
                "-o", LIB_PATH, src, "-lm"]
         subprocess.check_call(cmd)
     return LIB_PATH
@@ -107,12 +108,19 @@ def lib():
             ("orc_fmr_restrict", [ctypes.POINTER(_FmrDesc), ctypes.c_int, dp, dp], ctypes.c_int),
             ("orc_fmr_step", [ctypes.POINTER(_FmrDesc), ctypes.POINTER(dp), ctypes.c_double, ctypes.c_double, dp],
              ctypes.c_int),
+            ("orc_set_threads", [ctypes.c_int], ctypes.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Host threads the oracle's parallel loops use (n <= 0 keeps the current
+    setting); returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _dp(a: np.ndarray):

@@ -3,12 +3,20 @@
  * INFRASTRUCTURE ONLY (see hydro_oracle.h).  Plain loops, one step of the
  * method at a time, separate arrays for every intermediate; no blocking,
  * fusion or reordering beyond what the paper's equations state.
+ *
+ * Loops whose iterations are independent (cells, and lines of cells along a
+ * dimension) may run on several host threads (OpenMP); every iteration does
+ * the same arithmetic whatever the thread count, so results are bitwise the
+ * same on one thread or many.
  */
 #include "hydro_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NG 2 /* ghost layers: the 3-cell generalised-minmod and the 5-cell learned stencil */
 
@@ -17,6 +25,17 @@ static int nvars(const orc_desc *d) { return d->ndim + 2; }
 static int64_t ncells(const orc_desc *d) { return d->n[0] * d->n[1] * d->n[2]; }
 
 static double cell_width(const orc_desc *d, int q) { return (d->hi[q] - d->lo[q]) / (double)d->n[q]; }
+
+int orc_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
 
 static int valid_desc(const orc_desc *d)
 {
@@ -358,19 +377,23 @@ static int fill_primitives(const orc_desc *d, const double *U, const double *Uex
     int nd = d->ndim, nv = nvars(d);
     int64_t N = ncells(d), M = G->m[0] * G->m[1] * G->m[2];
     int status = ORC_OK;
-    double u[5], w[5];
+#pragma omp parallel for schedule(static) reduction(min : status)
     for (int64_t k = 0; k < d->n[2]; ++k)
         for (int64_t j = 0; j < d->n[1]; ++j)
             for (int64_t i = 0; i < d->n[0]; ++i) {
+                double u[5], w[5];
                 int64_t c = (k * d->n[1] + j) * d->n[0] + i;
                 for (int v = 0; v < nv; ++v) u[v] = U[v * N + c];
                 if (!cons_to_prim_1(nd, d->gamma, u, w)) status = ORC_ESTATE;
                 int64_t g = gidx(G, i, j, k);
                 for (int v = 0; v < nv; ++v) Wg[v * M + g] = w[v];
             }
+    /* ghosts read interior cells only, so the planes are independent */
+#pragma omp parallel for schedule(static) reduction(min : status)
     for (int64_t k = -G->g[2]; k < d->n[2] + G->g[2]; ++k)
         for (int64_t j = -G->g[1]; j < d->n[1] + G->g[1]; ++j)
             for (int64_t i = -G->g[0]; i < d->n[0] + G->g[0]; ++i) {
+                double u[5], w[5];
                 int inside = i >= 0 && i < d->n[0] && j >= 0 && j < d->n[1] && k >= 0 && k < d->n[2];
                 if (inside) continue;
                 if (Uext) {
@@ -474,6 +497,7 @@ static int rhs_core(const orc_desc *d, const double *U, const double *Uext, doub
     int status = fill_primitives(d, U, Uext, &G, Wg);
 
     /* sources: S = (0, rho a, rho v . a) for a uniform acceleration a */
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < N; ++c) {
         L[c] = 0.0;
         double power = 0.0;
@@ -487,12 +511,16 @@ static int rhs_core(const orc_desc *d, const double *U, const double *Uext, doub
     for (int q = 0; q < nd; ++q) {
         int64_t nq = d->n[q];
         double dq = cell_width(d, q);
-        /* one line along q at a time; the line holds cells -NG .. nq+NG-1 */
+        /* one line along q at a time; the line holds cells -NG .. nq+NG-1.
+         * Lines are independent (each writes L only at its own cells). */
         int64_t len = nq + 2 * NG;
+        int64_t t1n = d->n[(q + 1) % 3], t2n = d->n[(q + 2) % 3];
+#pragma omp parallel
+        {
         double *wl = (double *)malloc(sizeof(double) * nv * len);
         double *sig = (double *)malloc(sizeof(double) * nv * (nq + 2)); /* cells -1 .. nq */
         double *F = (double *)malloc(sizeof(double) * nv * (nq + 1));   /* faces -1/2 .. nq-1/2 */
-        int64_t t1n = d->n[(q + 1) % 3], t2n = d->n[(q + 2) % 3];
+#pragma omp for collapse(2) schedule(static)
         for (int64_t b = 0; b < t2n; ++b)
             for (int64_t a = 0; a < t1n; ++a) {
                 int64_t idx3[3];
@@ -583,6 +611,7 @@ static int rhs_core(const orc_desc *d, const double *U, const double *Uext, doub
         free(wl);
         free(sig);
         free(F);
+        }
     }
     free(Wg);
     return status;
@@ -601,11 +630,13 @@ int orc_step(const orc_desc *d, double *U, double dt)
     double *K1 = (double *)malloc(sizeof(double) * T);
     double *U1 = (double *)malloc(sizeof(double) * T);
     int s1 = orc_rhs(d, U, L);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < T; ++i) {
         K1[i] = dt * L[i];
         U1[i] = U[i] + K1[i];
     }
     int s2 = orc_rhs(d, U1, L);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < T; ++i) {
         double K2 = dt * L[i];
         U[i] = U[i] + 0.5 * (K1[i] + K2);

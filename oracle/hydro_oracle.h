@@ -151,6 +151,11 @@ int orc_fmr_restrict(const orc_fmr_desc *f, int l, const double *Uchild, double 
  * coarse step. */
 int orc_fmr_step(const orc_fmr_desc *f, double *const *U, double cfl, double dt_fixed, double *dt_out);
 
+/* Host threads for the loops with independent iterations (nthreads <= 0:
+ * keep the current count); returns the count in effect (1 without OpenMP).
+ * Results do not depend on it. */
+int orc_set_threads(int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

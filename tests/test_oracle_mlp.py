@@ -118,3 +118,59 @@ def test_flat_stencils_give_zero_inputs_and_slope():
         assert oracle.limiter_learned(P, w) == 0.0
         x, s, _ = mlp.stencil_features(w[None, :])
         assert s[0] > 0.0 and np.all(x == 0.0)
+
+
+# ------------------------------------------------------------- Adam ----
+# Kingma & Ba, "Adam: a method for stochastic optimization" (2015), Alg. 1:
+# m_t = b1 m + (1 - b1) g, v_t = b2 v + (1 - b2) g^2, mh = m_t / (1 - b1^t),
+# vh = v_t / (1 - b2^t), p -= lr mh / (sqrt(vh) + eps).
+
+
+def test_adam_first_step_from_zero_moments_is_normalised_gradient():
+    """From zero moments the bias corrections give mh = g and vh = g^2, so the
+    first update is -lr g / (|g| + eps) element by element."""
+    rng = np.random.default_rng(21)
+    P = rng.normal(size=mlp.NPARAM)
+    g = rng.normal(size=mlp.NPARAM) * 10.0 ** rng.uniform(-6, 2, size=mlp.NPARAM)
+    lr = 3e-3
+    P1, m, v = mlp.adam(P, g, np.zeros_like(P), np.zeros_like(P), 1, lr=lr)
+    assert np.allclose(P1 - P, -lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+    assert np.allclose(m, 0.1 * g, rtol=1e-15) and np.allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_every_step_by_the_same_amount():
+    """With a constant gradient the bias-corrected moments equal g and g^2 at
+    every step t, so each step moves by -lr g / (|g| + eps); a wrong
+    step count in the bias correction breaks this from the second step on."""
+    g = np.array([2.0, -0.5, 1e-3, -7.0])
+    P = np.zeros(4)
+    m, v = np.zeros(4), np.zeros(4)
+    for t in range(1, 30):
+        P2, m, v = mlp.adam(P, g, m, v, t, lr=1e-2)
+        assert np.allclose(P2 - P, -1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-10), t
+        P = P2
+
+
+def test_adam_two_steps_hand_computed():
+    """Gradients 1 then -2 on one parameter, lr 0.1: m2 = 0.9 * 0.1 - 0.2 =
+    -0.11, v2 = 0.999 * 0.001 + 0.004 = 0.004999, mh = -0.11 / 0.19,
+    vh = 0.004999 / 0.001999; the two updates are -0.1 / (1 + 1e-8) and
+    0.1 * (0.11 / 0.19) / (sqrt(0.004999 / 0.001999) + 1e-8)."""
+    from fractions import Fraction as F
+    import math
+
+    m1, v1 = F(1, 10), F(1, 1000)
+    m2 = F(9, 10) * m1 + F(1, 10) * (-2)
+    v2 = F(999, 1000) * v1 + F(1, 1000) * 4
+    assert m2 == F(-11, 100) and v2 == F(4999, 1000000)
+    mh = m2 / (1 - F(9, 10) ** 2)
+    vh = v2 / (1 - F(999, 1000) ** 2)
+    step1 = -0.1 / (1.0 + 1e-8)
+    step2 = -0.1 * float(mh) / (math.sqrt(float(vh)) + 1e-8)
+    P = np.array([0.5])
+    P1, m, v = mlp.adam(P, np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=0.1)
+    assert P1[0] == pytest.approx(0.5 + step1, rel=1e-15)
+    P2, m, v = mlp.adam(P1, np.array([-2.0]), m, v, 2, lr=0.1)
+    assert m[0] == pytest.approx(-0.11, rel=1e-14) and v[0] == pytest.approx(0.004999, rel=1e-14)
+    assert P2[0] == pytest.approx(0.5 + step1 + step2, rel=1e-14)
+    assert step2 > 0.0  # the second gradient reverses the motion

@@ -355,6 +355,44 @@ def test_gravity_source_balances_hydrostatic_pressure():
         assert np.max(np.abs(oracle.rhs(d_bad, oracle.prim_to_cons(d_bad, W))[1, 2:-2])) > 0.2
 
 
+def test_gravity_source_uniform_free_fall_closed_form():
+    """A uniform state on a periodic box under a constant acceleration a has
+    no flux divergence, so the balance law reduces to dS/dt = rho a and
+    dG/dt = S . a (the source (0, rho a, rho v . a) of Sec. 4.3.2).  The
+    momentum grows linearly and the energy quadratically; Heun's method
+    integrates polynomials of degree two exactly, so after any number of
+    steps S = S0 + rho a t and G = G0 + (S0 . a) t + rho |a|^2 t^2 / 2 to
+    rounding.  A dropped, mis-signed or mis-scaled energy term (rho v . a)
+    fails the energy check; using the step's initial S in both stages loses
+    the t^2 term."""
+    rho, p, gamma = 1.7, 0.9, 1.4
+    for ndim in (1, 2, 3):
+        n = (6, 5, 4)[:ndim] + (1,) * (3 - ndim)
+        a = np.array((0.3, -0.2, 0.5)[:ndim])
+        v0 = np.array((0.4, -0.1, 0.25)[:ndim])
+        assert abs(v0 @ a) > 0.1
+        N = int(np.prod(n))
+        W = np.zeros((ndim + 2, N))
+        W[0], W[1:1 + ndim], W[-1] = rho, v0[:, None], p
+        for solver in (oracle.HLL, oracle.HLLC):
+            d = oracle.Desc(ndim, n, (0, 0, 0), (1, 1, 1), gamma, ((0, 0),) * 3, solver=solver, theta=2.0,
+                            accel=tuple(a) + (0.0,) * (3 - ndim))
+            U0 = oracle.prim_to_cons(d, W)
+            S0, G0 = rho * v0, U0[-1, 0]
+            U, dt = U0, 0.013
+            for k in range(1, 8):
+                U = oracle.step(d, U, dt)
+                t = k * dt
+                S_want = S0 + rho * a * t
+                G_want = G0 + (S0 @ a) * t + 0.5 * rho * (a @ a) * t * t
+                assert np.max(np.abs(U[0] - rho)) <= 1e-15
+                assert np.max(np.abs(U[1:1 + ndim] - S_want[:, None])) <= 1e-14, (ndim, solver, k)
+                assert np.max(np.abs(U[-1] - G_want)) <= 1e-14 * G_want, (ndim, solver, k)
+            # the energy the source adds over the run differs from zero by
+            # far more than the tolerance, so the check sees the term
+            assert abs(U[-1, 0] - G0) > 1e-3
+
+
 # ---------------------------------------------------------------- dt ----
 
 def test_cfl_dt_uniform_state_closed_form():
@@ -520,3 +558,22 @@ def test_switch_equals_hllc_without_shocks_and_on_planar_shocks():
         assert np.allclose(U1, U2, rtol=1e-13, atol=1e-13 * np.abs(U).max())
         U = U1
     assert oracle.shock_bits(d2, U).any()
+
+
+def test_oracle_threads_give_bitwise_identical_steps():
+    """The oracle's parallel loops have independent iterations: one thread
+    and several give the same bits (3D HLLC with gravity and walls, and the
+    learned limiter in 2D)."""
+    prob = wl.rayleigh_taylor_3d(12)
+    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+    U0 = oracle.prim_to_cons(d, prob.flat())
+    before = oracle.set_threads()
+    try:
+        out = []
+        for nt in (1, 4):
+            oracle.set_threads(nt)
+            U = oracle.run_steps(d, U0.copy(), 3, 0.3)
+            out.append(U)
+        assert np.array_equal(out[0], out[1])
+    finally:
+        oracle.set_threads(before)
