@@ -1,6 +1,6 @@
 """Benchmark: zone-updates/s of the two-stage finite-volume step on one MI355X.
 
-Workload: the 3D periodic smooth-flow patch (256^3 cells on the unit cube,
+Workload: the 3D periodic smooth-flow patch (512^3 cells on the unit cube,
 gamma = 5/3, rho = 1 + 0.2 x mean of 8 random-phase modes with |k| <= 4,
 p = 1, velocities 0.1 x mean of 8 modes each, seed 1207), FP32 state and
 fluxes, HLLC flux, monotonized-central limiter (theta = 2), C_CFL = 0.4.
@@ -8,12 +8,18 @@ One step = both Runge-Kutta stages with the CFL time step chosen on the
 device from the rate the previous second stage reduced (no host round trip),
 i.e. primitive recovery, ghost mapping, slopes, face states, Riemann fluxes,
 divergence, Runge-Kutta combination and the dt min-reduction.  The state is
-resident in HBM before timing starts.
+resident in HBM before timing starts; the K timed steps are one replay of a
+HIP graph captured beforehand, with HIP events around every stage launch
+inside it (recorded on the stream the kernels run on).
 
-Prints one JSON line.  Extra fields report the HLL run, a 512^3 patch, the
-512 batched tubes, 2D Kelvin-Helmholtz and 3D Rayleigh-Taylor with the plain
-and the learned limiter, the two limiters compared at matched L1, the
-per-kernel roofline and the FP64 CPU oracle timed on a bounded sample.
+Prints one JSON line.  The roofline is the HBM roofline of the dominant
+stage kernel (algorithmic bytes per launch over its mean event-timed
+duration, against 8 TB/s), with its FP32 vector-ALU view beside it.  Extra
+fields report the 256^3 patch with HLL and HLLC, the shock switch, the 512
+batched tubes, the multilevel runs, 2D Kelvin-Helmholtz and 3D
+Rayleigh-Taylor with the plain and the learned limiter, and the two limiters
+compared at matched L1.  cpu_baseline times the FP64 CPU oracle on a bounded
+sample on all host threads and on one.
 """
 import argparse
 import json
@@ -28,10 +34,11 @@ METRIC = "zone-updates/s per RK2 step and % HBM roofline; plain vs learned limit
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {1: 40.0, 2: 60.0}  # stage 1 reads U^n, writes U1; stage 2 reads U1, U^n, writes U^{n+1} (5 FP32 vars)
 
-# The stage kernels are bound by vector-ALU issue, not by HBM, so the roofline
-# is the FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed
+# The FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed
 # FP32) x 2.4 GHz.  Packed FP32 is switched off in the library, which halves
-# what the kernels can reach (78.6 TFLOP/s).
+# what the kernels can reach (78.6 TFLOP/s); the stage kernels issue about as
+# many vector instructions as the method has operations, so this side view
+# shows how close they run to the issue limit.
 ALU_PEAK_TFLOPS = 157.3
 ALU_PEAK_UNPACKED_TFLOPS = 78.6
 # Algorithmic FP32 operations per cell and stage of the 3D method (each add,
@@ -69,10 +76,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--eager", action="store_true", help="launch the timed steps one by one instead of as a graph")
     ap.add_argument("--solver", default="hllc", choices=["hll", "hllc"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the HLL and 512^3 extra runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every extra workload")
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
                                                    "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch",
@@ -95,7 +103,7 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
-def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4):
+def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4, graph=True):
     import torch
 
     from paper_1207_3392_amd import hydro
@@ -103,28 +111,50 @@ def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4):
 
     prob = wl.smooth_periodic_3d(n)
     p = hydro.Patch(prob, precision=32)
+    del prob
     cfg = p.kernel_config()
     sv = {"hll": hydro.HLL, "hllc": hydro.HLLC, "hllc_switch": hydro.HLLC_SWITCH}[solver]
     p.advance(warmup, cfl, solver=sv)
     torch.cuda.synchronize()
-    p.set_timing(timing)
+    p.set_timing(timing and not graph)
+    if graph:  # capture outside the timed region
+        p.advance_graph(steps, cfl, solver=sv, prepare_only=True)
     p.kernel_times()  # reset
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    p.advance(steps, cfl, solver=sv)
+    ev0.record()  # the patch stream is torch's current stream
+    if graph:
+        p.advance_graph(steps, cfl, solver=sv)
+    else:
+        p.advance(steps, cfl, solver=sv)
+    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    event_ms = ev0.elapsed_time(ev1)
+    if graph and timing:
+        # per-kernel durations: HIP events cannot be recorded inside a
+        # captured graph here, so the same steps run once more launch by
+        # launch, each stage kernel bracketed by events on the patch stream
+        p.set_timing(True)
+        p.kernel_times()
+        p.advance(steps, cfl, solver=sv)
     ms, launches = p.kernel_times()
     p.cfl_dt(cfl)  # raises if the state went non-physical
     ncell = n ** 3
+    stage_ms = [float(ms[0] / max(launches[0], 1)), float(ms[1] / max(launches[1], 1))]
     res = {
         "wall_s": wall,
         "ms_per_step": 1e3 * wall / steps,
         "zone_updates_per_s": ncell * steps / wall,
         "kernel": cfg,
-        "stage_ms": [float(ms[0] / max(launches[0], 1)), float(ms[1] / max(launches[1], 1))],
+        "stage_ms": stage_ms,
+        "event_ms_per_step": event_ms / steps,
         "ncell": ncell,
         "solver": solver,
+        "launch": "graph" if graph else "eager",
+        "kernel_timing": ("eager pass of the same steps right after the graph-timed replay" if graph
+                          else "the timed launches"),
     }
     p.close()
     del p
@@ -293,8 +323,10 @@ def matched_l1(cost_ratio_2d=None):
 
 
 def roofline(res):
-    """ALU roofline of the dominant stage kernel, with its HBM fraction beside it
-    (algorithmic bytes per launch over the same HIP-event duration)."""
+    """HBM roofline of the dominant stage kernel: algorithmic bytes per launch
+    (the state passes the stage must make, 40 B per cell for the first stage
+    and 60 B for the second in 3D FP32) over its mean HIP-event duration,
+    against 8 TB/s; the FP32 vector-ALU view of the same launches beside it."""
     ncell = res["ncell"]
     # dominant kernel: the stage with the larger mean duration
     k = 1 if res["stage_ms"][1] >= res["stage_ms"][0] else 0
@@ -305,36 +337,65 @@ def roofline(res):
     gbs = bytes_ / dur_s / 1e9
     traffic = measured_traffic(res, k)
     return {
-        "bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
+        "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
         "kernel": f"stage {k + 1}", "mean_ms": round(res["stage_ms"][k], 4),
-        "algorithmic_flops_per_launch": flops,
-        "frac_of_unpacked_fp32_peak": round(tflops / ALU_PEAK_UNPACKED_TFLOPS, 4),
-        "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": bytes_,
-                "measured_gbs": round(traffic / dur_s / 1e9, 1) if traffic else None},
+        "kernel_timing": res.get("kernel_timing"),
+        "algorithmic_bytes_per_launch": bytes_,
+        "measured_gbs": round(traffic / dur_s / 1e9, 1) if traffic else None,
+        "alu": {"achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "algorithmic_flops_per_launch": flops,
+                "frac_of_unpacked_fp32_peak": round(tflops / ALU_PEAK_UNPACKED_TFLOPS, 4)},
     }
 
 
-def cpu_baseline(budget_s=12.0):
-    import numpy as np
+def host_cpus():
+    """Host CPU description: usable threads and the model name."""
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
+
+def cpu_baseline(budget_s=10.0):
+    """The FP64 oracle on the same periodic smooth flow (a bounded sample:
+    a 96^3 patch on all usable host threads, a 48^3 patch on one), stepped
+    with its own CFL time step for about budget_s each."""
     import oracle
     from paper_1207_3392_amd import workloads as wl
 
     oracle.build()
-    n = 48
-    prob = wl.smooth_periodic_3d(n)
-    d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
-    U = oracle.prim_to_cons(d, prob.flat())
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        U = oracle.step(d, U, oracle.cfl_dt(d, U, 0.4))
-        steps += 1
-    wall = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / wall, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n}^3 patch of the same periodic smooth flow, {steps} steps (FP64, single thread)"}
+    cpus = host_cpus()
+
+    def run(n, threads):
+        used = oracle.set_threads(threads)
+        prob = wl.smooth_periodic_3d(n)
+        d = oracle.Desc.from_problem(prob, solver=oracle.HLLC)
+        U = oracle.prim_to_cons(d, prob.flat())
+        U = oracle.step(d, U, oracle.cfl_dt(d, U, 0.4))  # warm-up
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            U = oracle.step(d, U, oracle.cfl_dt(d, U, 0.4))
+            steps += 1
+        wall = time.perf_counter() - t0
+        return n ** 3 * steps / wall, steps, used
+
+    threads = max(1, min(cpus["nproc"] or 1, int(cpus["omp_num_threads"] or 0) or 1 << 30))
+    v_all, s_all, used = run(96, threads)
+    v_one, s_one, _ = run(48, 1)
+    return {"value": v_all, "unit": "zone-updates/s", "cores": used, "kind": "oracle",
+            "sample": f"96^3 patch of the same periodic smooth flow, {s_all} steps (FP64, {used} threads, OpenMP "
+                      f"over independent cells and lines); one thread: 48^3, {s_one} steps",
+            "one_core": {"value": v_one, "cores": 1}, "host": cpus}
 
 
 def main():
@@ -365,7 +426,7 @@ def main():
         print(json.dumps({args.only: run()}), flush=True)
         return
 
-    main_res = time_patch(args.n, args.solver, args.steps, args.warmup)
+    main_res = time_patch(args.n, args.solver, args.steps, args.warmup, graph=not args.eager)
     extra = {}
     if not args.no_extra:
         def guarded(name, fn):
@@ -376,33 +437,28 @@ def main():
             except Exception as e:  # noqa: BLE001
                 extra[name] = {"error": f"{type(e).__name__}: {e}"}
 
-        def other_solver():
-            # HLL at C = 0.3: with the minimum over dimensions in the CFL
-            # condition, C = 0.4 in 3D amplifies roundoff, and the more
-            # diffusive HLL flux breaks down after about 70 steps of this flow
-            # in FP32 (HLLC stays physical); the cost per step does not depend on C
-            other = "hll" if args.solver == "hllc" else "hllc"
-            r = time_patch(args.n, other, args.steps, args.warmup, cfl=0.3)
-            return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
-                    "stage_ms": r["stage_ms"], "cfl": 0.3}
+        def patch(n, solver, cfl, steps=args.steps):
+            r = time_patch(n, solver, steps, args.warmup, cfl=cfl)
+            out = {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
+                   "stage_ms": r["stage_ms"], "cfl": cfl}
+            if solver in ("hll", "hllc"):
+                out["roofline"] = roofline(r)
+            return out
 
-        def big():
-            r = time_patch(512, args.solver, 20, 3)
-            return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
-                    "stage_ms": r["stage_ms"], "roofline": roofline(r)}
-
-        guarded(f"{'hll' if args.solver == 'hllc' else 'hllc'}_{args.n}", other_solver)
-        guarded(f"{args.solver}_512", big)
-
-        def switch():
-            # HLLC with HLL at faces transverse to shocks: the shock-flag pass
-            # runs before each stage (this flow has no shocks, so every face
-            # still takes HLLC; the cost is the flags and the switch kernels)
-            r = time_patch(args.n, "hllc_switch", args.steps, args.warmup)
-            return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
-                    "stage_ms": r["stage_ms"]}
-
-        guarded(f"hllc_switch_{args.n}", switch)
+        # HLL at C = 0.3: with the minimum over dimensions in the CFL
+        # condition, C = 0.4 in 3D amplifies roundoff, and the more diffusive
+        # HLL flux breaks down after about 70 steps of this flow in FP32 (HLLC
+        # stays physical); the cost per step does not depend on C
+        other = "hll" if args.solver == "hllc" else "hllc"
+        guarded(f"{other}_{args.n}", lambda: patch(args.n, other, 0.3 if other == "hll" else 0.4))
+        # the smooth-flow configuration at 256^3, both solvers, 100 steps
+        guarded("hllc_256", lambda: patch(256, "hllc", 0.4, 100))
+        guarded("hll_256", lambda: patch(256, "hll", 0.3, 100))
+        # HLLC with HLL at faces transverse to shocks (this flow has no
+        # shocks, so every face still takes HLLC; the cost is the detector
+        # and the switch kernels)
+        guarded(f"hllc_switch_{args.n}", lambda: patch(args.n, "hllc_switch", 0.4))
+        guarded("hllc_switch_256", lambda: patch(256, "hllc_switch", 0.4, 100))
         guarded("batched_tubes", time_batch)
         guarded("fmr_sedov3d", time_fmr)
         guarded("fmr_sedov2d_7levels", lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1))
@@ -428,9 +484,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D periodic smooth flow {args.n}^3, gamma 5/3, {args.solver.upper()}, "
                                f"MC limiter, C_CFL 0.4, device-side dt", "cells": main_res["ncell"],
-                   "kernel": main_res["kernel"]},
+                   "kernel": main_res["kernel"], "launch": main_res["launch"]},
         "roofline": roofline(main_res),
         "stage_ms": main_res["stage_ms"],
+        "event_ms_per_step": main_res["event_ms_per_step"],
         "extra": extra,
     }
     if not args.no_cpu:

@@ -131,6 +131,21 @@ hy_status hy_cfl_dt(hy_patch *p, double cfl, double *dt_out);
  * t_end the remaining steps leave the state unchanged.  Asynchronous. */
 hy_status hy_advance(hy_patch *p, int nsteps, double cfl, double t_end, int solver);
 
+/* The same nsteps device-dt steps as hy_advance, enqueued on the patch
+ * stream as one HIP graph launch (the stage launches of every step only: no
+ * memset, no event, no host wait).  The graph is captured on a private
+ * stream of the library, instantiated, and kept per starting parity of the
+ * patch's two state buffers; it is captured again when nsteps, cfl, t_end,
+ * solver or the launch shape differ from the kept one.
+ * hy_advance_graph_prepare does the capture alone (nothing runs, the state
+ * is untouched), so a caller can keep it out of a timed region.  The
+ * per-kernel timing of hy_set_timing covers launches outside graphs only
+ * (a caller times a replay with its own events around it).  Refined
+ * multilevel levels are rejected (HY_EUNSUPPORTED).  Results equal
+ * hy_advance's bit for bit.  Asynchronous (apart from the capture). */
+hy_status hy_advance_graph_prepare(hy_patch *p, int nsteps, double cfl, double t_end, int solver);
+hy_status hy_advance_graph(hy_patch *p, int nsteps, double cfl, double t_end, int solver);
+
 /* Simulation time accumulated by hy_step / hy_advance since hy_set_state.
  * Synchronising. */
 hy_status hy_get_time(hy_patch *p, double *t_out);

@@ -16,7 +16,7 @@ hipError_t launch_samples(const float *Wc, const float *sub, int ndim, const int
                           hipStream_t s);
 hipError_t launch_train_grad(const MlpDevice *m, const float *x, const float *t, const int *idx, int64_t batch,
                              float *partial, float *loss_partial, int nblocks, float *grad, float *loss, hipStream_t s);
-hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, float b1, float b2, float eps,
-                       int step, hipStream_t s);
+hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, double b1, double b2,
+                       float eps, int step, hipStream_t s);
 
 }  // namespace hy

@@ -66,6 +66,16 @@ struct hy_patch {
     int nrec[2] = {0, 0};
     double ms[2] = {0.0, 0.0};
     int64_t launches[2] = {0, 0};
+    // hy_advance_graph: the captured steps, one graph per starting parity
+    struct GraphKey {
+        int nsteps = -1, solver = -1;
+        double cfl = 0.0, t_end = 0.0;
+        hy::LaunchCfg cfg{0, 0, 0};
+    };
+    hipStream_t capture = nullptr;
+    bool capturing = false;  // no timing events while capturing
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    GraphKey gkey[2];
 };
 
 namespace {
@@ -195,7 +205,7 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
         if (e != hipSuccess) return e;
     }
     const int k = stage - 1;
-    const bool rec = p->timing && p->nrec[k] < kTimingPool;
+    const bool rec = p->timing && !p->capturing && p->nrec[k] < kTimingPool;
     if (rec) {
         e = hipEventRecord(p->ev[k][2 * p->nrec[k]], p->stream);
         if (e != hipSuccess) return e;
@@ -286,6 +296,87 @@ void pick_config(hy_patch *p)
     } else {
         p->cfg.zchunk = 1;
     }
+}
+
+}  // namespace
+
+namespace {
+
+bool same_key(const hy_patch::GraphKey &k, int nsteps, int solver, double cfl, double t_end, const hy::LaunchCfg &cfg)
+{
+    return k.nsteps == nsteps && k.solver == solver && k.cfl == cfl && k.t_end == t_end && k.cfg.bx == cfg.bx &&
+           k.cfg.by == cfg.by && k.cfg.zchunk == cfg.zchunk;
+}
+
+// Folds the timing events of the launches recorded so far into the totals
+// (synchronising).
+hipError_t fold_times(hy_patch *p)
+{
+    if (p->nrec[0] == 0 && p->nrec[1] == 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        for (int i = 0; i < p->nrec[k] && e == hipSuccess; ++i) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, p->ev[k][2 * i], p->ev[k][2 * i + 1]);
+            p->ms[k] += t;
+        }
+        p->launches[k] += p->nrec[k];
+        p->nrec[k] = 0;
+    }
+    return e;
+}
+
+// Captures nsteps device-dt steps from the current parity into
+// p->gexec[parity] (kernel launches only: no memset, event or host wait).
+// Nothing runs.
+hy_status capture_steps(hy_patch *p, int nsteps, int solver, double cfl, double t_end)
+{
+    const int par = p->parity;
+    if (p->gexec[par]) (void)hipGraphExecDestroy(p->gexec[par]);
+    p->gexec[par] = nullptr;
+    p->gkey[par] = hy_patch::GraphKey{};
+    hipError_t e = hipSuccess;
+    if (!p->capture) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipStream_t caller = p->stream;
+    e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    p->stream = p->capture;
+    p->capturing = true;
+    hipError_t el = hipSuccess;
+    for (int i = 0; i < nsteps && el == hipSuccess; ++i) el = one_step(p, solver, hy::DT_DEVICE, 0.0, cfl, t_end);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->capture, &g);
+    p->capturing = false;
+    p->stream = caller;
+    p->parity = par;  // captured, not run
+    if (el != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(el != hipSuccess ? el : e, "step capture");
+    }
+    e = hipGraphInstantiate(&p->gexec[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        p->gexec[par] = nullptr;
+        return hip_fail(e, "graph instantiate");
+    }
+    hy_patch::GraphKey &k = p->gkey[par];
+    k.nsteps = nsteps;
+    k.solver = solver;
+    k.cfl = cfl;
+    k.t_end = t_end;
+    k.cfg = p->cfg;
+    return HY_OK;
+}
+
+hy_status check_advance(hy_patch *p, int nsteps, double cfl, double t_end, int solver)
+{
+    if (!p) return fail(HY_EINVAL, "null patch");
+    if (nsteps < 0) return fail(HY_EINVAL, "nsteps must be >= 0");
+    if (!(cfl > 0.0) || !std::isfinite(cfl) || std::isnan(t_end)) return fail(HY_EINVAL, "bad cfl or t_end");
+    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
+    if (p->d.limiter == HY_LIM_LEARNED && !p->mlp_set) return fail(HY_EINVAL, "learned limiter without weights");
+    return HY_OK;
 }
 
 }  // namespace
@@ -414,15 +505,31 @@ hy_status hy_step(hy_patch *p, double dt, int solver)
 
 hy_status hy_advance(hy_patch *p, int nsteps, double cfl, double t_end, int solver)
 {
-    if (!p) return fail(HY_EINVAL, "null patch");
-    if (nsteps < 0) return fail(HY_EINVAL, "nsteps must be >= 0");
-    if (!(cfl > 0.0) || !std::isfinite(cfl) || std::isnan(t_end)) return fail(HY_EINVAL, "bad cfl or t_end");
-    if (solver != HY_HLL && solver != HY_HLLC && solver != HY_HLLC_SWITCH) return fail(HY_EINVAL, "unknown solver");
-    if (p->d.limiter == HY_LIM_LEARNED && !p->mlp_set) return fail(HY_EINVAL, "learned limiter without weights");
+    hy_status st = check_advance(p, nsteps, cfl, t_end, solver);
+    if (st != HY_OK) return st;
     for (int i = 0; i < nsteps; ++i) {
         hipError_t e = one_step(p, solver, hy::DT_DEVICE, 0.0, cfl, t_end);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
     }
+    return HY_OK;
+}
+
+hy_status hy_advance_graph_prepare(hy_patch *p, int nsteps, double cfl, double t_end, int solver)
+{
+    hy_status st = check_advance(p, nsteps, cfl, t_end, solver);
+    if (st != HY_OK) return st;
+    if (p->padded) return fail(HY_EUNSUPPORTED, "refined levels step through the multilevel calls");
+    if (p->gexec[p->parity] && same_key(p->gkey[p->parity], nsteps, solver, cfl, t_end, p->cfg)) return HY_OK;
+    return capture_steps(p, nsteps, solver, cfl, t_end);
+}
+
+hy_status hy_advance_graph(hy_patch *p, int nsteps, double cfl, double t_end, int solver)
+{
+    hy_status st = hy_advance_graph_prepare(p, nsteps, cfl, t_end, solver);
+    if (st != HY_OK) return st;
+    hipError_t e = hipGraphLaunch(p->gexec[p->parity], p->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    if (nsteps & 1) p->parity ^= 1;
     return HY_OK;
 }
 
@@ -526,16 +633,9 @@ hy_status hy_kernel_times(hy_patch *p, double ms[2], int64_t launches[2])
 {
     if (!p || !ms || !launches) return fail(HY_EINVAL, "null argument");
     hipError_t e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(e, "synchronise");
+    if (e == hipSuccess) e = fold_times(p);
+    if (e != hipSuccess) return hip_fail(e, "event timing");
     for (int k = 0; k < 2; ++k) {
-        for (int i = 0; i < p->nrec[k]; ++i) {
-            float t = 0.f;
-            e = hipEventElapsedTime(&t, p->ev[k][2 * i], p->ev[k][2 * i + 1]);
-            if (e != hipSuccess) return hip_fail(e, "event elapsed");
-            p->ms[k] += t;
-        }
-        p->launches[k] += p->nrec[k];
-        p->nrec[k] = 0;
         ms[k] = p->ms[k];
         launches[k] = p->launches[k];
         p->ms[k] = 0.0;
@@ -687,8 +787,11 @@ hy_status hy_destroy(hy_patch *p)
 {
     if (!p) return HY_OK;
     hipStreamSynchronize(p->stream);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
+        if (p->gexec[k]) hipGraphExecDestroy(p->gexec[k]);
         for (auto &ev : p->ev[k]) hipEventDestroy(ev);
+    }
+    if (p->capture) hipStreamDestroy(p->capture);
     delete p;
     return HY_OK;
 }
@@ -1229,7 +1332,7 @@ hy_status hy_trainer_step(hy_trainer *tr, const float *x_dev, const float *t_dev
     hipError_t e = hy::launch_train_grad(tr->m, x_dev, t_dev, idx_dev, batch, tr->partial, tr->lpart, hy::TRAIN_BLOCKS,
                                          tr->grad, tr->loss, tr->stream);
     tr->step += 1;
-    if (e == hipSuccess) e = hy::launch_adam(tr->m, tr->grad, tr->m1, tr->m2, lr, 0.9f, 0.999f, 1e-8f, tr->step, tr->stream);
+    if (e == hipSuccess) e = hy::launch_adam(tr->m, tr->grad, tr->m1, tr->m2, lr, 0.9, 0.999, 1e-8f, tr->step, tr->stream);
     if (e != hipSuccess) return hip_fail(e, "training step");
     return HY_OK;
 }

@@ -21,6 +21,8 @@
 
 #include <hip/hip_bf16.h>
 
+#include <cmath>
+
 namespace hy {
 namespace {
 
@@ -445,16 +447,18 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const float *__restrict__ p
     }
 }
 
+// Adam (Kingma & Ba): b1, b2 the decay rates and ob1 = 1 - b1, ob2 = 1 - b2,
+// each rounded to FP32 from its FP64 value; c1, c2 the bias corrections.
 __global__ void __launch_bounds__(256) k_adam(MlpDevice *m, const float *__restrict__ grad, float *__restrict__ mom1,
-                                              float *__restrict__ mom2, float lr, float b1, float b2, float eps,
-                                              float c1, float c2)
+                                              float *__restrict__ mom2, float lr, float b1, float b2, float ob1,
+                                              float ob2, float eps, float c1, float c2)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= MLP_NPARAM) return;
     float *p = reinterpret_cast<float *>(m) + i;  // MlpDevice is the flat parameter vector (ABI order)
     const float g = grad[i];
-    const float a = b1 * mom1[i] + (1.f - b1) * g;
-    const float v = b2 * mom2[i] + (1.f - b2) * g * g;
+    const float a = b1 * mom1[i] + ob1 * g;
+    const float v = b2 * mom2[i] + ob2 * g * g;
     mom1[i] = a;
     mom2[i] = v;
     *p -= lr * (a * c1) / (sqrtf(v * c2) + eps);
@@ -497,12 +501,15 @@ hipError_t launch_train_grad(const MlpDevice *m, const float *x, const float *t,
     return hipGetLastError();
 }
 
-hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, float b1, float b2, float eps,
-                       int step, hipStream_t s)
+hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, double b1, double b2,
+                       float eps, int step, hipStream_t s)
 {
-    const float c1 = 1.0f / (1.0f - powf(b1, (float)step));
-    const float c2 = 1.0f / (1.0f - powf(b2, (float)step));
-    hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, m, grad, m1, m2, lr, b1, b2, eps, c1, c2);
+    // 1 - beta and the bias corrections 1 / (1 - beta^t) are formed in FP64:
+    // in FP32, 1 - 0.999^t cancels to a few significant digits at small t
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)step)));
+    hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, m, grad, m1, m2, lr, (float)b1,
+                       (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), eps, c1, c2);
     return hipGetLastError();
 }
 

@@ -75,6 +75,8 @@ SIGNATURES = {
     "hy_step": [_P, ctypes.c_double, ctypes.c_int],
     "hy_cfl_dt": [_P, ctypes.c_double, _dp],
     "hy_advance": [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int],
+    "hy_advance_graph_prepare": [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int],
+    "hy_advance_graph": [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int],
     "hy_get_time": [_P, _dp],
     "hy_conserved_totals": [_P, _dp],
     "hy_kinetic_energy": [_P, _dp],
@@ -240,6 +242,13 @@ class Patch:
 
     def advance(self, nsteps: int, cfl: float, t_end: float = float("inf"), solver: int = HLLC):
         check(lib().hy_advance(self.handle, int(nsteps), float(cfl), float(t_end), int(solver)), "advance")
+
+    def advance_graph(self, nsteps: int, cfl: float, t_end: float = float("inf"), solver: int = HLLC,
+                      prepare_only: bool = False):
+        """hy_advance as one replay of a captured HIP graph (prepare_only:
+        capture without running)."""
+        fn = lib().hy_advance_graph_prepare if prepare_only else lib().hy_advance_graph
+        check(fn(self.handle, int(nsteps), float(cfl), float(t_end), int(solver)), "advance_graph")
 
     def time(self) -> float:
         out = ctypes.c_double(0.0)

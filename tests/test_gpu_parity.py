@@ -188,6 +188,44 @@ def test_device_dt_loop_matches_host_loop():
     assert b.time() == pytest.approx(t_end, rel=1e-14)
 
 
+@pytest.mark.parametrize("solver", [hydro.HLLC, hydro.HLLC_SWITCH])
+def test_graph_replayed_steps_equal_launched_steps(solver):
+    """hy_advance_graph replays captured device-dt steps: bit for bit the
+    eager hy_advance result, for odd step counts (the graph kept per starting
+    parity), repeated replays with state reads between them, a new t_end
+    (recapture), and with the timing switch on (events stay out of the
+    graph: the replays add no timed launches, eager launches still count)."""
+    prob = wl.random_smooth_patch(3, (70, 20, 13), seed=31, bc=wl.BC_PERIODIC)
+    a = hydro.Patch(prob, precision=32)
+    b = hydro.Patch(prob, precision=32)
+    b.set_timing(True)
+    b.advance_graph(3, 0.3, solver=solver, prepare_only=True)  # capture only: nothing runs
+    assert np.array_equal(a.get_state(), b.get_state()) and b.time() == 0.0
+    b.kernel_times()
+    for rep in range(3):
+        a.advance(3, 0.3, solver=solver)
+        b.advance_graph(3, 0.3, solver=solver)
+        assert np.array_equal(a.get_state(), b.get_state()), rep
+        assert a.time() == b.time()
+    ms, launches = b.kernel_times()
+    assert list(launches) == [0, 0]
+    a.advance(1, 0.3, solver=solver)
+    b.advance(1, 0.3, solver=solver)
+    ms, launches = b.kernel_times()
+    assert list(launches) == [1, 1] and ms[0] > 0 and ms[1] > 0
+    assert np.array_equal(a.get_state(), b.get_state())
+    t_end = a.time() + 1.5 * a.cfl_dt(0.3)
+    a.advance(4, 0.3, t_end=t_end, solver=solver)
+    b.advance_graph(4, 0.3, t_end=t_end, solver=solver)
+    assert np.array_equal(a.get_state(), b.get_state()) and b.time() == pytest.approx(t_end, rel=1e-14)
+    b.set_timing(False)
+    a.advance(2, 0.3, solver=solver)
+    b.advance_graph(2, 0.3, solver=solver)
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+
+
 def test_one_dimensional_problem_along_x_and_z_fp32():
     """A 1D Sod tube run along z of a 3D patch matches the 1D run along x.
     The two axes go through separately compiled code paths (LDS plane versus
