@@ -267,6 +267,20 @@ hy_status hy_lim_sample_count(const hy_patch *fine, int64_t *nsamples);
 hy_status hy_lim_samples_scratch_bytes(const hy_patch *fine, size_t *bytes);
 hy_status hy_lim_make_samples(hy_patch *fine, void *dev_scratch, size_t scratch_bytes, float *x_dev, float *t_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * samples as hy_lim_make_samples, bit for bit, with the staging (coarse
+ * primitives and sub-cell averages) in a library-owned static device array
+ * of 64 MiB per GPU, held until the process ends, instead of a caller
+ * scratch.  The caller passes the patch and the outputs x_dev, t_dev as
+ * above.  HY_ENOMEM (nothing launched) when hy_lim_samples_scratch_bytes
+ * exceeds 64 MiB.  Allocates nothing; the first call on a GPU looks up the
+ * array's address there.  Every call on one GPU shares its array, which
+ * keeps the last call's contents (each call writes all it reads, so nothing
+ * needs clearing): calls that overlap on one GPU (other streams or threads)
+ * race and must be serialised by the caller.  Asynchronous. */
+hy_status hy_lim_make_samples_noalloc(hy_patch *fine, float *x_dev, float *t_dev);
+
 /* Learned slopes of the current state of a HY_LIM_LEARNED patch (weights
  * set): out_dev (caller device buffer of ndim * nv * ncell FP32) receives
  * sigma[(q * nv + v) * ncell + cell], the per-cell difference slope of

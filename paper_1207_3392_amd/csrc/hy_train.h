@@ -10,6 +10,14 @@ namespace hy {
 
 constexpr int TRAIN_BLOCKS = 256;
 
+// The static staging array of the allocation-free sample entry point: bytes
+// per GPU, and the devices it serves.
+constexpr size_t SAMPLES_STATIC_BYTES = (size_t)64 << 20;
+constexpr int MAX_DEVICES = 64;
+// Device address of that array on `device` (looked up once per device with
+// the device current, then cached).
+hipError_t samples_static_scratch(int device, float **ptr);
+
 hipError_t launch_coarsen4(const float *U, int64_t vs, int ndim, const int nf[3], float gm1, float *Wc, float *sub,
                            hipStream_t s);
 hipError_t launch_samples(const float *Wc, const float *sub, int ndim, const int nc[3], float *x, float *t,

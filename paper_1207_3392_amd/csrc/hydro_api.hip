@@ -1274,6 +1274,32 @@ hy_status hy_lim_make_samples(hy_patch *fine, void *dev_scratch, size_t scratch_
     return HY_OK;
 }
 
+hy_status hy_lim_make_samples_noalloc(hy_patch *fine, float *x_dev, float *t_dev)
+{
+    hy_status st = check_sample_patch(fine);
+    if (st != HY_OK) return st;
+    if (!x_dev || !t_dev) return fail(HY_EINVAL, "null buffer");
+    size_t need = 0;
+    hy_lim_samples_scratch_bytes(fine, &need);
+    if (need > hy::SAMPLES_STATIC_BYTES)
+        return fail(HY_ENOMEM, "patch too large for the 64 MiB static sample staging");
+    hipPointerAttribute_t attr{};
+    hipError_t e = hipPointerGetAttributes(&attr, fine->A);
+    if (e != hipSuccess) return hip_fail(e, "patch device");
+    float *Wc = nullptr;
+    e = hy::samples_static_scratch(attr.device, &Wc);
+    if (e != hipSuccess) return hip_fail(e, "static staging address");
+    const int64_t nc = coarse_cells(fine);
+    float *sub = Wc + (size_t)(fine->d.ndim + 2) * nc;
+    const int nf[3] = {(int)fine->d.n[0], (int)fine->d.n[1], (int)fine->d.n[2]};
+    const int ncd[3] = {nf[0] / 4, fine->d.ndim >= 2 ? nf[1] / 4 : 1, fine->d.ndim == 3 ? nf[2] / 4 : 1};
+    e = hy::launch_coarsen4((const float *)fine->A, fine->vstride, fine->d.ndim, nf, (float)(fine->d.gamma - 1.0), Wc,
+                            sub, fine->stream);
+    if (e == hipSuccess) e = hy::launch_samples(Wc, sub, fine->d.ndim, ncd, x_dev, t_dev, fine->stream);
+    if (e != hipSuccess) return hip_fail(e, "sample kernels");
+    return HY_OK;
+}
+
 hy_status hy_lim_slopes(hy_patch *p, float *out_dev)
 {
     if (!p || !out_dev) return fail(HY_EINVAL, "null argument");

@@ -22,6 +22,7 @@
 #include <hip/hip_bf16.h>
 
 #include <cmath>
+#include <mutex>
 
 namespace hy {
 namespace {
@@ -499,6 +500,36 @@ hipError_t launch_train_grad(const MlpDevice *m, const float *x, const float *t,
     hipLaunchKernelGGL(k_grad_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, partial, nblocks,
                        loss_partial, grad, loss);
     return hipGetLastError();
+}
+
+// Staging of hy_lim_make_samples_noalloc: the coarse primitives and sub-cell
+// averages live in this library-owned array instead of a caller scratch.
+// Host code never passes the symbol itself to a kernel (on the host it names
+// a stand-in, not device memory); it uses the per-device address that
+// hipGetSymbolAddress returns.
+static __device__ __align__(256) float scratch[SAMPLES_STATIC_BYTES / sizeof(float)];
+
+hipError_t samples_static_scratch(int device, float **ptr)
+{
+    static std::mutex mu;
+    static float *addr[MAX_DEVICES] = {};
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void *a = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) {
+            const hipError_t er = hipSetDevice(cur);
+            if (e == hipSuccess) e = er;
+        }
+        if (e != hipSuccess) return e;
+        addr[device] = (float *)a;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, double b1, double b2,

@@ -135,6 +135,7 @@ EXTRA_SIGNATURES = {
     "hy_lim_sample_count": [_P, _i64p],
     "hy_lim_samples_scratch_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "hy_lim_make_samples": [_P, _P, ctypes.c_size_t, _P, _P],
+    "hy_lim_make_samples_noalloc": [_P, _P, _P],
     "hy_lim_slopes": [_P, _P],
     "hy_trainer_workspace_bytes": [ctypes.POINTER(ctypes.c_size_t)],
     "hy_trainer_init": [_P, ctypes.c_size_t, _fp, _P, ctypes.POINTER(_P)],
@@ -298,6 +299,18 @@ class Patch:
         torch.cuda.current_stream(self.device).synchronize()
         del scratch
         return x, t
+
+    def make_samples_noalloc(self, x, t):
+        """make_samples into caller tensors x (n, 4), t (n) (float32, on this
+        patch's device), staged in the library's static device array (no
+        allocation; raises HY_ENOMEM beyond its 64 MiB)."""
+        check(lib().hy_lim_make_samples_noalloc(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                                ctypes.c_void_p(t.data_ptr())), "lim_make_samples_noalloc")
+
+    def sample_count(self) -> int:
+        ns = ctypes.c_int64(0)
+        check(lib().hy_lim_sample_count(self.handle, ctypes.byref(ns)), "lim_sample_count")
+        return int(ns.value)
 
     def learned_slopes(self):
         """Clamped learned slopes of the current state, (ndim * nv, ncell) on the device."""
