@@ -170,7 +170,7 @@ struct FluxSet {
 };
 
 template <int ND, int SOLVER, typename T>
-__global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs, T gamma, T gm1, T inv_gm1, T theta2,
+__global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs, T gamma, T gm1, T inv_gm1, T theta,
                                                   const double *dt)
 {
     const double w = 0.5 * *dt;
@@ -179,15 +179,15 @@ __global__ void __launch_bounds__(FB) k_box_flux(const T *u, Grid g, FluxSet fs,
     const int t = blockIdx.x * FB + threadIdx.x;
     const Box &b = fs.b[bx];
     if (q == 0)
-        box_faces<ND, 0, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+        box_faces<ND, 0, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta, w, fs.assign[bx] != 0,
                                      fs.acc[bx][0][0], fs.acc[bx][0][1]);
     if constexpr (ND >= 2)
         if (q == 1)
-            box_faces<ND, 1, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+            box_faces<ND, 1, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta, w, fs.assign[bx] != 0,
                                      fs.acc[bx][1][0], fs.acc[bx][1][1]);
     if constexpr (ND >= 3)
         if (q == 2)
-            box_faces<ND, 2, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta2, w, fs.assign[bx] != 0,
+            box_faces<ND, 2, SOLVER>(u, g, b, t, side, gamma, gm1, inv_gm1, theta, w, fs.assign[bx] != 0,
                                      fs.acc[bx][2][0], fs.acc[bx][2][1]);
 }
 
@@ -352,16 +352,16 @@ __global__ void __launch_bounds__(TB) k_leaf_totals(const T *u, Grid g, Box b, B
 
 template <int ND, typename T>
 hipError_t box_flux_nd(const T *u, const Grid &g, const FluxSet &fs, int nbox, int solver, T gamma, T gm1, T inv_gm1,
-                       T theta2, const double *w, hipStream_t s)
+                       T theta, const double *w, hipStream_t s)
 {
     int most = 0;
     for (int k = 0; k < nbox; ++k)
         for (int q = 0; q < ND; ++q) most = std::max(most, fs.b[k].n[(q + 1) % 3] * fs.b[k].n[(q + 2) % 3]);
     const dim3 grid((most + FB - 1) / FB, nbox * ND * 2);
     if (solver == SOLVER_HLL)
-        hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLL, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta2, w);
+        hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLL, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta, w);
     else
-        hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLLC, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta2, w);
+        hipLaunchKernelGGL((k_box_flux<ND, SOLVER_HLLC, T>), grid, dim3(FB), 0, s, u, g, fs, gamma, gm1, inv_gm1, theta, w);
     return hipGetLastError();
 }
 
@@ -414,10 +414,9 @@ hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes
         for (int q = 0; q < 3; ++q)
             for (int side = 0; side < 2; ++side) fs.acc[k][q][side] = acc[k][q][side];
     }
-    const T theta2 = T(2) * theta;
-    if (ndim == 1) return box_flux_nd<1>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta2, w, s);
-    if (ndim == 2) return box_flux_nd<2>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta2, w, s);
-    return box_flux_nd<3>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta2, w, s);
+    if (ndim == 1) return box_flux_nd<1>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta, w, s);
+    if (ndim == 2) return box_flux_nd<2>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta, w, s);
+    return box_flux_nd<3>(u, g, fs, nbox, solver, gamma, gm1, inv_gm1, theta, w, s);
 }
 
 template <typename T>

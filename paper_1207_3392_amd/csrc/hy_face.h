@@ -75,6 +75,29 @@ __device__ __forceinline__ T slope2_mm(T wm, T w0, T wp, T theta2)
     return med3_(fmin(a, fmin(b, c)), fmax(a, fmax(b, c)), T(0));
 }
 
+// The generalised-minmod slope of eq. MinMod divided by theta: scaling every
+// argument of MM by 1 / theta (a positive factor commutes with MM) gives
+// MM(dm, (dm + dp) k, dp) with k = 1 / (2 theta), evaluated as
+// med3(min3, max3, 0) as above; the face values are then w +/- hs * slope
+// with hs = theta / 2.  The factors theta leave the per-cell work this way.
+template <typename T>
+__device__ __forceinline__ T slope_mm(T wm, T w0, T wp, T k)
+{
+    const T dm = w0 - wm, dp = wp - w0;
+    const T b = (dm + dp) * k;
+    return med3_(fmin(dm, fmin(b, dp)), fmax(dm, fmax(b, dp)), T(0));
+}
+
+// The per-patch constants of slope_mm and of the face values, formed the
+// same way by every kernel that computes a face flux of the same state.
+template <typename T> struct ThetaLim {
+    T k, hs;
+};
+template <typename T> __device__ __forceinline__ ThetaLim<T> theta_lim(T theta)
+{
+    return ThetaLim<T>{T(0.5) / theta, T(0.5) * theta};
+}
+
 // ------------------------------------------------------ Riemann solvers ----
 
 // Flux normal to Q from the primitive face states wl (left), wr (right).
@@ -125,26 +148,31 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
         for (int v = 0; v < ND + 2; ++v) wk[v] = useL ? wl[v] : wr[v];
         const T sK = useL ? -am : ap;
         const T rK = wk[0], vK = wk[1 + Q], pK = wk[IP];
+        // supersonic (s_K = 0): a middle speed equal to v_K makes the middle
+        // state U_K itself, so the flux below is F_K
+        const T sm = sup ? vK : am_;
         T kk = T(0);
 #pragma unroll
         for (int d = 0; d < ND; ++d) kk += wk[1 + d] * wk[1 + d];
         const T EK = pK * inv_gm1 + T(0.5) * rK * kk;
-        const T mK = rK * vK;
         // middle state from the jump conditions across the K-side outer wave
+        // (s_K - sm is nonzero: opposite signs, or v_K != 0 when supersonic)
         const T qk = sK - vK;
-        const T inv = sup ? T(0) : rcp_(sup ? T(1) : sK - am_);
-        const T rs = rK * qk * inv;
-        const T ps = pK + rK * qk * (am_ - vK);
-        const T Gs = (qk * EK - pK * vK + ps * am_) * inv;
-        // F = F_K + s_K (U*_K - U_K); s_K = 0 in the supersonic cases
-        const T fd = mK + sK * (rs - rK);
+        const T inv = rcp_(sK - sm);
+        const T rq = rK * qk;
+        const T rs = rq * inv;
+        const T ps = pK + rq * (sm - vK);
+        const T Gs = (qk * EK - pK * vK + ps * sm) * inv;
+        // F_K + s_K (U*_K - U_K) equals the physical flux of the middle state
+        // (the jump conditions across the s_K wave), formed directly
+        const T fd = rs * sm;
         f[0] = fd;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            if (d == Q) f[1 + d] = mK * vK + pK + sK * (rs * am_ - mK);
+            if (d == Q) f[1 + d] = fd * sm + ps;
             else f[1 + d] = fd * wk[1 + d];
         }
-        f[IP] = (EK + pK) * vK + sK * (Gs - EK);
+        f[IP] = (Gs + ps) * sm;
     }
 }
 
@@ -184,7 +212,7 @@ __device__ __forceinline__ void load_prim(const T *u, const Grid &g, int64_t c, 
 // thread per face position transverse to Q.
 template <int ND, int Q, int SOLVER, typename T>
 __device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &b, int t, int side, T gamma, T gm1,
-                                          T inv_gm1, T theta2, double w, bool assign, double *acc_lo, double *acc_hi)
+                                          T inv_gm1, T theta, double w, bool assign, double *acc_lo, double *acc_hi)
 {
     constexpr int R1 = Q == 0 ? 1 : 0, R2 = Q == 2 ? 1 : 2;  // transverse dimensions, the lower one fastest
     const int faces = b.n[R1] * b.n[R2];
@@ -202,10 +230,11 @@ __device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &
             load_prim<ND>(u, g, at(g, c3[0], c3[1], c3[2]), gm1, w4[s]);
         }
         T wl[ND + 2], wr[ND + 2], fl[ND + 2];
+        const ThetaLim<T> lim = theta_lim(theta);
 #pragma unroll
         for (int v = 0; v < ND + 2; ++v) {
-            wl[v] = w4[1][v] + T(0.25) * slope2_mm(w4[0][v], w4[1][v], w4[2][v], theta2);
-            wr[v] = w4[2][v] - T(0.25) * slope2_mm(w4[1][v], w4[2][v], w4[3][v], theta2);
+            wl[v] = w4[1][v] + lim.hs * slope_mm(w4[0][v], w4[1][v], w4[2][v], lim.k);
+            wr[v] = w4[2][v] - lim.hs * slope_mm(w4[1][v], w4[2][v], w4[3][v], lim.k);
         }
         face_flux<ND, Q, SOLVER>(wl, wr, fl, gamma, inv_gm1, false);
         double *acc = side == 0 ? acc_lo : acc_hi;

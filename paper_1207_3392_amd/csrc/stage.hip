@@ -45,6 +45,20 @@ __device__ __forceinline__ double stage_dt(const StageArgs<T> &a)
     return dt > 0.0 ? dt : 0.0;
 }
 
+// A value every lane holds alike, moved to a scalar register so the vector
+// register budget of the per-cell work does not carry it.
+__device__ __forceinline__ float uniform_(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform_(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 constexpr int FLIP = 1 << 30;      // set on a mapped index whose source is a mirror image
 constexpr int IDX = FLIP - 1;
 
@@ -107,18 +121,17 @@ __device__ __forceinline__ void stage_box_faces(const StageArgs<T> &a, int fid, 
     const Grid g{{a.vm[0], a.vm[1], a.vm[2]}, a.vstride};
     const Box &b = a.bf.b[k];
     const double w = 0.5 * *a.dt_dev;
-    const T theta2 = T(2) * a.theta;
     const bool as = a.bf.assign[k] != 0;
     if (q == 0)
-        box_faces<ND, 0, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, theta2, w, as, a.bf.acc[k][0][0],
+        box_faces<ND, 0, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, a.theta, w, as, a.bf.acc[k][0][0],
                                  a.bf.acc[k][0][1]);
     if constexpr (ND >= 2)
         if (q == 1)
-            box_faces<ND, 1, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, theta2, w, as,
+            box_faces<ND, 1, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, a.theta, w, as,
                                      a.bf.acc[k][1][0], a.bf.acc[k][1][1]);
     if constexpr (ND >= 3)
         if (q == 2)
-            box_faces<ND, 2, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, theta2, w, as,
+            box_faces<ND, 2, SOLVER>(a.uin, g, b, t, side, a.gamma, a.gm1, a.inv_gm1, a.theta, w, as,
                                      a.bf.acc[k][2][0], a.bf.acc[k][2][1]);
 }
 
@@ -191,10 +204,12 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int y0 = (ND >= 2) ? byi * BY : 0;
     const int z0 = (ND == 3) ? bzi * a.zchunk : 0;
     const int nplanes = (ND == 3) ? (z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
-    const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1, theta2 = T(2) * a.theta;
-    // face value = w +/- HS * slope: the minmod path stores twice the slope
-    // (median form), the learned path the slope itself
-    constexpr T HS = LIM == LIM_LEARNED ? T(0.5) : T(0.25);
+    const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1;
+    // face value = w +/- hs * slope: the minmod path keeps the slope divided
+    // by theta (slope_mm), the learned path the slope itself
+    const ThetaLim<T> tl = theta_lim(a.theta);
+    const T lk = uniform_(tl.k);
+    const T hs = LIM == LIM_LEARNED ? T(0.5) : uniform_(tl.hs);
     const bool grav = a.accel[0] != T(0) || a.accel[1] != T(0) || a.accel[2] != T(0);  // uniform
 
     // per-variable base pointers (uniform), 32-bit cell offsets below
@@ -227,6 +242,14 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 
     const double dtd = stage_dt<ND>(a);
     const T dt = (T)dtd;
+    // the step's weight of a flux difference per unit width, and of the source
+    const T wdt = STAGE == 1 ? dt : T(0.5) * dt;
+    T cdt[3], cacc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        cdt[d] = uniform_(wdt * a.idx[d]);
+        cacc[d] = uniform_(wdt * a.accel[d]);
+    }
     if constexpr (STAGE == 1) {
         if (blockIdx.x == 0 && tid < RATE_SLOTS) {
             a.ctl->rate[a.parity ^ 1][tid] = 0ull;
@@ -308,16 +331,16 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
         for (int v = 0; v < NP; ++v) {
             if constexpr (LIM != LIM_LEARNED) {
-                sm1[v] = slope2_mm(wm2[v], wm1[v], WA[v], theta2);
-                SA[v] = slope2_mm(wm1[v], WA[v], WB[v], theta2);
+                sm1[v] = slope_mm(wm2[v], wm1[v], WA[v], lk);
+                SA[v] = slope_mm(wm1[v], WA[v], WB[v], lk);
             } else {
                 sm1[v] = learned_slope<ND>(a, 2, v, gx, gy, z0 - 1);
                 SA[v] = learned_slope<ND>(a, 2, v, gx, gy, z0);
             }
         }
         T fl[NP], fr[NP];
-        face_state(wm1, sm1, HS, fl);
-        face_state(WA, SA, -HS, fr);
+        face_state(wm1, sm1, hs, fl);
+        face_state(WA, SA, -hs, fr);
         bool hll = false;
         if constexpr (SOLVER == SOLVER_HLLC_SWITCH) hll = (a.flags[(unsigned)(z0 * plane) + colo] >> 2) & 1u;
         face_flux<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1, hll);
@@ -438,8 +461,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 if constexpr (LIM != LIM_LEARNED)
-                    sSx[v][row][col + 1] = slope2_mm(sW[v][row + OY][col + 1], sW[v][row + OY][col + 2],
-                                                    sW[v][row + OY][col + 3], theta2);
+                    sSx[v][row][col + 1] = slope_mm(sW[v][row + OY][col + 1], sW[v][row + OY][col + 2],
+                                                    sW[v][row + OY][col + 3], lk);
                 else
                     sSx[v][row][col + 1] = learned_slope<ND>(a, 0, v, x0 + col, y0 + row, kz);
             }
@@ -448,8 +471,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 if constexpr (LIM != LIM_LEARNED)
-                    sSy[v][row + 1][col] = slope2_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
-                                                    sW[v][row + 3][col + 2], theta2);
+                    sSy[v][row + 1][col] = slope_mm(sW[v][row + 1][col + 2], sW[v][row + 2][col + 2],
+                                                    sW[v][row + 3][col + 2], lk);
                 else
                     sSy[v][row + 1][col] = learned_slope<ND>(a, 1, v, x0 + col, y0 + row, kz);
             }
@@ -476,7 +499,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             to_w(U2, W2, fxo, fyo, fz2);
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM != LIM_LEARNED) Sk1[v] = slope2_mm(Wk[v], Wk1[v], W2[v], theta2);
+                if constexpr (LIM != LIM_LEARNED) Sk1[v] = slope_mm(Wk[v], Wk1[v], W2[v], lk);
                 else Sk1[v] = lsz[v];
             }
         }
@@ -509,8 +532,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                wl[v] = sW[v][row + OY][col + 1] + HS * sSx[v][row][col];
-                wr[v] = sW[v][row + OY][col + 2] - HS * sSx[v][row][col + 1];
+                wl[v] = sW[v][row + OY][col + 1] + hs * sSx[v][row][col];
+                wr[v] = sW[v][row + OY][col + 2] - hs * sSx[v][row][col + 1];
             }
             // switch: the decision stored with the face's high cell (at a
             // non-periodic high wall, with the last cell)
@@ -528,8 +551,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
-                wl[v] = sW[v][row + 1][col + 2] + HS * sSy[v][row][col];
-                wr[v] = sW[v][row + 2][col + 2] - HS * sSy[v][row + 1][col];
+                wl[v] = sW[v][row + 1][col + 2] + hs * sSy[v][row][col];
+                wr[v] = sW[v][row + 2][col + 2] - hs * sSy[v][row + 1][col];
             }
             bool hll = false;
             if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
@@ -549,8 +572,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (ND == 3) {
             T fl[NP], fr[NP];
-            face_state(Wk, Sk, HS, fl);
-            face_state(Wk1, Sk1, -HS, fr);
+            face_state(Wk, Sk, hs, fl);
+            face_state(Wk1, Sk1, -hs, fr);
             bool hll = false;
             if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
                 const bool wall = kz + 1 >= nz && a.bc[2][1] != BC_PERIODIC;
@@ -571,38 +594,39 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         __syncthreads();
 
         // ---- phase 3: divergence, source, Runge-Kutta combination ----
-        T L[NP];
-#pragma unroll
-        for (int v = 0; v < NP; ++v) L[v] = (sFx[v][ty][tx] - sFx[v][ty][tx + 1]) * a.idx[0];
-        if constexpr (ND >= 2) {
-#pragma unroll
-            for (int v = 0; v < NP; ++v) L[v] += (sFy[v][ty][tx] - sFy[v][ty + 1][tx]) * a.idx[1];
-        }
-        if constexpr (ND == 3) {
-#pragma unroll
-            for (int v = 0; v < NP; ++v) L[v] += (Flo[v] - Fhi[v]) * a.idx[2];
-        }
-        if (grav) {
-            // uniform acceleration: momentum += rho a, energy += S . a
-            T pw = T(0);
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                L[1 + d] += Uk[0] * a.accel[d];
-                pw += Uk[1 + d] * a.accel[d];
-            }
-            L[IP] += pw;
-        }
+        // stage 1: U + dt L; stage 2: (U^n + U^(1) + dt L) / 2, with the
+        // factors dt / dq (dt / (2 dq)) of every face-flux difference uniform
         T out[NP];
         if constexpr (STAGE == 1) {
 #pragma unroll
-            for (int v = 0; v < NP; ++v) out[v] = Uk[v] + dt * L[v];
+            for (int v = 0; v < NP; ++v) out[v] = Uk[v];
         } else {
             if constexpr (LATE) {
 #pragma unroll
                 for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
             }
 #pragma unroll
-            for (int v = 0; v < NP; ++v) out[v] = T(0.5) * (u0[v] + Uk[v] + dt * L[v]);
+            for (int v = 0; v < NP; ++v) out[v] = T(0.5) * (u0[v] + Uk[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NP; ++v) out[v] += cdt[0] * (sFx[v][ty][tx] - sFx[v][ty][tx + 1]);
+        if constexpr (ND >= 2) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) out[v] += cdt[1] * (sFy[v][ty][tx] - sFy[v][ty + 1][tx]);
+        }
+        if constexpr (ND == 3) {
+#pragma unroll
+            for (int v = 0; v < NP; ++v) out[v] += cdt[2] * (Flo[v] - Fhi[v]);
+        }
+        if (grav) {
+            // uniform acceleration: momentum += rho a, energy += S . a
+            T pw = T(0);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                out[1 + d] += Uk[0] * cacc[d];
+                pw += Uk[1 + d] * cacc[d];
+            }
+            out[IP] += pw;
         }
         if (own_valid) {
             const unsigned c = zko + colv;
