@@ -28,24 +28,26 @@ __device__ __forceinline__ float soundf(float g, float p, float r)
     return gp * __builtin_amdgcn_rsqf(gp * r);
 }
 
-// twice the generalised minmod slope (see stage.hip): med3(min3, max3, 0) of
-// (2 theta dm, dm + dp, 2 theta dp)
-__device__ __forceinline__ float slope2(float wm, float w0, float wp, float th2)
+// The generalised minmod slope of eq. MinMod divided by theta (see
+// hy_face.h): med3(min3, max3, 0) of (dm, (dm + dp) k, dp), k = 1 / (2 theta);
+// face values w +/- (theta / 2) slope.
+__device__ __forceinline__ float slope_k(float wm, float w0, float wp, float k)
 {
     const float dm = w0 - wm, dp = wp - w0;
-    const float a = th2 * dm, b = dm + dp, c = th2 * dp;
-    return __builtin_amdgcn_fmed3f(fminf(a, fminf(b, c)), fmaxf(a, fmaxf(b, c)), 0.f);
+    const float b = (dm + dp) * k;
+    return __builtin_amdgcn_fmed3f(fminf(dm, fminf(b, dp)), fmaxf(dm, fmaxf(b, dp)), 0.f);
 }
 
-// 1D flux from primitive face states (rho, v, p)
-__device__ __forceinline__ void flux1(const float (&wl)[3], const float (&wr)[3], float (&f)[3], float g,
+// 1D flux from primitive face states (rho, v, p); sg = sqrt(gamma)
+__device__ __forceinline__ void flux1(const float (&wl)[3], const float (&wr)[3], float (&f)[3], float sg,
                                       float igm1, int solver)
 {
     const float rl = wl[0], vl = wl[1], pl = wl[2];
     const float rr = wr[0], vr = wr[1], pr = wr[2];
-    const float cl = soundf(g, pl, rl), cr = soundf(g, pr, rr);
-    const float ap = fmaxf(0.f, fmaxf(vl + cl, vr + cr));
-    const float am = fmaxf(0.f, fmaxf(cl - vl, cr - vr));
+    // sound speeds sg sqrt(p / rho), with sg folded into the signal speeds
+    const float ul = pl * __builtin_amdgcn_rsqf(pl * rl), ur = pr * __builtin_amdgcn_rsqf(pr * rr);
+    const float ap = fmaxf(0.f, fmaxf(sg * ul + vl, sg * ur + vr));
+    const float am = fmaxf(0.f, fmaxf(sg * ul - vl, sg * ur - vr));
     if (solver == 0) {
         const float El = pl * igm1 + 0.5f * rl * vl * vl, Er = pr * igm1 + 0.5f * rr * vr * vr;
         const float ml = rl * vl, mr = rr * vr;
@@ -63,22 +65,28 @@ __device__ __forceinline__ void flux1(const float (&wl)[3], const float (&wr)[3]
         }
         return;
     }
+    // HLLC: Batten's middle speed, the middle state on the side K it selects
+    // from the jump conditions across the s_K wave, and its physical flux
+    // (equal to F_K + s_K (U*_K - U_K)); supersonic: middle speed v_K, so the
+    // middle state is U_K and the flux F_K
     const float ql = am + vl, qr = ap - vr;
-    const float a_m = (rr * vr * qr + rl * vl * ql - (pr - pl)) * rcpf_(rr * qr + rl * ql);
+    const float A = rr * qr, B = rl * ql;
+    const float a_m = (A * vr + (B * vl + (pl - pr))) * rcpf_(A + B);
     const bool sup = (am == 0.f) | (ap == 0.f);
     const bool useL = (am == 0.f) | ((ap != 0.f) & (a_m >= 0.f));
     const float rK = useL ? rl : rr, vK = useL ? vl : vr, pK = useL ? pl : pr;
     const float sK = useL ? -am : ap;
+    const float sm = sup ? vK : a_m;
     const float EK = pK * igm1 + 0.5f * rK * vK * vK;
-    const float mK = rK * vK;
     const float qk = sK - vK;
-    const float inv = sup ? 0.f : rcpf_(sup ? 1.f : sK - a_m);
-    const float rs = rK * qk * inv;
-    const float ps = pK + rK * qk * (a_m - vK);
-    const float Gs = (qk * EK - pK * vK + ps * a_m) * inv;
-    f[0] = mK + sK * (rs - rK);
-    f[1] = mK * vK + pK + sK * (rs * a_m - mK);
-    f[2] = (EK + pK) * vK + sK * (Gs - EK);
+    const float inv = rcpf_(sK - sm);
+    const float rq = rK * qk;
+    const float ps = pK + rq * (sm - vK);
+    const float Gs = (qk * EK - pK * vK + ps * sm) * inv;
+    const float fd = rq * inv * sm;
+    f[0] = fd;
+    f[1] = fd * sm + ps;
+    f[2] = (Gs + ps) * sm;
 }
 
 __global__ void k_batch_reset(BatchCtl *ctl)
@@ -86,8 +94,9 @@ __global__ void k_batch_reset(BatchCtl *ctl)
     ctl->next = 0u;
 }
 
-// BT threads per workgroup, BATCH_NMAX / BT cells per thread
-template <int BT>
+// BT threads per workgroup, CPT cells per thread (BT * CPT >= the batch's
+// longest tube; the smaller CPT that fits keeps the state in fewer registers)
+template <int BT, int CPT>
 __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes, const int *__restrict__ order,
                                               float *__restrict__ U, int64_t ntot, BatchCtl *ctl,
                                               TubeStatus *__restrict__ status, int ntubes, int nmax)
@@ -97,7 +106,6 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
     float *sF = lds + 3 * (nmax + 4);  // 3 x (nmax + 1): face fluxes
     __shared__ float sred[BT / 64];
     __shared__ int sidx;
-    constexpr int CPT = BATCH_NMAX / BT;  // cells per thread
     const int tid = threadIdx.x;
     const int SW = nmax + 4, SF = nmax + 1;
     const double t_end = ctl->t_end, cfl = ctl->cfl;
@@ -113,7 +121,8 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
         const int ti = order[q];
         const TubeDesc d = tubes[ti];
         const int n = d.n;
-        const float g = d.gamma, gm1 = d.gamma - 1.f, igm1 = 1.f / (d.gamma - 1.f), th2 = 2.f * d.theta;
+        const float g = d.gamma, gm1 = d.gamma - 1.f, igm1 = 1.f / (d.gamma - 1.f);
+        const float sg = sqrtf(d.gamma), lk = 0.5f / d.theta, hs = 0.5f * d.theta;
         const float idx = d.idx;
 
         // conserved state of the owned cells (cell i = tid + k * BT)
@@ -183,10 +192,10 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
 #pragma unroll
                 for (int v = 0; v < 3; ++v) {
                     const float *w = sW + v * SW + f;  // w[0..3] = cells f-2 .. f+1
-                    wl[v] = w[1] + 0.25f * slope2(w[0], w[1], w[2], th2);
-                    wr[v] = w[2] - 0.25f * slope2(w[1], w[2], w[3], th2);
+                    wl[v] = w[1] + hs * slope_k(w[0], w[1], w[2], lk);
+                    wr[v] = w[2] - hs * slope_k(w[1], w[2], w[3], lk);
                 }
-                flux1(wl, wr, fl, g, igm1, solver);
+                flux1(wl, wr, fl, sg, igm1, solver);
 #pragma unroll
                 for (int v = 0; v < 3; ++v) sF[v * SF + f] = fl[v];
             }
@@ -204,6 +213,8 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                 break;
             }
             const float dtf = (float)dt;
+            // the step's weight of a face-flux difference, per stage
+            const float c1 = dtf * idx, c2 = 0.5f * c1;
             // stage 1: U1 = U^n + dt L(U^n); the primitives of U^n are in LDS
             faces();
 #pragma unroll
@@ -211,7 +222,7 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                 const int i = tid + k * BT;
 #pragma unroll
                 for (int v = 0; v < 3; ++v)
-                    Us[k][v] = i < n ? U0[k][v] + dtf * (sF[v * SF + i] - sF[v * SF + i + 1]) * idx : 1.f;
+                    Us[k][v] = i < n ? U0[k][v] + c1 * (sF[v * SF + i] - sF[v * SF + i + 1]) : 1.f;
             }
             // (no barrier: the flux reads above end before any thread passes
             // the barrier in fill, and only the next faces() writes sF)
@@ -223,7 +234,7 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                 const int i = tid + k * BT;
 #pragma unroll
                 for (int v = 0; v < 3; ++v)
-                    U0[k][v] = i < n ? 0.5f * (U0[k][v] + Us[k][v] + dtf * (sF[v * SF + i] - sF[v * SF + i + 1]) * idx)
+                    U0[k][v] = i < n ? 0.5f * (U0[k][v] + Us[k][v]) + c2 * (sF[v * SF + i] - sF[v * SF + i + 1])
                                      : 1.f;
             }
             r = fill(U0, true);
@@ -261,12 +272,23 @@ hipError_t launch_batch_reset(BatchCtl *ctl, hipStream_t s)
 }
 
 namespace {
-const void *batch_kernel(int bt)
+// Two register footprints per workgroup size: tubes up to 4096 cells, or up
+// to BATCH_NMAX (6144).
+constexpr int SMALL_NMAX = 4096;
+
+template <int BT>
+const void *batch_kernel_bt(int nmax)
+{
+    if (nmax <= SMALL_NMAX) return (const void *)k_batch<BT, SMALL_NMAX / BT>;
+    return (const void *)k_batch<BT, BATCH_NMAX / BT>;
+}
+
+const void *batch_kernel(int bt, int nmax)
 {
     switch (bt) {
-    case 256: return (const void *)k_batch<256>;
-    case 512: return (const void *)k_batch<512>;
-    default: return (const void *)k_batch<1024>;
+    case 256: return batch_kernel_bt<256>(nmax);
+    case 512: return batch_kernel_bt<512>(nmax);
+    default: return batch_kernel_bt<1024>(nmax);
     }
 }
 }  // namespace
@@ -279,7 +301,7 @@ hipError_t prepare_batch(int nmax)
     hipError_t e = hipSuccess;
     for (int bt : {256, 512, 1024})
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(batch_kernel(bt), hipFuncAttributeMaxDynamicSharedMemorySize,
+            e = hipFuncSetAttribute(batch_kernel(bt, nmax), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)batch_lds_bytes(nmax));
     return e;
 }
@@ -287,22 +309,12 @@ hipError_t prepare_batch(int nmax)
 hipError_t launch_batch(const TubeDesc *tubes, const int *order, float *U, int64_t ntot, BatchCtl *ctl,
                         TubeStatus *status, int ntubes, int nmax, int nblocks, int bt, hipStream_t s)
 {
+    if (nmax < 1 || nmax > BATCH_NMAX || !batch_bt_supported(bt)) return hipErrorInvalidValue;
     const size_t lds = batch_lds_bytes(nmax);
-    switch (bt) {
-    case 256:
-        hipLaunchKernelGGL(k_batch<256>, dim3(nblocks), dim3(256), lds, s, tubes, order, U, ntot, ctl, status, ntubes,
-                           nmax);
-        break;
-    case 512:
-        hipLaunchKernelGGL(k_batch<512>, dim3(nblocks), dim3(512), lds, s, tubes, order, U, ntot, ctl, status, ntubes,
-                           nmax);
-        break;
-    default:
-        hipLaunchKernelGGL(k_batch<1024>, dim3(nblocks), dim3(1024), lds, s, tubes, order, U, ntot, ctl, status,
-                           ntubes, nmax);
-        break;
-    }
-    return hipGetLastError();
+    void *args[] = {(void *)&tubes, (void *)&order, (void *)&U, (void *)&ntot, (void *)&ctl,
+                    (void *)&status, (void *)&ntubes, (void *)&nmax};
+    const hipError_t e = hipLaunchKernel(batch_kernel(bt, nmax), dim3(nblocks), dim3(bt), args, lds, s);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 size_t batch_lds_bytes(int nmax) { return sizeof(float) * (3 * (size_t)(nmax + 4) + 3 * (size_t)(nmax + 1)); }
@@ -310,7 +322,7 @@ size_t batch_lds_bytes(int nmax) { return sizeof(float) * (3 * (size_t)(nmax + 4
 int batch_blocks_per_cu(int nmax, int bt)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel(bt), bt, batch_lds_bytes(nmax)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(bt, nmax), bt, batch_lds_bytes(nmax)) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;

@@ -6,7 +6,7 @@
 
 namespace hy {
 
-constexpr int BATCH_NMAX = 6144;  // cells per tube (LDS-resident); 6, 12 or 24 per thread
+constexpr int BATCH_NMAX = 6144;  // cells per tube (LDS-resident); up to 6, 12 or 24 per thread
 
 struct TubeDesc {
     int n;
@@ -33,7 +33,8 @@ struct BatchCtl {
 };
 
 hipError_t launch_batch_reset(BatchCtl *ctl, hipStream_t s);
-// bt = threads per workgroup: 256, 512 or 1024 (BATCH_NMAX / bt cells per thread)
+// bt = threads per workgroup: 256, 512 or 1024 (4096 / bt cells per thread
+// when the longest tube has at most 4096 cells, else BATCH_NMAX / bt)
 bool batch_bt_supported(int bt);
 hipError_t launch_batch(const TubeDesc *tubes, const int *order, float *U, int64_t ntot, BatchCtl *ctl,
                         TubeStatus *status, int ntubes, int nmax, int nblocks, int bt, hipStream_t s);

@@ -18,6 +18,15 @@ template <typename T> __device__ __forceinline__ T rcp_(T x);
 template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double rcp_<double>(double x) { return 1.0 / x; }
 
+// sqrt(p / rho), the sound speed divided by sqrt(gamma), evaluated as
+// p rsqrt(p rho); the solvers fold sqrt(gamma) into the signal speeds
+template <typename T> __device__ __forceinline__ T sound1_(T p, T rho);
+template <> __device__ __forceinline__ float sound1_<float>(float p, float r)
+{
+    return p * __builtin_amdgcn_rsqf(p * r);
+}
+template <> __device__ __forceinline__ double sound1_<double>(double p, double r) { return sqrt(p / r); }
+
 // c_s = sqrt(gamma p / rho), evaluated as (gamma p) rsqrt(gamma p rho)
 template <typename T> __device__ __forceinline__ T sound_(T gamma, T p, T rho);
 template <> __device__ __forceinline__ float sound_<float>(float g, float p, float r)
@@ -101,17 +110,20 @@ template <typename T> __device__ __forceinline__ ThetaLim<T> theta_lim(T theta)
 // ------------------------------------------------------ Riemann solvers ----
 
 // Flux normal to Q from the primitive face states wl (left), wr (right).
+// sg = sqrt(gamma) (formed once per kernel by the caller, the same way
+// everywhere: sqrt_gamma below).
 template <int ND, int Q, int SOLVER, typename T>
 __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2],
-                                        T gamma, T inv_gm1)
+                                        T sg, T inv_gm1)
 {
     constexpr int IP = ND + 1;
     const T rl = wl[0], vl = wl[1 + Q], pl = wl[IP];
     const T rr = wr[0], vr = wr[1 + Q], pr = wr[IP];
-    const T cl = sound_(gamma, pl, rl), cr = sound_(gamma, pr, rr);
-    // outer speed estimates alpha_+/- = max(0, +/-lambda_+/-(L), +/-lambda_+/-(R))
-    const T ap = max3_(T(0), vl + cl, vr + cr);
-    const T am = max3_(T(0), cl - vl, cr - vr);
+    const T ul = sound1_(pl, rl), ur = sound1_(pr, rr);
+    // outer speed estimates alpha_+/- = max(0, +/-lambda_+/-(L), +/-lambda_+/-(R)),
+    // c = sg u
+    const T ap = max3_(T(0), sg * ul + vl, sg * ur + vr);
+    const T am = max3_(T(0), sg * ul - vl, sg * ur - vr);
     if constexpr (SOLVER == 0) {
         T kl = T(0), kr = T(0);
 #pragma unroll
@@ -136,9 +148,11 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
                        wD * (rr * wr[1 + d] - rl * wl[1 + d]);
         f[IP] = wL * ((El + pl) * vl) + wR * ((Er + pr) * vr) - wD * (Er - El);
     } else {
-        // Batten's middle-wave speed (eq. MiddleWaveSpeed)
+        // Batten's middle-wave speed (eq. MiddleWaveSpeed):
+        // (A v_R + B v_L + p_L - p_R) / (A + B), A = rho_R (a+ - v_R), B = rho_L (a- + v_L)
         const T ql = am + vl, qr = ap - vr;
-        const T am_ = (rr * vr * qr + rl * vl * ql - (pr - pl)) * rcp_(rr * qr + rl * ql);
+        const T A = rr * qr, B = rl * ql;
+        const T am_ = (A * vr + (B * vl + (pl - pr))) * rcp_(A + B);
         // eq. FluxHLLC: alpha_- = 0 selects L, then alpha_+ = 0 selects R,
         // then the sign of alpha_m selects the middle state on its side
         const bool sup = (am == T(0)) | (ap == T(0));
@@ -180,17 +194,19 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
 // set (a shock flagged along a direction transverse to this face), HLLC
 // elsewhere; the other solvers ignore hll.
 template <int ND, int Q, int SOLVER, typename T>
-__device__ __forceinline__ void face_flux(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2], T gamma,
+__device__ __forceinline__ void face_flux(const T (&wl)[ND + 2], const T (&wr)[ND + 2], T (&f)[ND + 2], T sg,
                                           T inv_gm1, bool hll)
 {
     if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-        if (hll) riemann<ND, Q, SOLVER_HLL>(wl, wr, f, gamma, inv_gm1);
-        else riemann<ND, Q, SOLVER_HLLC>(wl, wr, f, gamma, inv_gm1);
+        if (hll) riemann<ND, Q, SOLVER_HLL>(wl, wr, f, sg, inv_gm1);
+        else riemann<ND, Q, SOLVER_HLLC>(wl, wr, f, sg, inv_gm1);
     } else {
         (void)hll;
-        riemann<ND, Q, SOLVER>(wl, wr, f, gamma, inv_gm1);
+        riemann<ND, Q, SOLVER>(wl, wr, f, sg, inv_gm1);
     }
 }
+
+template <typename T> __device__ __forceinline__ T sqrt_gamma(T gamma) { return sqrt(gamma); }
 
 // ------------------------------------------------ box face fluxes ----
 
@@ -236,7 +252,7 @@ __device__ __forceinline__ void box_faces(const T *u, const Grid &g, const Box &
             wl[v] = w4[1][v] + lim.hs * slope_mm(w4[0][v], w4[1][v], w4[2][v], lim.k);
             wr[v] = w4[2][v] - lim.hs * slope_mm(w4[1][v], w4[2][v], w4[3][v], lim.k);
         }
-        face_flux<ND, Q, SOLVER>(wl, wr, fl, gamma, inv_gm1, false);
+        face_flux<ND, Q, SOLVER>(wl, wr, fl, sqrt_gamma(gamma), inv_gm1, false);
         double *acc = side == 0 ? acc_lo : acc_hi;
 #pragma unroll
         for (int v = 0; v < ND + 2; ++v) {

@@ -205,6 +205,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     const int z0 = (ND == 3) ? bzi * a.zchunk : 0;
     const int nplanes = (ND == 3) ? (z0 + a.zchunk <= nz ? a.zchunk : nz - z0) : 1;
     const T gamma = a.gamma, gm1 = a.gm1, igm1 = a.inv_gm1;
+    const T sg = uniform_(sqrt_gamma(gamma));
     // face value = w +/- hs * slope: the minmod path keeps the slope divided
     // by theta (slope_mm), the learned path the slope itself
     const ThetaLim<T> tl = theta_lim(a.theta);
@@ -343,7 +344,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         face_state(WA, SA, -hs, fr);
         bool hll = false;
         if constexpr (SOLVER == SOLVER_HLLC_SWITCH) hll = (a.flags[(unsigned)(z0 * plane) + colo] >> 2) & 1u;
-        face_flux<ND, 2, SOLVER>(fl, fr, FA, gamma, igm1, hll);
+        face_flux<ND, 2, SOLVER>(fl, fr, FA, sg, igm1, hll);
     } else {
         load(colo, UA);
         to_w(UA, WA, fxo, fyo, false);
@@ -543,7 +544,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 const bool wall = x0 + col >= nx && a.bc[0][1] != BC_PERIODIC;
                 hll = (b >> (wall ? 3 : 0)) & 1u;
             }
-            face_flux<ND, 0, SOLVER>(wl, wr, fl, gamma, igm1, hll);
+            face_flux<ND, 0, SOLVER>(wl, wr, fl, sg, igm1, hll);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFx[v][row][col] = fl[v];
         };
@@ -560,7 +561,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 const bool wall = y0 + row >= ny && a.bc[1][1] != BC_PERIODIC;
                 hll = (b >> (wall ? 4 : 1)) & 1u;
             }
-            face_flux<ND, 1, SOLVER>(wl, wr, fl, gamma, igm1, hll);
+            face_flux<ND, 1, SOLVER>(wl, wr, fl, sg, igm1, hll);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
         };
@@ -581,7 +582,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 const unsigned b = a.flags[(wall ? zko : zoff(kz + 1, fd)) + colo];
                 hll = (b >> (wall ? 5 : 2)) & 1u;
             }
-            face_flux<ND, 2, SOLVER>(fl, fr, Fhi, gamma, igm1, hll);
+            face_flux<ND, 2, SOLVER>(fl, fr, Fhi, sg, igm1, hll);
         }
         if constexpr (ND >= 2) {
             if (tid < BX) face_y(BY, tid);
