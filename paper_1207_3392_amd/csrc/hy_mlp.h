@@ -29,8 +29,14 @@ void mlp_pack(const float *flat, MlpDevice *out);
 // lane's MFMA positions) and accumulator inputs (FP32 biases), built once per
 // weight upload so the slope kernel loads them instead of converting the FP32
 // weights in every workgroup.
+// Every pre-activation of the network is scaled by 2^-k (k from the weights,
+// so that each lies in [-1/2, 1/2] for any input in [-1, 1]); the kernels
+// take the output times up = 2^k.  Power-of-two scaling commutes with every
+// rounding involved, so the result is the unscaled network's, bit for bit.
 struct MlpImage {
     uint4 lane[64][12];
+    float up;
+    float pad[63];
 };
 
 // Builds *img from *mlp on the device (one wave).

@@ -78,26 +78,29 @@ __device__ __forceinline__ b8 bf8(const s4 lo, const s4 hi)
     return __builtin_bit_cast(b8, w);
 }
 
-// ReLU of four floats, rounded to bf16: rounding keeps the sign, so the ReLU
-// acts on the packed bf16 bit patterns, one packed 16-bit integer max per pair
-// (negative values and -0 are negative integers); equal to bf4(relu(.)) bit for bit.
-__device__ __forceinline__ unsigned pk_relu_bf16(float a, float b)
+// The K = 32 operand of the next layer from the two output blocks of a
+// 16-stencil batch: every value packed to bf16 with the conversion's output
+// clamped to [0, 1], which for pre-activations of magnitude below 1 (the
+// scaled network) is the ReLU of the rounded value, bit for bit: negative
+// values and -0 give +0.  The inputs are results of matrix instructions, which
+// a vector instruction may read only 12 cycles after they issue, and the
+// outputs feed matrix instructions, which may read a vector result only 2
+// cycles after it is written; the compiler's hazard tracking does not look
+// into inline assembly, so the wait states are part of it.
+__device__ __forceinline__ b8 relu_pack_clamped(const f4 lo, const f4 hi)
 {
-    typedef short s2 __attribute__((ext_vector_type(2)));
-    const b2 h = __builtin_convertvector((f2){a, b}, b2);
-    const s2 r = __builtin_elementwise_max(__builtin_bit_cast(s2, h), (s2){0, 0});
-    return __builtin_bit_cast(unsigned, r);
+    unsigned r0, r1, r2, r3;
+    asm("s_nop 11\n\t"
+        "v_cvt_pk_bf16_f32 %0, %4, %5 clamp\n\t"
+        "v_cvt_pk_bf16_f32 %1, %6, %7 clamp\n\t"
+        "v_cvt_pk_bf16_f32 %2, %8, %9 clamp\n\t"
+        "v_cvt_pk_bf16_f32 %3, %10, %11 clamp\n\t"
+        "s_nop 1"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+        : "v"(lo[0]), "v"(lo[1]), "v"(lo[2]), "v"(lo[3]), "v"(hi[0]), "v"(hi[1]), "v"(hi[2]), "v"(hi[3]));
+    const u4 w = {r0, r1, r2, r3};
+    return __builtin_bit_cast(b8, w);
 }
-
-__device__ __forceinline__ s4 bf4_relu(float a, float b, float c, float d)
-{
-    const u2 r = {pk_relu_bf16(a, b), pk_relu_bf16(c, d)};
-    return __builtin_bit_cast(s4, r);
-}
-
-// max(x, 0) on the bit pattern: negative floats (and -0) are negative
-// integers, so one integer max is ReLU without canonicalising the operand.
-__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 // Layer 2 runs as one K = 32 product per output block (v_mfma_f32_16x16x32_bf16:
 // lane (grp, col) holds A[col][8 grp + jj] and B[8 grp + jj][col], jj = 0..7).
@@ -114,18 +117,49 @@ struct MlpRegs {
     f4 c3;        // b3 as accumulator input
 };
 
-__device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, MlpRegs &R)
+__device__ __forceinline__ float bf_value(float x)
 {
+    const unsigned u = (unsigned)(unsigned short)bf(x) << 16;
+    return __uint_as_float(u);
+}
+
+// k with 2^k > 2 max(B1, B2), B1 = max_m sum_j |bf16(W1[m][j])| + |b1[m]|
+// (inputs lie in [-1, 1]) and B2 = max_m sum_j |bf16(W2[m][j])| B1 + |b2[m]|
+// (0 <= h1 <= B1): then every pre-activation times 2^-k lies in [-1/2, 1/2]
+// (the factor 2 covers the FP32 accumulation and bf16 rounding).
+__device__ __forceinline__ int mlp_upscale(const MlpDevice *m)
+{
+    float b1 = 0.f, b2 = 0.f;
+    for (int r = 0; r < MLP_H; ++r) {
+        float a = fabsf(m->b1[r]);
+        for (int j = 0; j < MLP_IN; ++j) a += fabsf(bf_value(m->w1[r][j]));
+        b1 = fmaxf(b1, a);
+    }
+    for (int r = 0; r < MLP_H; ++r) {
+        float a = 0.f;
+        for (int j = 0; j < MLP_H; ++j) a += fabsf(bf_value(m->w2[r][j]));
+        b2 = fmaxf(b2, a * b1 + fabsf(m->b2[r]));
+    }
+    int e = 0;
+    (void)frexpf(2.f * fmaxf(b1, b2), &e);  // 2 max(B1, B2) < 2^e
+    return e < 0 ? 0 : e;
+}
+
+// The lane's operands of the network scaled by 2^-k (k = mlp_upscale): W1
+// and every bias times 2^-k (exact: a power of two), W2 and w3 as they are.
+__device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, int k, MlpRegs &R)
+{
+    const float dn = ldexpf(1.f, -k);
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
         for (int g = 0; g < 4; ++g)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) R.a1[g][mb][j] = grp == g ? bf(m->w1[16 * mb + col][j]) : (short)0;
+            for (int j = 0; j < 4; ++j) R.a1[g][mb][j] = grp == g ? bf(m->w1[16 * mb + col][j] * dn) : (short)0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            R.c1[mb][j] = m->b1[16 * mb + 4 * grp + j];
-            R.c2[mb][j] = m->b2[16 * mb + 4 * grp + j];
+            R.c1[mb][j] = m->b1[16 * mb + 4 * grp + j] * dn;
+            R.c2[mb][j] = m->b2[16 * mb + 4 * grp + j] * dn;
         }
         const float *w2r = m->w2[16 * mb + col];
         R.a2[mb] = bf8(bf4(w2r[4 * grp], w2r[4 * grp + 1], w2r[4 * grp + 2], w2r[4 * grp + 3]),
@@ -135,7 +169,7 @@ __device__ __forceinline__ void load_regs(const MlpDevice *m, int grp, int col, 
     R.a3 = bf8(bf4(w3[4 * grp], w3[4 * grp + 1], w3[4 * grp + 2], w3[4 * grp + 3]),
                bf4(w3[16 + 4 * grp], w3[17 + 4 * grp], w3[18 + 4 * grp], w3[19 + 4 * grp]));
 #pragma unroll
-    for (int j = 0; j < 4; ++j) R.c3[j] = m->b3;
+    for (int j = 0; j < 4; ++j) R.c3[j] = m->b3 * dn;
 }
 
 static_assert(sizeof(MlpRegs) == sizeof(uint4) * 12, "lane image layout");
@@ -143,33 +177,39 @@ static_assert(sizeof(MlpRegs) == sizeof(uint4) * 12, "lane image layout");
 // Network output for the lane's own input x[0..3] (all 64 lanes must be active,
 // and every lane's input finite: 0 x inf in a zero block of an operand would
 // spread a NaN to the other lanes of the same column).
+// The four 16-stencil batches are independent: each layer is issued for all
+// of them before the next, so the matrix instructions of one batch overlap
+// the ReLU and packing of another instead of the wave waiting on each result.
+// Returns the output of the scaled network (the true output times 1 / up).
 __device__ __forceinline__ float mlp_wave(const float (&x)[4], const MlpRegs &R, int grp)
 {
     const s4 xb = bf4(x[0], x[1], x[2], x[3]);
+    f4 d1[4][2];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+            d1[g][mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[g][mb], xb, R.c1[mb], 0, 0, 0);
+    b8 hb[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) hb[g] = relu_pack_clamped(d1[g][0], d1[g][1]);
+    f4 d2[4][2];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+            d2[g][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a2[mb], hb[g], R.c2[mb], 0, 0, 0);
+    b8 h2[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) h2[g] = relu_pack_clamped(d2[g][0], d2[g][1]);
     float part[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        s4 h1[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const f4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[g][mb], xb, R.c1[mb], 0, 0, 0);
-            h1[mb] = bf4_relu(d[0], d[1], d[2], d[3]);
-        }
-        const b8 hb = bf8(h1[0], h1[1]);
-        s4 h2[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a2[mb], hb, R.c2[mb], 0, 0, 0);
-            h2[mb] = bf4_relu(d[0], d[1], d[2], d[3]);
-        }
-        const f4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a3, bf8(h2[0], h2[1]), R.c3, 0, 0, 0);
-        part[g] = y[0];
-    }
+    for (int g = 0; g < 4; ++g) part[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.a3, h2[g], R.c3, 0, 0, 0)[0];
     return grp == 0 ? part[0] : (grp == 1 ? part[1] : (grp == 2 ? part[2] : part[3]));
 }
 
-// sigma from the 5-cell stencil w[0..4] (centre w[2])
-__device__ __forceinline__ float learned_sigma(const float (&w)[5], const MlpRegs &R, int grp)
+// sigma from the 5-cell stencil w[0..4] (centre w[2]); up as in MlpImage
+__device__ __forceinline__ float learned_sigma(const float (&w)[5], const MlpRegs &R, int grp, float up)
 {
     float d[4];
 #pragma unroll
@@ -185,7 +225,7 @@ __device__ __forceinline__ float learned_sigma(const float (&w)[5], const MlpReg
     float x[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = d[k] * rs;
-    const float sigma = s * mlp_wave(x, R, grp);
+    const float sigma = s * (mlp_wave(x, R, grp) * up);  // the product with up is exact
     const float dm = d[1], dp = d[2];
     const float sg = dp > 0.f ? 1.f : -1.f;
     const float lim = 2.f * fminf(fabsf(dm), fabsf(dp));
@@ -248,6 +288,7 @@ __global__ void __launch_bounds__(ND == 1 ? 64 : 256)
     const int nrow = Q == 0 ? ny * nz : nq;
     MlpRegs M;
     __builtin_memcpy(&M, &img->lane[lane][0], sizeof(M));
+    const float up = img->up;
 
     for (int i = tid; i < RA * CA; i += NT) {
         const int r = i / CA, c = i % CA;
@@ -289,14 +330,17 @@ __global__ void __launch_bounds__(ND == 1 ? 64 : 256)
         float w5[5];
 #pragma unroll
         for (int s5 = 0; s5 < 5; ++s5) w5[s5] = Q == 0 ? sW[v][r][lane + s5] : sW[v][r + s5][lane];
-        const float sg = learned_sigma(w5, M, grp);
+        const float sg = learned_sigma(w5, M, grp, up);
         const int rowi = b0 + r;
         if (x < nx && rowi < nrow) {
-            int64_t cell;
-            if constexpr (Q == 0) cell = (int64_t)rowi * nx + x;
-            else if constexpr (Q == 1) cell = ((int64_t)cf * ny + rowi) * nx + x;
-            else cell = ((int64_t)rowi * ny + cf) * nx + x;
-            slopes[(int64_t)(Q * NP + v) * svs + cell] = sg;
+            // a variable's slope array is below 4 GiB (checked on the host):
+            // 32-bit byte offsets from its (wave-uniform) base
+            unsigned cell;
+            if constexpr (Q == 0) cell = (unsigned)rowi * (unsigned)nx + (unsigned)x;
+            else if constexpr (Q == 1) cell = ((unsigned)cf * (unsigned)ny + (unsigned)rowi) * (unsigned)nx + (unsigned)x;
+            else cell = ((unsigned)rowi * (unsigned)ny + (unsigned)cf) * (unsigned)nx + (unsigned)x;
+            char *base = (char *)(slopes + (int64_t)(Q * NP + v) * svs);
+            *(float *)(base + cell * 4u) = sg;
         }
     }
 }
@@ -316,21 +360,25 @@ void ls_launch(const float *u, float *slopes, int nx, int ny, int nz, int64_t vs
 __global__ void __launch_bounds__(64) k_mlp_image(const MlpDevice *__restrict__ mlp, MlpImage *__restrict__ img)
 {
     const int lane = threadIdx.x, grp = lane >> 4, col = lane & 15;
+    const int k = mlp_upscale(mlp);
     MlpRegs R;
-    load_regs(mlp, grp, col, R);
+    load_regs(mlp, grp, col, k, R);
     __builtin_memcpy(&img->lane[lane][0], &R, sizeof(R));
+    if (lane == 0) img->up = ldexpf(1.f, k);
 }
 
 __global__ void __launch_bounds__(256) k_mlp_forward(const MlpDevice *__restrict__ mlp, const float *__restrict__ x,
                                                      float *__restrict__ y, int64_t batch)
 {
     const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
+    const int k = mlp_upscale(mlp);
+    const float up = ldexpf(1.f, k);
     MlpRegs R;
-    load_regs(mlp, grp, col, R);
+    load_regs(mlp, grp, col, k, R);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t ii = i < batch ? i : batch - 1;
     const float xi[4] = {x[4 * ii], x[4 * ii + 1], x[4 * ii + 2], x[4 * ii + 3]};
-    const float out = mlp_wave(xi, R, grp);
+    const float out = mlp_wave(xi, R, grp) * up;
     if (i < batch) y[i] = out;
 }
 
