@@ -71,7 +71,6 @@ struct StageArgs {
     T *uout;          // output (U^(1) in stage 1; U^{n+1} over U^n in stage 2)
     const T *u0;      // stage 2: U^n, read only at the thread's own cell (aliases uout)
     const float *slopes;  // learned limiter: (ndim * nv, ncell) slopes of the stage input
-    const uint8_t *flags; // HLLC switch: per cell, bit q = HLL at the low face along q, bit 3+q at a wall's high face
     int64_t n[3];
     int64_t vstride;  // elements between variables
     T idx[3];         // 1 / dq
@@ -100,15 +99,8 @@ template <typename T>
 hipError_t launch_stage(int ndim, int solver, int stage, int limiter, const LaunchCfg &cfg,
                         const StageArgs<T> &a, hipStream_t s);
 
-// Face decisions of the HLLC switch for the state u (defined in shock.hip).
-// det receives the detector bits (bit q: the pressures of the two neighbours
-// along q differ by more than eps times the smaller one and the normal
-// velocity decreases across the cell); flags the decisions: bit q = HLL at
-// the cell's low face along q, bit 3 + q = HLL at the high face of a cell at
-// the high end of a non-periodic dimension q.
-template <typename T>
-hipError_t launch_shock_flags(const T *u, uint8_t *det, uint8_t *flags, const int64_t n[3], int64_t vstride, int ndim,
-                              const int bc[3][2], T gm1, T eps, hipStream_t s);
+// Threshold of the HLLC switch's shock detector (relative pressure jump
+// across a cell; the stage kernel evaluates the detector).
 constexpr double SHOCK_EPS = 0.5;
 
 // Device-side helpers (defined in reduce.hip).

@@ -46,8 +46,6 @@ struct hy_patch {
     void *A = nullptr;  // U^n (and U^{n+1}, written in place by stage 2)
     void *B = nullptr;  // U^(1)
     float *slopes = nullptr;
-    uint8_t *det = nullptr;    // HLLC switch: detector bits of the stage input
-    uint8_t *flags = nullptr;  // HLLC switch: face decisions of the stage input
     hy::MlpDevice *mlp = nullptr;
     hy::MlpImage *mlpimg = nullptr;
     bool mlp_set = false;
@@ -117,7 +115,7 @@ hy_status check_desc(const hy_patch_desc *d)
 }
 
 struct Layout {
-    size_t ctl, partials, A, B, slopes, det, flags, mlp, mlpimg, total;
+    size_t ctl, partials, A, B, slopes, mlp, mlpimg, total;
     int64_t vstride;
 };
 
@@ -142,10 +140,6 @@ Layout layout(const hy_patch_desc &d)
     o = align_up(o + es * nv * (size_t)L.vstride, 256);
     L.slopes = o;
     if (d.limiter == HY_LIM_LEARNED) o = align_up(o + sizeof(float) * d.ndim * nv * (size_t)L.vstride, 256);
-    L.det = o;
-    o = align_up(o + (size_t)ncells(d), 256);
-    L.flags = o;
-    o = align_up(o + (size_t)ncells(d), 256);
     L.total = o + 256;  // slack for aligning the caller's base pointer
     return L;
 }
@@ -162,7 +156,6 @@ hy::StageArgs<T> stage_args(hy_patch *p, int stage, int dt_mode, double dt, doub
     a.uout = stage == 1 ? B : A;
     a.u0 = A;
     a.slopes = p->slopes;
-    a.flags = p->flags;
     for (int q = 0; q < 3; ++q) {
         a.n[q] = p->padded ? p->inner[q] : d.n[q];
         a.voff[q] = p->padded && q < d.ndim ? 2 : 0;  // the interior of a padded level
@@ -196,12 +189,6 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
         const T *uin = (const T *)(stage == 1 ? p->A : p->B);
         e = hy::launch_learned_slopes((const float *)uin, p->slopes, p->d.n, p->vstride, p->vstride, p->d.ndim,
                                       (float)(p->d.gamma - 1.0), p->d.bc, p->mlpimg, p->stream);
-        if (e != hipSuccess) return e;
-    }
-    if (solver == HY_HLLC_SWITCH && p->d.ndim >= 2) {
-        const T *uin = (const T *)(stage == 1 ? p->A : p->B);
-        e = hy::launch_shock_flags<T>(uin, p->det, p->flags, p->d.n, p->vstride, p->d.ndim, p->d.bc, (T)(p->d.gamma - 1.0),
-                                      (T)hy::SHOCK_EPS, p->stream);
         if (e != hipSuccess) return e;
     }
     const int k = stage - 1;
@@ -417,8 +404,6 @@ hy_status hy_init_patch(const hy_patch_desc *desc, void *dev_workspace, size_t b
     p->A = base + L.A;
     p->B = base + L.B;
     p->slopes = desc->limiter == HY_LIM_LEARNED ? (float *)(base + L.slopes) : nullptr;
-    p->det = (uint8_t *)(base + L.det);
-    p->flags = (uint8_t *)(base + L.flags);
     p->stream = (hipStream_t)hip_stream;
     pick_config(p);
     hipError_t e = hy::launch_ctl_init(p->ctl, p->stream);
@@ -706,14 +691,6 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
     if (d.limiter == HY_LIM_LEARNED)  // stage 1 reads the slopes of U^n
         e = hy::launch_learned_slopes((const float *)p->A, p->slopes, d.n, p->vstride, p->vstride, d.ndim,
                                       (float)(d.gamma - 1.0), d.bc, p->mlpimg, p->stream);
-    if (e == hipSuccess && solver == HY_HLLC_SWITCH && d.ndim >= 2) {  // and the switch the shock flags of U^n
-        if (d.precision == 64)
-            e = hy::launch_shock_flags<double>((const double *)p->A, p->det, p->flags, d.n, p->vstride, d.ndim, d.bc,
-                                               d.gamma - 1.0, hy::SHOCK_EPS, p->stream);
-        else
-            e = hy::launch_shock_flags<float>((const float *)p->A, p->det, p->flags, d.n, p->vstride, d.ndim, d.bc,
-                                              (float)(d.gamma - 1.0), (float)hy::SHOCK_EPS, p->stream);
-    }
     // One trial = the two stages of a step with dt = 0, both reading U^n and
     // writing only the scratch state U^(1) (the second stage with U^n as its
     // input and as its U^n term, so it does the second stage's full work);

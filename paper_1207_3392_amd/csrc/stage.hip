@@ -159,6 +159,18 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     __shared__ T sFx[NP][BY][BX + 1];   // x faces 0 .. BX (face f between cells f-1, f)
     __shared__ T sFy[NP][FYR][BX];      // y faces 0 .. BY
     __shared__ int sMap[WX + RY];       // mapped x of columns -2 .. BX+1, then mapped y of rows -2 .. BY+1
+    // HLLC switch: the shock-detector bits of the current plane (cells of
+    // rows -1 .. BY and columns -1 .. BX, corners unused), and in 3D the
+    // pressure and in-plane velocities of the next plane over the same cells
+    constexpr bool SW = SOLVER == SOLVER_HLLC_SWITCH;
+    constexpr bool SW3 = SW && ND == 3;
+    __shared__ uint8_t sB[SW ? BY + 2 : 1][SW ? BX + 2 : 1];
+    __shared__ T sN[SW3 ? 3 : 1][SW3 ? BY + 2 : 1][SW3 ? BX + 2 : 1];
+    // (3D switch) p and v_z of the plane below the current one, own and ring
+    // cells: each thread reads and rewrites only its own cells' entries
+    __shared__ T sC[SW3 ? 2 : 1][SW3 ? BY + 2 : 1][SW3 ? BX + 2 : 1];
+    // (3D switch) v_z of the ring cells in the next plane (p sits in sN)
+    __shared__ T sV[SW3 ? BY + 2 : 1][SW3 ? BX + 2 : 1];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
@@ -297,6 +309,51 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         }
     }
 
+    // HLLC switch, detector of Sec. 3.2's switch (the reading the oracle
+    // takes): a cell is in a shock moving along q when the pressures of its
+    // neighbours along q differ by more than eps times the smaller one and
+    // the velocity along q decreases across it; a face normal to r takes HLL
+    // when one of its two cells is flagged along some q != r.  Ring item tid
+    // (the first 2 BX + 2 BY threads): rows -1 and BY of the tile, then
+    // columns -1 and BX of its rows; its ghost values come through the same
+    // boundary map (and mirror signs) as the halo.
+    constexpr int NRING = 2 * BX + 2 * BY;
+    const bool ringt = SW && tid < NRING;
+    // the ring cell's tile row and column (formed where used, so nothing of
+    // it stays in registers through the march)
+    auto ring_rc = [&](int &r, int &c) {
+        if (tid < 2 * BX) {
+            r = tid < BX ? -1 : BY;
+            c = tid < BX ? tid : tid - BX;
+        } else {
+            const int e = tid - 2 * BX;
+            r = e >> 1;
+            c = (e & 1) ? BX : -1;
+        }
+    };
+    const T seps = (T)SHOCK_EPS;
+    auto shock = [&](T pa, T pb, T va, T vb) -> bool {
+        return (fabs(pb - pa) > seps * fmin(pa, pb)) & (vb - va < T(0));
+    };
+    // x and y bits of the cell at tile (row r, column c) of the current plane
+    auto bits_w = [&](int r, int c) -> unsigned {
+        unsigned b = shock(sW[IP][r + OY][c + 1], sW[IP][r + OY][c + 3], sW[1][r + OY][c + 1], sW[1][r + OY][c + 3]);
+        if constexpr (ND >= 2)
+            b |= shock(sW[IP][r + OY - 1][c + 2], sW[IP][r + OY + 1][c + 2], sW[2][r + OY - 1][c + 2],
+                       sW[2][r + OY + 1][c + 2])
+                 << 1;
+        return b;
+    };
+    // x and y bits of the own cell in the plane held by sN
+    auto bits_n = [&]() -> unsigned {
+        if constexpr (SW3) {
+            return (unsigned)shock(sN[0][ty + 1][tx], sN[0][ty + 1][tx + 2], sN[1][ty + 1][tx], sN[1][ty + 1][tx + 2]) |
+                   ((unsigned)shock(sN[0][ty][tx + 1], sN[0][ty + 2][tx + 1], sN[2][ty][tx + 1], sN[2][ty + 2][tx + 1])
+                    << 1);
+        }
+        return 0u;
+    };
+
     bool bad = false;
     T rate = T(0);
 
@@ -313,6 +370,19 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     auto face_state = [&](const T (&w)[NP], const T (&s)[NP], T h, T (&out)[NP]) {
 #pragma unroll
         for (int v = 0; v < NP; ++v) out[v] = w[v] + h * s[v];
+    };
+    // the ring cell of this thread at plane z: pressure and the three
+    // velocities, mirror signs applied (3D switch)
+    auto ring_prim = [&](int z, int r, int c, T &p, T &vxr, T &vyr, T &vzr) {
+        bool fz = false;
+        T u[NP], w[NP];
+        const int rmx = sMap[c + 2], rmy = sMap[WX + r + 2];
+        load(zoff(z, fz) + (unsigned)((rmy & IDX) * sx + (rmx & IDX)), u);
+        (void)to_prim<ND>(u, w, gm1);
+        p = w[IP];
+        vxr = (rmx & FLIP) ? -w[1] : w[1];
+        vyr = (rmy & FLIP) ? -w[2] : w[2];
+        vzr = fz ? -w[3] : w[3];
     };
 
     // register z window: W (primitives), U (conserved), S (z slopes) and F
@@ -343,7 +413,41 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         face_state(wm1, sm1, hs, fl);
         face_state(WA, SA, -hs, fr);
         bool hll = false;
-        if constexpr (SOLVER == SOLVER_HLLC_SWITCH) hll = (a.flags[(unsigned)(z0 * plane) + colo] >> 2) & 1u;
+        if constexpr (SW3) {
+            // the face below the chunk: x and y bits of planes z0 - 1 and z0
+            // (their in-plane neighbours through sN, one plane at a time)
+            T p, vxr, vyr, vzr;
+            int rr = 0, rc = 0;
+            ring_rc(rr, rc);
+            sN[0][ty + 1][tx + 1] = wm1[IP];
+            sN[1][ty + 1][tx + 1] = wm1[1];
+            sN[2][ty + 1][tx + 1] = wm1[2];
+            if (ringt) {
+                ring_prim(z0 - 1, rr, rc, p, vxr, vyr, vzr);
+                sN[0][rr + 1][rc + 1] = p;
+                sN[1][rr + 1][rc + 1] = vxr;
+                sN[2][rr + 1][rc + 1] = vyr;
+                sC[0][rr + 1][rc + 1] = p;
+                sC[1][rr + 1][rc + 1] = vzr;
+            }
+            sC[0][ty + 1][tx + 1] = wm1[IP];
+            sC[1][ty + 1][tx + 1] = wm1[3];
+            __syncthreads();
+            const unsigned xym = bits_n();
+            __syncthreads();
+            sN[0][ty + 1][tx + 1] = WA[IP];
+            sN[1][ty + 1][tx + 1] = WA[1];
+            sN[2][ty + 1][tx + 1] = WA[2];
+            if (ringt) {
+                ring_prim(z0, rr, rc, p, vxr, vyr, vzr);
+                sN[0][rr + 1][rc + 1] = p;
+                sN[1][rr + 1][rc + 1] = vxr;
+                sN[2][rr + 1][rc + 1] = vyr;
+            }
+            __syncthreads();
+            hll = (xym | bits_n()) != 0u;
+            __syncthreads();
+        }
         face_flux<ND, 2, SOLVER>(fl, fr, FA, sg, igm1, hll);
     } else {
         load(colo, UA);
@@ -430,6 +534,24 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
 #pragma unroll
         for (int v = 0; v < NP; ++v) sW[v][ty + OY][tx + 2] = Wk[v];
+        // switch (3D): the next plane's p and in-plane velocities of the own
+        // cell and the ring cell (whose p and v_z also give its z bit)
+        // (the ring cell's p and v_z there wait in sN's and the z slot of sC)
+        if constexpr (SW3) {
+            sN[0][ty + 1][tx + 1] = Wk1[IP];
+            sN[1][ty + 1][tx + 1] = Wk1[1];
+            sN[2][ty + 1][tx + 1] = Wk1[2];
+            if (ringt) {
+                int rr, rc;
+                ring_rc(rr, rc);
+                T p, vxr, vyr, vzr;
+                ring_prim(kz + 1, rr, rc, p, vxr, vyr, vzr);
+                sN[0][rr + 1][rc + 1] = p;
+                sN[1][rr + 1][rc + 1] = vxr;
+                sN[2][rr + 1][rc + 1] = vyr;
+                sV[rr + 1][rc + 1] = vzr;
+            }
+        }
         T hcur[HPT][NP];
         if constexpr (LATE) {
             load_halo(kz, hcur);
@@ -521,6 +643,33 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 for (int v = 0; v < NP; ++v) sSx[v][ering >> 1][(ering & 1) ? BX + 1 : 0] = lrx[v];
             }
         }
+        if constexpr (SW) {
+            // detector bits of plane kz: own cell and ring cell (the z bit
+            // from the planes below and above; the current plane then becomes
+            // the one below); the own cell's byte also keeps its x and y bits
+            // of the next plane in bits 4 and 5 for its z face
+            unsigned ob = bits_w(ty, tx);
+            if constexpr (SW3) {
+                ob |= (unsigned)shock(sC[0][ty + 1][tx + 1], Wk1[IP], sC[1][ty + 1][tx + 1], Wk1[3]) << 2;
+                sC[0][ty + 1][tx + 1] = Wk[IP];
+                sC[1][ty + 1][tx + 1] = Wk[3];
+                ob |= bits_n() << 4;
+            }
+            sB[ty + 1][tx + 1] = (uint8_t)ob;
+            if (ringt) {
+                int rr, rc;
+                ring_rc(rr, rc);
+                unsigned rb = bits_w(rr, rc);
+                if constexpr (SW3) {
+                    rb |= (unsigned)shock(sC[0][rr + 1][rc + 1], sN[0][rr + 1][rc + 1], sC[1][rr + 1][rc + 1],
+                                          sV[rr + 1][rc + 1])
+                          << 2;
+                    sC[0][rr + 1][rc + 1] = sW[IP][rr + OY][rc + 2];
+                    sC[1][rr + 1][rc + 1] = sW[3][rr + OY][rc + 2];
+                }
+                sB[rr + 1][rc + 1] = (uint8_t)rb;
+            }
+        }
         if (ring1) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         if (ring2) __builtin_amdgcn_s_setprio(3);
@@ -536,14 +685,9 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 wl[v] = sW[v][row + OY][col + 1] + hs * sSx[v][row][col];
                 wr[v] = sW[v][row + OY][col + 2] - hs * sSx[v][row][col + 1];
             }
-            // switch: the decision stored with the face's high cell (at a
-            // non-periodic high wall, with the last cell)
+            // switch: HLL when either cell is flagged along y or z
             bool hll = false;
-            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-                const unsigned b = a.flags[zko + (unsigned)((sMap[WX + row + 2] & IDX) * nx + (sMap[col + 2] & IDX))];
-                const bool wall = x0 + col >= nx && a.bc[0][1] != BC_PERIODIC;
-                hll = (b >> (wall ? 3 : 0)) & 1u;
-            }
+            if constexpr (SW) hll = ((sB[row + 1][col] | sB[row + 1][col + 1]) & 6u) != 0u;
             face_flux<ND, 0, SOLVER>(wl, wr, fl, sg, igm1, hll);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFx[v][row][col] = fl[v];
@@ -555,12 +699,9 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 wl[v] = sW[v][row + 1][col + 2] + hs * sSy[v][row][col];
                 wr[v] = sW[v][row + 2][col + 2] - hs * sSy[v][row + 1][col];
             }
+            // switch: HLL when either cell is flagged along x or z
             bool hll = false;
-            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-                const unsigned b = a.flags[zko + (unsigned)((sMap[WX + row + 2] & IDX) * nx + (sMap[col + 2] & IDX))];
-                const bool wall = y0 + row >= ny && a.bc[1][1] != BC_PERIODIC;
-                hll = (b >> (wall ? 4 : 1)) & 1u;
-            }
+            if constexpr (SW) hll = ((sB[row][col + 1] | sB[row + 1][col + 1]) & 5u) != 0u;
             face_flux<ND, 1, SOLVER>(wl, wr, fl, sg, igm1, hll);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
@@ -575,12 +716,11 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             T fl[NP], fr[NP];
             face_state(Wk, Sk, hs, fl);
             face_state(Wk1, Sk1, -hs, fr);
+            // switch: HLL when the cell of plane kz or kz + 1 is flagged along x or y
             bool hll = false;
-            if constexpr (SOLVER == SOLVER_HLLC_SWITCH) {
-                const bool wall = kz + 1 >= nz && a.bc[2][1] != BC_PERIODIC;
-                bool fd = false;
-                const unsigned b = a.flags[(wall ? zko : zoff(kz + 1, fd)) + colo];
-                hll = (b >> (wall ? 5 : 2)) & 1u;
+            if constexpr (SW3) {
+                const unsigned b = sB[ty + 1][tx + 1];
+                hll = ((b | (b >> 4)) & 3u) != 0u;
             }
             face_flux<ND, 2, SOLVER>(fl, fr, Fhi, sg, igm1, hll);
         }

@@ -50,6 +50,29 @@ def test_mfma_inference_matches_oracle():
     tr.close()
 
 
+def test_mfma_inference_is_exactly_homogeneous_under_power_of_two_scaling():
+    """The network is positively homogeneous: scaling W1 and every bias by 2^j
+    scales the output by 2^j.  With bf16 operands and FP32 accumulation this
+    holds bit for bit (powers of two commute with rounding), also when the
+    weights' bound moves the kernel's internal power-of-two shift (j up to 40)
+    and when it is zero (all weights tiny)."""
+    P = random_params(17)
+    rng = np.random.default_rng(18)
+    X = rng.uniform(-1, 1, size=(4096, 4)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(P)
+    tr = hydro.Trainer(P)
+    y0 = tr.eval(Xd).cpu().numpy()
+    tr.close()
+    assert np.any(y0 != 0)
+    for j in (1, 7, 40, -20):
+        Pj = mlp.pack(W1 * 2.0 ** j, b1 * 2.0 ** j, W2, b2 * 2.0 ** j, w3, b3 * 2.0 ** j).astype(np.float32)
+        tr = hydro.Trainer(Pj)
+        yj = tr.eval(Xd).cpu().numpy()
+        tr.close()
+        assert np.array_equal(yj, (y0.astype(np.float64) * 2.0 ** j).astype(np.float32)), j
+
+
 def _abs_gradient(P, X, T, bf16=True):
     """Per-parameter sum over the batch of the magnitudes of the terms that
     make up the oracle's gradient (the backward pass on |.| of every factor,
