@@ -54,20 +54,20 @@ ALU_PEAK_UNPACKED_TFLOPS = 78.6
 #   new state 36 (stage 2 only).
 FLOPS_PER_CELL = {"hllc": {1: 478, 2: 524}, "hll": {1: 448, 2: 494}}
 
-# Measured HBM bytes per launch of the 3D FP32 HLLC stage kernels (64x8 tile),
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this benchmark, scaled by
-# what the same counters read for a 1 GiB device copy (FETCH x2.0, WRITE x1.0);
-# the summaries are kept under profiles/.  The figures hold only for the
-# kernel source and launch configuration they were taken on (the source is
-# identified by its digest); after any change the traffic is reported as null
-# until the counters are retaken.
+# Measured HBM bytes per launch of the 3D FP32 HLLC stage kernels on the
+# 512^3 patch (64x8 tile), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of
+# this benchmark, scaled by what the same counters read for a 1 GiB device
+# copy (FETCH x2.0, WRITE x1.0); the summary is profiles/stage3d_512_hllc.md.
+# The figures hold only for the kernel source and launch configuration they
+# were taken on (the source is identified by its digest); after any change the
+# traffic is reported as null until the counters are retaken.
 TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/csrc/hy_internal.h",
                    "paper_1207_3392_amd/csrc/hy_face.h")
 TRAFFIC = {
-    "digest": "9e28e9522d4396debc3698f1bb5dcd4a768f051a8b1f3da164977c5540646465",
-    "ncell": 256 ** 3,
+    "digest": "88354780b014346948c24d78b89b69ce29a1b1c0f05b3dc7fc2fe3f0c234603a",
+    "ncell": 512 ** 3,
     "kernel": "k_stage<nd=3,f32,tile=64x8> zchunk=64",
-    "bytes_per_launch": {1: 703892827, 2: 1096550656},
+    "bytes_per_launch": {1: 5934428022, 2: 9410935894},
 }
 
 

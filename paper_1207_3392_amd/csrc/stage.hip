@@ -485,32 +485,33 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             for (int v = 0; v < NP; ++v) u0[v] = own_valid ? at(u0p[v], zko + colv) : T(0);
         }
 
-        // learned limiter: the own cell's x and y slopes (and the z slope of
-        // plane kz+1) and this thread's ring slope are loaded here and stored
-        // in phase 1, so their latency overlaps phase 0 and its barrier
-        T lsx[NP], lsy[NP], lsz[NP], lry[NP], lrx[NP];
+        // learned limiter: the own cell's x and y slopes and this thread's
+        // ring slope go from the slope array straight into the LDS slope
+        // tiles (free until phase 2) before the first barrier, so none of
+        // them is held in registers across it; the z slope of plane kz+1 is
+        // loaded in phase 1, where it is used
+        T lsx[NP], lsy[NP], lry[NP], lrx[NP];
         const int ering = tid - (NT - 2 * BY);  // x ring item of the last threads
         if constexpr (LIM == LIM_LEARNED) {
             if (own_valid) {
-                // an interior cell: the slopes sit at its own offset (and one
-                // plane up for z, unless that plane is past the last one)
+                // an interior cell: the slopes sit at its own offset
                 const unsigned o = zko + colv;
-                const bool ztop = ND == 3 && kz + 1 >= nz;
 #pragma unroll
                 for (int v = 0; v < NP; ++v) {
                     lsx[v] = (T)at(a.slopes + (int64_t)v * a.vstride, o);
                     if constexpr (ND >= 2) lsy[v] = (T)at(a.slopes + (int64_t)(NP + v) * a.vstride, o);
-                    if constexpr (ND == 3)
-                        lsz[v] = ztop ? learned_slope<ND>(a, 2, v, gx, gy, kz + 1)
-                                      : (T)at(a.slopes + (int64_t)(2 * NP + v) * a.vstride, o + (unsigned)plane);
                 }
             } else {  // a ghost column of a partial tile: boundary-mapped slopes
 #pragma unroll
                 for (int v = 0; v < NP; ++v) {
                     lsx[v] = learned_slope<ND>(a, 0, v, gx, gy, kz);
                     if constexpr (ND >= 2) lsy[v] = learned_slope<ND>(a, 1, v, gx, gy, kz);
-                    if constexpr (ND == 3) lsz[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
                 }
+            }
+#pragma unroll
+            for (int v = 0; v < NP; ++v) {
+                sSx[v][ty][tx + 1] = lsx[v];
+                if constexpr (ND >= 2) sSy[v][ty + 1][tx] = lsy[v];
             }
             // ring slope of cell (rx, ry): direct inside the domain, boundary
             // mapped for a ghost (in 3D the extra code path costs more
@@ -526,9 +527,17 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 }
             };
             if constexpr (ND >= 2) {
-                if (tid < 2 * BX) ring_slope(1, x0 + (tid < BX ? tid : tid - BX), y0 + (tid < BX ? -1 : BY), lry);
+                if (tid < 2 * BX) {
+                    ring_slope(1, x0 + (tid < BX ? tid : tid - BX), y0 + (tid < BX ? -1 : BY), lry);
+#pragma unroll
+                    for (int v = 0; v < NP; ++v) sSy[v][tid < BX ? 0 : BY + 1][tid < BX ? tid : tid - BX] = lry[v];
+                }
             }
-            if (ering >= 0) ring_slope(0, x0 + ((ering & 1) ? BX : -1), y0 + (ering >> 1), lrx);
+            if (ering >= 0) {
+                ring_slope(0, x0 + ((ering & 1) ? BX : -1), y0 + (ering >> 1), lrx);
+#pragma unroll
+                for (int v = 0; v < NP; ++v) sSx[v][ering >> 1][(ering & 1) ? BX + 1 : 0] = lrx[v];
+            }
         }
 
         // ---- phase 0: primitives of plane kz into LDS (own cell + halo) ----
@@ -611,19 +620,20 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         if constexpr (LIM != LIM_LEARNED) {
             slope_x(ty, tx);
             if constexpr (ND >= 2) slope_y(ty, tx);
-        } else {
-#pragma unroll
-            for (int v = 0; v < NP; ++v) {
-                sSx[v][ty][tx + 1] = lsx[v];
-                if constexpr (ND >= 2) sSy[v][ty + 1][tx] = lsy[v];
-            }
         }
         if constexpr (ND == 3) {
             to_w(U2, W2, fxo, fyo, fz2);
+            if constexpr (LIM != LIM_LEARNED) {
 #pragma unroll
-            for (int v = 0; v < NP; ++v) {
-                if constexpr (LIM != LIM_LEARNED) Sk1[v] = slope_mm(Wk[v], Wk1[v], W2[v], lk);
-                else Sk1[v] = lsz[v];
+                for (int v = 0; v < NP; ++v) Sk1[v] = slope_mm(Wk[v], Wk1[v], W2[v], lk);
+            } else if (own_valid && kz + 1 < nz) {
+                // the z slope of plane kz+1: one plane up at the own offset
+                const unsigned o = zko + colv + (unsigned)plane;
+#pragma unroll
+                for (int v = 0; v < NP; ++v) Sk1[v] = (T)at(a.slopes + (int64_t)(2 * NP + v) * a.vstride, o);
+            } else {  // past the last plane, or a ghost column: boundary-mapped
+#pragma unroll
+                for (int v = 0; v < NP; ++v) Sk1[v] = learned_slope<ND>(a, 2, v, gx, gy, kz + 1);
             }
         }
         if constexpr (LIM != LIM_LEARNED) {
@@ -631,17 +641,6 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 if (tid < 2 * BX) slope_y(tid < BX ? -1 : BY, tid < BX ? tid : tid - BX);
             }
             if (ering >= 0) slope_x(ering >> 1, (ering & 1) ? BX : -1);
-        } else {
-            if constexpr (ND >= 2) {
-                if (tid < 2 * BX) {
-#pragma unroll
-                    for (int v = 0; v < NP; ++v) sSy[v][tid < BX ? 0 : BY + 1][tid < BX ? tid : tid - BX] = lry[v];
-                }
-            }
-            if (ering >= 0) {
-#pragma unroll
-                for (int v = 0; v < NP; ++v) sSx[v][ering >> 1][(ering & 1) ? BX + 1 : 0] = lrx[v];
-            }
         }
         if constexpr (SW) {
             // detector bits of plane kz: own cell and ring cell (the z bit

@@ -18,6 +18,7 @@ the smooth density wave (Sec. 4.1.1), also against fine plain runs.
 Usage:
     python -m paper_1207_3392_amd.limiter_study train --out weights.npy
     python -m paper_1207_3392_amd.limiter_study eval --weights weights.npy --json out.json
+    python -m paper_1207_3392_amd.limiter_study c3 --json out.json
 """
 from __future__ import annotations
 
@@ -137,12 +138,12 @@ def restrict(a: np.ndarray, n: int) -> np.ndarray:
     return a.reshape(n, r, n, r).mean(axis=(1, 3))
 
 
-def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64, diag=None):
+def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64, diag=None, progress=None):
     """Density at each requested time (plain limiter if params is None),
     with the wall time of the whole run.  With a dict ``diag`` (2D), also
     E_kin,y at each time (diag["ekin_y"]) and the kinetic-energy spectrum at
     the last time (diag["spectrum"] = (k, e)); their cost is outside the wall
-    time."""
+    time.  ``progress`` (a callable) hears the simulation time every ~10 s."""
     import torch
 
     cfl = prob.cfl if cfl is None else cfl
@@ -153,11 +154,15 @@ def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64, d
         p.set_state(prob.W)
     out = {}
     wall = 0.0
+    last = time.perf_counter()
     for T in times:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while p.time() < T * (1 - 1e-12):
             p.advance(chunk, cfl, t_end=T, solver=hydro.HLLC)
+            if progress is not None and time.perf_counter() - last > 10.0:
+                last = time.perf_counter()
+                progress(f"{prob.name} {prob.n[0]}: t = {p.time():.4f}")
         U = p.get_state(hydro.CONSERVED)
         wall += time.perf_counter() - t0
         shape = (prob.n[1], prob.n[0]) if prob.ndim == 2 else (prob.n[0],)
@@ -199,20 +204,20 @@ def spectral_error(k, e, kr, er, n, level: float = 1e-9):
     return float(np.mean(np.abs(np.log(e[keep] / er[keep]))))
 
 
-def ladder(name, make, ns, n_ref, times, params, log=print, diagnose=False):
+def ladder(name, make, ns, n_ref, times, params, log=print, diagnose=False, progress=None):
     """L1 of plain and learned runs at each N against the restricted fine plain
     run; with ``diagnose`` (2D) also E_kin,y(t) of every run and the kinetic
     energy spectra at the last time (Sec. 4.3.1's yardsticks)."""
     dref = {} if diagnose else None
-    ref, ref_wall = run_to_times(make(n_ref), times, diag=dref)
+    ref, ref_wall = run_to_times(make(n_ref), times, diag=dref, progress=progress)
     log(f"{name}: reference {n_ref} in {ref_wall:.1f} s")
     rows = []
     spectra = {}
     for n in ns:
         dp = {} if diagnose else None
         dl = {} if diagnose else None
-        pl, wp = run_to_times(make(n), times, diag=dp)
-        le, wlr = run_to_times(make(n), times, params=params, diag=dl)
+        pl, wp = run_to_times(make(n), times, diag=dp, progress=progress)
+        le, wlr = run_to_times(make(n), times, params=params, diag=dl, progress=progress)
         if diagnose:
             kr, er = dref["spectrum"]
             spectra[n] = {
@@ -261,6 +266,38 @@ def evaluate(params, kh_ns=(128, 256, 512, 1024), kh_ref=4096, kh_times=(0.5, 1.
     return res
 
 
+def c3(params, ns=(512, 1024, 2048), n_ref=8192, T=1.5, log=print):
+    """The Kelvin-Helmholtz comparison at its full size: plain and learned
+    runs at 2048^2 (and 512^2, 1024^2 for the matched-L1 reading) to t = 1.5
+    against a plain 8192^2 run restricted to each N, for the sharp shear
+    layers of the Sec. 4.3.1 setup (seed 1207; no convergence in N is
+    expected there, so E_kin,y and the spectrum are the yardsticks) and for
+    the smooth-layer variant of the ladders above.  Records L1, E_kin,y at
+    t = 0.5, 1, 1.5, the spectral error at t = 1.5, the wall times, and the
+    time the learned run takes over the time the plain method needs for the
+    same L1 (a 2D run costs N^3)."""
+    out = {}
+    times = (0.5, 1.0, T)
+    for key, make in (("sharp_layers", lambda n: wl.kelvin_helmholtz(n, seed=1207)),
+                      ("smooth_layers", lambda n: wl.kelvin_helmholtz(n, seed=HELD_OUT_SEED, width=EVAL_WIDTH,
+                                                                       random_amp=0.0))):
+        r = ladder(key, make, ns, n_ref, times, params, log=log, diagnose=True, progress=log)
+        last = [x for x in r["rows"] if x["t"] == T]
+        wall = {x["n"]: (x["wall_plain"], x["wall_learned"]) for x in last}
+        for m in r["matched"]:
+            if m["t"] != T:
+                continue
+            n = m["n_learned"]
+            n_eq = m["plain_n_for_same_l1"]
+            # plain wall time at the resolution with the same L1, from the
+            # measured plain wall time at N scaled as N^3
+            if n_eq == n_eq:
+                m["time_ratio_learned_over_plain"] = wall[n][1] / (wall[n][0] * (n_eq / n) ** 3)
+        out[key] = r
+        log(f"{key}: " + json.dumps([{k: v for k, v in m.items()} for m in r["matched"] if m["t"] == T]))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -279,6 +316,11 @@ def main(argv=None):
     e.add_argument("--kh-ns", default="128,256,512,1024")
     e.add_argument("--kh-ref", type=int, default=4096)
     e.add_argument("--json", default="")
+    c = sub.add_parser("c3", help="the 2048^2 Kelvin-Helmholtz comparison to t = 1.5 against 8192^2")
+    c.add_argument("--weights", default="", help="weights (.npy); default: the shipped network")
+    c.add_argument("--n-ref", type=int, default=8192)
+    c.add_argument("--ns", default="512,1024,2048")
+    c.add_argument("--json", default="")
     a = ap.parse_args(argv)
 
     def log(msg):
@@ -292,6 +334,13 @@ def main(argv=None):
         if a.json:
             with open(a.json, "w") as f:
                 json.dump(info, f, indent=1)
+    elif a.cmd == "c3":
+        params = (np.load(a.weights, allow_pickle=False).astype(np.float32) if a.weights
+                  else limiter.trained_params())
+        res = c3(params, tuple(int(s) for s in a.ns.split(",")), a.n_ref, log=log)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
     else:
         params = np.load(a.weights, allow_pickle=False).astype(np.float32)
         res = evaluate(params, tuple(int(s) for s in a.kh_ns.split(",")), a.kh_ref, log=log)
