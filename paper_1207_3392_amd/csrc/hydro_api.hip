@@ -58,6 +58,10 @@ struct hy_patch {
     bool padded = false;
     int64_t inner[3] = {1, 1, 1};
     hy::LaunchCfg cfg{64, 8, 32};
+    // the HLLC -> HLL switch's own shape: its stage kernels hold more state
+    // per thread, which a 64x4 tile at three workgroups per CU affords
+    // without spilling (3D FP32)
+    hy::LaunchCfg cfg_sw{64, 8, 32};
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
@@ -75,6 +79,14 @@ struct hy_patch {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     GraphKey gkey[2];
 };
+
+namespace {
+// the launch shape a solver's stage kernels take
+hy::LaunchCfg &cfg_of(hy_patch *p, int solver)
+{
+    return solver == HY_HLLC_SWITCH ? p->cfg_sw : p->cfg;
+}
+}  // namespace
 
 namespace {
 
@@ -198,7 +210,9 @@ hipError_t run_stage(hy_patch *p, int solver, int stage, int dt_mode, double dt,
         if (e != hipSuccess) return e;
     }
     hy::StageArgs<T> a = stage_args<T>(p, stage, dt_mode, dt, cfl, t_end);
-    e = hy::launch_stage<T>(p->d.ndim, solver, stage, stage_limiter(p), p->cfg, a, p->stream);
+    const hy::LaunchCfg &c = cfg_of(p, solver);
+    a.zchunk = c.zchunk;
+    e = hy::launch_stage<T>(p->d.ndim, solver, stage, stage_limiter(p), c, a, p->stream);
     if (e != hipSuccess) return e;
     if (rec) {
         e = hipEventRecord(p->ev[k][2 * p->nrec[k] + 1], p->stream);
@@ -283,7 +297,22 @@ void pick_config(hy_patch *p)
     } else {
         p->cfg.zchunk = 1;
     }
+    p->cfg_sw = p->cfg;
+    if (d.ndim == 3 && d.precision == 32 && !std::getenv("HY_TILE")) {
+        // 64x4 tiles, three per CU: at least ~1536 workgroups (two rounds)
+        const int64_t tiles = ((n[0] + 63) / 64) * ((n[1] + 3) / 4);
+        int64_t chunks = (1536 + tiles - 1) / tiles;
+        chunks = std::max<int64_t>(chunks, (n[2] + 63) / 64);
+        if (chunks > n[2] / 8) chunks = n[2] / 8;
+        if (chunks < 1) chunks = 1;
+        p->cfg_sw = {64, 4, (int)((n[2] + chunks - 1) / chunks)};
+        if (const char *e = std::getenv("HY_ZCHUNK")) {
+            const int zc = std::atoi(e);
+            if (zc >= 1 && zc <= n[2]) p->cfg_sw.zchunk = zc;
+        }
+    }
 }
+
 
 }  // namespace
 
@@ -352,7 +381,7 @@ hy_status capture_steps(hy_patch *p, int nsteps, int solver, double cfl, double 
     k.solver = solver;
     k.cfl = cfl;
     k.t_end = t_end;
-    k.cfg = p->cfg;
+    k.cfg = cfg_of(p, solver);
     return HY_OK;
 }
 
@@ -504,7 +533,7 @@ hy_status hy_advance_graph_prepare(hy_patch *p, int nsteps, double cfl, double t
     hy_status st = check_advance(p, nsteps, cfl, t_end, solver);
     if (st != HY_OK) return st;
     if (p->padded) return fail(HY_EUNSUPPORTED, "refined levels step through the multilevel calls");
-    if (p->gexec[p->parity] && same_key(p->gkey[p->parity], nsteps, solver, cfl, t_end, p->cfg)) return HY_OK;
+    if (p->gexec[p->parity] && same_key(p->gkey[p->parity], nsteps, solver, cfl, t_end, cfg_of(p, solver))) return HY_OK;
     return capture_steps(p, nsteps, solver, cfl, t_end);
 }
 
@@ -656,6 +685,7 @@ hy_status hy_set_launch_cfg(hy_patch *p, const hy_launch_cfg *cfg)
     p->cfg.bx = cfg->bx;
     p->cfg.by = cfg->by;
     p->cfg.zchunk = cfg->zchunk;
+    p->cfg_sw = p->cfg;
     return HY_OK;
 }
 
@@ -670,7 +700,8 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
     // fit plus the default rule's own choice
     std::vector<hy::LaunchCfg> cand;
     const int tiles[4][2] = {{64, 8}, {64, 4}, {32, 8}, {32, 16}};
-    const hy::LaunchCfg dflt = p->cfg;
+    hy::LaunchCfg &cur = cfg_of(p, solver);
+    const hy::LaunchCfg dflt = cur;
     for (const auto &t : tiles) {
         const int bx = d.ndim == 1 ? 64 : t[0], by = d.ndim == 1 ? 1 : t[1];
         if (!tile_supported(d, bx, by)) continue;
@@ -698,18 +729,19 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
     // the next step's first stage resets.  U^n, the time and the rate of U^n
     // are left as they were.
     auto launch = [&](const hy::LaunchCfg &c) {
-        p->cfg = c;
         hipError_t r = hipSuccess;
         for (int stage = 1; stage <= 2 && r == hipSuccess; ++stage) {
             if (d.precision == 64) {
                 hy::StageArgs<double> a = stage_args<double>(p, stage, hy::DT_HOST, 0.0, 0.0, 0.0);
                 a.uin = a.u0 = (const double *)p->A;
                 a.uout = (double *)p->B;
+                a.zchunk = c.zchunk;
                 r = hy::launch_stage<double>(d.ndim, solver, stage, stage_limiter(p), c, a, p->stream);
             } else {
                 hy::StageArgs<float> a = stage_args<float>(p, stage, hy::DT_HOST, 0.0, 0.0, 0.0);
                 a.uin = a.u0 = (const float *)p->A;
                 a.uout = (float *)p->B;
+                a.zchunk = c.zchunk;
                 r = hy::launch_stage<float>(d.ndim, solver, stage, stage_limiter(p), c, a, p->stream);
             }
         }
@@ -749,7 +781,7 @@ hy_status hy_autotune(hy_patch *p, int solver, int reps, hy_launch_cfg *best, do
     }
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
-    p->cfg = e == hipSuccess ? bcfg : dflt;
+    cur = e == hipSuccess ? bcfg : dflt;
     if (e != hipSuccess) return hip_fail(e, "autotune launches");
     if (best) {
         best->bx = bcfg.bx;

@@ -25,6 +25,7 @@
 #include "hy_face.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace hy {
 namespace {
@@ -313,20 +314,25 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     // takes): a cell is in a shock moving along q when the pressures of its
     // neighbours along q differ by more than eps times the smaller one and
     // the velocity along q decreases across it; a face normal to r takes HLL
-    // when one of its two cells is flagged along some q != r.  Ring item tid
-    // (the first 2 BX + 2 BY threads): rows -1 and BY of the tile, then
-    // columns -1 and BX of its rows; its ghost values come through the same
-    // boundary map (and mirror signs) as the halo.
+    // when one of its two cells is flagged along some q != r.  Ring item rt
+    // (rows -1 and BY of the tile, then columns -1 and BX of its rows) goes to
+    // thread RING0 + rt: whole wavefronts after the first 2 BX threads, which
+    // carry the y-ring slopes, so the ring work of the two does not pile up on
+    // the same wavefronts; its ghost values come through the same boundary
+    // map (and mirror signs) as the halo.
     constexpr int NRING = 2 * BX + 2 * BY;
-    const bool ringt = SW && tid < NRING;
+    constexpr int RING0 = ((NT - NRING < 2 * BX ? NT - NRING : 2 * BX) / 64) * 64;
+    static_assert(!SW || (RING0 >= 0 && RING0 + NRING <= NT), "ring items fit the workgroup");
+    const int rt = tid - RING0;
+    const bool ringt = SW && rt >= 0 && rt < NRING;
     // the ring cell's tile row and column (formed where used, so nothing of
     // it stays in registers through the march)
     auto ring_rc = [&](int &r, int &c) {
-        if (tid < 2 * BX) {
-            r = tid < BX ? -1 : BY;
-            c = tid < BX ? tid : tid - BX;
+        if (rt < 2 * BX) {
+            r = rt < BX ? -1 : BY;
+            c = rt < BX ? rt : rt - BX;
         } else {
-            const int e = tid - 2 * BX;
+            const int e = rt - 2 * BX;
             r = e >> 1;
             c = (e & 1) ? BX : -1;
         }
@@ -463,10 +469,13 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         for (int j = 0; j < HPT; ++j)
             if (hlds[j] >= 0) load(zo + hoff[j], h[j]);
     };
-    // (the switch kernels hold both flux forms and the learned-limiter ones
-    // the prefetched slopes; to stay within the register budget they load the
-    // halo and the second stage's U^n when they are used instead of ahead)
-    constexpr bool LATE = SOLVER == SOLVER_HLLC_SWITCH || LIM == LIM_LEARNED;
+    // (the learned-limiter kernels hold the prefetched slopes and the switch
+    // kernels the detector's state; to stay within the register budget of
+    // four waves per SIMD they load the halo and the second stage's U^n when
+    // they are used instead of ahead.  The switch's 64x4 tile runs three
+    // workgroups per CU, its LDS allowing no more, which leaves it room for
+    // both prefetches)
+    constexpr bool LATE = (SW && !(BX == 64 && BY == 4)) || LIM == LIM_LEARNED;
     if constexpr (!LATE) load_halo(z0, hnext);
 
     T *sWf = &sW[0][0][0];
@@ -614,7 +623,8 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
         const int wv = tid >> 6;
         // (3D only: measured 5 % faster at 256^3; the single-plane 2D blocks
         // gain nothing)
-        const bool ring1 = ND == 3 && (wv < (2 * BX + 63) / 64 || wv >= (NT - 2 * BY) / 64);
+        const bool ring1 = ND == 3 && (wv < (2 * BX + 63) / 64 || wv >= (NT - 2 * BY) / 64 ||
+                                       (SW && wv >= RING0 / 64 && wv < (RING0 + NRING + 63) / 64));
         const bool ring2 = ND == 3 && (wv < (BX + 63) / 64 || wv >= (NT - BY) / 64);
         if (ring1) __builtin_amdgcn_s_setprio(2);
         if constexpr (LIM != LIM_LEARNED) {
@@ -642,6 +652,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
             }
             if (ering >= 0) slope_x(ering >> 1, (ering & 1) ? BX : -1);
         }
+        unsigned zb = 0u;  // switch: the own cell's byte (x, y bits of kz and kz + 1)
         if constexpr (SW) {
             // detector bits of plane kz: own cell and ring cell (the z bit
             // from the planes below and above; the current plane then becomes
@@ -655,6 +666,7 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 ob |= bits_n() << 4;
             }
             sB[ty + 1][tx + 1] = (uint8_t)ob;
+            zb = ob;
             if (ringt) {
                 int rr, rc;
                 ring_rc(rr, rc);
@@ -669,67 +681,93 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
                 sB[rr + 1][rc + 1] = (uint8_t)rb;
             }
         }
+        // the z face kz+1/2 of the own column, here rather than with the x
+        // and y faces: its left state's plane (W and z slope of kz) is then
+        // dead before the x and y Riemann solves, which lowers their
+        // register pressure
+        constexpr int SV = SW ? SOLVER_HLLC : SOLVER;
+        using Main = std::integral_constant<int, SV>;
+        using Hll = std::integral_constant<int, SOLVER_HLL>;
+        // a flagged face right after its HLLC evaluation (its inputs are
+        // still in LDS or live registers, so the redo holds nothing longer)
+        auto redo = [&](bool flagged, auto fn) {
+            if constexpr (SW) {
+                if (__builtin_amdgcn_ballot_w64(flagged) != 0ull) {
+                    // the redo reads its face states again rather than keeping
+                    // the first evaluation's alive through it
+                    asm volatile("" ::: "memory");
+                    if (flagged) fn();
+                }
+            }
+        };
+        // face z kz+1/2 of the own column (the cell of plane kz or kz + 1
+        // flagged along x or y)
+        auto face_z = [&](auto kind) -> bool {
+            T fl[NP], fr[NP];
+            face_state(Wk, Sk, hs, fl);
+            face_state(Wk1, Sk1, -hs, fr);
+            if constexpr (decltype(kind)::value != SV) {
+                // (the redo: opaque copies, so the face states are formed
+                // again instead of being kept from the first evaluation)
+#pragma unroll
+                for (int v = 0; v < NP; ++v) asm volatile("" : "+v"(fl[v]), "+v"(fr[v]));
+            }
+            riemann<ND, 2, decltype(kind)::value>(fl, fr, Fhi, sg, igm1);
+            if constexpr (SW3) return ((zb | (zb >> 4)) & 3u) != 0u;
+            return false;
+        };
+        if constexpr (ND == 3) redo(face_z(Main{}), [&] { (void)face_z(Hll{}); });
         if (ring1) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         if (ring2) __builtin_amdgcn_s_setprio(3);
 
         // ---- phase 2: x and y face fluxes, each face once ----
-        // own faces (the low x and y face of the own cell), the z face
-        // kz+1/2, then the ring: face column BX (last threads) and face row
-        // BY (first threads)
-        auto face_x = [&](int row, int col) {
+        // own faces (the low x and y face of the own cell), then the ring:
+        // face column BX (last threads) and face row BY (first threads).  The
+        // switch evaluates HLLC at every face and notes the faces whose cells
+        // carry a transverse shock bit; those are evaluated again with HLL
+        // right after, in a branch the wavefront skips when none of its faces
+        // is flagged
+        // face x at (row, col) between cells col-1 and col; returns whether
+        // the switch wants HLL there (either cell flagged along y or z)
+        auto face_x = [&](int row, int col, auto kind) -> bool {
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 wl[v] = sW[v][row + OY][col + 1] + hs * sSx[v][row][col];
                 wr[v] = sW[v][row + OY][col + 2] - hs * sSx[v][row][col + 1];
             }
-            // switch: HLL when either cell is flagged along y or z
-            bool hll = false;
-            if constexpr (SW) hll = ((sB[row + 1][col] | sB[row + 1][col + 1]) & 6u) != 0u;
-            face_flux<ND, 0, SOLVER>(wl, wr, fl, sg, igm1, hll);
+            riemann<ND, 0, decltype(kind)::value>(wl, wr, fl, sg, igm1);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFx[v][row][col] = fl[v];
+            if constexpr (SW) return ((sB[row + 1][col] | sB[row + 1][col + 1]) & 6u) != 0u;
+            return false;
         };
-        auto face_y = [&](int row, int col) {
+        // face y (either cell flagged along x or z)
+        auto face_y = [&](int row, int col, auto kind) -> bool {
             T wl[NP], wr[NP], fl[NP];
 #pragma unroll
             for (int v = 0; v < NP; ++v) {
                 wl[v] = sW[v][row + 1][col + 2] + hs * sSy[v][row][col];
                 wr[v] = sW[v][row + 2][col + 2] - hs * sSy[v][row + 1][col];
             }
-            // switch: HLL when either cell is flagged along x or z
-            bool hll = false;
-            if constexpr (SW) hll = ((sB[row][col + 1] | sB[row + 1][col + 1]) & 5u) != 0u;
-            face_flux<ND, 1, SOLVER>(wl, wr, fl, sg, igm1, hll);
+            riemann<ND, 1, decltype(kind)::value>(wl, wr, fl, sg, igm1);
 #pragma unroll
             for (int v = 0; v < NP; ++v) sFy[v][row][col] = fl[v];
+            if constexpr (SW) return ((sB[row][col + 1] | sB[row + 1][col + 1]) & 5u) != 0u;
+            return false;
         };
+        const int fe = tid - (NT - BY);  // x ring face of the last threads
         // the scheduling barriers keep the solver instances from being
         // interleaved, which would only raise register pressure
-        face_x(ty, tx);
+        redo(face_x(ty, tx, Main{}), [&] { (void)face_x(ty, tx, Hll{}); });
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (ND >= 2) face_y(ty, tx);
+        if constexpr (ND >= 2) redo(face_y(ty, tx, Main{}), [&] { (void)face_y(ty, tx, Hll{}); });
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (ND == 3) {
-            T fl[NP], fr[NP];
-            face_state(Wk, Sk, hs, fl);
-            face_state(Wk1, Sk1, -hs, fr);
-            // switch: HLL when the cell of plane kz or kz + 1 is flagged along x or y
-            bool hll = false;
-            if constexpr (SW3) {
-                const unsigned b = sB[ty + 1][tx + 1];
-                hll = ((b | (b >> 4)) & 3u) != 0u;
-            }
-            face_flux<ND, 2, SOLVER>(fl, fr, Fhi, sg, igm1, hll);
-        }
         if constexpr (ND >= 2) {
-            if (tid < BX) face_y(BY, tid);
+            if (tid < BX) redo(face_y(BY, tid, Main{}), [&] { (void)face_y(BY, tid, Hll{}); });
         }
-        {
-            const int e = tid - (NT - BY);
-            if (e >= 0) face_x(e, BX);
-        }
+        if (fe >= 0) redo(face_x(fe, BX, Main{}), [&] { (void)face_x(fe, BX, Hll{}); });
         if (ring2) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
 
