@@ -161,6 +161,25 @@ hy_status hy_conserved_totals(hy_patch *p, double out[5]);
  * cells (bitwise reproducible); zeros for absent components.  Synchronising. */
 hy_status hy_kinetic_energy(hy_patch *p, double out[3]);
 
+/* Kinetic-energy spectrum of the Kelvin-Helmholtz analysis (Sec. 4.3.1) of
+ * the patch's current state U^n, on the device: e[s], s = 0 .. nshell - 1,
+ * is the energy density on the shell of wavenumbers |k| = 2 pi s / L (width
+ * dk = 2 pi / L, s the integer nearest to the length of the integer
+ * wavevector), from the discrete Fourier coefficients (divided by the cell
+ * count) of the components of sqrt(rho) v with the box taken as periodic,
+ * normalised so that sum_s e[s] dk is the integral of rho |v|^2 / 2 over the
+ * box.  A 2D patch of N x N cells, N a power of two from 2 to 8192, on a
+ * square box of side L (else HY_EUNSUPPORTED); nshell = floor(sqrt(2) N / 2
+ * + 1/2) + 1.  The transform is FP64 and the shell sums are 64-bit
+ * fixed-point at a scale of 2^-61 of the total (bitwise reproducible; each
+ * term is truncated by less than 2^-61 of the total).
+ * hy_spectrum_workspace_bytes gives the device workspace the call needs
+ * (32 N^2 bytes plus a little; the caller owns it, nothing is kept); e is
+ * host memory of cap >= nshell doubles (else HY_EINVAL, with *nshell set);
+ * HY_ESTATE when a density is not positive.  Synchronising. */
+hy_status hy_spectrum_workspace_bytes(hy_patch *p, size_t *bytes);
+hy_status hy_kinetic_spectrum(hy_patch *p, void *dev_workspace, size_t bytes, double *e, int cap, int *nshell);
+
 /* Learned limiter weights: n = 1249 FP32 values, W1[32][4], b1[32],
  * W2[32][32], b2[32], w3[32], b3.  Copied to the device (W1, W2 and w3 in
  * bfloat16, biases in FP32).  Required before stepping with HY_LIM_LEARNED.  Synchronising. */

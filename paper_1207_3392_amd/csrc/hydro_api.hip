@@ -236,6 +236,22 @@ hipError_t one_step(hy_patch *p, int solver, int dt_mode, double dt, double cfl,
     return e;
 }
 
+// the spectrum's shape checks: a 2D patch of N x N cells (N a power of two,
+// 2 .. 8192) on a square box
+hy_status spectrum_check(hy_patch *p, int *n_out)
+{
+    if (!p) return fail(HY_EINVAL, "null patch");
+    const hy_patch_desc &d = p->d;
+    if (d.ndim != 2 || p->padded) return fail(HY_EUNSUPPORTED, "the spectrum takes a 2D patch");
+    const int64_t n = d.n[0];
+    if (d.n[1] != n || n < 2 || n > 8192 || (n & (n - 1)) != 0)
+        return fail(HY_EUNSUPPORTED, "the spectrum needs N x N cells, N a power of two from 2 to 8192");
+    const double lx = d.hi[0] - d.lo[0], ly = d.hi[1] - d.lo[1];
+    if (!(std::fabs(lx - ly) <= 1e-12 * std::fmax(lx, ly))) return fail(HY_EUNSUPPORTED, "the spectrum needs a square box");
+    *n_out = (int)n;
+    return HY_OK;
+}
+
 hy_status read_ctl(hy_patch *p, hy::DevCtl *out)
 {
     hipError_t e = hipMemcpyAsync(out, p->ctl, sizeof(hy::DevCtl), hipMemcpyDeviceToHost, p->stream);
@@ -610,6 +626,41 @@ hy_status hy_kinetic_energy(hy_patch *p, double out[3])
     hy_status st = read_ctl(p, &c);
     if (st != HY_OK) return st;
     for (int q = 0; q < 3; ++q) out[q] = c.totals[5 + q];
+    return c.err ? fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value") : HY_OK;
+}
+
+hy_status hy_spectrum_workspace_bytes(hy_patch *p, size_t *bytes)
+{
+    if (!bytes) return fail(HY_EINVAL, "null output");
+    int n = 0;
+    hy_status st = spectrum_check(p, &n);
+    if (st != HY_OK) return st;
+    *bytes = hy::spectrum_workspace_bytes(n);
+    return HY_OK;
+}
+
+hy_status hy_kinetic_spectrum(hy_patch *p, void *dev_workspace, size_t bytes, double *e, int cap, int *nshell)
+{
+    int n = 0;
+    hy_status st = spectrum_check(p, &n);
+    if (st != HY_OK) return st;
+    if (!dev_workspace || !e || !nshell) return fail(HY_EINVAL, "null argument");
+    const int ns = hy::spectrum_shells(n);
+    *nshell = ns;
+    if (cap < ns) return fail(HY_EINVAL, "output shorter than the shell count");
+    if (bytes < hy::spectrum_workspace_bytes(n)) return fail(HY_ENOMEM, "workspace too small");
+    const double box = p->d.hi[0] - p->d.lo[0];
+    double *e_dev = nullptr;
+    hipError_t err = p->d.precision == 64
+                         ? hy::launch_spectrum<double>((const double *)p->A, p->vstride, n, box, dev_workspace, &e_dev,
+                                                       p->ctl, p->stream)
+                         : hy::launch_spectrum<float>((const float *)p->A, p->vstride, n, box, dev_workspace, &e_dev,
+                                                      p->ctl, p->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(e, e_dev, (size_t)ns * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    if (err != hipSuccess) return hip_fail(err, "spectrum launch");
+    hy::DevCtl c;
+    st = read_ctl(p, &c);
+    if (st != HY_OK) return st;
     return c.err ? fail(HY_ESTATE, "a kernel met rho <= 0, p <= 0 or a non-finite value") : HY_OK;
 }
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import json
+import math
 import os
 from typing import Optional, Sequence
 
@@ -80,6 +81,8 @@ SIGNATURES = {
     "hy_get_time": [_P, _dp],
     "hy_conserved_totals": [_P, _dp],
     "hy_kinetic_energy": [_P, _dp],
+    "hy_spectrum_workspace_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "hy_kinetic_spectrum": [_P, ctypes.c_void_p, ctypes.c_size_t, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "hy_set_mlp": [_P, _fp, ctypes.c_size_t],
     "hy_set_timing": [_P, ctypes.c_int],
     "hy_kernel_times": [_P, _dp, _i64p],
@@ -266,6 +269,24 @@ class Patch:
         out = np.zeros(3)
         check(lib().hy_kinetic_energy(self.handle, _dptr(out)), "kinetic_energy")
         return out
+
+    def kinetic_spectrum(self):
+        """Kinetic-energy spectrum of a 2D N x N patch on the device: (k, e)
+        with k = 2 pi s / L for the shells s = 0, 1, ... (hy_kinetic_spectrum)."""
+        import torch
+
+        nb = ctypes.c_size_t(0)
+        check(lib().hy_spectrum_workspace_bytes(self.handle, ctypes.byref(nb)), "spectrum_workspace_bytes")
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        n = int(self.desc.n[0])
+        cap = int(math.floor(math.sqrt(2.0) * (n // 2) + 0.5)) + 1
+        e = np.zeros(cap)
+        ns = ctypes.c_int(0)
+        check(lib().hy_kinetic_spectrum(self.handle, ctypes.c_void_p(ws.data_ptr()), nb, _dptr(e), cap,
+                                        ctypes.byref(ns)), "kinetic_spectrum")
+        del ws
+        box = float(self.desc.hi[0] - self.desc.lo[0])
+        return 2.0 * math.pi / box * np.arange(ns.value), e[:ns.value]
 
     def set_mlp(self, params):
         w = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())

@@ -170,8 +170,7 @@ def run_to_times(prob, times, params=None, cfl: float = None, chunk: int = 64, d
         if diag is not None:
             diag.setdefault("ekin_y", []).append(float(p.kinetic_energy()[1]))
             if T == times[-1]:
-                W = p.get_state(hydro.PRIMITIVE).reshape((prob.ndim + 2,) + shape)
-                diag["spectrum"] = diagnostics.kinetic_spectrum(W, prob.hi[0] - prob.lo[0])
+                diag["spectrum"] = diagnostics.kinetic_spectrum(p)
     p.close()
     return out, wall
 
