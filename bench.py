@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
                                                    "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch",
-                                                   "fmr_sedov3d", "fmr_sedov2d_7levels"],
+                                                   "fmr_sedov3d", "fmr_sedov2d_7levels", "kh_spectrum_2048"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -207,6 +207,32 @@ def time_kh(n=2048, steps=20, learned=False):
     p.cfl_dt(0.4)
     p.close()
     return {"zone_updates_per_s": n * n * steps / wall, "ms_per_step": 1e3 * wall / steps}
+
+
+def time_spectrum(n=2048, reps=20):
+    """The device kinetic-energy spectrum (Sec. 4.3.1) of the 2D
+    Kelvin-Helmholtz state at n^2 after 20 HLLC steps: milliseconds per call
+    (synchronising, shell sums copied to the host) and the HBM bytes its
+    passes move per call over that time (the FP32 state's three read
+    components, then the FP64 complex array written by the x pass, read and
+    written by the transpose and by the y pass, read by the binning:
+    12 + 16 + 32 + 32 + 16 = 108 bytes per cell)."""
+    import torch
+
+    from paper_1207_3392_amd import hydro
+    from paper_1207_3392_amd import workloads as wl
+
+    p = hydro.Patch(wl.kelvin_helmholtz(n), precision=32)
+    p.advance(20, 0.4, solver=hydro.HLLC)
+    p.kinetic_spectrum()  # warm-up (code load, workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        k, e = p.kinetic_spectrum()
+    wall = (time.perf_counter() - t0) / reps
+    p.close()
+    return {"n": n, "ms_per_call": 1e3 * wall, "shells": int(e.size),
+            "algorithmic_gbs": 108.0 * n * n / wall / 1e9}
 
 
 def time_fmr(nd=3, n0=128, nlev=4, steps=4, warmup=1):
@@ -420,6 +446,7 @@ def main():
                "kh_2048_learned": lambda: time_kh(learned=True), "rt_512_plain": lambda: time_rt(learned=False),
                "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1,
                "fmr_sedov3d": time_fmr,
+               "kh_spectrum_2048": time_spectrum,
                "fmr_sedov2d_7levels": lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1),
                "hllc_switch": lambda: {k: v for k, v in time_patch(args.n, "hllc_switch", args.steps,
                                                                     args.warmup).items() if k != "kernel"}}[args.only]
@@ -464,6 +491,7 @@ def main():
         guarded("fmr_sedov2d_7levels", lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1))
         guarded("kh_2048_plain", lambda: time_kh(learned=False))
         guarded("kh_2048_learned", lambda: time_kh(learned=True))
+        guarded("kh_spectrum_2048", time_spectrum)
         guarded("rt_512_plain", lambda: time_rt(learned=False))
         guarded("rt_512_learned", lambda: time_rt(learned=True))
         kp, kl = extra.get("kh_2048_plain", {}), extra.get("kh_2048_learned", {})

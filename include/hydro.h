@@ -202,7 +202,7 @@ hy_status hy_kernel_config(hy_patch *p, char *buf, size_t len);
  * 64x8, 64x4, 32x8 and (FP32) 32x16 in 2D and 3D, 64x1 in 1D; a patch starts
  * with a shape picked from its size (64x8, at least ~512 workgroups, at most
  * 64 planes per chunk).  The HLLC -> HLL switch keeps a shape of its own
- * (3D FP32: 64x4, at least ~1536 workgroups; else the same): hy_get_launch_cfg
+ * (3D FP32: 32x8, at least ~1536 workgroups; else the same): hy_get_launch_cfg
  * reports the HLL/HLLC shape, hy_set_launch_cfg sets the shape of every
  * solver, hy_autotune the shape of the solver it tunes. */
 typedef struct {

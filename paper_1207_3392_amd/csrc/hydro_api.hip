@@ -59,8 +59,8 @@ struct hy_patch {
     int64_t inner[3] = {1, 1, 1};
     hy::LaunchCfg cfg{64, 8, 32};
     // the HLLC -> HLL switch's own shape: its stage kernels hold more state
-    // per thread, which a 64x4 tile at three workgroups per CU affords
-    // without spilling (3D FP32)
+    // per thread, which a 32x8 tile at three waves per SIMD affords without
+    // spilling (3D FP32)
     hy::LaunchCfg cfg_sw{64, 8, 32};
     // timing
     bool timing = false;
@@ -315,13 +315,13 @@ void pick_config(hy_patch *p)
     }
     p->cfg_sw = p->cfg;
     if (d.ndim == 3 && d.precision == 32 && !std::getenv("HY_TILE")) {
-        // 64x4 tiles, three per CU: at least ~1536 workgroups (two rounds)
-        const int64_t tiles = ((n[0] + 63) / 64) * ((n[1] + 3) / 4);
+        // 32x8 tiles, three per CU: at least ~1536 workgroups (two rounds)
+        const int64_t tiles = ((n[0] + 31) / 32) * ((n[1] + 7) / 8);
         int64_t chunks = (1536 + tiles - 1) / tiles;
         chunks = std::max<int64_t>(chunks, (n[2] + 63) / 64);
         if (chunks > n[2] / 8) chunks = n[2] / 8;
         if (chunks < 1) chunks = 1;
-        p->cfg_sw = {64, 4, (int)((n[2] + chunks - 1) / chunks)};
+        p->cfg_sw = {32, 8, (int)((n[2] + chunks - 1) / chunks)};
         if (const char *e = std::getenv("HY_ZCHUNK")) {
             const int zc = std::atoi(e);
             if (zc >= 1 && zc <= n[2]) p->cfg_sw.zchunk = zc;

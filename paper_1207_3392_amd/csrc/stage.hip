@@ -139,7 +139,10 @@ __device__ __forceinline__ void stage_box_faces(const StageArgs<T> &a, int fid, 
 // At least 4 waves per SIMD: the LDS plane tile admits two 512-thread
 // workgroups per CU, so registers beyond 128 per lane would only cost occupancy.
 template <int ND, typename T, int SOLVER, int STAGE, int LIM, int BX, int BY>
-__global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
+// 512-thread tiles: four waves per SIMD (two workgroups per CU); 256-thread
+// tiles: three, which leaves the 3D kernels room to prefetch without spilling
+// (their LDS would allow four workgroups, but the registers then spill)
+__global__ void __launch_bounds__(BX *BY, (BX * BY == 256) ? 3 : 4) k_stage(const StageArgs<T> a)
 {
     constexpr int NP = ND + 2;
     constexpr int IP = ND + 1;
@@ -472,10 +475,9 @@ __global__ void __launch_bounds__(BX *BY, 4) k_stage(const StageArgs<T> a)
     // (the learned-limiter kernels hold the prefetched slopes and the switch
     // kernels the detector's state; to stay within the register budget of
     // four waves per SIMD they load the halo and the second stage's U^n when
-    // they are used instead of ahead.  The switch's 64x4 tile runs three
-    // workgroups per CU, its LDS allowing no more, which leaves it room for
-    // both prefetches)
-    constexpr bool LATE = (SW && !(BX == 64 && BY == 4)) || LIM == LIM_LEARNED;
+    // they are used instead of ahead.  The switch's 256-thread tiles run at
+    // three waves per SIMD, which leaves them room for both prefetches)
+    constexpr bool LATE = (SW && NT == 512) || LIM == LIM_LEARNED;
     if constexpr (!LATE) load_halo(z0, hnext);
 
     T *sWf = &sW[0][0][0];
