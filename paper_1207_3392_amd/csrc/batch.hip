@@ -29,13 +29,14 @@ __device__ __forceinline__ float soundf(float g, float p, float r)
 }
 
 // The generalised minmod slope of eq. MinMod divided by theta (see
-// hy_face.h): med3(min3, max3, 0) of (dm, (dm + dp) k, dp), k = 1 / (2 theta);
-// face values w +/- (theta / 2) slope.
+// hy_face.h): MM(dm, (dm + dp) k, dp) = MM(MM(dm, dp), (dm + dp) k),
+// k = 1 / (2 theta), the two-argument minmod being med3(x, y, 0); face
+// values w +/- (theta / 2) slope.
 __device__ __forceinline__ float slope_k(float wm, float w0, float wp, float k)
 {
     const float dm = w0 - wm, dp = wp - w0;
     const float b = (dm + dp) * k;
-    return __builtin_amdgcn_fmed3f(fminf(dm, fminf(b, dp)), fmaxf(dm, fmaxf(b, dp)), 0.f);
+    return __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(dm, dp, 0.f), b, 0.f);
 }
 
 // 1D flux from primitive face states (rho, v, p); sg = sqrt(gamma)

@@ -73,28 +73,33 @@ template <> __device__ __forceinline__ double med3_<double>(double a, double b, 
 
 // Twice the generalised-minmod slope of eq. MinMod as a per-cell difference:
 // with a = 2 theta dm, b = dm + dp, c = 2 theta dp, MM(a, b, c) (the argument
-// of least magnitude when all share a sign, else 0) equals
-// med3(min(a, b, c), max(a, b, c), 0), and MM(a, b, c) = 2 MM(theta dm,
-// (dm + dp) / 2, theta dp) exactly.  Face values are then w +/- slope / 4.
+// of least magnitude when all share a sign, else 0) = 2 MM(theta dm,
+// (dm + dp) / 2, theta dp) exactly, evaluated as MM(MM(a, c), b) (b shares
+// the sign of a and c when they agree; see slope_mm).  Face values are then
+// w +/- slope / 4.
 template <typename T>
 __device__ __forceinline__ T slope2_mm(T wm, T w0, T wp, T theta2)
 {
     const T dm = w0 - wm, dp = wp - w0;
     const T a = theta2 * dm, b = dm + dp, c = theta2 * dp;
-    return med3_(fmin(a, fmin(b, c)), fmax(a, fmax(b, c)), T(0));
+    return med3_(med3_(a, c, T(0)), b, T(0));
 }
 
 // The generalised-minmod slope of eq. MinMod divided by theta: scaling every
 // argument of MM by 1 / theta (a positive factor commutes with MM) gives
-// MM(dm, (dm + dp) k, dp) with k = 1 / (2 theta), evaluated as
-// med3(min3, max3, 0) as above; the face values are then w +/- hs * slope
-// with hs = theta / 2.  The factors theta leave the per-cell work this way.
+// MM(dm, (dm + dp) k, dp) with k = 1 / (2 theta); the face values are then
+// w +/- hs * slope with hs = theta / 2.  The factors theta leave the per-cell
+// work this way.  The middle argument b = (dm + dp) k carries the sign of
+// dm and dp whenever those two agree, so MM(dm, b, dp) = MM(MM(dm, dp), b),
+// and the two-argument minmod is med3(x, y, 0) (the argument nearer to zero
+// when they share a sign, else 0): two median instructions, the same value
+// as med3(min3, max3, 0) bit for bit (each form selects one of its inputs).
 template <typename T>
 __device__ __forceinline__ T slope_mm(T wm, T w0, T wp, T k)
 {
     const T dm = w0 - wm, dp = wp - w0;
     const T b = (dm + dp) * k;
-    return med3_(fmin(dm, fmin(b, dp)), fmax(dm, fmax(b, dp)), T(0));
+    return med3_(med3_(dm, dp, T(0)), b, T(0));
 }
 
 // The per-patch constants of slope_mm and of the face values, formed the
