@@ -80,14 +80,14 @@ __device__ __forceinline__ void flux1(const float (&wl)[3], const float (&wr)[3]
     const float sm = sup ? vK : a_m;
     const float EK = pK * igm1 + 0.5f * rK * vK * vK;
     const float qk = sK - vK;
-    const float inv = rcpf_(sK - sm);
     const float rq = rK * qk;
     const float ps = pK + rq * (sm - vK);
-    const float Gs = (qk * EK - pK * vK + ps * sm) * inv;
-    const float fd = rq * inv * sm;
+    // (E* + p*) sm = (q_K E_K - p_K v_K + p* s_K) sm / (s_K - sm), as in hy_face.h
+    const float ism = rcpf_(sK - sm) * sm;
+    const float fd = rq * ism;
     f[0] = fd;
     f[1] = fd * sm + ps;
-    f[2] = (Gs + ps) * sm;
+    f[2] = (qk * EK - pK * vK + ps * sK) * ism;
 }
 
 __global__ void k_batch_reset(BatchCtl *ctl)

@@ -43,6 +43,14 @@ template <typename T> __device__ __forceinline__ T max3_(T a, T b, T c) { return
 
 // ------------------------------------------------------ fluid variables ----
 
+// x > 0 and finite: one class test in FP32 (positive normal or subnormal)
+template <typename T> __device__ __forceinline__ bool pos_finite(T x);
+template <> __device__ __forceinline__ bool pos_finite<float>(float x) { return __builtin_amdgcn_classf(x, 0x180); }
+template <> __device__ __forceinline__ bool pos_finite<double>(double x)
+{
+    return __builtin_amdgcn_class(x, 0x180);
+}
+
 // primitives (rho, v, p) from conserved (D, S, G), m = 1; returns false on
 // rho <= 0, p <= 0 or a non-finite value
 template <int ND, typename T>
@@ -57,8 +65,7 @@ __device__ __forceinline__ bool to_prim(const T (&u)[ND + 2], T (&w)[ND + 2], T 
     }
     w[0] = u[0];
     w[ND + 1] = gm1 * (u[ND + 1] - T(0.5) * ke);
-    const T big = T(3.0e38);
-    return (w[0] > T(0)) & (w[ND + 1] > T(0)) & (w[0] < big) & (w[ND + 1] < big);
+    return pos_finite(w[0]) & pos_finite(w[ND + 1]);
 }
 
 template <typename T> __device__ __forceinline__ T med3_(T a, T b, T c);
@@ -175,23 +182,25 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
         for (int d = 0; d < ND; ++d) kk += wk[1 + d] * wk[1 + d];
         const T EK = pK * inv_gm1 + T(0.5) * rK * kk;
         // middle state from the jump conditions across the K-side outer wave
-        // (s_K - sm is nonzero: opposite signs, or v_K != 0 when supersonic)
+        // (s_K - sm is nonzero: opposite signs, or v_K != 0 when supersonic):
+        // rho* = rho_K q_K / (s_K - sm), p* = p_K + rho_K q_K (sm - v_K),
+        // E* = (q_K E_K - p_K v_K + p* sm) / (s_K - sm), q_K = s_K - v_K
         const T qk = sK - vK;
-        const T inv = rcp_(sK - sm);
         const T rq = rK * qk;
-        const T rs = rq * inv;
         const T ps = pK + rq * (sm - vK);
-        const T Gs = (qk * EK - pK * vK + ps * sm) * inv;
         // F_K + s_K (U*_K - U_K) equals the physical flux of the middle state
-        // (the jump conditions across the s_K wave), formed directly
-        const T fd = rs * sm;
+        // (the jump conditions across the s_K wave), formed directly: mass
+        // flux rho* sm, and energy flux (E* + p*) sm = (q_K E_K - p_K v_K +
+        // p* s_K) sm / (s_K - sm) (the p* sm terms cancel)
+        const T ism = rcp_(sK - sm) * sm;
+        const T fd = rq * ism;
         f[0] = fd;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             if (d == Q) f[1 + d] = fd * sm + ps;
             else f[1 + d] = fd * wk[1 + d];
         }
-        f[IP] = (Gs + ps) * sm;
+        f[IP] = (qk * EK - pK * vK + ps * sK) * ism;
     }
 }
 
