@@ -365,6 +365,13 @@ __global__ void __launch_bounds__(BX *BY, (BX * BY == 256) ? 3 : 4) k_stage(cons
 
     bool bad = false;
     T rate = T(0);
+    // (uniform) mirror images only where a face reflects, and the CFL rate
+    // as (max_q |v_q| + c) / dq when the cells are cubes (the same value:
+    // (x + c) / dq rounds monotonically in x)
+    bool mir = false;
+#pragma unroll
+    for (int q = 0; q < ND; ++q) mir |= (a.bc[q][0] == BC_REFLECT) | (a.bc[q][1] == BC_REFLECT);
+    const bool cubic = (ND < 2 || a.idx[1] == a.idx[0]) && (ND < 3 || a.idx[2] == a.idx[0]);
 
     auto to_w = [&](const T (&u)[NP], T (&w)[NP], bool fx, bool fy, bool fz) {
         bad |= !to_prim<ND>(u, w, gm1);
@@ -817,8 +824,15 @@ __global__ void __launch_bounds__(BX *BY, (BX * BY == 256) ? 3 : 4) k_stage(cons
                 T wo[NP];
                 bad |= !to_prim<ND>(out, wo, gm1);
                 const T cs = sound_(gamma, wo[IP], wo[0]);
+                if (cubic) {
+                    T vm = fabs(wo[1]);
 #pragma unroll
-                for (int d = 0; d < ND; ++d) rate = fmax(rate, (fabs(wo[1 + d]) + cs) * a.idx[d]);
+                    for (int d = 1; d < ND; ++d) vm = fmax(vm, fabs(wo[1 + d]));
+                    rate = fmax(rate, (vm + cs) * a.idx[0]);
+                } else {
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) rate = fmax(rate, (fabs(wo[1 + d]) + cs) * a.idx[d]);
+                }
             }
         }
     };
