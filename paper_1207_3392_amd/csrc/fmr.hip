@@ -8,6 +8,7 @@
 // (in its padded mode on refined levels).
 #include "hy_fmr.h"
 #include "hy_face.h"
+#include "hy_ride.h"
 
 #include <algorithm>
 
@@ -19,145 +20,10 @@ constexpr int TB = 256;  // threads per block of the reductions
 
 constexpr int SB = 256;  // threads per block of the exterior-shell kernels
 
-// The exterior cells of a padded array, enumerated flat: first the rows that
-// lie wholly in the exterior (every x), then the NG cells at each x end of
-// the remaining rows.
-template <int ND>
-__host__ __device__ inline int shell_full_rows(const Grid &g)
-{
-    if constexpr (ND == 1) return 0;
-    if constexpr (ND == 2) return 2 * FMR_NG;
-    return 2 * FMR_NG * g.m[1] + (g.m[2] - 2 * FMR_NG) * 2 * FMR_NG;
-}
-
-template <int ND>
-__host__ __device__ inline int shell_cells(const Grid &g)
-{
-    int part = 1;
-    if constexpr (ND >= 2) part *= g.m[1] - 2 * FMR_NG;
-    if constexpr (ND >= 3) part *= g.m[2] - 2 * FMR_NG;
-    return shell_full_rows<ND>(g) * g.m[0] + part * 2 * FMR_NG;
-}
-
-template <int ND>
-__device__ __forceinline__ void shell_cell(const Grid &g, int s, int (&c)[3])
-{
-    const int full = shell_full_rows<ND>(g) * g.m[0];
-    c[1] = 0;
-    c[2] = 0;
-    if (s < full) {
-        const int r = s / g.m[0];
-        c[0] = s - r * g.m[0];
-        if constexpr (ND == 2) {
-            c[1] = r < FMR_NG ? r : g.m[1] - 2 * FMR_NG + r;
-        } else if constexpr (ND == 3) {
-            const int slab = FMR_NG * g.m[1];  // rows of the low (or high) z exterior
-            if (r < 2 * slab) {
-                const int h = r / slab, rr = r - h * slab;
-                c[2] = (h ? g.m[2] - FMR_NG : 0) + rr / g.m[1];
-                c[1] = rr % g.m[1];
-            } else {
-                const int rr = r - 2 * slab, jj = rr % (2 * FMR_NG);
-                c[2] = FMR_NG + rr / (2 * FMR_NG);
-                c[1] = jj < FMR_NG ? jj : g.m[1] - 2 * FMR_NG + jj;
-            }
-        }
-    } else {
-        const int p = s - full, row = p / (2 * FMR_NG), x = p - row * 2 * FMR_NG;
-        c[0] = x < FMR_NG ? x : g.m[0] - 2 * FMR_NG + x;
-        if constexpr (ND == 2) c[1] = FMR_NG + row;
-        if constexpr (ND == 3) {
-            const int ny = g.m[1] - 2 * FMR_NG;
-            c[2] = FMR_NG + row / ny;
-            c[1] = FMR_NG + row % ny;
-        }
-    }
-}
-
-__device__ __forceinline__ void clock_op(FmrClock *c, int op, int l, int nlev, unsigned long long *rate_bits,
-                                         double cfl, double dt_fixed)
-{
-    switch (op) {
-    case CLOCK_RESET:
-        for (int i = 0; i < nlev; ++i) c[i].t = 0.0;
-        for (int k = 0; k < FMR_RATE_SLOTS; ++k) rate_bits[k] = 0ull;
-        break;
-    case CLOCK_DEEPEST:
-    case CLOCK_DEEPEST_KEEP: {
-        unsigned long long rb = 0ull;
-        for (int k = 0; k < FMR_RATE_SLOTS; ++k) {
-            rb = rb > rate_bits[k] ? rb : rate_bits[k];
-            if (op == CLOCK_DEEPEST) rate_bits[k] = 0ull;
-        }
-        c[l].dt = dt_fixed > 0.0 ? dt_fixed : cfl / __longlong_as_double((long long)rb);
-        break;
-    }
-    case CLOCK_COARSE: c[l].dt = c[l + 1].t - c[l].t; break;
-    case CLOCK_PROVISIONAL: c[l].dtp = c[l + 1].t - c[l].t; break;
-    case CLOCK_ADVANCE: c[l].t += c[l].dt; break;
-    default: break;
-    }
-}
-
 template <int ND, typename T>
-__global__ void __launch_bounds__(SB) k_prolong(T *fine, T *fine2, Grid fg, const T *parent, Grid pg, Box pb, T gm1,
-                                                 T inv_gm1, ClockOps ck)
+__global__ void __launch_bounds__(SB) k_prolong(RideJob<T> j)
 {
-    // clock updates that ride on this launch (none of its threads reads the
-    // clocks; the kernels after it do)
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ck.c) {
-        clock_op(ck.c, ck.op0, ck.l0, ck.nlev, ck.rate, ck.cfl, ck.dt_fixed);
-        clock_op(ck.c, ck.op1, ck.l1, ck.nlev, ck.rate, ck.cfl, ck.dt_fixed);
-    }
-    const int sc = blockIdx.x * SB + threadIdx.x;
-    if (sc < shell_cells<ND>(fg)) {
-        int c3[3];
-        shell_cell<ND>(fg, sc, c3);
-        int p3[3], s3[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (q < ND) {
-                const int r = c3[q] - FMR_NG;  // offset from the first interior cell
-                p3[q] = pb.lo[q] + (r >> 1);   // floor(r / 2)
-                s3[q] = r & 1;                 // 0: low child, 1: high child
-            } else {
-                p3[q] = 0;
-                s3[q] = 0;
-            }
-        }
-        T w0[ND + 2], wc[ND + 2];
-        load_prim<ND>(parent, pg, at(pg, p3[0], p3[1], p3[2]), gm1, w0);
-#pragma unroll
-        for (int v = 0; v < ND + 2; ++v) wc[v] = w0[v];
-#pragma unroll
-        for (int q = 0; q < ND; ++q) {
-            int lo3[3] = {p3[0], p3[1], p3[2]}, hi3[3] = {p3[0], p3[1], p3[2]};
-            lo3[q] -= 1;
-            hi3[q] += 1;
-            T wm[ND + 2], wp[ND + 2];
-            load_prim<ND>(parent, pg, at(pg, lo3[0], lo3[1], lo3[2]), gm1, wm);
-            load_prim<ND>(parent, pg, at(pg, hi3[0], hi3[1], hi3[2]), gm1, wp);
-            // minmod (theta = 1) as twice the slope; the child sits at +/- 1/4
-            // of the parent width, so it moves by +/- slope2 / 8
-            const T h = s3[q] ? T(0.125) : T(-0.125);
-#pragma unroll
-            for (int v = 0; v < ND + 2; ++v) wc[v] += h * slope2_mm(wm[v], w0[v], wp[v], T(2));
-        }
-        const int64_t c = at(fg, c3[0], c3[1], c3[2]);
-        T uc[ND + 2], ke = T(0);
-        uc[0] = wc[0];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            uc[1 + d] = wc[0] * wc[1 + d];
-            ke += wc[1 + d] * wc[1 + d];
-        }
-        uc[ND + 1] = wc[ND + 1] * inv_gm1 + T(0.5) * wc[0] * ke;
-#pragma unroll
-        for (int v = 0; v < ND + 2; ++v) {
-            fine[v * fg.vs + c] = uc[v];
-            if (fine2) fine2[v * fg.vs + c] = uc[v];
-        }
-    }
+    ride_run<ND>(j, blockIdx.x, threadIdx.x, SB);
 }
 
 // Up to two boxes of one array in one launch: blockIdx.y = (box * ND + Q) * 2
@@ -262,9 +128,13 @@ __device__ __forceinline__ void restrict_cell(T *parent, const Grid &pg, const B
 // The two sets of cells are disjoint, and neither reads what the other writes.
 template <int ND, typename T>
 __global__ void __launch_bounds__(FB) k_reflux_restrict(T *u, Grid g, Box b, RefluxSet r, const T *child, Grid cg,
-                                                        int rblocks)
+                                                        int rblocks, int rcblocks, RideJob<T> ride)
 {
     const int bid = blockIdx.x;
+    if (bid >= rcblocks) {  // a job riding on the launch
+        ride_run<ND>(ride, bid - rcblocks, threadIdx.x, FB);
+        return;
+    }
     if (bid < ND * rblocks) {
         const int q = bid / rblocks, t = (bid - q * rblocks) * FB + threadIdx.x;
         if (q == 0) reflux_faces<ND, 0>(u, g, b, t, r.c[0][0], r.c[0][1], r.f[0][0], r.f[0][1], r.idq[0]);
@@ -385,19 +255,35 @@ hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int n
 }
 
 template <typename T>
+RideJob<T> prolong_job(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
+                       int ndim, T gm1, const ClockOps &ck)
+{
+    RideJob<T> j{};
+    j.fine = fine;
+    j.fine2 = fine2;
+    j.fg = fg;
+    j.parent = parent;
+    j.pg = pg;
+    j.pb = parent_box;
+    j.gm1 = gm1;
+    j.inv_gm1 = T(1) / gm1;
+    j.cells = fine == nullptr ? 0 : ndim == 1 ? shell_cells<1>(fg) : ndim == 2 ? shell_cells<2>(fg) : shell_cells<3>(fg);
+    j.blocks = 0;
+    j.ck = ck;
+    return j;
+}
+
+template <typename T>
 hipError_t launch_prolong(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
                           int ndim, T gamma, T gm1, const ClockOps &ck, hipStream_t s)
 {
     (void)gamma;
-    const T inv_gm1 = T(1) / gm1;
-    const int cells = ndim == 1 ? shell_cells<1>(fg) : ndim == 2 ? shell_cells<2>(fg) : shell_cells<3>(fg);
-    const dim3 grid((cells + SB - 1) / SB);
-    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
-                           inv_gm1, ck);
-    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
-                           inv_gm1, ck);
-    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(SB), 0, s, fine, fine2, fg, parent, pg, parent_box, gm1,
-                           inv_gm1, ck);
+    RideJob<T> j = prolong_job<T>(fine, fine2, fg, parent, pg, parent_box, ndim, gm1, ck);
+    j.blocks = std::max(1, (j.cells + SB - 1) / SB);
+    const dim3 grid((unsigned)j.blocks);
+    if (ndim == 1) hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(SB), 0, s, j);
+    else if (ndim == 2) hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(SB), 0, s, j);
+    else hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(SB), 0, s, j);
     return hipGetLastError();
 }
 
@@ -422,7 +308,7 @@ hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes
 template <typename T>
 hipError_t launch_reflux_restrict(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
                                   const double *const fine[3][2], const double idq[3], const T *child, const Grid &cg,
-                                  hipStream_t s)
+                                  const RideJob<T> *ride, hipStream_t s)
 {
     RefluxSet r{};
     int most = 0;
@@ -439,15 +325,22 @@ hipError_t launch_reflux_restrict(T *u, const Grid &g, const Box &child_box, int
     }
     const int rblocks = (most + FB - 1) / FB;
     const int64_t cells = (int64_t)child_box.n[0] * child_box.n[1] * child_box.n[2];
-    const int64_t blocks = (int64_t)ndim * rblocks + (cells + FB - 1) / FB;
+    const int64_t rcblocks = (int64_t)ndim * rblocks + (cells + FB - 1) / FB;
+    RideJob<T> j{};
+    if (ride) {
+        j = *ride;
+        j.blocks = (j.cells > 0 || j.ck.c) ? std::max(1, (j.cells + FB - 1) / FB) : 0;
+    }
+    const int64_t blocks = rcblocks + j.blocks;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks);
+    const int rc = (int)rcblocks;
     if (ndim == 1)
-        hipLaunchKernelGGL((k_reflux_restrict<1, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks);
+        hipLaunchKernelGGL((k_reflux_restrict<1, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks, rc, j);
     else if (ndim == 2)
-        hipLaunchKernelGGL((k_reflux_restrict<2, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks);
+        hipLaunchKernelGGL((k_reflux_restrict<2, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks, rc, j);
     else
-        hipLaunchKernelGGL((k_reflux_restrict<3, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks);
+        hipLaunchKernelGGL((k_reflux_restrict<3, T>), grid, dim3(FB), 0, s, u, g, child_box, r, child, cg, rblocks, rc, j);
     return hipGetLastError();
 }
 
@@ -484,7 +377,9 @@ hipError_t launch_leaf_totals(const T *u, const Grid &g, const Box &box, const B
                                            const int *, int, int, T, T, T, T, const double *, hipStream_t);          \
     template hipError_t launch_reflux_restrict<T>(T *, const Grid &, const Box &, int, const double *const[3][2],    \
                                                   const double *const[3][2], const double[3], const T *,             \
-                                                  const Grid &, hipStream_t);                                        \
+                                                  const Grid &, const RideJob<T> *, hipStream_t);                    \
+    template RideJob<T> prolong_job<T>(T *, T *, const Grid &, const T *, const Grid &, const Box &, int, T,          \
+                                       const ClockOps &);                                                            \
     template hipError_t launch_box_rate<T>(const T *, const Grid &, const Box &, int, T, T, const double[3],         \
                                            unsigned long long *, hipStream_t);                                       \
     template hipError_t launch_leaf_totals<T>(const T *, const Grid &, const Box &, const Box &, int, double,        \

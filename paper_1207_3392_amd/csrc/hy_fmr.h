@@ -17,12 +17,10 @@ namespace hy {
 
 constexpr int FMR_NG = 2;
 
-// A level's clock in device memory: its time, the step of its next full
-// step and of its next provisional half-step.  Kernels read their steps from
-// here, so a global step needs no host round trip.
-struct FmrClock {
-    double t, dt, dtp, pad;
-};
+// A level's clock (FmrClock, hy_internal.h) lives in device memory: its
+// time, the step of its next full step and of its next provisional
+// half-step.  Kernels read their steps from there, so a global step needs no
+// host round trip.
 
 enum {
     CLOCK_RESET = 0,
@@ -51,13 +49,7 @@ constexpr int FMR_RATE_SLOTS = 32;
 hipError_t launch_clock(FmrClock *clock, int op0, int l0, int op1, int l1, int nlev, unsigned long long *rate_bits,
                         double cfl, double dt_fixed, hipStream_t s);
 
-// Clock updates carried by another launch (c == nullptr: none).
-struct ClockOps {
-    FmrClock *c;
-    int op0, l0, op1, l1, nlev;
-    unsigned long long *rate;
-    double cfl, dt_fixed;
-};
+// Clock updates carried by another launch: ClockOps (hy_internal.h).
 
 // Exterior of the padded level (fine) from its parent: each exterior cell at
 // fine offset r from the level's first interior cell takes its parent
@@ -92,10 +84,18 @@ hipError_t launch_box_flux(const T *u, const Grid &g, int nbox, const Box *boxes
 // restriction (every parent cell of child_box becomes the mean of its 2^d
 // children, the child being a padded level, interior at offset NG).  The two
 // touch disjoint parent cells.
+// A job riding on the launch (ride != nullptr: RideJob, hy_internal.h) runs
+// in extra workgroups after these.
 template <typename T>
 hipError_t launch_reflux_restrict(T *u, const Grid &g, const Box &child_box, int ndim, const double *const coarse[3][2],
                                   const double *const fine[3][2], const double idq[3], const T *child, const Grid &cg,
-                                  hipStream_t s);
+                                  const RideJob<T> *ride, hipStream_t s);
+
+// The RideJob that launch_prolong's arguments describe (cells set, blocks
+// left for the host launch's launcher).
+template <typename T>
+RideJob<T> prolong_job(T *fine, T *fine2, const Grid &fg, const T *parent, const Grid &pg, const Box &parent_box,
+                       int ndim, T gm1, const ClockOps &ck);
 
 // max over the cells of box of (|v_q| + c_s) / dq into the FMR_RATE_SLOTS
 // words rate_bits (the bits of a positive double; unsigned atomic max).

@@ -65,6 +65,36 @@ struct BoxFluxes {
     int blocks;
 };
 
+// A multilevel level's clock in device memory (its time, the step of its
+// next full step and of its next provisional half-step) and clock updates
+// carried by another launch (c == nullptr: none); see hy_fmr.h.
+struct FmrClock {
+    double t, dt, dtp, pad;
+};
+struct ClockOps {
+    FmrClock *c;
+    int op0, l0, op1, l1, nlev;
+    unsigned long long *rate;
+    double cfl, dt_fixed;
+};
+
+// Work that rides on another launch of the multilevel step: the prolongation
+// of a padded level's exterior from its parent (cells > 0) and/or clock
+// updates (ck.c), done by `blocks` extra workgroups appended to the host
+// launch (the launcher sets blocks for its workgroup size).  The host launch
+// must neither read nor write what the job touches; see hy_fmr.h.
+template <typename T>
+struct RideJob {
+    T *fine, *fine2;
+    Grid fg;
+    const T *parent;
+    Grid pg;
+    Box pb;
+    T gm1, inv_gm1;
+    int cells, blocks;
+    ClockOps ck;
+};
+
 template <typename T>
 struct StageArgs {
     const T *uin;     // state read with the stencil (U^n in stage 1, U^(1) in stage 2)
@@ -86,6 +116,8 @@ struct StageArgs {
     const double *dt_dev;  // DT_PTR: the step
     int voff[3], vm[3];    // LIM_THETA_PADDED: first updated cell and extents of the storage
     BoxFluxes bf;          // LIM_THETA_PADDED: face fluxes of the input computed in the same launch
+    int nbfwg;             // LIM_THETA_PADDED: workgroups of bf (set by the launcher)
+    RideJob<T> ride;       // LIM_THETA_PADDED: a job riding on the launch (after bf's workgroups)
 };
 
 struct LaunchCfg {

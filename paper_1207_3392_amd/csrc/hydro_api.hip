@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1487,6 +1488,31 @@ hy_status hy_trainer_destroy(hy_trainer *tr)
 // end, for the error latches and the coarse step.
 #include "hy_fmr.h"
 
+// A job for fmr_ride (host side, precision-free): the prolongation of a
+// padded level's exterior from its parent (fine != null; arguments of
+// hy::launch_prolong) and the clock updates ck.
+struct FmrRide {
+    void *fine, *fine2;
+    hy::Grid fg;
+    const void *parent;
+    hy::Grid pg;
+    hy::Box pb;
+    int ndim;
+    double gm1;
+    hy::ClockOps ck;
+};
+
+template <typename T>
+hy::RideJob<T> ride_job(const FmrRide &r)
+{
+    if (r.fine)
+        return hy::prolong_job<T>((T *)r.fine, (T *)r.fine2, r.fg, (const T *)r.parent, r.pg, r.pb, r.ndim, (T)r.gm1,
+                                  r.ck);
+    hy::RideJob<T> j{};
+    j.ck = r.ck;
+    return j;
+}
+
 struct hy_fmr {
     hy_fmr_desc d;
     int nlev = 0, nv = 0;
@@ -1510,6 +1536,13 @@ struct hy_fmr {
     unsigned long long *rate = nullptr;
     hy::FmrClock *clock = nullptr;
     int pending_advance = -1;  // level whose clock advance rides on the next clock launch
+    // the last launch of a level's step (the second stage of the deepest
+    // level, else the coarse/fine replacement and restriction from its
+    // child), held back so that the parent's prolongation or clock update
+    // that comes next can ride on it (fmr_ride); launched with ride == null
+    // otherwise (fmr_flush)
+    int held_level = -1;
+    std::function<hipError_t(const FmrRide *ride)> held;
     int solver = HY_HLLC;
     double cfl = 0.4, dt_fixed = 0.0;
     // the launches of one global step, captured once per (solver, cfl,
@@ -1596,14 +1629,57 @@ hy_status fmr_layout(const hy_fmr_desc *d, FmrLayout *L)
     return HY_OK;
 }
 
+// Launches the held launch as it is.  Every other launch of the multilevel
+// step goes after this.
+hipError_t fmr_flush(hy_fmr *f)
+{
+    if (!f->held) return hipSuccess;
+    auto fn = std::move(f->held);
+    f->held = nullptr;
+    f->held_level = -1;
+    return fn(nullptr);
+}
+
+void fmr_hold(hy_fmr *f, int level, std::function<hipError_t(const FmrRide *)> fn)
+{
+    f->held = std::move(fn);
+    f->held_level = level;
+}
+
+// Launches job r (the parent's prolongation and/or clock updates of level l)
+// riding on the held launch when that is the end of level l + 1's step (it
+// then touches nothing the job does: the held launch writes level l + 1 (its
+// state, its own boundary fluxes, or the child's restriction into it) and
+// reads only its own step from the clocks, the job writes level l's
+// exterior, reads level l - 1, and updates the clocks of level l and the
+// advance of level l + 1's time); else after flushing it, in a launch of its
+// own.  Returns false in *rode when it did not ride.
+hipError_t fmr_ride(hy_fmr *f, int l, const FmrRide &r, bool *rode)
+{
+    *rode = false;
+    if (f->held && f->held_level == l + 1) {
+        auto fn = std::move(f->held);
+        f->held = nullptr;
+        f->held_level = -1;
+        *rode = true;
+        return fn(&r);
+    }
+    return fmr_flush(f);
+}
+
 // A clock update on the stream; a pending advance of a level's time goes
 // first in the same launch.
 hipError_t fmr_clock(hy_fmr *f, int op, int l, unsigned long long *rate = nullptr)
 {
     const int pre = f->pending_advance;
     f->pending_advance = -1;
-    return hy::launch_clock(f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, l, f->nlev, rate ? rate : f->rate,
-                            f->cfl, f->dt_fixed, f->stream);
+    FmrRide r{};
+    r.ck = {f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, l, f->nlev, rate ? rate : f->rate, f->cfl, f->dt_fixed};
+    bool rode = false;
+    hipError_t e = op >= 0 || pre >= 0 ? fmr_ride(f, l, r, &rode) : fmr_flush(f);
+    if (e != hipSuccess || rode) return e;
+    return hy::launch_clock(f->clock, r.ck.op0, r.ck.l0, r.ck.op1, r.ck.l1, f->nlev, r.ck.rate, f->cfl, f->dt_fixed,
+                            f->stream);
 }
 
 // Level l's time advances by its step; the update joins the next clock launch
@@ -1640,6 +1716,13 @@ hipError_t fmr_prolong(hy_fmr *f, int l, int op = -1, int lop = 0, unsigned long
     if (pre >= 0 || op >= 0)
         ck = {f->clock, pre >= 0 ? hy::CLOCK_ADVANCE : -1, pre, op, lop, f->nlev, rate ? rate : f->rate, f->cfl,
               f->dt_fixed};
+    // rides on the end of the child's step when that was the last launch
+    // (never for the deepest level, whose exterior comes from the parent's
+    // state of the launches just before)
+    const FmrRide r{arrA<T>(L), arrB<T>(L), L.g, src, P.g, pb, f->d.base.ndim, g - 1.0, ck};
+    bool rode = false;
+    hipError_t e = fmr_ride(f, l, r, &rode);
+    if (e != hipSuccess || rode) return e;
     return hy::launch_prolong<T>(arrA<T>(L), arrB<T>(L), L.g, src, P.g, pb, f->d.base.ndim, (T)g, (T)(g - 1.0), ck,
                                  f->stream);
 }
@@ -1651,7 +1734,8 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
 {
     hy_fmr::Level &L = f->lev[l];
     hy_patch *p = L.p;
-    hipError_t e;
+    hipError_t e = fmr_flush(f);
+    if (e != hipSuccess) return e;
     if (provisional) {
         p->dt_dev = &f->clock[l].dtp;
         if (l > 0) {
@@ -1713,8 +1797,21 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
                     for (int q = 0; q < 3; ++q)
                         for (int sd = 0; sd < 2; ++sd) a.bf.acc[k][q][sd] = acc[k][q][sd];
                 }
-                e = hy::launch_stage<T>(nd, f->solver, stage, hy::LIM_THETA_PADDED, p->cfg, a, p->stream);
-                if (e != hipSuccess) return e;
+                if (stage == 2 && !child) {
+                    // the deepest level's second stage ends its step: held
+                    // for the parent's prolongation or clock update to ride on
+                    const int solver = f->solver;
+                    const hy::LaunchCfg cfg = p->cfg;
+                    hipStream_t st = p->stream;
+                    fmr_hold(f, l, [a, nd, solver, cfg, st](const FmrRide *r) {
+                        hy::StageArgs<T> b = a;
+                        if (r) b.ride = ride_job<T>(*r);
+                        return hy::launch_stage<T>(nd, solver, 2, hy::LIM_THETA_PADDED, cfg, b, st);
+                    });
+                } else {
+                    e = hy::launch_stage<T>(nd, f->solver, stage, hy::LIM_THETA_PADDED, p->cfg, a, p->stream);
+                    if (e != hipSuccess) return e;
+                }
                 L.own_fresh = false;
                 continue;
             }
@@ -1775,8 +1872,8 @@ hy_status fmr_step_level(hy_fmr *f, int l)
         e = deepest ? fmr_prolong<T>(f, l, hy::CLOCK_DEEPEST_KEEP, l, &L.p->ctl->rate[L.p->parity][0])
                     : fmr_prolong<T>(f, l, hy::CLOCK_COARSE, l);
     } else if (deepest) {  // one level: a rate pass over it
-        e = hipSuccess;
-        if (!(f->dt_fixed > 0.0)) {
+        e = fmr_flush(f);
+        if (e == hipSuccess && !(f->dt_fixed > 0.0)) {
             const double g = f->d.base.gamma;
             e = hy::launch_box_rate<T>(arrA<T>(L), L.g, L.own, nd, (T)g, (T)(g - 1.0), L.idq, f->rate, f->stream);
         }
@@ -1795,7 +1892,31 @@ hy_status fmr_step_level(hy_fmr *f, int l)
                 c[q][s] = L.coarse_acc[q][s];
                 fa[q][s] = C.own_acc[q][s];
             }
-        e = hy::launch_reflux_restrict<T>(arrA<T>(L), L.g, L.child, nd, c, fa, L.idq, arrA<T>(C), C.g, f->stream);
+        // held: it ends this level's step, and the parent's prolongation or
+        // clock update (or the coarse level's final clock advance) that
+        // comes next can ride on it
+        struct Args {
+            T *u;
+            hy::Grid g, cg;
+            hy::Box child;
+            const double *c[3][2], *fa[3][2];
+            double idq[3];
+            const T *uc;
+        } ra{arrA<T>(L), L.g, C.g, L.child, {}, {}, {L.idq[0], L.idq[1], L.idq[2]}, arrA<T>(C)};
+        for (int q = 0; q < 3; ++q)
+            for (int sd = 0; sd < 2; ++sd) {
+                ra.c[q][sd] = c[q][sd];
+                ra.fa[q][sd] = fa[q][sd];
+            }
+        hipStream_t st = f->stream;
+        e = fmr_flush(f);
+        if (e == hipSuccess)
+            fmr_hold(f, l, [ra, nd, st](const FmrRide *r) {
+                hy::RideJob<T> j{};
+                if (r) j = ride_job<T>(*r);
+                return hy::launch_reflux_restrict<T>(ra.u, ra.g, ra.child, nd, ra.c, ra.fa, ra.idq, ra.uc, ra.cg,
+                                                     r ? &j : nullptr, st);
+            });
     }
     if (e == hipSuccess) e = fmr_defer_advance(f, l);
     if (e != hipSuccess) return hip_fail(e, "level step");
@@ -1811,11 +1932,33 @@ hy_status fmr_enqueue(hy_fmr *f, hipStream_t s)
         f->lev[l].prov = false;
     }
     f->pending_advance = -1;
+    f->held = nullptr;
+    f->held_level = -1;
     hipError_t e = fmr_clock(f, hy::CLOCK_RESET, 0);
     if (e != hipSuccess) return hip_fail(e, "clock reset");
     hy_status st = f->d.base.precision == 64 ? fmr_evolve_level<double>(f, 0) : fmr_evolve_level<float>(f, 0);
-    if (st != HY_OK) return st;
-    e = fmr_clock(f, -1, 0);  // the coarse level's final advance
+    if (st != HY_OK) {
+        f->held = nullptr;
+        f->held_level = -1;
+        return st;
+    }
+    // the coarse level's final advance, riding on its restriction from
+    // level 1 when that was the last launch
+    const int pre = f->pending_advance;
+    f->pending_advance = -1;
+    if (pre >= 0 && f->held && f->held_level == 0) {
+        FmrRide r{};
+        r.ck = {f->clock, hy::CLOCK_ADVANCE, pre, -1, 0, f->nlev, f->rate, f->cfl, f->dt_fixed};
+        auto fn = std::move(f->held);
+        f->held = nullptr;
+        f->held_level = -1;
+        e = fn(&r);
+    } else {
+        e = fmr_flush(f);
+        if (e == hipSuccess && pre >= 0)
+            e = hy::launch_clock(f->clock, hy::CLOCK_ADVANCE, pre, -1, 0, f->nlev, f->rate, f->cfl, f->dt_fixed,
+                                 f->stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "clock advance");
     return HY_OK;
 }

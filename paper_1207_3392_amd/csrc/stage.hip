@@ -23,6 +23,7 @@
 // with the normal velocity negated).
 #include "hy_internal.h"
 #include "hy_face.h"
+#include "hy_ride.h"
 
 #include <math.h>
 #include <type_traits>
@@ -185,10 +186,13 @@ __global__ void __launch_bounds__(BX *BY, (BX * BY == 256) ? 3 : 4) k_stage(cons
     constexpr bool PAD = LIM == LIM_THETA_PADDED;
     static_assert(!PAD || SOLVER != SOLVER_HLLC_SWITCH, "padded arrays take HLL or HLLC");
     if constexpr (PAD) {
-        // the workgroups after the tiles compute box face fluxes (whole
-        // workgroups, before any barrier)
+        // the workgroups after the tiles compute box face fluxes, then those
+        // after them run the job riding on the launch (whole workgroups,
+        // before any barrier)
         if ((int)blockIdx.x >= a.ntiles) {
-            stage_box_faces<ND, SOLVER, NT>(a, (int)blockIdx.x - a.ntiles, tid);
+            const int fid = (int)blockIdx.x - a.ntiles;
+            if (fid < a.nbfwg) stage_box_faces<ND, SOLVER, NT>(a, fid, tid);
+            else ride_run<ND>(a.ride, fid - a.nbfwg, tid, NT);
             return;
         }
     }
@@ -875,6 +879,7 @@ hipError_t launch_one(const LaunchCfg &cfg, StageArgs<T> a, hipStream_t s)
     const int chunks = ND == 3 ? (int)((a.n[2] + cfg.zchunk - 1) / cfg.zchunk) : 1;
     a.ntiles = a.tiles_x * a.tiles_y * chunks;
     int64_t blocks = a.ntiles;
+    a.nbfwg = 0;
     if constexpr (LIM == LIM_THETA_PADDED) {
         if (a.bf.nbox > 0) {
             if (a.bf.nbox > 2 || a.dt_mode != DT_PTR || !a.dt_dev) return hipErrorInvalidValue;
@@ -885,8 +890,12 @@ hipError_t launch_one(const LaunchCfg &cfg, StageArgs<T> a, hipStream_t s)
                     most = most > a.bf.b[k].n[r1] * a.bf.b[k].n[r2] ? most : a.bf.b[k].n[r1] * a.bf.b[k].n[r2];
                 }
             a.bf.blocks = (most + BX * BY - 1) / (BX * BY);
-            blocks += (int64_t)a.bf.nbox * ND * 2 * a.bf.blocks;
+            a.nbfwg = a.bf.nbox * ND * 2 * a.bf.blocks;
+            blocks += a.nbfwg;
         }
+        const int rb = (a.ride.cells + BX * BY - 1) / (BX * BY);
+        a.ride.blocks = (a.ride.cells > 0 || a.ride.ck.c) ? (rb > 1 ? rb : 1) : 0;
+        blocks += a.ride.blocks;
     }
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_stage<ND, T, SOLVER, STAGE, LIM, BX, BY>), dim3((unsigned)blocks), dim3(BX, BY, 1), 0, s, a);
