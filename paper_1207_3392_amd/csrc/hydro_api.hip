@@ -1539,9 +1539,12 @@ struct hy_fmr {
     // the last launch of a level's step (the second stage of the deepest
     // level, else the coarse/fine replacement and restriction from its
     // child), held back so that the parent's prolongation or clock update
-    // that comes next can ride on it (fmr_ride); launched with ride == null
+    // that comes next can ride on it (fmr_ride); or a refined level's
+    // provisional first stage, on which the deepest level's prolongation can
+    // ride unless the deepest level is its child; launched with ride == null
     // otherwise (fmr_flush)
     int held_level = -1;
+    bool held_prov = false;
     std::function<hipError_t(const FmrRide *ride)> held;
     int solver = HY_HLLC;
     double cfl = 0.4, dt_fixed = 0.0;
@@ -1640,10 +1643,11 @@ hipError_t fmr_flush(hy_fmr *f)
     return fn(nullptr);
 }
 
-void fmr_hold(hy_fmr *f, int level, std::function<hipError_t(const FmrRide *)> fn)
+void fmr_hold(hy_fmr *f, int level, std::function<hipError_t(const FmrRide *)> fn, bool prov = false)
 {
     f->held = std::move(fn);
     f->held_level = level;
+    f->held_prov = prov;
 }
 
 // Launches job r (the parent's prolongation and/or clock updates of level l)
@@ -1657,7 +1661,13 @@ void fmr_hold(hy_fmr *f, int level, std::function<hipError_t(const FmrRide *)> f
 hipError_t fmr_ride(hy_fmr *f, int l, const FmrRide &r, bool *rode)
 {
     *rode = false;
-    if (f->held && f->held_level == l + 1) {
+    // (a provisional first stage of level m writes level m's stage state and
+    // reads level m and its clock; the deepest level's prolongation reads its
+    // parent's state and its own rate words and writes its exterior and
+    // clock: independent unless m is the parent)
+    const bool ok = f->held_prov ? (l == f->nlev - 1 && f->held_level <= l - 2 && r.fine != nullptr)
+                                 : f->held_level == l + 1;
+    if (f->held && ok) {
         auto fn = std::move(f->held);
         f->held = nullptr;
         f->held_level = -1;
@@ -1748,7 +1758,15 @@ hipError_t fmr_level_step(hy_fmr *f, int l, bool provisional)
                 a.n[q] = f->d.box_n[l + 1][q] + 4;
                 a.voff[q] = (int)f->d.box_lo[l + 1][q];  // NG + (box_lo - 2) in storage
             }
-            e = hy::launch_stage<T>(p->d.ndim, f->solver, 1, hy::LIM_THETA_PADDED, p->cfg, a, p->stream);
+            // held: the deepest level's prolongation may come next and ride on it
+            const int nd = p->d.ndim, solver = f->solver;
+            const hy::LaunchCfg cfg = p->cfg;
+            hipStream_t st = p->stream;
+            fmr_hold(f, l, [a, nd, solver, cfg, st](const FmrRide *r) {
+                hy::StageArgs<T> b = a;
+                if (r) b.ride = ride_job<T>(*r);
+                return hy::launch_stage<T>(nd, solver, 1, hy::LIM_THETA_PADDED, cfg, b, st);
+            }, true);
         } else {
             e = run_stage<T>(p, f->solver, 1, hy::DT_PTR, 0.0, 0.0, 0.0);
         }
@@ -1946,7 +1964,7 @@ hy_status fmr_enqueue(hy_fmr *f, hipStream_t s)
     // level 1 when that was the last launch
     const int pre = f->pending_advance;
     f->pending_advance = -1;
-    if (pre >= 0 && f->held && f->held_level == 0) {
+    if (pre >= 0 && f->held && !f->held_prov && f->held_level == 0) {
         FmrRide r{};
         r.ck = {f->clock, hy::CLOCK_ADVANCE, pre, -1, 0, f->nlev, f->rate, f->cfl, f->dt_fixed};
         auto fn = std::move(f->held);
