@@ -837,9 +837,9 @@ static void note(fmr_ctx *c, int st)
     if (st != ORC_OK && c->status == ORC_OK) c->status = st;
 }
 
-/* Stepper(l)%Step: one two-stage step of level l with its exterior held in
- * ext[l].  provisional: the first stage alone (the coarse half-step of Alg.
- * EvolveLevel), no replacement.  acc, when given, accumulates the level's
+/* One two-stage step of level l with its exterior held in ext[l].
+ * provisional: the first stage alone (the coarse level's provisional stage
+ * between its child's two steps), no replacement.  acc, when given, accumulates the level's
  * own boundary fluxes integrated over the step (ForParents). */
 static void level_step(fmr_ctx *c, int l, double dt, int provisional, double *acc[3][2])
 {
@@ -922,76 +922,50 @@ static void level_step(fmr_ctx *c, int l, double dt, int provisional, double *ac
     free(L);
 }
 
-static void evolve_level(fmr_ctx *c, int l, double *acc[3][2]);
-
-/* Alg. StepLevel */
-static void step_level(fmr_ctx *c, int l, double *acc[3][2])
+/* The coarse level's share of its child's two steps: the child's boundary
+ * fluxes accumulated over them (acc, on the child's faces) restricted to
+ * this level's faces of the child box, each coarse face the mean of its
+ * 2^(d-1) fine faces. */
+static void restrict_boundary_fluxes(fmr_ctx *c, int l, double *const acc[3][2])
 {
     const orc_fmr_desc *f = c->f;
+    const orc_desc *cd = &c->lev[l + 1];
     int nv = nvars(&f->base), nd = f->base.ndim;
-    if (l + 1 < f->nlev) {
-        /* the child's boundary fluxes over its two steps (ForParentsNext) */
-        const orc_desc *cd = &c->lev[l + 1];
-        double *next[3][2];
-        memset(next, 0, sizeof(next));
-        for (int q = 0; q < nd; ++q)
-            for (int s = 0; s < 2; ++s) next[q][s] = (double *)calloc((size_t)(nv * face_count(cd->n, q)), sizeof(double));
-        evolve_level(c, l + 1, next);
-        /* restricted to this level's faces of the child box: mean over the
-         * 2^(d-1) fine faces of each coarse face */
-        int64_t cn[3] = {f->box_n[l + 1][0], f->box_n[l + 1][1], f->box_n[l + 1][2]};
-        for (int q = 0; q < nd; ++q) {
-            int r1 = (q + 1) % 3, r2 = (q + 2) % 3;
-            int64_t nf = face_count(cn, q), nff = face_count(cd->n, q);
-            int a1 = r1 < nd ? 2 : 1, a2 = r2 < nd ? 2 : 1;
-            for (int s = 0; s < 2; ++s)
-                for (int v = 0; v < nv; ++v)
-                    for (int64_t t2 = 0; t2 < cn[r2]; ++t2)
-                        for (int64_t t1 = 0; t1 < cn[r1]; ++t1) {
-                            double sum = 0.0;
-                            for (int o2 = 0; o2 < a2; ++o2)
-                                for (int o1 = 0; o1 < a1; ++o1)
-                                    sum += next[q][s][v * nff + (a2 * t2 + o2) * cd->n[r1] + a1 * t1 + o1];
-                            c->from_children[l][q][s][v * nf + t2 * cn[r1] + t1] = sum / (double)(a1 * a2);
-                        }
-        }
-        for (int q = 0; q < nd; ++q)
-            for (int s = 0; s < 2; ++s) free(next[q][s]);
+    int64_t cn[3] = {f->box_n[l + 1][0], f->box_n[l + 1][1], f->box_n[l + 1][2]};
+    for (int q = 0; q < nd; ++q) {
+        int r1 = (q + 1) % 3, r2 = (q + 2) % 3;
+        int64_t nf = face_count(cn, q), nff = face_count(cd->n, q);
+        int a1 = r1 < nd ? 2 : 1, a2 = r2 < nd ? 2 : 1;
+        for (int s = 0; s < 2; ++s)
+            for (int v = 0; v < nv; ++v)
+                for (int64_t t2 = 0; t2 < cn[r2]; ++t2)
+                    for (int64_t t1 = 0; t1 < cn[r1]; ++t1) {
+                        double sum = 0.0;
+                        for (int o2 = 0; o2 < a2; ++o2)
+                            for (int o1 = 0; o1 < a1; ++o1)
+                                sum += acc[q][s][v * nff + (a2 * t2 + o2) * cd->n[r1] + a1 * t1 + o1];
+                        c->from_children[l][q][s][v * nf + t2 * cn[r1] + t1] = sum / (double)(a1 * a2);
+                    }
     }
-    if (l > 0) note(c, orc_fmr_prolong(f, l, c->U[l - 1], c->ext[l]));
-    double dt;
-    if (l == f->nlev - 1) {
-        if (c->dt_fixed > 0.0) {
-            dt = c->dt_fixed;
-        } else {
-            note(c, orc_cfl_dt(&c->lev[l], c->U[l], c->cfl, &dt));
-        }
-    } else {
-        dt = c->T[l + 1] - c->T[l];
-    }
-    level_step(c, l, dt, 0, acc);
-    if (l + 1 < f->nlev) note(c, orc_fmr_restrict(f, l + 1, c->U[l + 1], c->U[l]));
-    c->T[l] += dt;
 }
 
-/* Alg. EvolveLevel */
-static void evolve_level(fmr_ctx *c, int l, double *acc[3][2])
-{
-    if (l >= c->f->nlev) return;
-    step_level(c, l, acc);
-    if (l == 0) return;
-    const orc_desc *pd = &c->lev[l - 1];
-    int64_t T = nvars(pd) * ncells(pd);
-    double *old = (double *)malloc(sizeof(double) * T);
-    memcpy(old, c->U[l - 1], sizeof(double) * T);
-    if (l - 1 > 0) note(c, orc_fmr_prolong(c->f, l - 1, c->U[l - 2], c->ext[l - 1]));
-    level_step(c, l - 1, c->T[l] - c->T[l - 1], 1, NULL);
-    step_level(c, l, acc);
-    memcpy(c->U[l - 1], old, sizeof(double) * T);
-    free(old);
-}
-
-/* Alg. Evolve, one pass of its loop: every level advances to the same time. */
+/* One global step of the nested levels (Sec. 3.6, Algs. Evolve, EvolveLevel
+ * and StepLevel), written as the time-ordered schedule those algorithms
+ * produce.  Level l takes two steps for each step of level l - 1, so the
+ * deepest level D takes 2^D steps; its step is the CFL step, and each
+ * coarser level's step spans its child's two steps, so a coarse level steps
+ * only after its child has.  Between the child's first and second step the
+ * coarse level takes a provisional first stage over the child's first step
+ * (from a saved copy of its state, restored afterwards), so that the child's
+ * exterior for its second step is prolonged from the coarse state at the
+ * child's time.  A full coarse step replaces the fluxes through the child
+ * box's faces by the child's (their time integral over its two steps) and is
+ * followed by the restriction of the child onto the cells it covers.  In
+ * schedule terms: after the deepest step k, level l (from D - 1 up) has just
+ * seen its child finish that child's step number m = (k + 1) / 2^(D-1-l); an
+ * odd m (a first step) calls for the provisional stage of level l and ends
+ * the cascade, an even m for the full step of level l, after which its own
+ * parent is looked at. */
 int orc_fmr_step(const orc_fmr_desc *f, double *const *U, double cfl, double dt_fixed, double *dt_out)
 {
     if (!fmr_valid(f) || !U || !dt_out) return ORC_EINVAL;
@@ -1003,26 +977,73 @@ int orc_fmr_step(const orc_fmr_desc *f, double *const *U, double cfl, double dt_
     c.cfl = cfl;
     c.dt_fixed = dt_fixed;
     int nv = nvars(&f->base), nd = f->base.ndim;
+    /* own[l]: level l's boundary fluxes accumulated over its parent's
+     * current step; saved[l]: level l's state during its provisional stage */
+    double *own[ORC_FMR_MAXLEV][3][2];
+    double *saved[ORC_FMR_MAXLEV];
+    memset(own, 0, sizeof(own));
+    memset(saved, 0, sizeof(saved));
     for (int l = 0; l < f->nlev; ++l) {
         orc_fmr_level(f, l, &c.lev[l]);
         if (l > 0) {
             ghost_geom G = make_geom(&c.lev[l]);
             c.ext[l] = (double *)calloc((size_t)(nv * G.m[0] * G.m[1] * G.m[2]), sizeof(double));
+            for (int q = 0; q < nd; ++q)
+                for (int s = 0; s < 2; ++s)
+                    own[l][q][s] = (double *)calloc((size_t)(nv * face_count(c.lev[l].n, q)), sizeof(double));
         }
-        if (l + 1 < f->nlev)
+        if (l + 1 < f->nlev) {
             for (int q = 0; q < nd; ++q)
                 for (int s = 0; s < 2; ++s)
                     c.from_children[l][q][s] =
                         (double *)calloc((size_t)(nv * face_count(f->box_n[l + 1], q)), sizeof(double));
+            saved[l] = (double *)malloc(sizeof(double) * (size_t)(nv * ncells(&c.lev[l])));
+        }
     }
-    evolve_level(&c, 0, NULL);
+    const int D = f->nlev - 1;
+    const long nsteps = 1L << D;
+    for (long k = 0; k < nsteps && c.status == ORC_OK; ++k) {
+        /* the deepest level's step: exterior from its parent, CFL step */
+        double dt;
+        if (D > 0) note(&c, orc_fmr_prolong(f, D, c.U[D - 1], c.ext[D]));
+        if (c.dt_fixed > 0.0) dt = c.dt_fixed;
+        else note(&c, orc_cfl_dt(&c.lev[D], c.U[D], c.cfl, &dt));
+        level_step(&c, D, dt, 0, D > 0 ? own[D] : NULL);
+        c.T[D] += dt;
+        for (int l = D - 1; l >= 0; --l) {
+            const long m = (k + 1) >> (D - 1 - l);
+            const int64_t T = nv * ncells(&c.lev[l]);
+            if (m & 1) {
+                /* the child's first step is done: the provisional stage */
+                memcpy(saved[l], c.U[l], sizeof(double) * (size_t)T);
+                if (l > 0) note(&c, orc_fmr_prolong(f, l, c.U[l - 1], c.ext[l]));
+                level_step(&c, l, c.T[l + 1] - c.T[l], 1, NULL);
+                break;
+            }
+            /* both child steps are done: the full step of level l */
+            memcpy(c.U[l], saved[l], sizeof(double) * (size_t)T);
+            restrict_boundary_fluxes(&c, l, own[l + 1]);
+            for (int q = 0; q < nd; ++q)
+                for (int s = 0; s < 2; ++s)
+                    memset(own[l + 1][q][s], 0, sizeof(double) * (size_t)(nv * face_count(c.lev[l + 1].n, q)));
+            if (l > 0) note(&c, orc_fmr_prolong(f, l, c.U[l - 1], c.ext[l]));
+            dt = c.T[l + 1] - c.T[l];
+            level_step(&c, l, dt, 0, l > 0 ? own[l] : NULL);
+            note(&c, orc_fmr_restrict(f, l + 1, c.U[l + 1], c.U[l]));
+            c.T[l] += dt;
+        }
+    }
     for (int l = 1; l < f->nlev; ++l)
         if (c.T[l] != c.T[0]) note(&c, ORC_EINVAL);
     *dt_out = c.T[0];
     for (int l = 0; l < f->nlev; ++l) {
         free(c.ext[l]);
+        free(saved[l]);
         for (int q = 0; q < 3; ++q)
-            for (int s = 0; s < 2; ++s) free(c.from_children[l][q][s]);
+            for (int s = 0; s < 2; ++s) {
+                free(c.from_children[l][q][s]);
+                free(own[l][q][s]);
+            }
     }
     return c.status;
 }
