@@ -149,7 +149,8 @@ __global__ void __launch_bounds__(BT) k_batch(const TubeDesc *__restrict__ tubes
                     const float D = S[k][0], ir = rcpf_(D);
                     const float v = S[k][1] * ir;
                     const float p = gm1 * (S[k][2] - 0.5f * S[k][1] * v);
-                    bad |= !((D > 0.f) & (p > 0.f) & (D < 3e38f) & (p < 3e38f));
+                    // rho and p positive and finite (one class test each)
+                    bad |= !(__builtin_amdgcn_classf(D, 0x180) & __builtin_amdgcn_classf(p, 0x180));
                     sW[0 * SW + i + 2] = D;
                     sW[1 * SW + i + 2] = v;
                     sW[2 * SW + i + 2] = p;

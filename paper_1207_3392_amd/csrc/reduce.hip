@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(RB) k_cfl_rate(const T *u, int64_t ncell, int6
             v[d] = s / D;
         }
         const T p = gm1 * (u[c + (ndim + 1) * vs] - T(0.5) * s2 / D);
-        bad |= !((D > T(0)) && (p > T(0)) && (D < T(3e38)) && (p < T(3e38)));
+        bad |= !((D > T(0)) && (p > T(0)) && isfinite(D) && isfinite(p));  // positive and finite
         const T cs = sqrt_(gamma * p / D);
         const double id[3] = {idx0, idx1, idx2};
         for (int d = 0; d < ndim; ++d) r = fmax(r, ((double)fabs(v[d]) + (double)cs) * id[d]);
