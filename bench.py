@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--tile", default="", help="override the plane tile, e.g. 64x8 or 32x16")
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
                                                    "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch",
-                                                   "fmr_sedov3d", "fmr_sedov2d_7levels", "kh_spectrum_2048"],
+                                                   "fmr_sedov3d", "fmr_sedov2d_7levels", "kh_spectrum_2048",
+                                                   "hllc_slab"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -104,13 +105,17 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
-def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4, graph=True):
+def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4, graph=True, nz=None):
+    """The smooth-flow patch n x n x nz (nz = n by default; a thinner patch
+    keeps cubic cells: its z extent shrinks to nz / n)."""
     import torch
 
     from paper_1207_3392_amd import hydro
     from paper_1207_3392_amd import workloads as wl
 
-    prob = wl.smooth_periodic_3d(n)
+    nz = n if nz is None else nz
+    prob = wl.smooth_periodic_3d(n, nz=nz)
+    prob.hi = (prob.hi[0], prob.hi[1], prob.lo[2] + nz / n)
     p = hydro.Patch(prob, precision=32)
     del prob
     cfg = p.kernel_config()
@@ -142,7 +147,7 @@ def time_patch(n, solver, steps, warmup, timing=True, cfl=0.4, graph=True):
         p.advance(steps, cfl, solver=sv)
     ms, launches = p.kernel_times()
     p.cfl_dt(cfl)  # raises if the state went non-physical
-    ncell = n ** 3
+    ncell = n * n * nz
     stage_ms = [float(ms[0] / max(launches[0], 1)), float(ms[1] / max(launches[1], 1))]
     res = {
         "wall_s": wall,
@@ -376,6 +381,11 @@ def roofline(res):
     }
 
 
+def slab_figures(r):
+    return {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
+            "stage_ms": r["stage_ms"], "kernel": r["kernel"], "roofline": roofline(r)}
+
+
 def host_cpus():
     """Host CPU description: usable threads and the model name."""
     usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -450,7 +460,8 @@ def main():
                "kh_spectrum_2048": time_spectrum,
                "fmr_sedov2d_7levels": lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1),
                "hllc_switch": lambda: {k: v for k, v in time_patch(args.n, "hllc_switch", args.steps,
-                                                                    args.warmup).items() if k != "kernel"}}[args.only]
+                                                                    args.warmup).items() if k != "kernel"},
+               "hllc_slab": lambda: slab_figures(time_patch(512, "hllc", args.steps, args.warmup, nz=64))}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -465,8 +476,8 @@ def main():
             except Exception as e:  # noqa: BLE001
                 extra[name] = {"error": f"{type(e).__name__}: {e}"}
 
-        def patch(n, solver, cfl, steps=args.steps):
-            r = time_patch(n, solver, steps, args.warmup, cfl=cfl)
+        def patch(n, solver, cfl, steps=args.steps, nz=None):
+            r = time_patch(n, solver, steps, args.warmup, cfl=cfl, nz=nz)
             out = {"zone_updates_per_s": r["zone_updates_per_s"], "ms_per_step": r["ms_per_step"],
                    "stage_ms": r["stage_ms"], "cfl": cfl}
             if solver in ("hll", "hllc"):
@@ -482,6 +493,10 @@ def main():
         # the smooth-flow configuration at 256^3, both solvers, 100 steps
         guarded("hllc_256", lambda: patch(256, "hllc", 0.4, 100))
         guarded("hll_256", lambda: patch(256, "hll", 0.3, 100))
+        # one GPU's share of the 512^3 patch split into 8 z-slabs: 512 x 512
+        # x 64 cubic cells (periodic in z here, where a split run would read
+        # its z halo from the neighbours' exchanged planes)
+        guarded("hllc_slab_512x512x64", lambda: patch(512, "hllc", 0.4, nz=64))
         # HLLC with HLL at faces transverse to shocks (this flow has no
         # shocks, so every face still takes HLLC; the cost is the detector
         # and the switch kernels)

@@ -195,14 +195,18 @@ def test_rayleigh_taylor_512_200_steps_learned_vs_plain_and_oracle_subbox():
     assert diff < 1e-4, diff  # measured 2.2e-6: at t = 0.06 the interface has barely moved
 
 
-@pytest.mark.parametrize("solver,cfl", [(oracle.HLLC, 0.4), (oracle.HLL, 0.3), (oracle.HLLC_SWITCH, 0.4)])
-def test_smooth_periodic_512_graph_replayed_step_sampled(solver, cfl):
+@pytest.mark.parametrize("solver,cfl,nz", [(oracle.HLLC, 0.4, 512), (oracle.HLL, 0.3, 512),
+                                           (oracle.HLLC_SWITCH, 0.4, 512), (oracle.HLLC, 0.4, 64)])
+def test_smooth_periodic_512_graph_replayed_step_sampled(solver, cfl, nz):
     """The 512^3 periodic smooth flow (FP32, gamma 5/3) in the benchmark's
-    launch configuration: two launched steps, then one step replayed from a
-    captured graph with the step size from the device's CFL reduction.  The
-    step size matches the oracle's CFL step of the whole state, and sampled
-    sub-boxes match the oracle's step of a box with a 4-cell halo."""
-    prob = wl.smooth_periodic_3d(512)
+    launch configuration, and the 512 x 512 x 64 slab of cubic cells (one
+    GPU's share of the 512^3 patch split eight ways): two launched steps, then
+    one step replayed from a captured graph with the step size from the
+    device's CFL reduction.  The step size matches the oracle's CFL step of
+    the whole state, and sampled sub-boxes match the oracle's step of a box
+    with a 4-cell halo."""
+    prob = wl.smooth_periodic_3d(512, nz=nz)
+    prob.hi = (prob.hi[0], prob.hi[1], prob.lo[2] + nz / 512)
     d = oracle.Desc.from_problem(prob, solver=solver, theta=2.0, shock_fp32=True)
     p = hydro.Patch(prob, precision=32)
     p.advance(2, cfl, solver=solver)
@@ -216,7 +220,7 @@ def test_smooth_periodic_512_graph_replayed_step_sampled(solver, cfl):
     assert dt == pytest.approx(oracle.cfl_dt(d, U0, cfl), rel=2e-6)
     rng = np.random.default_rng(5)
     for _ in range(6):
-        lo = rng.integers(0, 512, size=3)
+        lo = rng.integers(0, (512, 512, nz))
         ref, idx, cmp = oracle_box_step(prob, U0, lo, 8, 4, ("wrap",) * 3, dt, solver=solver, theta=2.0,
                                         shock_fp32=True)
         got = gpu_box(prob, U1, idx, cmp)
