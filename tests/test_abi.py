@@ -58,6 +58,36 @@ def test_workspace_size_and_host_validation():
     assert b"FP32" in L.hy_last_error()
 
 
+def test_batch_workspace_and_host_validation():
+    """Host checks of the batched tubes: 1D FP32 generalised-minmod tubes of
+    2 .. 6144 cells; longer tubes, an empty batch, other dimensions,
+    precisions, limiters or a source term are refused before any device
+    work."""
+    L = hydro.lib()
+
+    def tube(n, precision=32, **kw):
+        return hydro.make_desc(1, (n, 1, 1), (0, 0, 0), (1, 1, 1), 1.4, ((1, 1), (0, 0), (0, 0)),
+                               precision=precision, **kw)
+
+    def nbytes(descs):
+        arr = (hydro.PatchDesc * max(len(descs), 1))(*descs)
+        nb = ctypes.c_size_t(0)
+        return L.hy_batch_workspace_bytes(arr, len(descs), ctypes.byref(nb)), nb.value
+
+    st, nb = nbytes([tube(2), tube(6144), tube(3)])
+    assert st == hydro.HY_OK and nb >= 2 * 3 * 4 * (2 + 6144 + 3)
+    assert nbytes([tube(6145)])[0] == hydro.HY_EINVAL
+    assert nbytes([tube(1)])[0] == hydro.HY_EINVAL
+    assert nbytes([])[0] == hydro.HY_EINVAL
+    assert nbytes([tube(64), tube(64, precision=64)])[0] == hydro.HY_EUNSUPPORTED
+    two_d = hydro.make_desc(2, (8, 8, 1), (0, 0, 0), (1, 1, 1), 1.4, ((1, 1),) * 3, precision=32)
+    assert nbytes([two_d])[0] == hydro.HY_EUNSUPPORTED
+    assert nbytes([tube(64, limiter=hydro.LIM_LEARNED)])[0] == hydro.HY_EUNSUPPORTED
+    grav = tube(64)
+    grav.accel[0] = 0.1
+    assert nbytes([grav])[0] == hydro.HY_EUNSUPPORTED
+
+
 def _fmr_desc(ndim, n, boxes, limiter=0, precision=32):
     f = hydro.FmrDesc()
     f.base = hydro.make_desc(ndim, n, (0, 0, 0), (1, 1, 1), 1.4, ((1, 1),) * 3, precision=precision,

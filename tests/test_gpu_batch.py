@@ -54,6 +54,52 @@ def test_small_batch_matches_oracle(solver):
     B.close()
 
 
+def test_extreme_tube_sizes_match_oracle():
+    """Tubes of the smallest and the largest sizes the batch takes (2, 3 and
+    5 cells; 6143 and 6144, which select the register footprint for tubes
+    longer than 4096 cells) under each boundary kind, against the oracle;
+    the 256-thread workgroups give bitwise the same tubes as the 1024-thread
+    ones, and the tiny tubes run alone (the footprint for tubes up to 4096
+    cells) the same as beside the longest."""
+    base = wl.batched_tubes(15, seed=31)
+    sizes = (2, 3, 5, 6143, 6144)
+    probs = []
+    for k, t in enumerate(base):
+        n = sizes[k % 5]
+        pr = wl.tube_problem(wl.Tube(n, t.left, t.right, (n // 2) / n), t_end=0.002)
+        b = (wl.BC_OUTFLOW, wl.BC_REFLECT, wl.BC_PERIODIC)[k // 5]
+        pr.bc = ((b, b), (0, 0), (0, 0))
+        probs.append(pr)
+    B = hydro.Batch(probs)
+    got = {}
+    for bt in (1024, 256):
+        for i, pr in enumerate(probs):
+            B.set_state(i, pr.W)
+        B.set_block(bt)
+        B.run_to(0.002, 0.4, hydro.HLLC)
+        got[bt] = [B.get_state(i, hydro.PRIMITIVE) for i in range(len(probs))]
+        for i in range(len(probs)):
+            steps, t = B.status(i)
+            assert t == pytest.approx(0.002, rel=1e-12) and steps > 0, (bt, i)
+    B.close()
+    # the tiny tubes alone take the footprint for tubes up to 4096 cells
+    small = [i for i, pr in enumerate(probs) if pr.n[0] < 6]
+    S = hydro.Batch([probs[i] for i in small])
+    S.run_to(0.002, 0.4, hydro.HLLC)
+    for j, i in enumerate(small):
+        assert np.array_equal(S.get_state(j, hydro.PRIMITIVE), got[1024][i]), i
+    S.close()
+    for i, pr in enumerate(probs):
+        assert np.array_equal(got[256][i], got[1024][i]), i
+        d = oracle.Desc.from_problem(pr, solver=oracle.HLLC)
+        U, osteps = oracle.run(d, oracle.prim_to_cons(d, pr.flat()), 0.002, 0.4)
+        Wr = oracle.cons_to_prim(d, U)
+        W = got[1024][i]
+        l1 = rel_l1(W[[0, 2]], Wr[[0, 2]])
+        assert np.all(l1 < 1e-5), (i, pr.n, l1)
+        assert np.max(np.abs(W[1] - Wr[1])) < 1e-3 * (np.max(np.abs(Wr[1])) + 1.0), (i, pr.n)
+
+
 def test_batch_replays_and_matches_single_patch_kernel():
     """Two replays of the captured graph give bitwise identical results, and
     a tube advanced by the batch equals the same tube advanced by the patch
