@@ -97,6 +97,18 @@ def test_3d_random_patch_ragged(prec, solver, bc):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("solver", [oracle.HLL, oracle.HLLC])
+@pytest.mark.parametrize("bc", [wl.BC_PERIODIC, wl.BC_OUTFLOW, wl.BC_REFLECT])
+def test_smallest_patches(prec, solver, bc):
+    """Patches of the fewest cells an active dimension takes (two: every
+    ghost layer maps onto the interior) and a few more, in 1D, 2D and 3D."""
+    for k, n in enumerate(((2,), (3,), (2, 2), (3, 2), (2, 5), (2, 2, 2), (3, 2, 4), (2, 3, 2))):
+        prob = wl.random_smooth_patch(len(n), n, seed=500 + 10 * bc + k, bc=bc)
+        U, R = one_step_case(prob, solver, prec, theta=1.4, nsteps=2, cfl=0.3)
+        assert_close(U, R, prec, n)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
 def test_3d_mixed_boundaries_and_gravity(prec):
     prob = wl.random_smooth_patch(3, (20, 9, 18), seed=7)
     prob.bc = ((0, 0), (1, 2), (2, 2))
