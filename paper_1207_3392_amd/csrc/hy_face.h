@@ -145,20 +145,28 @@ __device__ __forceinline__ void riemann(const T (&wl)[ND + 2], const T (&wr)[ND 
         }
         const T El = pl * inv_gm1 + T(0.5) * rl * kl;
         const T Er = pr * inv_gm1 + T(0.5) * rr * kr;
-        const T ml = rl * vl, mr = rr * vr;  // mass fluxes
-        // F = (a+ F_L + a- F_R - a+ a- (U_R - U_L)) / (a+ + a-), formed one
-        // variable at a time with the weights folded; a+ + a- = 0 (both sides
-        // at rest with c = 0) gives the mean of the two fluxes
+        // F = (a+ F_L + a- F_R - a+ a- (U_R - U_L)) / (a+ + a-).  With the
+        // physical flux F = v U + P (P: p in the normal momentum, p v in the
+        // energy) each side's state enters once:
+        //   F = cL U_L + cR U_R + wL P_L + wR P_R,
+        //   wL = a+ / (a+ + a-), wR = a- / (a+ + a-),
+        //   cL = wL (v_L + a-), cR = wR (v_R - a+).
+        // a+ + a- = 0 (both sides at rest with c = 0, so a+ = a- = 0) takes
+        // wL = wR = 1/2, which makes the same coefficients the mean of the
+        // two fluxes.
         const T den = ap + am;
         const bool pos = den > T(0);
         const T inv = pos ? rcp_(den) : T(0);
-        const T wL = pos ? ap * inv : T(0.5), wR = pos ? am * inv : T(0.5), wD = ap * am * inv;
-        f[0] = wL * ml + wR * mr - wD * (rr - rl);
+        const T wL = pos ? ap * inv : T(0.5), wR = pos ? am * inv : T(0.5);
+        const T cL = wL * (vl + am), cR = wR * (vr - ap);
+        const T gL = cL * rl, gR = cR * rr;  // the coefficients of the velocities in the momentum
+        f[0] = gL + gR;
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-            f[1 + d] = wL * (ml * wl[1 + d] + (d == Q ? pl : T(0))) + wR * (mr * wr[1 + d] + (d == Q ? pr : T(0))) -
-                       wD * (rr * wr[1 + d] - rl * wl[1 + d]);
-        f[IP] = wL * ((El + pl) * vl) + wR * ((Er + pr) * vr) - wD * (Er - El);
+        for (int d = 0; d < ND; ++d) {
+            if (d == Q) f[1 + d] = gL * wl[1 + d] + (gR * wr[1 + d] + (wL * pl + wR * pr));
+            else f[1 + d] = gL * wl[1 + d] + gR * wr[1 + d];
+        }
+        f[IP] = cL * El + (cR * Er + (wL * (pl * vl) + wR * (pr * vr)));
     } else {
         // Batten's middle-wave speed (eq. MiddleWaveSpeed):
         // (A v_R + B v_L + p_L - p_R) / (A + B), A = rho_R (a+ - v_R), B = rho_L (a- + v_L)
