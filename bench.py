@@ -65,10 +65,10 @@ TRAFFIC_SOURCES = ("paper_1207_3392_amd/csrc/stage.hip", "paper_1207_3392_amd/cs
                    "paper_1207_3392_amd/csrc/hy_face.h", "paper_1207_3392_amd/csrc/hy_ride.h",
                    "paper_1207_3392_amd/csrc/hy_fmr.h")
 TRAFFIC = {
-    "digest": "6c74da890d75f3d7a985bcef10cf847636892ab9c9a69c791047df8329f9fe4f",
+    "digest": "bb87021a86bd64c51b36a15b22c84a6c0c671165a1dc834b266959067077e1e0",
     "ncell": 512 ** 3,
     "kernel": "k_stage<nd=3,f32,tile=64x8> zchunk=64",
-    "bytes_per_launch": {1: 6028217221, 2: 9374582414},
+    "bytes_per_launch": {1: 6000718703, 2: 9367109005},
 }
 
 
