@@ -50,20 +50,21 @@ __device__ __forceinline__ void flux1(const float (&wl)[3], const float (&wr)[3]
     const float ap = fmaxf(0.f, fmaxf(sg * ul + vl, sg * ur + vr));
     const float am = fmaxf(0.f, fmaxf(sg * ul - vl, sg * ur - vr));
     if (solver == 0) {
+        // HLL with each side's state entering once, as in hy_face.h:
+        // F = cL U_L + cR U_R + wL P_L + wR P_R (P: p in the momentum, p v in
+        // the energy), wL = a+ / (a+ + a-), wR = a- / (a+ + a-), cL = wL (v_L
+        // + a-), cR = wR (v_R - a+); a+ + a- = 0 takes wL = wR = 1/2 (the
+        // mean of the two fluxes)
         const float El = pl * igm1 + 0.5f * rl * vl * vl, Er = pr * igm1 + 0.5f * rr * vr * vr;
-        const float ml = rl * vl, mr = rr * vr;
-        const float Fl[3] = {ml, ml * vl + pl, (El + pl) * vl};
-        const float Fr[3] = {mr, mr * vr + pr, (Er + pr) * vr};
-        const float Ul[3] = {rl, ml, El}, Ur[3] = {rr, mr, Er};
         const float den = ap + am;
-        if (den > 0.f) {
-            const float inv = rcpf_(den), apam = ap * am;
-#pragma unroll
-            for (int v = 0; v < 3; ++v) f[v] = (ap * Fl[v] + am * Fr[v] - apam * (Ur[v] - Ul[v])) * inv;
-        } else {
-#pragma unroll
-            for (int v = 0; v < 3; ++v) f[v] = 0.5f * (Fl[v] + Fr[v]);
-        }
+        const bool pos = den > 0.f;
+        const float inv = pos ? rcpf_(den) : 0.f;
+        const float wL = pos ? ap * inv : 0.5f, wR = pos ? am * inv : 0.5f;
+        const float cL = wL * (vl + am), cR = wR * (vr - ap);
+        const float gL = cL * rl, gR = cR * rr;
+        f[0] = gL + gR;
+        f[1] = gL * vl + (gR * vr + (wL * pl + wR * pr));
+        f[2] = cL * El + (cR * Er + (wL * (pl * vl) + wR * (pr * vr)));
         return;
     }
     // HLLC: Batten's middle speed, the middle state on the side K it selects
