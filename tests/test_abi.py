@@ -52,6 +52,16 @@ def test_workspace_size_and_host_validation():
     ]
     for d in bad:
         assert L.hy_patch_workspace_bytes(ctypes.byref(d), ctypes.byref(nb)) == hydro.HY_EINVAL
+    # the largest patches: one variable's array below 4 GiB (32-bit cell
+    # offsets in the kernels), n_x <= 2^20, n_y and n_z <= 65535
+    big = hydro.make_desc(3, (1000, 1000, 1000), (0, 0, 0), (1, 1, 1), 5 / 3, ((0, 0),) * 3, precision=32)
+    assert L.hy_patch_workspace_bytes(ctypes.byref(big), ctypes.byref(nb)) == hydro.HY_OK
+    assert nb.value >= 2 * 5 * 10 ** 9 * 4
+    for n, prec in (((1024, 1024, 1024), 32), ((1000, 1000, 600), 64), ((1 << 20 | 1, 1, 1), 32),
+                    ((64, 65536, 1), 32)):
+        too = hydro.make_desc(len([v for v in n if v > 1]) if n[2] == 1 else 3, n, (0, 0, 0), (1, 1, 1), 1.4,
+                              ((0, 0),) * 3, precision=prec)
+        assert L.hy_patch_workspace_bytes(ctypes.byref(too), ctypes.byref(nb)) == hydro.HY_EINVAL, n
     learned64 = hydro.make_desc(2, (8, 8, 1), (0, 0, 0), (1, 1, 1), 1.4, ((0, 0),) * 3, precision=64,
                                 limiter=hydro.LIM_LEARNED)
     assert L.hy_patch_workspace_bytes(ctypes.byref(learned64), ctypes.byref(nb)) == hydro.HY_EUNSUPPORTED
