@@ -226,3 +226,51 @@ def test_smooth_periodic_512_graph_replayed_step_sampled(solver, cfl, nz):
         got = gpu_box(prob, U1, idx, cmp)
         err = np.abs(got - ref) / scale(ref)
         assert err.max() < 2e-5 and err.mean() < 2e-6, (tuple(lo), err.max(), err.mean())
+
+
+def test_largest_patch_one_step_sampled():
+    """The largest patch the library takes in FP32: 1023 x 1023 x 1024 cells,
+    each variable's array 4.29e9 bytes, just under the 4 GiB that the
+    kernels' 32-bit byte offsets address (the host refuses one cell layer
+    more).  A smooth periodic shear flow with an FP32-representable
+    conserved state; one HLLC step checked on sampled sub-boxes, among them
+    boxes at the far end of the arrays (the largest offsets)."""
+    n = (1023, 1023, 1024)
+    nv = 5
+    gamma = 5.0 / 3.0
+    prob = wl.Problem(3, n, (0.0, 0.0, 0.0), (1.0, 1.0, 1024 / 1023), gamma, ((0, 0),) * 3, None, theta=2.0)
+    c = [np.cos(2 * np.pi * (np.arange(m) + 0.5) / m) for m in n]
+    s = [np.sin(2 * np.pi * (np.arange(m) + 0.5) / m) for m in n]
+    U = np.empty((nv, n[2], n[1], n[0]))
+    rho = U[0]
+    rho[...] = 1.0
+    rho += 0.1 * c[0][None, None, :]
+    rho += 0.1 * c[1][None, :, None]
+    rho += 0.1 * c[2][:, None, None]
+    np.multiply(rho, 0.1 * s[1][None, :, None], out=U[1])  # S_x = rho v_x(y)
+    np.multiply(rho, 0.1 * s[2][:, None, None], out=U[2])  # S_y = rho v_y(z)
+    np.multiply(rho, 0.1 * s[0][None, None, :], out=U[3])  # S_z = rho v_z(x)
+    for k in range(4):
+        U[k] = U[k].astype(np.float32)
+    # G = p / (gamma - 1) + |S|^2 / (2 rho), p = 1
+    G = U[4]
+    np.square(U[1], out=G)
+    G += np.square(U[2])
+    G += np.square(U[3])
+    G /= 2.0 * rho
+    G += 1.0 / (gamma - 1.0)
+    U[4] = G.astype(np.float32)
+    U = U.reshape(nv, -1)
+    p = hydro.Patch(prob, precision=32, set_initial=False)
+    p.set_state(U, hydro.CONSERVED)
+    dt = p.cfl_dt(0.4)
+    p.step(dt, hydro.HLLC)
+    U1 = p.get_state(hydro.CONSERVED)
+    p.close()
+    rng = np.random.default_rng(9)
+    los = [rng.integers(0, n) for _ in range(4)] + [np.array(n) - 8, np.array(n) - 5]
+    for lo in los:
+        ref, idx, cmp = oracle_box_step(prob, U, lo, 8, 4, ("wrap",) * 3, dt, solver=oracle.HLLC, theta=2.0)
+        got = gpu_box(prob, U1, idx, cmp)
+        err = np.abs(got - ref) / scale(ref)
+        assert err.max() < 2e-5 and err.mean() < 2e-6, (tuple(lo), err.max(), err.mean())
