@@ -266,7 +266,8 @@ hy_status hy_batch_autotune(hy_batch *b, double t_end, double cfl, int solver, i
 hy_status hy_batch_last_ms(hy_batch *b, double *ms);
 /* State of tube i; synchronising; HY_ESTATE if that tube met a bad state. */
 hy_status hy_batch_get_state(hy_batch *b, int i, int kind, double *host_soa_out);
-/* Steps taken and time reached by tube i in the last run; synchronising. */
+/* Steps taken and time reached by tube i in the last run (0 steps at t = 0
+ * before the first run); synchronising. */
 hy_status hy_batch_status(hy_batch *b, int i, int64_t *steps, double *t);
 hy_status hy_batch_destroy(hy_batch *b);
 

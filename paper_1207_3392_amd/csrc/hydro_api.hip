@@ -995,9 +995,14 @@ hy_status hy_batch_init(const hy_patch_desc *descs, int count, void *dev_workspa
     std::iota(ord.begin(), ord.end(), 0);
     hy::BatchCtl c{};
     c.max_steps = kBatchMaxSteps;
+    // every tube's status starts as "no step taken, no error": the
+    // workspace is the caller's memory and may hold anything
+    const std::vector<hy::TubeStatus> st0(count, hy::TubeStatus{});
     int dev = 0, cus = 0;
     hipError_t e = hipMemcpyAsync(b->tubes, td.data(), sizeof(hy::TubeDesc) * count, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->order, ord.data(), sizeof(int) * count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->status, st0.data(), sizeof(hy::TubeStatus) * count, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ctl, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hy::prepare_batch(b->nmax);

@@ -100,6 +100,24 @@ def test_extreme_tube_sizes_match_oracle():
         assert np.max(np.abs(W[1] - Wr[1])) < 1e-3 * (np.max(np.abs(Wr[1])) + 1.0), (i, pr.n)
 
 
+def test_status_before_the_first_run():
+    """A new batch reports every tube at 0 steps, t = 0, no error, whatever
+    the workspace memory held before (here a freed block filled with ones,
+    which the allocator is likely to hand out again)."""
+    import torch
+
+    probs = [wl.tube_problem(t, t_end=0.01) for t in wl.batched_tubes(5, seed=3, nmin=64, nmax=300)]
+    junk = torch.full((512 << 10,), 255, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    B = hydro.Batch(probs)
+    for i, pr in enumerate(probs):
+        assert B.status(i) == (0, 0.0), i
+        W = B.get_state(i, hydro.PRIMITIVE)
+        assert np.allclose(W, pr.flat(), rtol=1e-6, atol=0), i
+    B.close()
+
+
 def test_batch_replays_and_matches_single_patch_kernel():
     """Two replays of the captured graph give bitwise identical results, and
     a tube advanced by the batch equals the same tube advanced by the patch
