@@ -334,6 +334,30 @@ def test_smooth_periodic_256_sampled_against_oracle(solver):
 
 
 @pytest.mark.parametrize("nd", [2, 3])
+def test_graph_replayed_learned_steps_equal_launched_steps(nd):
+    """The learned limiter's steps (slope launches, then the stage kernels
+    reading the slopes) replayed from a captured graph: bit for bit the eager
+    steps, over repeated replays."""
+    from paper_1207_3392_amd import limiter
+
+    n = (70, 20) if nd == 2 else (70, 20, 13)
+    prob = wl.random_smooth_patch(nd, n, seed=33, bc=wl.BC_PERIODIC)
+    P = limiter.trained_params()
+    a = hydro.Patch(prob, precision=32, limiter=hydro.LIM_LEARNED)
+    b = hydro.Patch(prob, precision=32, limiter=hydro.LIM_LEARNED)
+    a.set_mlp(P)
+    b.set_mlp(P)
+    b.advance_graph(3, 0.3, solver=hydro.HLLC, prepare_only=True)
+    for rep in range(3):
+        a.advance(3, 0.3, solver=hydro.HLLC)
+        b.advance_graph(3, 0.3, solver=hydro.HLLC)
+        assert np.array_equal(a.get_state(), b.get_state()), rep
+        assert a.time() == b.time()
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("nd", [2, 3])
 def test_launch_shapes_give_identical_results_and_autotune(nd, tmp_path):
     """Every supported plane tile computes the same cells with the same
     arithmetic, so two steps agree bit for bit for a given z chunk; z chunks
