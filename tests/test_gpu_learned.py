@@ -215,6 +215,31 @@ def test_learned_limiter_step_matches_oracle():
         p.close()
 
 
+@pytest.mark.parametrize("bc", [wl.BC_PERIODIC, wl.BC_OUTFLOW, wl.BC_REFLECT])
+def test_learned_limiter_on_the_smallest_patches(bc):
+    """The learned limiter's 5-cell stencil on patches of two to five cells
+    along a dimension: every stencil reaches ghost cells, whose slopes come
+    from the boundary map (periodic source, zero for outflow, mirrored for a
+    reflecting wall), against the oracle's step."""
+    P = random_params(8, scale=0.2)
+    for k, n in enumerate(((2,), (5,), (2, 3), (5, 2), (2, 2, 2), (3, 2, 5))):
+        prob = wl.random_smooth_patch(len(n), n, seed=70 + 10 * bc + k, bc=bc)
+        d = oracle.Desc.from_problem(prob, solver=oracle.HLLC, limiter=oracle.LIM_LEARNED,
+                                     mlp=P.astype(np.float64), mlp_bf16=True)
+        p = hydro.Patch(prob, precision=32, limiter=hydro.LIM_LEARNED, set_initial=False)
+        p.set_mlp(P)
+        p.set_state(prob.W)
+        U0 = p.get_state(hydro.CONSERVED)
+        dt = oracle.cfl_dt(d, U0, 0.3)
+        p.step(dt, hydro.HLLC)
+        U1 = p.get_state(hydro.CONSERVED)
+        p.close()
+        ref = oracle.step(d, U0, dt)
+        s = np.max(np.abs(ref), axis=1, keepdims=True)
+        err = np.abs(U1 - ref) / s
+        assert np.mean(err) < 2e-5 and err.max() < 2e-3, (n, np.mean(err), err.max())
+
+
 def test_training_samples_match_oracle():
     prob = wl.kelvin_helmholtz(64)
     p = hydro.Patch(prob, precision=32)
