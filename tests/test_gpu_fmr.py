@@ -263,3 +263,22 @@ def test_multilevel_blast_tracks_the_single_level_run():
     assert abs(T[0] - T0[0]) < 1e-6 * T0[0] and abs(T[4] - T0[4]) < 1e-5 * T0[4]
     F.close()
     P.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("solver", [hydro.HLL, hydro.HLLC])
+def test_uniform_flow_stays_uniform(prec, solver):
+    """A uniform moving flow over nested levels (prolongation of a uniform
+    parent, coarse/fine replacement of equal fluxes, restriction of equal
+    children) stays uniform through three global steps to a few roundings."""
+    eps = 2.0 ** -52 if prec == 64 else 2.0 ** -23
+    for lv in (wl.smooth_levels(2, 32, 3, uniform=True), wl.smooth_levels(3, 16, 2, uniform=True)):
+        F = hydro.Fmr(lv, precision=prec)
+        U0 = [F.get_state(l, hydro.CONSERVED) for l in range(F.nlev)]
+        for _ in range(3):
+            F.step(0.4, solver=solver)
+        for l in range(F.nlev):
+            U = F.get_state(l, hydro.CONSERVED)
+            s = np.max(np.abs(U0[l]), axis=1, keepdims=True)
+            assert np.max(np.abs(U - U0[l]) / s) <= 8 * eps, (lv.base.ndim, l, np.max(np.abs(U - U0[l]) / s))
+        F.close()
