@@ -106,6 +106,15 @@ def test_spectrum_kelvin_helmholtz_full_size():
     p.close()
 
 
+def test_spectrum_largest_transform():
+    """N = 8192, the largest transform the device spectrum takes (one row of
+    2^13 points in LDS): every shell against the oracle's."""
+    prob = wl.random_smooth_patch(2, (8192, 8192), seed=8192, amp=0.3)
+    p = hydro.Patch(prob, precision=32)
+    _compare(p, prob)
+    p.close()
+
+
 def test_spectrum_rejects_unsupported_patches():
     cases = [wl.random_smooth_patch(2, (48, 48), seed=1),   # not a power of two
              wl.random_smooth_patch(2, (64, 32), seed=2),   # not square
