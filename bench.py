@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--only", default="", choices=["", "batched_tubes", "kh_2048_plain", "kh_2048_learned",
                                                    "rt_512_plain", "rt_512_learned", "matched_l1", "hllc_switch",
                                                    "fmr_sedov3d", "fmr_sedov2d_7levels", "kh_spectrum_2048",
-                                                   "hllc_slab"],
+                                                   "hllc_slab", "limiter_training"],
                     help="run only this extra workload and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (5 times), to calibrate HBM byte counters")
@@ -216,6 +216,47 @@ def time_kh(n=2048, steps=200, learned=False):
     p.cfl_dt(0.4)
     p.close()
     return {"zone_updates_per_s": n * n * steps / wall, "ms_per_step": 1e3 * wall / steps}
+
+
+def time_training(n=8192, batch=65536, steps=400):
+    """The learned limiter's training path (Sec. 4.3.1 flow, the task's
+    training configuration): samples from the Kelvin-Helmholtz state at n^2
+    restricted 4x per dimension (8 stencils per coarse cell: 4 primitives x 2
+    dimensions), then Adam steps on random batches of the samples (forward
+    and backward on the matrix cores, fixed-order gradient sum, FP32 master
+    weights).  A training step is about 3 x 2368 flops per sample (forward,
+    and the backward's two products per layer)."""
+    import torch
+
+    from paper_1207_3392_amd import hydro, limiter
+    from paper_1207_3392_amd import workloads as wl
+
+    p = hydro.Patch(wl.kelvin_helmholtz(n), precision=32)
+    x, t = p.make_samples()  # warm-up (code load)
+    del x, t
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, t = p.make_samples()  # synchronising
+    sample_s = time.perf_counter() - t0
+    p.close()
+    ns = int(t.numel())
+    gen = torch.Generator(device=x.device)
+    gen.manual_seed(1207)
+    idx = [torch.randint(0, ns, (batch,), device=x.device, dtype=torch.int32, generator=gen) for _ in range(8)]
+    tr = hydro.Trainer(limiter.init_params(1207), device=str(x.device))
+    for k in range(20):
+        tr.step(x, t, idx[k % 8], 1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        tr.step(x, t, idx[k % 8], 1e-3)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / steps
+    loss = tr.loss()
+    tr.close()
+    return {"fine_n": n, "samples": ns, "sample_ms": 1e3 * sample_s, "samples_per_s": ns / sample_s,
+            "batch": batch, "train_step_ms": 1e3 * step_s, "train_samples_per_s": batch / step_s,
+            "train_tflops": 3 * 2368 * batch / step_s / 1e12, "loss": loss}
 
 
 def time_spectrum(n=2048, reps=20):
@@ -463,6 +504,7 @@ def main():
                "rt_512_learned": lambda: time_rt(learned=True), "matched_l1": matched_l1,
                "fmr_sedov3d": time_fmr,
                "kh_spectrum_2048": time_spectrum,
+               "limiter_training": time_training,
                "fmr_sedov2d_7levels": lambda: time_fmr(nd=2, n0=256, nlev=7, steps=4, warmup=1),
                "hllc_switch": lambda: {k: v for k, v in time_patch(args.n, "hllc_switch", args.steps,
                                                                     args.warmup).items() if k != "kernel"},
@@ -513,6 +555,7 @@ def main():
         guarded("kh_2048_plain", lambda: time_kh(learned=False))
         guarded("kh_2048_learned", lambda: time_kh(learned=True))
         guarded("kh_spectrum_2048", time_spectrum)
+        guarded("limiter_training", time_training)
         guarded("rt_512_plain", lambda: time_rt(learned=False))
         guarded("rt_512_learned", lambda: time_rt(learned=True))
         kp, kl = extra.get("kh_2048_plain", {}), extra.get("kh_2048_learned", {})

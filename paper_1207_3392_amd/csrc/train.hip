@@ -431,20 +431,43 @@ __global__ void __launch_bounds__(64 * TW) k_train_grad(const MlpDevice *__restr
     }
 }
 
-// fixed-order sum of the workgroup partials
-__global__ void __launch_bounds__(256) k_grad_reduce(const float *__restrict__ partial, int nblocks, const float *__restrict__ loss_partial,
-                                                     float *__restrict__ grad, float *__restrict__ loss)
+// Fixed-order sum of the workgroup partials.  Workgroup g takes parameters
+// 64 g .. 64 g + 63 (the workgroup after the last one the loss); its wave w
+// sums rows w R .. w R + R - 1 in order (R = nblocks / GR_W rounded up), one
+// parameter per lane, and the GR_W wave sums are then added in wave order
+// through LDS: the same order on every call, and every wave's loads are
+// independent of each other (one pass per row instead of one per parameter
+// and row).
+constexpr int GR_W = 16;  // waves per workgroup of the gradient sum
+
+__global__ void __launch_bounds__(64 * GR_W) k_grad_reduce(const float *__restrict__ partial, int nblocks,
+                                                           const float *__restrict__ loss_partial,
+                                                           float *__restrict__ grad, float *__restrict__ loss)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < MLP_NPARAM) {
-        float s = 0.f;
-        for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * MLP_NPARAM + i];
-        grad[i] = s;
+    __shared__ float sp[GR_W][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool is_loss = (int)blockIdx.x == (MLP_NPARAM + 63) / 64;
+    const int i = (int)blockIdx.x * 64 + lane;
+    const int rows = (nblocks + GR_W - 1) / GR_W;
+    const int b0 = w * rows, b1 = min(b0 + rows, nblocks);
+    float s = 0.f;
+    if (is_loss) {
+        if (lane == 0)
+            for (int b = b0; b < b1; ++b) s += loss_partial[b];
+    } else if (i < MLP_NPARAM) {
+        for (int b = b0; b < b1; ++b) s += partial[(int64_t)b * MLP_NPARAM + i];
     }
-    if (i == MLP_NPARAM) {
-        float s = 0.f;
-        for (int b = 0; b < nblocks; ++b) s += loss_partial[b];
-        *loss = s;
+    sp[w][lane] = s;
+    __syncthreads();
+    if (w == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < GR_W; ++k) t += sp[k][lane];
+        if (is_loss) {
+            if (lane == 0) *loss = t;
+        } else if (i < MLP_NPARAM) {
+            grad[i] = t;
+        }
     }
 }
 
@@ -497,7 +520,7 @@ hipError_t launch_train_grad(const MlpDevice *m, const float *x, const float *t,
 {
     hipLaunchKernelGGL(k_train_grad, dim3(nblocks), dim3(64 * TW), 0, s, m, x, t, idx, batch, 1.0f / (float)batch,
                        partial, loss_partial);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, partial, nblocks,
+    hipLaunchKernelGGL(k_grad_reduce, dim3((MLP_NPARAM + 63) / 64 + 1), dim3(64 * GR_W), 0, s, partial, nblocks,
                        loss_partial, grad, loss);
     return hipGetLastError();
 }
