@@ -22,9 +22,23 @@ hipError_t launch_coarsen4(const float *U, int64_t vs, int ndim, const int nf[3]
                            hipStream_t s);
 hipError_t launch_samples(const float *Wc, const float *sub, int ndim, const int nc[3], float *x, float *t,
                           hipStream_t s);
+// One Adam step (Kingma & Ba) on the parameter vector m with moments m1, m2:
+// b1, b2 the decay rates and ob1 = 1 - b1, ob2 = 1 - b2, each rounded to
+// FP32 from its FP64 value; c1, c2 the bias corrections 1 / (1 - b^step),
+// formed in FP64 (in FP32, 1 - 0.999^t cancels to a few significant digits
+// at small t).  m == nullptr: no step.
+struct AdamStep {
+    MlpDevice *m;
+    float *m1, *m2;
+    float lr, b1, b2, ob1, ob2, eps, c1, c2;
+};
+AdamStep adam_step(MlpDevice *m, float *m1, float *m2, float lr, double b1, double b2, float eps, int step);
+
+// The gradient of the loss over the batch (per-workgroup partials, then their
+// fixed-order sum into grad and loss) and, when adam.m is set, the Adam step
+// on it, applied by the workgroups that form the sum.
 hipError_t launch_train_grad(const MlpDevice *m, const float *x, const float *t, const int *idx, int64_t batch,
-                             float *partial, float *loss_partial, int nblocks, float *grad, float *loss, hipStream_t s);
-hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, double b1, double b2,
-                       float eps, int step, hipStream_t s);
+                             float *partial, float *loss_partial, int nblocks, float *grad, float *loss,
+                             const AdamStep &adam, hipStream_t s);
 
 }  // namespace hy

@@ -1421,10 +1421,10 @@ hy_status hy_trainer_step(hy_trainer *tr, const float *x_dev, const float *t_dev
 {
     if (!tr || !x_dev || !t_dev || !idx_dev) return fail(HY_EINVAL, "null argument");
     if (batch < 1 || !(lr > 0.f)) return fail(HY_EINVAL, "batch must be >= 1 and lr > 0");
-    hipError_t e = hy::launch_train_grad(tr->m, x_dev, t_dev, idx_dev, batch, tr->partial, tr->lpart, hy::TRAIN_BLOCKS,
-                                         tr->grad, tr->loss, tr->stream);
     tr->step += 1;
-    if (e == hipSuccess) e = hy::launch_adam(tr->m, tr->grad, tr->m1, tr->m2, lr, 0.9, 0.999, 1e-8f, tr->step, tr->stream);
+    const hy::AdamStep ad = hy::adam_step(tr->m, tr->m1, tr->m2, lr, 0.9, 0.999, 1e-8f, tr->step);
+    hipError_t e = hy::launch_train_grad(tr->m, x_dev, t_dev, idx_dev, batch, tr->partial, tr->lpart, hy::TRAIN_BLOCKS,
+                                         tr->grad, tr->loss, ad, tr->stream);
     if (e != hipSuccess) return hip_fail(e, "training step");
     return HY_OK;
 }
@@ -1435,7 +1435,7 @@ hy_status hy_trainer_gradient(hy_trainer *tr, const float *x_dev, const float *t
     if (!tr || !x_dev || !t_dev || !idx_dev || !grad_host || !loss_host) return fail(HY_EINVAL, "null argument");
     if (batch < 1) return fail(HY_EINVAL, "batch must be >= 1");
     hipError_t e = hy::launch_train_grad(tr->m, x_dev, t_dev, idx_dev, batch, tr->partial, tr->lpart, hy::TRAIN_BLOCKS,
-                                         tr->grad, tr->loss, tr->stream);
+                                         tr->grad, tr->loss, hy::AdamStep{}, tr->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(grad_host, tr->grad, sizeof(float) * hy::MLP_NPARAM, hipMemcpyDeviceToHost, tr->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(loss_host, tr->loss, sizeof(float), hipMemcpyDeviceToHost, tr->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(tr->stream);

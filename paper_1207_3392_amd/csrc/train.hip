@@ -437,12 +437,14 @@ __global__ void __launch_bounds__(64 * TW) k_train_grad(const MlpDevice *__restr
 // parameter per lane, and the GR_W wave sums are then added in wave order
 // through LDS: the same order on every call, and every wave's loads are
 // independent of each other (one pass per row instead of one per parameter
-// and row).
+// and row).  With ad.m set, the lane that formed a parameter's gradient also
+// takes that parameter's Adam step (elementwise, so no other workgroup waits).
 constexpr int GR_W = 16;  // waves per workgroup of the gradient sum
 
 __global__ void __launch_bounds__(64 * GR_W) k_grad_reduce(const float *__restrict__ partial, int nblocks,
                                                            const float *__restrict__ loss_partial,
-                                                           float *__restrict__ grad, float *__restrict__ loss)
+                                                           float *__restrict__ grad, float *__restrict__ loss,
+                                                           AdamStep ad)
 {
     __shared__ float sp[GR_W][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -460,32 +462,23 @@ __global__ void __launch_bounds__(64 * GR_W) k_grad_reduce(const float *__restri
     sp[w][lane] = s;
     __syncthreads();
     if (w == 0) {
-        float t = 0.f;
+        float g = 0.f;
 #pragma unroll
-        for (int k = 0; k < GR_W; ++k) t += sp[k][lane];
+        for (int k = 0; k < GR_W; ++k) g += sp[k][lane];
         if (is_loss) {
-            if (lane == 0) *loss = t;
+            if (lane == 0) *loss = g;
         } else if (i < MLP_NPARAM) {
-            grad[i] = t;
+            grad[i] = g;
+            if (ad.m) {
+                float *p = reinterpret_cast<float *>(ad.m) + i;  // MlpDevice is the flat parameter vector (ABI order)
+                const float a = ad.b1 * ad.m1[i] + ad.ob1 * g;
+                const float v = ad.b2 * ad.m2[i] + ad.ob2 * g * g;
+                ad.m1[i] = a;
+                ad.m2[i] = v;
+                *p -= ad.lr * (a * ad.c1) / (sqrtf(v * ad.c2) + ad.eps);
+            }
         }
     }
-}
-
-// Adam (Kingma & Ba): b1, b2 the decay rates and ob1 = 1 - b1, ob2 = 1 - b2,
-// each rounded to FP32 from its FP64 value; c1, c2 the bias corrections.
-__global__ void __launch_bounds__(256) k_adam(MlpDevice *m, const float *__restrict__ grad, float *__restrict__ mom1,
-                                              float *__restrict__ mom2, float lr, float b1, float b2, float ob1,
-                                              float ob2, float eps, float c1, float c2)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= MLP_NPARAM) return;
-    float *p = reinterpret_cast<float *>(m) + i;  // MlpDevice is the flat parameter vector (ABI order)
-    const float g = grad[i];
-    const float a = b1 * mom1[i] + ob1 * g;
-    const float v = b2 * mom2[i] + ob2 * g * g;
-    mom1[i] = a;
-    mom2[i] = v;
-    *p -= lr * (a * c1) / (sqrtf(v * c2) + eps);
 }
 
 }  // namespace
@@ -516,12 +509,13 @@ hipError_t launch_samples(const float *Wc, const float *sub, int ndim, const int
 }
 
 hipError_t launch_train_grad(const MlpDevice *m, const float *x, const float *t, const int *idx, int64_t batch,
-                             float *partial, float *loss_partial, int nblocks, float *grad, float *loss, hipStream_t s)
+                             float *partial, float *loss_partial, int nblocks, float *grad, float *loss,
+                             const AdamStep &adam, hipStream_t s)
 {
     hipLaunchKernelGGL(k_train_grad, dim3(nblocks), dim3(64 * TW), 0, s, m, x, t, idx, batch, 1.0f / (float)batch,
                        partial, loss_partial);
     hipLaunchKernelGGL(k_grad_reduce, dim3((MLP_NPARAM + 63) / 64 + 1), dim3(64 * GR_W), 0, s, partial, nblocks,
-                       loss_partial, grad, loss);
+                       loss_partial, grad, loss, adam);
     return hipGetLastError();
 }
 
@@ -555,16 +549,21 @@ hipError_t samples_static_scratch(int device, float **ptr)
     return hipSuccess;
 }
 
-hipError_t launch_adam(MlpDevice *m, const float *grad, float *m1, float *m2, float lr, double b1, double b2,
-                       float eps, int step, hipStream_t s)
+AdamStep adam_step(MlpDevice *m, float *m1, float *m2, float lr, double b1, double b2, float eps, int step)
 {
-    // 1 - beta and the bias corrections 1 / (1 - beta^t) are formed in FP64:
-    // in FP32, 1 - 0.999^t cancels to a few significant digits at small t
-    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)step)));
-    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)step)));
-    hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, m, grad, m1, m2, lr, (float)b1,
-                       (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), eps, c1, c2);
-    return hipGetLastError();
+    AdamStep a{};
+    a.m = m;
+    a.m1 = m1;
+    a.m2 = m2;
+    a.lr = lr;
+    a.b1 = (float)b1;
+    a.b2 = (float)b2;
+    a.ob1 = (float)(1.0 - b1);
+    a.ob2 = (float)(1.0 - b2);
+    a.eps = eps;
+    a.c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)step)));
+    a.c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)step)));
+    return a;
 }
 
 }  // namespace hy
